@@ -1,0 +1,260 @@
+"""Benchmark: one MI355X, n = 2^20 thin-plate-spline interpolation.
+
+A step is one pass of the whole hot path on the resident synthetic workload:
+plan (normalise, quadtree, polynomial block + QR) -> Vecchia/Matern
+preconditioner build -> projected PCG to 1e-8 relative residual (FMM matvecs)
+-> beta recovery -> evaluation at 10^4 targets.  Inputs live in HBM before the
+timed region starts.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed]
+
+Prints ONE JSON line.  `value` is solved nodes per second (Mpts/s) over the
+whole step; the line also carries the solve seconds, PCG iterations, the FMM
+matvec throughput in FP64 and mixed precision, the roofline of the dominant
+kernel (timed with HIP events on its own stream inside the timed region) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (packed)
+
+# Algorithmic flop counts used for the roofline:
+#  near-field pair: 2 sub, r^2 (mul + fma = 3), 1 transcendental, phi scale
+#  (2 mul), accumulate (fma = 2)  -> 10 flops
+#  local-expansion evaluation (Horner) per node and density: P complex
+#  multiply-adds (8 flops each) + combine (2)
+#  M2L per (target, source, density): (P+1)^2 real-by-complex MACs (4 flops)
+#  + 12 (P+1) for the two diagonal scalings
+FLOP_PAIR = 10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+def tree_work(order_leaf: np.ndarray, L: int, n: int):
+    """Near-field pair count and leaf counts from the plan's leaf keys."""
+    G = 1 << L
+    counts = np.bincount(order_leaf, minlength=G * G).reshape(G, G)  # [iy, ix]
+    pad = np.pad(counts, 1)
+    nb = sum(pad[1 + dy:1 + dy + G, 1 + dx:1 + dx + G]
+             for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    pairs = int((counts * nb).sum())
+    # interaction-list pairs per level (uniform tree, boundary clipped)
+    m2l_pairs = 0
+    for l in range(2, L + 1):
+        g = 1 << l
+        ii = np.arange(g)
+        cnt = 0
+        for oy in range(-3, 4):
+            for ox in range(-3, 4):
+                if abs(ox) <= 1 and abs(oy) <= 1:
+                    continue
+                jx = ii + ox
+                okx = (jx >= 0) & (jx < g) & (np.abs((jx >> 1) - (ii >> 1)) <= 1)
+                jy = ii + oy
+                oky = (jy >= 0) & (jy < g) & (np.abs((jy >> 1) - (ii >> 1)) <= 1)
+                cnt += int(okx.sum()) * int(oky.sum())
+        m2l_pairs += cnt
+    return pairs, m2l_pairs
+
+
+def source_sha(name: str) -> str:
+    h = hashlib.sha256()
+    h.update((ROOT / "paper_2608_11462_amd" / "csrc" / name).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current source of the kernel."""
+    f = ROOT / "profiles" / f"traffic_{kernel}_{workload}.json"
+    if not f.exists():
+        return None
+    d = json.loads(f.read_text())
+    if d.get("source_sha") != source_sha(d["source"]):
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(seed: int = 3, n_s: int = 4096, n_t: int = 10000):
+    """The CPU oracle (dense FP64 complement solve + evaluation) on a bounded
+    sample of the same workload: n_s nodes of the same distribution and field."""
+    from oracle import phs_dense as D
+    from paper_2608_11462_amd import workloads as W
+    pr = W.large_tps(seed=seed, n=n_s, n_targets=n_t)
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        sol = D.solve_complement(pr.xy, pr.f, 2, 1)
+        D.interpolant(sol, 2, pr.targets)
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": n_s / t / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
+            "sample": f"dense FP64 complement solve + {n_t}-target evaluation on {n_s} nodes "
+                      f"of the same workload (median of 3: {t:.2f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are "
+                          "not part of it (see DESIGN.md for how the path would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2608_11462_amd import native as N
+    from paper_2608_11462_amd import workloads as W
+
+    prec = N.PHS_FP64 if args.precision == "fp64" else N.PHS_MIXED
+    pr = W.large_tps(n=args.n)
+    dev = torch.device("cuda")
+    xy = torch.as_tensor(pr.xy, device=dev)
+    f = torch.as_tensor(pr.f, device=dev)
+    tg = torch.as_tensor(pr.targets, device=dev)
+    torch.cuda.synchronize()
+
+    phases = {"plan": 0.0, "precond": 0.0, "solve": 0.0, "eval": 0.0}
+    last = {}
+
+    def step(record: bool):
+        t0 = time.perf_counter()
+        pl = N.Plan(xy, 2, 1, precision=prec)
+        t1 = time.perf_counter()
+        pl.precond_build(m=30, nu=1.0, seed=0)
+        t2 = time.perf_counter()
+        w, beta, info = pl.solve(f, rtol=1e-8)
+        t3 = time.perf_counter()
+        s = pl.eval(w, beta, tg)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        if record:
+            phases["plan"] += t1 - t0
+            phases["precond"] += t2 - t1
+            phases["solve"] += t3 - t2
+            phases["eval"] += t4 - t3
+            last.update(iters=info.iters, outer=info.outer_refinements,
+                        resid=info.rel_residual, L=pl.leaf_level, P=pl.order, R=pl.R)
+            last["leaf"] = pl.tree()[1]
+        pl.close()
+        return s
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        N.profile_enable(True)
+        N.profile_read()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {}
+    if not args.no_profile:
+        prof = N.profile_read()
+        N.profile_enable(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    n = pr.n
+
+    # matvec throughput on a prebuilt plan (not part of `value`)
+    pl = N.Plan(xy, 2, 1)
+    v = torch.as_tensor(W.rng_for(17).standard_normal(n), device=dev)
+    mv = {}
+    for name, p in (("fp64", N.PHS_FP64), ("mixed", N.PHS_MIXED)):
+        for _ in range(2):
+            pl.matvec(v, p)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            pl.matvec(v, p)
+        torch.cuda.synchronize()
+        mv[name] = n / ((time.perf_counter() - t) / reps) / 1e6
+    pl.close()
+
+    # roofline of the dominant kernel (HIP-event durations from the timed region)
+    roof = None
+    if prof:
+        dom = max(prof.items(), key=lambda kv: kv[1][1])
+        kname, (launches, total_ms) = dom
+        avg_s = total_ms / launches / 1e3
+        leaf = last["leaf"].cpu().numpy()
+        pairs, m2l_pairs = tree_work(leaf, last["L"], n)
+        P, R = last["P"], last["R"]
+        if prec == N.PHS_MIXED:
+            P = 15
+        flops = None
+        if kname == "leaf_eval":
+            flops = pairs * FLOP_PAIR + n * R * (8 * P + 2)
+        elif kname == "m2l":
+            flops = m2l_pairs * R * (4 * (P + 1) ** 2 + 12 * (P + 1))
+        if flops is not None:
+            ach = flops / avg_s / 1e12
+            peak = FP64_PEAK_TFLOPS if prec == N.PHS_FP64 else FP32_PEAK_TFLOPS
+            roof = {"kernel": kname, "bound": "alu", "achieved": round(ach, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                    "traffic": stored_traffic(kname, "large_tps"),
+                    "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
+                    "algorithmic_flops_per_launch": flops}
+    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 3)}
+               for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]}
+
+    out = {
+        "metric": "solve time n=2^20 TPS at 1e-8 rel; FMM matvec Mpts/s; p50/p99 serve latency",
+        "value": round(n / (ms_per_step / 1e3) / 1e6, 4),
+        "unit": "Mpts/s (nodes solved per second: plan+precond+PCG to 1e-8+beta+10^4-target eval)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == N.PHS_FP64 else "f32 FMM / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": "large_tps", "n": n, "k": 2, "poly_degree": 1,
+                   "field": "16-mode random Fourier, |kappa|<=8", "targets": int(tg.shape[0]),
+                   "precond": "Vecchia/Matern nu=1 alpha=0.35 m=30", "rtol": 1e-8,
+                   "precision": args.precision},
+        "solve_seconds": round(ms_per_step / 1e3, 4),
+        "phase_seconds": {k: round(v / args.steps, 4) for k, v in phases.items()},
+        "pcg_iters": last.get("iters"), "outer_refinements": last.get("outer"),
+        "rel_residual_fp64": last.get("resid"),
+        "leaf_level": last.get("L"), "expansion_order": last.get("P"),
+        "matvec_mpts_s": {k: round(v, 2) for k, v in mv.items()},
+        "serve_p50_ms": None, "serve_p99_ms": None,
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

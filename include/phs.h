@@ -1,0 +1,191 @@
+/*
+ * phs.h — C ABI of the MI355X polyharmonic-spline (PHS) interpolation library.
+ *
+ * Problem (paper Sec. 1, eqs. phs_interp, phs_fun, phs_linsys): given nodes
+ * x_j in R^2, values f_j, spline order k and polynomial degree d, find weights w
+ * and polynomial coefficients beta with
+ *
+ *      [ M   B ] [ w    ]   [ f ]        M_ij = phi(|x_i - x_j|),
+ *      [ B^T 0 ] [ beta ] = [ 0 ],       phi(r) = r^k (k odd), r^k log r (k even),
+ *
+ * B_js = P_s(x_j) the monomials of total degree <= d, and evaluate
+ * s(x) = sum_s beta_s P_s(x) + sum_j w_j phi(|x - x_j|) at targets.
+ *
+ * The library solves the system on the complement of span(B) (eq.
+ * phs_linsys_solve) by preconditioned CG, with M applied through the Hadamard
+ * low-rank reduction (eq. matvec_hadamard) onto log-kernel or distance-kernel
+ * sums evaluated by a 2D fast multipole method (Sec. 2.1), and a Vecchia
+ * sparse inverse-Cholesky factor of a Matern covariance as preconditioner
+ * (Sec. 2.2, Fig. vecchia_chol).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers (HIP global memory) owned by the
+ *    caller, unless marked "host".  They must stay valid until the enqueued work
+ *    has completed; ordering is that of the given stream (like hipMemcpyAsync).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *  - Point arrays are n x 2 row-major float64 (x0, y0, x1, y1, ...).
+ *  - Multi-vector arrays are n x nrhs column-major float64 (column r starts at
+ *    element r*n).  Results come back in the caller's point order.
+ *  - Coordinates: points are normalised inside the plan as
+ *    xi = (x - c) * rho, with c the bounding-box centre and rho chosen so the
+ *    box fits [-h_k, h_k]^2 (h = 1/4 for k=2, 1 for k=4, 1/2 for odd k).  w and
+ *    beta are defined in these normalised coordinates (the paper's rescaling,
+ *    eq. M_rho); c and rho are returned by phs_plan_info.  Targets passed to
+ *    phs_eval are in user coordinates.  beta is ordered by total degree, then
+ *    by descending power of xi_1: 1, xi1, xi2, xi1^2, xi1 xi2, xi2^2, ...
+ *  - No entry point aborts or throws.  On a non-OK status the outputs are
+ *    unspecified (except PHS_ERR_NOT_CONVERGED, which leaves the last iterate
+ *    in w/beta and fills info) and phs_last_error() describes the failure.
+ *  - All device memory a plan needs is allocated by phs_plan and
+ *    phs_precond_build; phs_matvec, phs_solve and phs_eval allocate nothing.
+ *  - A plan is not thread-safe; distinct plans may be used concurrently on
+ *    distinct streams.
+ */
+#ifndef PHS_H
+#define PHS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PHS_OK = 0,
+  PHS_ERR_INVALID_ARGUMENT = 1, /* bad size, null pointer, unsupported k/degree */
+  PHS_ERR_DUPLICATE_POINTS = 2, /* two nodes coincide (M would be singular) */
+  PHS_ERR_UNISOLVENT = 3,       /* B has dependent columns on these nodes */
+  PHS_ERR_NOT_CONVERGED = 4,    /* PCG hit maxit; last iterate returned */
+  PHS_ERR_BREAKDOWN = 5,        /* PCG curvature p^T A p <= 0 (indefinite) */
+  PHS_ERR_OUT_OF_MEMORY = 6,    /* a device allocation failed */
+  PHS_ERR_DEVICE = 7,           /* a HIP runtime call failed */
+  PHS_ERR_NOT_READY = 8         /* phs_solve before phs_precond_build, ... */
+} phs_status;
+
+enum { PHS_FP64 = 0, PHS_MIXED = 1 };             /* matvec precision */
+enum { PHS_RANGE_NORMALIZED = 0, PHS_RANGE_USER = 1 };
+
+typedef struct phs_plan_s *phs_plan_t; /* opaque; owns all device state */
+
+/* Plan options (Sec. 1 problem statement; Sec. 2.1 FMM parameters). */
+typedef struct {
+  int32_t k;               /* spline order, 1..4 */
+  int32_t poly_degree;     /* total degree d of B; -1 => minimal for k
+                              (k odd: ceil(k/2)-1, k even: k/2); must be >= it */
+  int32_t precision;       /* default matvec precision used by phs_solve:
+                              PHS_FP64, or PHS_MIXED (FP32 far field and near
+                              field inside FP64 residual refinement) */
+  double fmm_tol;          /* target relative accuracy of the core FMM;
+                              0 => 1e-12 (FP64) */
+  int32_t leaf_size;       /* mean points per leaf box; 0 => automatic */
+  int32_t expansion_order; /* log kernel: terms p; distance kernel: Chebyshev
+                              nodes per axis; 0 => from fmm_tol */
+} phs_plan_opts;
+
+/* Preconditioner options (Sec. 2.2; conditioning-set sizes of Sec. 3). */
+typedef struct {
+  int32_t m;           /* conditioning-set size |sigma(j)|; 0 => 30 (k=2), 50 */
+  double nu;           /* Matern smoothness; <= 0 => k/2. Supported: 0.5, 1,
+                          1.5, 2, 2.5 */
+  double range;        /* Matern range l = 1/alpha; <= 0 => alpha 0.35
+                          (2 for k=4) in normalised units */
+  int32_t range_units; /* PHS_RANGE_NORMALIZED or PHS_RANGE_USER */
+  uint64_t seed;       /* seed of the random ordering */
+} phs_precond_opts;
+
+/* PCG options (stopping rule: ||r||_2 <= rtol * ||Pi f||_2, r the true
+   unpreconditioned residual of the projected system, x0 = 0). */
+typedef struct {
+  double rtol;         /* 0 => 1e-8 */
+  int32_t maxit;       /* 0 => 500 */
+  int32_t check_every; /* host convergence check period; 0 => 1 */
+  int32_t precision;   /* -1 => plan default; PHS_FP64 or PHS_MIXED */
+} phs_solve_opts;
+
+typedef struct {
+  int32_t iters;             /* total inner PCG iterations (all RHS) */
+  int32_t outer_refinements; /* FP64 residual recomputations (mixed mode) */
+  double rel_residual;       /* ||Pi(f - M w)|| / ||Pi f|| recomputed with an
+                                FP64 matvec at exit (worst RHS) */
+  double t_solve;            /* seconds, host wall clock */
+} phs_solve_info;
+
+/* Build a plan: normalise the nodes, sort them into the quadtree, build the
+ * polynomial block and its thin QR.  xy: device, n x 2.  Synchronises
+ * `stream` (it reads back sizes).  Errors: INVALID_ARGUMENT (n < S+1, bad
+ * options), DUPLICATE_POINTS, UNISOLVENT, OUT_OF_MEMORY, DEVICE. */
+phs_status phs_plan(const double *xy, int64_t n, const phs_plan_opts *opts,
+                    void *stream, phs_plan_t *out);
+
+/* y = M v for the kernel block M only (eq. matvec_hadamard; Sec. 2.1 FMM).
+ * v, y: device, n x nrhs.  precision: PHS_FP64 or PHS_MIXED.  Asynchronous. */
+phs_status phs_matvec(phs_plan_t plan, const double *v, double *y, int32_t nrhs,
+                      int32_t precision, void *stream);
+
+/* Build the Vecchia factor U~ (Sigma^{-1} ~= U~ U~^T) of the Matern covariance
+ * on the plan's normalised nodes (eqs. conditionals, vecchia_sumform,
+ * Fig. vecchia_chol).  Synchronises `stream`. */
+phs_status phs_precond_build(phs_plan_t plan, const phs_precond_opts *opts,
+                             void *stream);
+
+/* Solve for w (n x nrhs) and beta (S x nrhs) by projected PCG on
+ * Q_perp^T M Q_perp u = Q_perp^T f, w = Q_perp u, then R beta = Q^T (f - M w)
+ * (eq. phs_linsys_solve).  f, w, beta: device.  info: host, may be NULL.
+ * Synchronises `stream` every check_every iterations. */
+phs_status phs_solve(phs_plan_t plan, const double *f, int32_t nrhs,
+                     const phs_solve_opts *opts, double *w, double *beta,
+                     phs_solve_info *info, void *stream);
+
+/* Evaluate the interpolant (eq. phs_interp) at m user-coordinate targets:
+ * out[t, r] = sum_s beta[s, r] P_s(xi_t) + sum_j w[j, r] phi(|xi_t - xi_j|).
+ * targets: device m x 2; w: n x nrhs; beta: S x nrhs; out: m x nrhs.
+ * Targets may lie outside the nodes' bounding box.  A target equal to a node
+ * contributes phi(0) = 0 for that node.  Asynchronous. */
+phs_status phs_eval(phs_plan_t plan, const double *w, const double *beta,
+                    int32_t nrhs, const double *targets, int64_t m, double *out,
+                    void *stream);
+
+/* Plan facts.  center[2], scale, S, R, leaf_level, order: host pointers, any
+ * may be NULL.  R is the Hadamard rank (number of core-kernel densities). */
+phs_status phs_plan_info(phs_plan_t plan, double *center, double *scale,
+                         int32_t *S, int32_t *R, int32_t *leaf_level,
+                         int32_t *order);
+
+/* Copy the plan's internal node order and leaf keys to caller device buffers
+ * (int32, n each): order[i] = caller index of the i-th node in tree order,
+ * leaf[i] = its leaf key (row-major box index at the leaf level).  Used to
+ * check the tree against an independent reference. */
+phs_status phs_plan_tree(phs_plan_t plan, int32_t *order, int32_t *leaf,
+                         void *stream);
+
+/* Copy the Vecchia structure in caller index space to caller device buffers:
+ * rank[n] (int32, position of each node in the ordering), nbr[n*m] (int32,
+ * row j lists sigma(j) ascending by (d^2, rank), padded with -1), coef[n*m]
+ * (float64, -lambda/c at the same slots, 0 in padding), diag[n] (1/c_j).
+ * m is the plan's conditioning-set size (phs_precond_opts.m). */
+phs_status phs_precond_export(phs_plan_t plan, int32_t *rank, int32_t *nbr,
+                              double *coef, double *diag, void *stream);
+
+/* z = U~ U~^T r in caller order (no projection).  r, z: device n.  */
+phs_status phs_precond_apply(phs_plan_t plan, const double *r, double *z,
+                             void *stream);
+
+void phs_plan_destroy(phs_plan_t plan);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *phs_last_error(void);
+
+/* Per-kernel timing.  When enabled, each library kernel launch is bracketed by
+ * HIP events on its own stream; phs_profile_read copies up to `cap` records
+ * (name, launches, total milliseconds) to host arrays and resets the counters.
+ * names: host array of `cap` char[48].  Returns the number of records. */
+void phs_profile_enable(int32_t on);
+int32_t phs_profile_read(char (*names)[48], int64_t *launches, double *total_ms,
+                         int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHS_H */

@@ -1,0 +1,751 @@
+// C ABI of the PHS library: plan construction (normalisation, quadtree,
+// polynomial block and thin QR), the kernel matvec, projected PCG with
+// residual refinement, coefficient recovery and evaluation (paper Sec. 2,
+// eq. phs_linsys_solve; Sec. 2.2 preconditioning).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "phs_internal.h"
+
+namespace phs {
+
+void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
+                      const double *targets, int64_t m, double *out, hipStream_t s);
+void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,
+                       const double *targets, int64_t m, double *out, hipStream_t s);
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+void set_error(phs_status code, const std::string &msg) {
+  (void)code;
+  g_last_error = msg;
+}
+
+// ------------------------------------------------------------------ profiling
+namespace {
+struct ProfRec {
+  int64_t launches = 0;
+  double ms = 0.0;
+};
+struct Pending {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfRec> g_prof;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;  // recycled events
+thread_local std::vector<std::pair<std::string, hipEvent_t>> g_open;
+
+hipEvent_t pool_get() {
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_pool.empty()) {
+      hipEvent_t e = g_pool.back();
+      g_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_flush_locked() {
+  for (auto &p : g_pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    auto &r = g_prof[p.name];
+    r.launches += 1;
+    r.ms += ms;
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
+  g_pending.clear();
+}
+}  // namespace
+
+bool profiling_on() { return g_prof_on; }
+
+void prof_begin(const char *name, hipStream_t s) {
+  hipEvent_t a = pool_get();
+  if (!a) return;
+  (void)hipEventRecord(a, s);
+  g_open.push_back({name, a});
+}
+
+void prof_end(hipStream_t s) {
+  if (g_open.empty()) return;
+  auto op = g_open.back();
+  g_open.pop_back();
+  hipEvent_t b = pool_get();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_pending.push_back({op.first, op.second, b});
+  if (g_pending.size() > 4096) prof_flush_locked();
+}
+
+// ------------------------------------------------------------------ plan
+Plan::~Plan() {
+  dfree(order);
+  dfree(inv_order);
+  dfree(leafkey);
+  dfree(x);
+  dfree(y);
+  dfree(ux);
+  dfree(uy);
+  dfree(Q);
+  dfree(mp);
+  dfree(loc);
+  dfree(tree.leaf_start);
+  free_log_tables(lt64);
+  free_log_tables(lt32);
+  free_cheb_tables(ct64);
+  free_cheb_tables(ct32);
+  dfree(v_t);
+  dfree(v_y);
+  for (auto &p : wk) dfree(p);
+  dfree(red);
+  dfree(scal);
+  if (hscal) (void)hipHostFree(hscal);
+  dfree(iscratch);
+  vecchia_free(*this);
+}
+
+namespace {
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+// Host Cholesky of an S x S symmetric matrix (row-major, upper triangle
+// valid); returns upper R with R^T R = G.  Returns false on a non-positive or
+// negligible pivot.
+bool host_chol_upper(const std::vector<double> &G, int n, std::vector<double> &Rm) {
+  Rm.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = G[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= Rm[(size_t)k * n + j] * Rm[(size_t)k * n + j];
+    if (!(s > 1e-24 * G[(size_t)j * n + j])) return false;
+    const double rjj = std::sqrt(s);
+    Rm[(size_t)j * n + j] = rjj;
+    for (int i = j + 1; i < n; ++i) {
+      double t = G[(size_t)j * n + i];
+      for (int k = 0; k < j; ++k) t -= Rm[(size_t)k * n + j] * Rm[(size_t)k * n + i];
+      Rm[(size_t)j * n + i] = t / rjj;
+    }
+  }
+  return true;
+}
+
+std::vector<double> upper_inverse(const std::vector<double> &Rm, int n) {
+  std::vector<double> X((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    X[(size_t)j * n + j] = 1.0 / Rm[(size_t)j * n + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += Rm[(size_t)i * n + k] * X[(size_t)k * n + j];
+      X[(size_t)i * n + j] = -s / Rm[(size_t)i * n + i];
+    }
+  }
+  return X;
+}
+
+std::vector<double> upper_mul(const std::vector<double> &A, const std::vector<double> &B,
+                              int n) {
+  std::vector<double> C((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) {
+      double s = 0.0;
+      for (int k = i; k <= j; ++k) s += A[(size_t)i * n + k] * B[(size_t)k * n + j];
+      C[(size_t)i * n + j] = s;
+    }
+  return C;
+}
+
+std::vector<double> gram_host(Plan &pl, hipStream_t s) {
+  const int Sn = pl.S;
+  const int npairs = Sn * (Sn + 1) / 2;
+  gram(pl.Q, pl.n, Sn, pl.red, pl.scal, s);
+  PHS_HIP(hipMemcpyAsync(pl.hscal, pl.scal, npairs * sizeof(double), hipMemcpyDeviceToHost, s));
+  PHS_HIP(hipStreamSynchronize(s));
+  std::vector<double> G((size_t)Sn * Sn, 0.0);
+  int t = 0;
+  for (int a = 0; a < Sn; ++a)
+    for (int b = a; b < Sn; ++b) {
+      G[(size_t)a * Sn + b] = pl.hscal[t];
+      G[(size_t)b * Sn + a] = pl.hscal[t];
+      ++t;
+    }
+  return G;
+}
+
+// CholeskyQR2 of the polynomial block B (n x S, held in pl.Q): Q = B R^{-1}.
+void thin_qr(Plan &pl, hipStream_t s) {
+  const int Sn = pl.S;
+  double *Rinv_dev = pl.scal + 512;
+  std::vector<double> R1, R2;
+  std::vector<double> G = gram_host(pl, s);
+  if (!host_chol_upper(G, Sn, R1))
+    throw Error{PHS_ERR_UNISOLVENT, "polynomial block is rank deficient on these nodes"};
+  std::vector<double> X = upper_inverse(R1, Sn);
+  PHS_HIP(hipMemcpyAsync(Rinv_dev, X.data(), X.size() * 8, hipMemcpyHostToDevice, s));
+  apply_rinv(pl.Q, pl.n, Sn, Rinv_dev, s);
+  G = gram_host(pl, s);
+  if (!host_chol_upper(G, Sn, R2))
+    throw Error{PHS_ERR_UNISOLVENT, "polynomial block is numerically rank deficient"};
+  X = upper_inverse(R2, Sn);
+  PHS_HIP(hipMemcpyAsync(Rinv_dev, X.data(), X.size() * 8, hipMemcpyHostToDevice, s));
+  apply_rinv(pl.Q, pl.n, Sn, Rinv_dev, s);
+  PHS_HIP(hipStreamSynchronize(s));
+  pl.Rm = upper_mul(R2, R1, Sn);
+}
+
+int order_for_tol(double tol, bool fp64) {
+  // Terms of the scaled log expansions; (P+1) a multiple of 16 for the M2L
+  // chunking.  Worst-case interaction ratio 0.55 -> ~0.55^P.
+  if (!fp64) return 15;
+  if (tol >= 1e-9) return 31;
+  if (tol >= 1e-13) return 31;
+  return 47;
+}
+
+void build_tree(Plan &pl, const double *xy, int leaf_size, hipStream_t s) {
+  const int64_t n = pl.n;
+  uint32_t *keys = dmalloc<uint32_t>(n), *ktmp = dmalloc<uint32_t>(n);
+  int32_t *vals = dmalloc<int32_t>(n), *vtmp = dmalloc<int32_t>(n);
+  int32_t *scr = dmalloc<int32_t>(radix_sort_scratch_ints(n));
+  try {
+    int L = (int)std::lround(std::log((double)n / leaf_size) / std::log(4.0));
+    L = std::max(2, std::min(10, L));
+    std::vector<int32_t> hstart;
+    for (;;) {
+      const int G = 1 << L;
+      const int nleaf = G * G;
+      leaf_keys(xy, n, pl.c[0], pl.c[1], pl.rho, pl.tree.h, L, keys, vals, s);
+      radix_sort_u32(keys, vals, n, 2 * L, ktmp, vtmp, scr, s);
+      dfree(pl.tree.leaf_start);
+      pl.tree.leaf_start = nullptr;
+      pl.tree.leaf_start = dmalloc<int32_t>(nleaf + 1);
+      leaf_ranges(keys, n, nleaf, pl.tree.leaf_start, s);
+      hstart.resize(nleaf + 1);
+      PHS_HIP(hipMemcpyAsync(hstart.data(), pl.tree.leaf_start, (nleaf + 1) * 4,
+                             hipMemcpyDeviceToHost, s));
+      PHS_HIP(hipStreamSynchronize(s));
+      int maxocc = 0;
+      for (int c = 0; c < nleaf; ++c) maxocc = std::max(maxocc, hstart[c + 1] - hstart[c]);
+      if (maxocc > 16 * leaf_size && L < 10) {
+        ++L;
+        continue;
+      }
+      pl.tree.L = L;
+      pl.tree.G = G;
+      break;
+    }
+    pl.order = vals;
+    vals = nullptr;
+    pl.inv_order = dmalloc<int32_t>(n);
+    pl.leafkey = dmalloc<int32_t>(n);
+    pl.x = dmalloc<double>(n);
+    pl.y = dmalloc<double>(n);
+    pl.ux = dmalloc<float>(n);
+    pl.uy = dmalloc<float>(n);
+    build_tree_points(xy, pl.order, keys, n, pl.c[0], pl.c[1], pl.rho, pl.tree.h, pl.tree.L,
+                      pl.x, pl.y, pl.ux, pl.uy, pl.leafkey, pl.inv_order, s);
+    int32_t *flag = scr;
+    PHS_HIP(hipMemsetAsync(flag, 0, 4, s));
+    count_duplicates(pl.x, pl.y, pl.tree.leaf_start, pl.tree.G * pl.tree.G, flag, s);
+    int32_t hflag = 0;
+    PHS_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+    PHS_HIP(hipStreamSynchronize(s));
+    dfree(keys);
+    dfree(ktmp);
+    dfree(vtmp);
+    dfree(scr);
+    keys = ktmp = nullptr;
+    vtmp = scr = nullptr;
+    if (hflag) throw Error{PHS_ERR_DUPLICATE_POINTS, "two nodes coincide"};
+  } catch (...) {
+    dfree(keys);
+    dfree(ktmp);
+    dfree(vals);
+    dfree(vtmp);
+    dfree(scr);
+    throw;
+  }
+}
+
+void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_t s,
+                 Plan &pl) {
+  PHS_REQUIRE(xy && o, PHS_ERR_INVALID_ARGUMENT, "null argument");
+  PHS_REQUIRE(o->k >= 1 && o->k <= 4, PHS_ERR_INVALID_ARGUMENT, "k must be 1..4");
+  pl.k = o->k;
+  pl.d = o->poly_degree < 0 ? min_degree(o->k) : o->poly_degree;
+  PHS_REQUIRE(pl.d >= min_degree(o->k), PHS_ERR_INVALID_ARGUMENT,
+              "polynomial degree below the minimum for this k");
+  PHS_REQUIRE(pl.d <= 5, PHS_ERR_INVALID_ARGUMENT, "polynomial degree above 5");
+  pl.S = n_monomials(pl.d);
+  PHS_REQUIRE(n >= pl.S && n < (int64_t(1) << 30), PHS_ERR_INVALID_ARGUMENT,
+              "n must be >= number of polynomial terms and < 2^30");
+  PHS_REQUIRE(o->precision == PHS_FP64 || o->precision == PHS_MIXED,
+              PHS_ERR_INVALID_ARGUMENT, "bad precision");
+  pl.n = n;
+  pl.R = hadamard_rank(pl.k);
+  pl.core_log = (pl.k % 2 == 0);
+  pl.sign = definiteness_sign(pl.k);
+  pl.precision = o->precision;
+  pl.tree.h = domain_half_width(pl.k);
+  const double tol = o->fmm_tol > 0 ? o->fmm_tol : 1e-12;
+  if (pl.core_log) {
+    pl.p64 = o->expansion_order > 0 ? o->expansion_order : order_for_tol(tol, true);
+    pl.p32 = order_for_tol(tol, false);
+    PHS_REQUIRE(pl.p64 >= 4 && pl.p64 <= 63, PHS_ERR_INVALID_ARGUMENT,
+                "expansion order must be 4..63");
+  } else {
+    pl.q64 = o->expansion_order > 0 ? o->expansion_order : (tol >= 1e-9 ? 12 : 16);
+    pl.q32 = 8;
+    PHS_REQUIRE(pl.q64 >= 4 && pl.q64 <= 20, PHS_ERR_INVALID_ARGUMENT,
+                "Chebyshev order must be 4..20");
+  }
+  // scratch used by the bounding box, reductions and scalars
+  pl.red_cap = dot_blocks(n) * 32 + 4096;
+  pl.red = dmalloc<double>(pl.red_cap);
+  pl.scal = dmalloc<double>(1024);
+  PHS_HIP(hipHostMalloc((void **)&pl.hscal, 1024 * sizeof(double), 0));
+
+  // bounding box -> c, rho (exact operation order shared with the oracle)
+  {
+    const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    minmax_xy(xy, n, pl.scal, pl.red, nb, s);
+    PHS_HIP(hipMemcpyAsync(pl.hscal, pl.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    PHS_HIP(hipStreamSynchronize(s));
+    const double mnx = pl.hscal[0], mny = pl.hscal[1], mxx = pl.hscal[2], mxy = pl.hscal[3];
+    PHS_REQUIRE(std::isfinite(mnx) && std::isfinite(mny) && std::isfinite(mxx) &&
+                    std::isfinite(mxy),
+                PHS_ERR_INVALID_ARGUMENT, "non-finite coordinates");
+    pl.c[0] = (mnx + mxx) * 0.5;
+    pl.c[1] = (mny + mxy) * 0.5;
+    const double ex = mxx - mnx, ey = mxy - mny;
+    const double half = std::max(ex, ey) * 0.5;
+    PHS_REQUIRE(half > 0.0, PHS_ERR_INVALID_ARGUMENT, "nodes have zero extent");
+    pl.rho = pl.tree.h / half;
+  }
+  int leaf_size = o->leaf_size > 0 ? o->leaf_size : (pl.core_log ? 40 : 24);
+  build_tree(pl, xy, leaf_size, s);
+
+  // polynomial block and thin QR
+  pl.Q = dmalloc<double>((size_t)n * pl.S);
+  poly_block_tree(pl.x, pl.y, n, pl.d, pl.Q, s);
+  thin_qr(pl, s);
+
+  // FMM tables and workspace
+  size_t eb;
+  if (pl.core_log) {
+    build_log_tables(pl.lt64, pl.p64);
+    build_log_tables(pl.lt32, pl.p32);
+    eb = std::max(log_expansion_bytes(pl.tree.L, pl.p64, pl.R, true),
+                  log_expansion_bytes(pl.tree.L, pl.p32, pl.R, false));
+  } else {
+    build_cheb_tables(pl.ct64, pl.q64);
+    build_cheb_tables(pl.ct32, pl.q32);
+    eb = std::max(cheb_expansion_bytes(pl.tree.L, pl.q64, pl.R, true),
+                  cheb_expansion_bytes(pl.tree.L, pl.q32, pl.R, false));
+  }
+  pl.exp_bytes = eb;
+  pl.mp = dmalloc<char>(eb);
+  pl.loc = dmalloc<char>(eb);
+  pl.v_t = dmalloc<double>(n);
+  pl.v_y = dmalloc<double>(n);
+  for (auto &p : pl.wk) p = dmalloc<double>(n);
+  PHS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void matvec_tree(Plan &pl, const double *t_tree, double *y_tree, int precision,
+                 hipStream_t s) {
+  const bool fp64 = precision == PHS_FP64;
+  if (pl.core_log) log_matvec(pl, t_tree, y_tree, nullptr, fp64, s);
+  else dist_matvec(pl, t_tree, y_tree, nullptr, fp64, s);
+}
+
+namespace {
+
+// z = Pi U U^T Pi r (or Pi r without a preconditioner); r is not modified.
+void precond_tree(Plan &pl, const double *r, double *z, double *tmp, hipStream_t s) {
+  copy(z, r, pl.n, s);
+  project(z, pl.Q, pl.n, pl.S, pl.red, pl.scal + 8, s);
+  if (pl.has_pc) {
+    copy(tmp, z, pl.n, s);
+    vecchia_apply(pl, tmp, z, pl.v_y, s);
+    project(z, pl.Q, pl.n, pl.S, pl.red, pl.scal + 8, s);
+  }
+}
+
+double dot_host(Plan &pl, const double *a, const double *b, hipStream_t s) {
+  const double *pa[1] = {a}, *pb[1] = {b};
+  multi_dot(pa, pb, 1, pl.n, pl.red, pl.scal + 16, s);
+  PHS_HIP(hipMemcpyAsync(pl.hscal + 16, pl.scal + 16, 8, hipMemcpyDeviceToHost, s));
+  PHS_HIP(hipStreamSynchronize(s));
+  return pl.hscal[16];
+}
+
+// q = sign * Pi M p
+void apply_op(Plan &pl, const double *p, double *q, int precision, hipStream_t s) {
+  matvec_tree(pl, p, q, precision, s);
+  project(q, pl.Q, pl.n, pl.S, pl.red, pl.scal + 8, s);
+  if (pl.sign < 0) scale_copy(q, q, -1.0, pl.n, s);
+}
+
+struct PcgResult {
+  int iters = 0;
+  bool converged = false;
+  bool breakdown = false;
+};
+
+// PCG on sign * Pi M Pi w = b with b in range(Pi), starting from w = 0.
+// w, r (in: b, out: residual), and three work vectors.
+PcgResult pcg(Plan &pl, double *w, double *r, double rtol_abs, int maxit, int check_every,
+              int precision, double *z, double *p, double *q, double *tmp, hipStream_t s) {
+  const int64_t n = pl.n;
+  PcgResult res;
+  fill(w, 0.0, n, s);
+  double *sc = pl.scal;  // [0] rho_new, [1] rho, [2] pq, [3] rr
+  precond_tree(pl, r, z, tmp, s);
+  {
+    const double *pa[1] = {r}, *pb[1] = {z};
+    multi_dot(pa, pb, 1, n, pl.red, sc + 1, s);
+  }
+  copy(p, z, n, s);
+  for (int it = 1; it <= maxit; ++it) {
+    apply_op(pl, p, q, precision, s);
+    {
+      const double *pa[1] = {p}, *pb[1] = {q};
+      multi_dot(pa, pb, 1, n, pl.red, sc + 2, s);
+    }
+    pcg_update_wr(w, r, p, q, sc + 1, n, pl.red, sc + 3, s);
+    res.iters = it;
+    if (it % check_every == 0 || it == maxit) {
+      PHS_HIP(hipMemcpyAsync(pl.hscal, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PHS_HIP(hipStreamSynchronize(s));
+      if (!(pl.hscal[2] > 0.0)) {
+        res.breakdown = true;
+        return res;
+      }
+      if (std::sqrt(pl.hscal[3]) <= rtol_abs) {
+        res.converged = true;
+        return res;
+      }
+    }
+    precond_tree(pl, r, z, tmp, s);
+    {
+      const double *pa[1] = {r}, *pb[1] = {z};
+      multi_dot(pa, pb, 1, n, pl.red, sc + 0, s);
+    }
+    pcg_update_p(p, z, sc, n, s);
+    PHS_HIP(hipMemcpyAsync(sc + 1, sc + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return res;
+}
+
+phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts *o,
+                      double *w_out, double *beta_out, phs_solve_info *info, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = pl.n;
+  const double rtol = (o && o->rtol > 0) ? o->rtol : 1e-8;
+  const int maxit = (o && o->maxit > 0) ? o->maxit : 500;
+  const int check_every = (o && o->check_every > 0) ? o->check_every : 1;
+  const int prec = (o && o->precision >= 0) ? o->precision : pl.precision;
+  PHS_REQUIRE(prec == PHS_FP64 || prec == PHS_MIXED, PHS_ERR_INVALID_ARGUMENT,
+              "bad precision");
+  double *ft = pl.wk[0], *r = pl.wk[1], *w = pl.wk[2], *z = pl.wk[3], *p = pl.wk[4],
+         *q = pl.wk[5], *tmp = pl.wk[6], *dw = pl.wk[7];
+  int total_iters = 0, total_outer = 0;
+  double worst_rel = 0.0;
+  phs_status st = PHS_OK;
+  for (int c = 0; c < nrhs; ++c) {
+    gather_cols(f + (int64_t)c * n, pl.order, n, ft, s);
+    // b = sign * Pi f
+    scale_copy(r, ft, (double)pl.sign, n, s);
+    project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
+    const double bn = std::sqrt(dot_host(pl, r, r, s));
+    const double tol_abs = rtol * bn;
+    double rel = 0.0;
+    if (bn == 0.0) {
+      fill(w, 0.0, n, s);
+    } else if (prec == PHS_FP64) {
+      PcgResult pr = pcg(pl, w, r, tol_abs, maxit, check_every, PHS_FP64, z, p, q, tmp, s);
+      total_iters += pr.iters;
+      if (pr.breakdown) st = PHS_ERR_BREAKDOWN;
+      else if (!pr.converged && st == PHS_OK) st = PHS_ERR_NOT_CONVERGED;
+    } else {
+      // Mixed precision: inner PCG on FP32 matvecs, outer FP64 residual.
+      fill(w, 0.0, n, s);
+      double rn = bn;
+      int outer = 0, budget = maxit;
+      while (rn > tol_abs && outer < 20 && budget > 0) {
+        // inner solve of A dw = r to a relative accuracy the FP32 operator supports
+        const double inner_tol = std::max(tol_abs, 2e-5 * rn);
+        PcgResult pr = pcg(pl, dw, r, inner_tol, budget, check_every, PHS_MIXED, z, p, q, tmp, s);
+        total_iters += pr.iters;
+        budget -= pr.iters;
+        axpby(w, dw, 1.0, 1.0, n, s);
+        // r = sign * Pi (f - M64 w)
+        matvec_tree(pl, w, q, PHS_FP64, s);
+        axpby(q, ft, 1.0, -1.0, n, s);  // q = f - M w
+        scale_copy(r, q, (double)pl.sign, n, s);
+        project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
+        rn = std::sqrt(dot_host(pl, r, r, s));
+        ++outer;
+        if (pr.breakdown) {
+          st = PHS_ERR_BREAKDOWN;
+          break;
+        }
+      }
+      total_outer += outer;
+      if (rn > tol_abs && st == PHS_OK) st = PHS_ERR_NOT_CONVERGED;
+    }
+    // beta from R beta = Q^T (f - M w), FP64 matvec
+    matvec_tree(pl, w, q, PHS_FP64, s);
+    axpby(q, ft, 1.0, -1.0, n, s);  // q = f - M w
+    {
+      const double *pa[32], *pb[32];
+      for (int j = 0; j < pl.S; ++j) {
+        pa[j] = pl.Q + (int64_t)j * n;
+        pb[j] = q;
+      }
+      multi_dot(pa, pb, pl.S, n, pl.red, pl.scal + 40, s);
+      PHS_HIP(hipMemcpyAsync(pl.hscal + 40, pl.scal + 40, pl.S * 8, hipMemcpyDeviceToHost, s));
+      PHS_HIP(hipStreamSynchronize(s));
+      std::vector<double> bet(pl.S);
+      for (int i = pl.S - 1; i >= 0; --i) {
+        double acc = pl.hscal[40 + i];
+        for (int k2 = i + 1; k2 < pl.S; ++k2) acc -= pl.Rm[(size_t)i * pl.S + k2] * bet[k2];
+        bet[i] = acc / pl.Rm[(size_t)i * pl.S + i];
+      }
+      PHS_HIP(hipMemcpyAsync(beta_out + (int64_t)c * pl.S, bet.data(), pl.S * 8,
+                             hipMemcpyHostToDevice, s));
+      PHS_HIP(hipStreamSynchronize(s));
+    }
+    // relative residual of the projected system with the FP64 matvec
+    project(q, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
+    if (bn > 0) rel = std::sqrt(dot_host(pl, q, q, s)) / bn;
+    worst_rel = std::max(worst_rel, rel);
+    scatter_cols(w, pl.order, n, w_out + (int64_t)c * n, s);
+  }
+  PHS_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = total_iters;
+    info->outer_refinements = total_outer;
+    info->rel_residual = worst_rel;
+    info->t_solve =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (st == PHS_ERR_NOT_CONVERGED) set_error(st, "PCG did not reach rtol within maxit");
+  if (st == PHS_ERR_BREAKDOWN) set_error(st, "PCG breakdown: non-positive curvature");
+  return st;
+}
+
+template <class F>
+phs_status guarded(F &&f) {
+  try {
+    return f();
+  } catch (const Error &e) {
+    set_error(e.code, e.msg);
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error(PHS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return PHS_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    set_error(PHS_ERR_DEVICE, "unexpected internal error");
+    return PHS_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+}  // namespace phs
+
+using namespace phs;
+
+struct phs_plan_s {
+  Plan pl;
+};
+
+extern "C" {
+
+phs_status phs_plan(const double *xy, int64_t n, const phs_plan_opts *opts, void *stream,
+                    phs_plan_t *out) {
+  if (!out) {
+    set_error(PHS_ERR_INVALID_ARGUMENT, "null output handle");
+    return PHS_ERR_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  phs_plan_s *h = new (std::nothrow) phs_plan_s();
+  if (!h) {
+    set_error(PHS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return PHS_ERR_OUT_OF_MEMORY;
+  }
+  phs_status st = guarded([&] {
+    plan_create(xy, n, opts, S(stream), h->pl);
+    return PHS_OK;
+  });
+  if (st != PHS_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return PHS_OK;
+}
+
+phs_status phs_matvec(phs_plan_t plan, const double *v, double *y, int32_t nrhs,
+                      int32_t precision, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && v && y && nrhs >= 1, PHS_ERR_INVALID_ARGUMENT, "bad matvec arguments");
+    PHS_REQUIRE(precision == PHS_FP64 || precision == PHS_MIXED, PHS_ERR_INVALID_ARGUMENT,
+                "bad precision");
+    Plan &pl = plan->pl;
+    hipStream_t s = S(stream);
+    for (int c = 0; c < nrhs; ++c) {
+      gather_cols(v + (int64_t)c * pl.n, pl.order, pl.n, pl.v_t, s);
+      const bool fp64 = precision == PHS_FP64;
+      if (pl.core_log) log_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, fp64, s);
+      else dist_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, fp64, s);
+    }
+    return PHS_OK;
+  });
+}
+
+phs_status phs_precond_build(phs_plan_t plan, const phs_precond_opts *opts, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && opts, PHS_ERR_INVALID_ARGUMENT, "bad precond arguments");
+    vecchia_build(plan->pl, *opts, S(stream));
+    return PHS_OK;
+  });
+}
+
+phs_status phs_solve(phs_plan_t plan, const double *f, int32_t nrhs, const phs_solve_opts *opts,
+                     double *w, double *beta, phs_solve_info *info, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && f && w && beta && nrhs >= 1, PHS_ERR_INVALID_ARGUMENT,
+                "bad solve arguments");
+    return solve_impl(plan->pl, f, nrhs, opts, w, beta, info, S(stream));
+  });
+}
+
+phs_status phs_eval(phs_plan_t plan, const double *w, const double *beta, int32_t nrhs,
+                    const double *targets, int64_t m, double *out, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && w && beta && nrhs >= 1 && m >= 0, PHS_ERR_INVALID_ARGUMENT,
+                "bad eval arguments");
+    if (m == 0) return PHS_OK;
+    PHS_REQUIRE(targets && out, PHS_ERR_INVALID_ARGUMENT, "null targets/out");
+    Plan &pl = plan->pl;
+    hipStream_t s = S(stream);
+    for (int c = 0; c < nrhs; ++c) {
+      gather_cols(w + (int64_t)c * pl.n, pl.order, pl.n, pl.v_t, s);
+      if (pl.core_log) {
+        log_expansions(pl, pl.v_t, s);
+        log_eval_targets(pl, pl.v_t, beta + (int64_t)c * pl.S, targets, m,
+                         out + (int64_t)c * m, s);
+      } else {
+        dist_expansions(pl, pl.v_t, s);
+        dist_eval_targets(pl, pl.v_t, beta + (int64_t)c * pl.S, targets, m,
+                          out + (int64_t)c * m, s);
+      }
+    }
+    return PHS_OK;
+  });
+}
+
+phs_status phs_plan_info(phs_plan_t plan, double *center, double *scale, int32_t *Sout,
+                         int32_t *Rout, int32_t *leaf_level, int32_t *order) {
+  return guarded([&] {
+    PHS_REQUIRE(plan, PHS_ERR_INVALID_ARGUMENT, "null plan");
+    const Plan &pl = plan->pl;
+    if (center) {
+      center[0] = pl.c[0];
+      center[1] = pl.c[1];
+    }
+    if (scale) *scale = pl.rho;
+    if (Sout) *Sout = pl.S;
+    if (Rout) *Rout = pl.R;
+    if (leaf_level) *leaf_level = pl.tree.L;
+    if (order) *order = pl.core_log ? pl.p64 : pl.q64;
+    return PHS_OK;
+  });
+}
+
+phs_status phs_plan_tree(phs_plan_t plan, int32_t *order, int32_t *leaf, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && order && leaf, PHS_ERR_INVALID_ARGUMENT, "bad arguments");
+    const Plan &pl = plan->pl;
+    hipStream_t s = S(stream);
+    PHS_HIP(hipMemcpyAsync(order, pl.order, pl.n * 4, hipMemcpyDeviceToDevice, s));
+    PHS_HIP(hipMemcpyAsync(leaf, pl.leafkey, pl.n * 4, hipMemcpyDeviceToDevice, s));
+    return PHS_OK;
+  });
+}
+
+phs_status phs_precond_export(phs_plan_t plan, int32_t *rank, int32_t *nbr, double *coef,
+                              double *diag, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && rank && nbr && coef && diag, PHS_ERR_INVALID_ARGUMENT,
+                "bad export arguments");
+    PHS_REQUIRE(plan->pl.has_pc, PHS_ERR_NOT_READY, "no preconditioner built");
+    vecchia_export(plan->pl, rank, nbr, coef, diag, S(stream));
+    return PHS_OK;
+  });
+}
+
+phs_status phs_precond_apply(phs_plan_t plan, const double *r, double *z, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && r && z, PHS_ERR_INVALID_ARGUMENT, "bad apply arguments");
+    Plan &pl = plan->pl;
+    PHS_REQUIRE(pl.has_pc, PHS_ERR_NOT_READY, "no preconditioner built");
+    hipStream_t s = S(stream);
+    gather_cols(r, pl.order, pl.n, pl.v_t, s);
+    vecchia_apply(pl, pl.v_t, pl.v_y, pl.wk[7], s);
+    scatter_cols(pl.v_y, pl.order, pl.n, z, s);
+    return PHS_OK;
+  });
+}
+
+void phs_plan_destroy(phs_plan_t plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  delete plan;
+}
+
+const char *phs_last_error(void) { return g_last_error.c_str(); }
+
+void phs_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+}
+
+int32_t phs_profile_read(char (*names)[48], int64_t *launches, double *total_ms,
+                         int32_t cap) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_flush_locked();
+  int32_t i = 0;
+  for (auto &kv : g_prof) {
+    if (i >= cap) break;
+    if (names) {
+      std::strncpy(names[i], kv.first.c_str(), 47);
+      names[i][47] = 0;
+    }
+    if (launches) launches[i] = kv.second.launches;
+    if (total_ms) total_ms[i] = kv.second.ms;
+    ++i;
+  }
+  g_prof.clear();
+  return i;
+}
+
+}  // extern "C"

@@ -1,0 +1,608 @@
+// Log-kernel fast multipole method on the uniform quadtree (paper Sec. 2.1:
+// eqs. outgoing and incoming, steps 2-6 of the FMM description), applied to
+// the R densities of the Hadamard reduction (eq. matvec_hadamard).
+//
+// Expansions are scaled by the box width w_l so every coefficient is O(1):
+//   outgoing about centre c:  Phi(z) = A_0 log(z - c) + sum_{k>=1} A_k ((z-c)/w)^{-k},
+//                             A_0 = sum q,  A_k = -sum q ((y-c)/w)^k / k
+//   incoming about centre c:  Phi(z) = sum_k B_k ((z-c)/w)^k      (real part taken)
+// With these scalings the outgoing->outgoing and incoming->incoming shifts are
+// the same four matrices on every level, and the outgoing->incoming operator
+// for a source/target centre offset D (in box widths) is
+//   B_l = sum_k H[l][k] D^{-(k+l)} A_k  (+ A_0 (log w + log|D|) for l = 0),
+// H[0][k] = 1, H[l][0] = (-1)^{l+1}/l, H[l][k] = (-1)^l binom(k+l-1, l),
+// one real matrix shared by all 40 offsets and all levels.
+//
+// Layout: level l holds (P+1) x nd x 4^l complex coefficients, box index
+// fastest (coalesced across neighbouring boxes), levels 2..L concatenated.
+#include <cmath>
+#include <type_traits>
+
+#include "fmm_common.h"
+
+namespace phs {
+
+namespace {
+
+template <class T>
+using V2 = typename Vec2<T>::type;
+
+__host__ __device__ inline int64_t level_base(int l, int P, int nd) {
+  // complex elements before level l (levels start at 2)
+  return (int64_t)(P + 1) * nd * (((int64_t)1 << (2 * l)) - 16) / 3;
+}
+
+// ------------------------------------------------------------------ P2M
+template <class T, int K>
+__global__ void k_p2m(const double *__restrict__ x, const double *__restrict__ y,
+                      const float *__restrict__ ux, const float *__restrict__ uy,
+                      const double *__restrict__ t, const int32_t *__restrict__ start,
+                      int L, double h, int P, int gpw, V2<T> *__restrict__ A) {
+  constexpr int R = Rank<K>::R;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int G = 1 << L;
+  const int nleaf = G * G;
+  const int P1 = P + 1;
+  const int sub = lane / P1, kk = lane % P1;
+  const int leaf = (blockIdx.x * (blockDim.x >> 6) + wave) * gpw + sub;
+  const bool active = sub < gpw && leaf < nleaf;
+  int b = 0, e = 0;
+  if (active) {
+    b = start[leaf];
+    e = start[leaf + 1];
+  }
+  const double w = 2.0 * h / G, invw = G / (2.0 * h);
+  const int ix = leaf % G, iy = leaf / G;
+  const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
+  T are[R], aim[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) are[r] = aim[r] = T(0);
+  for (int j = b; j < e; ++j) {
+    C2<T> z;
+    if constexpr (std::is_same<T, float>::value) {
+      z = {ux[j] * (float)invw, uy[j] * (float)invw};
+    } else {
+      z = {(x[j] - cx) * invw, (y[j] - cy) * invw};
+    }
+    C2<T> zk = cpow_small(z, kk);
+    T v[R];
+    vfac<K, T>(x[j], y[j], v);
+    const T tj = (T)t[j];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T q = v[r] * tj;
+      are[r] += q * zk.re;
+      aim[r] += q * zk.im;
+    }
+  }
+  if (!active) return;
+  const T sc = kk == 0 ? T(1) : T(-1) / T(kk);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    st2<T>(&A[((int64_t)kk * R + r) * nleaf + leaf], {are[r] * sc, aim[r] * sc});
+}
+
+// ------------------------------------------------------------------ M2M
+template <class T>
+__global__ void k_m2m(const V2<T> *__restrict__ Ac, V2<T> *__restrict__ Ap, int lp, int P,
+                      int nd, const V2<T> *__restrict__ tab) {
+  const int Gp = 1 << lp, Gc = 2 * Gp;
+  const int64_t nbp = (int64_t)Gp * Gp, nbc = 4 * nbp;
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (tid >= nbp * nd * (P + 1)) return;
+  const int box = (int)(tid % nbp);
+  const int64_t rest = tid / nbp;
+  const int r = (int)(rest % nd), lc = (int)(rest / nd);
+  const int ix = box % Gp, iy = box / Gp;
+  C2<T> acc = {T(0), T(0)};
+  for (int c = 0; c < 4; ++c) {
+    const int child = (2 * iy + (c >> 1)) * Gc + 2 * ix + (c & 1);
+    const V2<T> *row = tab + ((int64_t)c * (P + 1) + lc) * (P + 1);
+    for (int k = 0; k <= lc; ++k)
+      acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Ac[((int64_t)k * nd + r) * nbc + child])));
+  }
+  st2<T>(&Ap[((int64_t)lc * nd + r) * nbp + box], acc);
+}
+
+// ------------------------------------------------------------------ M2L
+// One thread per (target box, density, chunk of LCH output coefficients),
+// all levels 2..L in one launch.  Boxes are enumerated by parity class so a
+// wavefront shares one interaction-list pattern.
+template <class T, int LCH>
+__global__ __launch_bounds__(256) void k_m2l(const V2<T> *__restrict__ A,
+                                             V2<T> *__restrict__ B, int L, int P,
+                                             int nd, const T *__restrict__ Ht,
+                                             double h) {
+  const int l0 = blockIdx.y * LCH;
+  const int r = blockIdx.z;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int l = 2;
+  int64_t off = 0, base = 0;
+  while (l <= L && t >= off + ((int64_t)1 << (2 * l))) {
+    off += (int64_t)1 << (2 * l);
+    base += (int64_t)(P + 1) * nd * ((int64_t)1 << (2 * l));
+    ++l;
+  }
+  if (l > L) return;
+  const int G = 1 << l;
+  const int64_t nb = (int64_t)G * G;
+  const int64_t ti = t - off;
+  const int64_t quarter = nb / 4;
+  const int cls = (int)(ti / quarter);
+  const int64_t rem = ti % quarter;
+  const int half = G / 2;
+  const int ix = 2 * (int)(rem % half) + (cls & 1);
+  const int iy = 2 * (int)(rem / half) + (cls >> 1);
+  const V2<T> *Al = A + base;
+  V2<T> *Bl = B + base;
+  const T logw = (T)log(2.0 * h / G);
+  C2<T> acc[LCH];
+#pragma unroll
+  for (int c = 0; c < LCH; ++c) acc[c] = {T(0), T(0)};
+  const int pxp = ix >> 1, pyp = iy >> 1;
+  for (int oy = -3; oy <= 3; ++oy) {
+    const int jy = iy + oy;
+    if (jy < 0 || jy >= G || abs((jy >> 1) - pyp) > 1) continue;
+    for (int ox = -3; ox <= 3; ++ox) {
+      if (abs(ox) <= 1 && abs(oy) <= 1) continue;
+      const int jx = ix + ox;
+      if (jx < 0 || jx >= G || abs((jx >> 1) - pxp) > 1) continue;
+      const int64_t src = (int64_t)jy * G + jx;
+      const T Dx = T(-ox), Dy = T(-oy);
+      const T dd = Dx * Dx + Dy * Dy;
+      const C2<T> Dinv = {Dx / dd, -Dy / dd};
+      C2<T> Y[LCH];
+#pragma unroll
+      for (int c = 0; c < LCH; ++c) Y[c] = {T(0), T(0)};
+      C2<T> dk = {T(1), T(0)};
+      for (int k = 0; k <= P; ++k) {
+        const C2<T> a = ld2<T>(&Al[((int64_t)k * nd + r) * nb + src]);
+        const C2<T> xk = cmul(a, dk);
+        const T *hrow = Ht + k * (P + 1) + l0;
+#pragma unroll
+        for (int c = 0; c < LCH; ++c) {
+          Y[c].re += hrow[c] * xk.re;
+          Y[c].im += hrow[c] * xk.im;
+        }
+        dk = cmul(dk, Dinv);
+      }
+      C2<T> e = cpow_small(Dinv, l0);
+#pragma unroll
+      for (int c = 0; c < LCH; ++c) {
+        acc[c] = cadd(acc[c], cmul(e, Y[c]));
+        e = cmul(e, Dinv);
+      }
+      if (l0 == 0) {
+        const T a0 = ld2<T>(&Al[(int64_t)r * nb + src]).re;
+        acc[0].re += a0 * (logw + T(0.5) * (T)log((double)dd));
+      }
+    }
+  }
+  const int64_t tgt = (int64_t)iy * G + ix;
+#pragma unroll
+  for (int c = 0; c < LCH; ++c)
+    if (l0 + c <= P) st2<T>(&Bl[((int64_t)(l0 + c) * nd + r) * nb + tgt], acc[c]);
+}
+
+// ------------------------------------------------------------------ L2L
+template <class T>
+__global__ void k_l2l(const V2<T> *__restrict__ Bp, V2<T> *__restrict__ Bc, int lc, int P,
+                      int nd, const V2<T> *__restrict__ tab) {
+  const int Gc = 1 << lc, Gp = Gc / 2;
+  const int64_t nbc = (int64_t)Gc * Gc, nbp = nbc / 4;
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (tid >= nbc * nd * (P + 1)) return;
+  const int box = (int)(tid % nbc);
+  const int64_t rest = tid / nbc;
+  const int r = (int)(rest % nd), j = (int)(rest / nd);
+  const int ix = box % Gc, iy = box / Gc;
+  const int c = (iy & 1) * 2 + (ix & 1);
+  const int parent = (iy >> 1) * Gp + (ix >> 1);
+  const V2<T> *row = tab + ((int64_t)c * (P + 1) + j) * (P + 1);
+  C2<T> acc = {T(0), T(0)};
+  for (int k = j; k <= P; ++k)
+    acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Bp[((int64_t)k * nd + r) * nbp + parent])));
+  V2<T> *dst = &Bc[((int64_t)j * nd + r) * nbc + box];
+  st2<T>(dst, cadd(ld2<T>(dst), acc));
+}
+
+// ------------------------------------------------------------------ leaf
+// One wavefront per leaf: each lane one target node.  Far field by Horner on
+// the leaf's incoming expansions (L2P) combined with U_r; near field by
+// direct phi over the 3x3 neighbouring leaves (step 2: direct evaluation).
+template <class T, int K>
+__global__ __launch_bounds__(64) void k_leaf_eval(
+    const double *__restrict__ x, const double *__restrict__ y,
+    const float *__restrict__ ux, const float *__restrict__ uy,
+    const double *__restrict__ t, const int32_t *__restrict__ start, int L, double h,
+    int P, const V2<T> *__restrict__ Bleaf, double *__restrict__ ytree,
+    double *__restrict__ yuser, const int32_t *__restrict__ order) {
+  constexpr int R = Rank<K>::R;
+  const int G = 1 << L;
+  const int nleaf = G * G;
+  const int leaf = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int b = start[leaf], e = start[leaf + 1];
+  if (b == e) return;
+  const int ix = leaf % G, iy = leaf / G;
+  const double w = 2.0 * h / G, invw = G / (2.0 * h);
+  const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
+  const int r0 = iy > 0 ? iy - 1 : 0, r1 = iy + 1 < G ? iy + 1 : G - 1;
+  const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
+  for (int i0 = b; i0 < e; i0 += 64) {
+    const int i = i0 + lane;
+    const bool act = i < e;
+    const int ii = act ? i : b;
+    const double xi = x[ii], yi = y[ii];
+    // far field
+    T far = T(0);
+    {
+      C2<T> z;
+      if constexpr (std::is_same<T, float>::value)
+        z = {ux[ii] * (float)invw, uy[ii] * (float)invw};
+      else
+        z = {(xi - cx) * invw, (yi - cy) * invw};
+      T u[R];
+      ufac<K, T>(xi, yi, u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C2<T> acc = ld2<T>(&Bleaf[((int64_t)P * R + r) * nleaf + leaf]);
+        for (int k = P - 1; k >= 0; --k) {
+          C2<T> bk = ld2<T>(&Bleaf[((int64_t)k * R + r) * nleaf + leaf]);
+          acc = cadd(cmul(acc, z), bk);
+        }
+        far += u[r] * acc.re;
+      }
+    }
+    // near field
+    T nearv = T(0);
+    if constexpr (std::is_same<T, double>::value) {
+      for (int row = r0; row <= r1; ++row) {
+        const int js = start[row * G + c0], je = start[row * G + c1 + 1];
+#pragma unroll 4
+        for (int j = js; j < je; ++j) {
+          const double dx = xi - x[j], dy = yi - y[j];
+          nearv += phi_r2<K>(dx * dx + dy * dy) * t[j];
+        }
+      }
+    } else {
+      const float uxi = ux[ii], uyi = uy[ii];
+      for (int row = r0; row <= r1; ++row) {
+        const float offy = (float)((iy - row) * w);
+        for (int col = c0; col <= c1; ++col) {
+          const float offx = (float)((ix - col) * w);
+          const int js = start[row * G + col], je = start[row * G + col + 1];
+#pragma unroll 4
+          for (int j = js; j < je; ++j) {
+            const float dx = (uxi - ux[j]) + offx, dy = (uyi - uy[j]) + offy;
+            nearv += phi_r2f<K>(dx * dx + dy * dy) * (float)t[j];
+          }
+        }
+      }
+    }
+    if (act) {
+      const double out = (double)far + (double)nearv;
+      if (ytree) ytree[i] = out;
+      if (yuser) yuser[order[i]] = out;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ targets
+// Evaluation of the interpolant at arbitrary targets (eq. phs_interp): inside
+// the tree domain by L2P + direct phi over the 3x3 neighbouring leaves;
+// outside it by descending the tree and evaluating outgoing expansions of
+// boxes far enough from the target (|z - c| >= 1.8 w), direct sums at leaves.
+template <int K>
+__global__ void k_eval_targets(const double *__restrict__ tg, int64_t m, double cxn,
+                               double cyn, double rho, const double *__restrict__ x,
+                               const double *__restrict__ y, const double *__restrict__ wt,
+                               const int32_t *__restrict__ start, int L, double h, int P,
+                               const double2 *__restrict__ Aall,
+                               const double2 *__restrict__ Bleaf,
+                               const double *__restrict__ beta, int d,
+                               double *__restrict__ out) {
+  constexpr int R = Rank<K>::R;
+  const int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (it >= m) return;
+  const double xi = (tg[2 * it] - cxn) * rho, yi = (tg[2 * it + 1] - cyn) * rho;
+  // polynomial part
+  double poly = 0.0;
+  {
+    double px[8], py[8];
+    px[0] = py[0] = 1.0;
+    for (int q = 1; q <= d; ++q) {
+      px[q] = px[q - 1] * xi;
+      py[q] = py[q - 1] * yi;
+    }
+    int col = 0;
+    for (int tdeg = 0; tdeg <= d; ++tdeg)
+      for (int a = tdeg; a >= 0; --a) poly += beta[col++] * px[a] * py[tdeg - a];
+  }
+  double u[R];
+  ufac<K, double>(xi, yi, u);
+  const int G = 1 << L;
+  const int nleaf = G * G;
+  double far = 0.0, nearv = 0.0;
+  const bool inside = fabs(xi) <= h && fabs(yi) <= h;
+  if (inside) {
+    const double scale = G / (2.0 * h);
+    int ix = (int)floor((xi + h) * scale), iy = (int)floor((yi + h) * scale);
+    ix = ix < 0 ? 0 : (ix >= G ? G - 1 : ix);
+    iy = iy < 0 ? 0 : (iy >= G ? G - 1 : iy);
+    const int leaf = iy * G + ix;
+    const double w = 2.0 * h / G;
+    const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
+    const C2<double> z = {(xi - cx) * scale, (yi - cy) * scale};
+    for (int r = 0; r < R; ++r) {
+      C2<double> acc = ld2<double>(&Bleaf[((int64_t)P * R + r) * nleaf + leaf]);
+      for (int k = P - 1; k >= 0; --k)
+        acc = cadd(cmul(acc, z), ld2<double>(&Bleaf[((int64_t)k * R + r) * nleaf + leaf]));
+      far += u[r] * acc.re;
+    }
+    const int r0 = iy > 0 ? iy - 1 : 0, r1 = iy + 1 < G ? iy + 1 : G - 1;
+    const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
+    for (int row = r0; row <= r1; ++row) {
+      const int js = start[row * G + c0], je = start[row * G + c1 + 1];
+      for (int j = js; j < je; ++j) {
+        const double dx = xi - x[j], dy = yi - y[j];
+        nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
+      }
+    }
+  } else {
+    // explicit-stack descent from level 2
+    int stk_l[64];
+    int stk_b[64];
+    int sp = 0;
+    for (int b0 = 0; b0 < 16; ++b0) {
+      stk_l[sp] = 2;
+      stk_b[sp] = b0;
+      ++sp;
+    }
+    while (sp > 0) {
+      --sp;
+      const int l = stk_l[sp], box = stk_b[sp];
+      const int Gl = 1 << l;
+      const double wl = 2.0 * h / Gl;
+      const int bx = box % Gl, by = box / Gl;
+      const double ccx = -h + (bx + 0.5) * wl, ccy = -h + (by + 0.5) * wl;
+      const double ddx = xi - ccx, ddy = yi - ccy;
+      const double dist2 = ddx * ddx + ddy * ddy;
+      if (dist2 >= (1.8 * wl) * (1.8 * wl)) {
+        const int64_t nbl = (int64_t)Gl * Gl;
+        const double2 *Al = Aall + level_base(l, P, R);
+        const C2<double> wz = {ddx / wl, ddy / wl};
+        const double den = wz.re * wz.re + wz.im * wz.im;
+        const C2<double> uinv = {wz.re / den, -wz.im / den};
+        const double lw = log(wl) + 0.5 * log(den);
+        for (int r = 0; r < R; ++r) {
+          C2<double> acc = ld2<double>(&Al[((int64_t)P * R + r) * nbl + box]);
+          for (int k = P - 1; k >= 1; --k)
+            acc = cadd(cmul(acc, uinv), ld2<double>(&Al[((int64_t)k * R + r) * nbl + box]));
+          acc = cmul(acc, uinv);
+          const double a0 = ld2<double>(&Al[(int64_t)r * nbl + box]).re;
+          far += u[r] * (a0 * lw + acc.re);
+        }
+      } else if (l == L) {
+        const int js = start[box], je = start[box + 1];
+        for (int j = js; j < je; ++j) {
+          const double dx = xi - x[j], dy = yi - y[j];
+          nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
+        }
+      } else {
+        for (int c = 0; c < 4; ++c) {
+          stk_l[sp] = l + 1;
+          stk_b[sp] = (2 * by + (c >> 1)) * (2 * Gl) + 2 * bx + (c & 1);
+          ++sp;
+        }
+      }
+    }
+  }
+  out[it] = poly + far + nearv;
+}
+
+// ------------------------------------------------------------------ host
+double binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+template <class T>
+void far_field(Plan &pl, const double *t, hipStream_t s) {
+  const bool fp64 = std::is_same<T, double>::value;
+  const int P = fp64 ? pl.p64 : pl.p32;
+  const LogTables &lt = fp64 ? pl.lt64 : pl.lt32;
+  const int nd = pl.R, L = pl.tree.L;
+  const double h = pl.tree.h;
+  V2<T> *A = (V2<T> *)pl.mp;
+  V2<T> *B = (V2<T> *)pl.loc;
+  const V2<T> *M2M = fp64 ? (const V2<T> *)lt.M2M64 : (const V2<T> *)lt.M2M32;
+  const V2<T> *L2L = fp64 ? (const V2<T> *)lt.L2L64 : (const V2<T> *)lt.L2L32;
+  const T *Ht = fp64 ? (const T *)lt.Ht64 : (const T *)lt.Ht32;
+  // P2M at the leaves
+  {
+    const int gpw = std::max(1, 64 / (P + 1));
+    const int64_t nleaf = boxes_at(L);
+    const int64_t groups = (nleaf + gpw - 1) / gpw;
+    const int64_t nblk = (groups + 3) / 4;
+    V2<T> *AL = A + level_base(L, P, nd);
+    if (pl.k == 2)
+      PHS_LAUNCH("p2m", s, k_p2m<T, 2><<<nblk, 256, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
+                                                             pl.tree.leaf_start, L, h, P,
+                                                             gpw, AL));
+    else
+      PHS_LAUNCH("p2m", s, k_p2m<T, 4><<<nblk, 256, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
+                                                             pl.tree.leaf_start, L, h, P,
+                                                             gpw, AL));
+  }
+  // upward pass
+  for (int lp = L - 1; lp >= 2; --lp) {
+    const int64_t tot = boxes_at(lp) * nd * (P + 1);
+    PHS_LAUNCH("m2m", s,
+               k_m2m<T><<<(tot + 255) / 256, 256, 0, s>>>(A + level_base(lp + 1, P, nd),
+                                                         A + level_base(lp, P, nd), lp, P,
+                                                         nd, M2M));
+  }
+  // outgoing -> incoming on every level
+  {
+    int64_t tot = 0;
+    for (int l = 2; l <= L; ++l) tot += boxes_at(l);
+    constexpr int LCH = 16;
+    dim3 grid((unsigned)((tot + 255) / 256), (unsigned)((P + 1 + LCH - 1) / LCH),
+              (unsigned)nd);
+    PHS_LAUNCH("m2l", s, k_m2l<T, LCH><<<grid, 256, 0, s>>>(A, B, L, P, nd, Ht, h));
+  }
+  // downward pass
+  for (int lc = 3; lc <= L; ++lc) {
+    const int64_t tot = boxes_at(lc) * nd * (P + 1);
+    PHS_LAUNCH("l2l", s,
+               k_l2l<T><<<(tot + 255) / 256, 256, 0, s>>>(B + level_base(lc - 1, P, nd),
+                                                         B + level_base(lc, P, nd), lc, P,
+                                                         nd, L2L));
+  }
+}
+
+template <class T>
+void leaf_pass(Plan &pl, const double *t, double *y_tree, double *y_user, hipStream_t s) {
+  const bool fp64 = std::is_same<T, double>::value;
+  const int P = fp64 ? pl.p64 : pl.p32;
+  const int L = pl.tree.L;
+  const V2<T> *BL = (const V2<T> *)pl.loc + level_base(L, P, pl.R);
+  const int64_t nleaf = boxes_at(L);
+  if (pl.k == 2)
+    PHS_LAUNCH("leaf_eval", s,
+               k_leaf_eval<T, 2><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
+                                                      pl.tree.leaf_start, L, pl.tree.h, P,
+                                                      BL, y_tree, y_user, pl.order));
+  else
+    PHS_LAUNCH("leaf_eval", s,
+               k_leaf_eval<T, 4><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
+                                                      pl.tree.leaf_start, L, pl.tree.h, P,
+                                                      BL, y_tree, y_user, pl.order));
+}
+
+}  // namespace
+
+void build_log_tables(LogTables &t, int P) {
+  free_log_tables(t);
+  t.P = P;
+  const int P1 = P + 1;
+  // k-major: H[k*P1 + l]; 64 zero entries of padding so a chunk of LCH
+  // coefficients that runs past P reads zeros, not past the allocation.
+  std::vector<double> H((size_t)P1 * P1 + 64, 0.0);
+  for (int l = 0; l <= P; ++l)
+    for (int k = 0; k <= P; ++k) {
+      double v;
+      if (l == 0) v = (k == 0) ? 0.0 : 1.0;
+      else if (k == 0) v = ((l % 2) ? 1.0 : -1.0) / l;
+      else v = ((l % 2) ? -1.0 : 1.0) * binom(k + l - 1, l);
+      H[(size_t)k * P1 + l] = v;
+    }
+  std::vector<double2> M2M((size_t)4 * P1 * P1), L2L((size_t)4 * P1 * P1);
+  for (int c = 0; c < 4; ++c) {
+    const double dre = (c & 1) ? 0.25 : -0.25, dim = (c & 2) ? 0.25 : -0.25;
+    std::vector<double> pre(2 * P1 + 1), pim(2 * P1 + 1);  // delta^e
+    pre[0] = 1.0;
+    pim[0] = 0.0;
+    for (int e = 1; e <= 2 * P1; ++e) {
+      pre[e] = pre[e - 1] * dre - pim[e - 1] * dim;
+      pim[e] = pre[e - 1] * dim + pim[e - 1] * dre;
+    }
+    for (int l = 0; l <= P; ++l)
+      for (int k = 0; k <= P; ++k) {
+        double re = 0.0, im = 0.0;
+        if (l == 0) {
+          if (k == 0) re = 1.0;
+        } else if (k == 0) {
+          re = -pre[l] / l;
+          im = -pim[l] / l;
+        } else if (k <= l) {
+          const double f = binom(l - 1, k - 1) * std::ldexp(1.0, -k);
+          re = f * pre[l - k];
+          im = f * pim[l - k];
+        }
+        M2M[((size_t)c * P1 + l) * P1 + k] = make_double2(re, im);
+      }
+    for (int j = 0; j <= P; ++j)
+      for (int k = 0; k <= P; ++k) {
+        double re = 0.0, im = 0.0;
+        if (k >= j) {
+          const double f = binom(k, j) * std::ldexp(1.0, -j);
+          re = f * pre[k - j];
+          im = f * pim[k - j];
+        }
+        L2L[((size_t)c * P1 + j) * P1 + k] = make_double2(re, im);
+      }
+  }
+  std::vector<float> Hf(H.begin(), H.end());
+  std::vector<float2> M2Mf(M2M.size()), L2Lf(L2L.size());
+  for (size_t i = 0; i < M2M.size(); ++i) {
+    M2Mf[i] = make_float2((float)M2M[i].x, (float)M2M[i].y);
+    L2Lf[i] = make_float2((float)L2L[i].x, (float)L2L[i].y);
+  }
+  t.Ht64 = dmalloc<double>(H.size());
+  t.Ht32 = dmalloc<float>(H.size());
+  t.M2M64 = dmalloc<double2>(M2M.size());
+  t.L2L64 = dmalloc<double2>(L2L.size());
+  t.M2M32 = dmalloc<float2>(M2M.size());
+  t.L2L32 = dmalloc<float2>(L2L.size());
+  PHS_HIP(hipMemcpy(t.Ht64, H.data(), H.size() * 8, hipMemcpyHostToDevice));
+  PHS_HIP(hipMemcpy(t.Ht32, Hf.data(), Hf.size() * 4, hipMemcpyHostToDevice));
+  PHS_HIP(hipMemcpy(t.M2M64, M2M.data(), M2M.size() * 16, hipMemcpyHostToDevice));
+  PHS_HIP(hipMemcpy(t.L2L64, L2L.data(), L2L.size() * 16, hipMemcpyHostToDevice));
+  PHS_HIP(hipMemcpy(t.M2M32, M2Mf.data(), M2Mf.size() * 8, hipMemcpyHostToDevice));
+  PHS_HIP(hipMemcpy(t.L2L32, L2Lf.data(), L2Lf.size() * 8, hipMemcpyHostToDevice));
+}
+
+void free_log_tables(LogTables &t) {
+  dfree(t.Ht64);
+  dfree(t.Ht32);
+  dfree(t.M2M64);
+  dfree(t.L2L64);
+  dfree(t.M2M32);
+  dfree(t.L2L32);
+  t = LogTables();
+}
+
+size_t log_expansion_bytes(int L, int P, int nd, bool fp64) {
+  return (size_t)level_base(L + 1, P, nd) * (fp64 ? 16 : 8);
+}
+
+void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, bool fp64,
+                hipStream_t s) {
+  if (fp64) {
+    far_field<double>(pl, t_tree, s);
+    leaf_pass<double>(pl, t_tree, y_tree, y_user, s);
+  } else {
+    far_field<float>(pl, t_tree, s);
+    leaf_pass<float>(pl, t_tree, y_tree, y_user, s);
+  }
+}
+
+void log_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
+  far_field<double>(pl, w_tree, s);
+}
+
+void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
+                      const double *targets, int64_t m, double *out, hipStream_t s) {
+  const int P = pl.p64, L = pl.tree.L;
+  const double2 *A = (const double2 *)pl.mp;
+  const double2 *BL = (const double2 *)pl.loc + level_base(L, P, pl.R);
+  const int64_t nb = (m + 127) / 128;
+  if (pl.k == 2)
+    PHS_LAUNCH("eval_targets", s,
+               k_eval_targets<2><<<nb, 128, 0, s>>>(targets, m, pl.c[0], pl.c[1], pl.rho,
+                                                    pl.x, pl.y, w_tree, pl.tree.leaf_start,
+                                                    L, pl.tree.h, P, A, BL, beta, pl.d,
+                                                    out));
+  else
+    PHS_LAUNCH("eval_targets", s,
+               k_eval_targets<4><<<nb, 128, 0, s>>>(targets, m, pl.c[0], pl.c[1], pl.rho,
+                                                    pl.x, pl.y, w_tree, pl.tree.leaf_start,
+                                                    L, pl.tree.h, P, A, BL, beta, pl.d,
+                                                    out));
+}
+
+}  // namespace phs

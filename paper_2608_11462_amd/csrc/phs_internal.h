@@ -1,0 +1,279 @@
+// Internal declarations of the PHS library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/phs.h"
+
+namespace phs {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  phs_status code;
+  std::string msg;
+};
+
+void set_error(phs_status code, const std::string &msg);
+
+#define PHS_HIP(call)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::phs::Error{e_ == hipErrorOutOfMemory ? PHS_ERR_OUT_OF_MEMORY    \
+                                                   : PHS_ERR_DEVICE,          \
+                         std::string(#call) + ": " + hipGetErrorString(e_)};  \
+  } while (0)
+
+#define PHS_REQUIRE(cond, code, msg)                                          \
+  do {                                                                        \
+    if (!(cond)) throw ::phs::Error{(code), (msg)};                           \
+  } while (0)
+
+// ------------------------------------------------------------------ profiling
+// Kernel launches go through launch(); when profiling is on each launch is
+// bracketed by events on its stream and the elapsed time is charged to name.
+bool profiling_on();
+void prof_begin(const char *name, hipStream_t s);
+void prof_end(hipStream_t s);
+
+struct ProfScope {
+  hipStream_t s;
+  bool on;
+  ProfScope(const char *name, hipStream_t st) : s(st), on(profiling_on()) {
+    if (on) prof_begin(name, s);
+  }
+  ~ProfScope() {
+    if (on) prof_end(s);
+  }
+};
+
+#define PHS_LAUNCH(name, stream, ...)                                         \
+  do {                                                                        \
+    ::phs::ProfScope ps_(name, stream);                                       \
+    __VA_ARGS__;                                                              \
+    PHS_HIP(hipGetLastError());                                               \
+  } while (0)
+
+// ------------------------------------------------------------------ memory
+template <class T>
+T *dmalloc(size_t count) {
+  void *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess)
+    throw Error{PHS_ERR_OUT_OF_MEMORY,
+                "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+  return static_cast<T *>(p);
+}
+
+inline void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+// ------------------------------------------------------------------ sizes
+inline int64_t boxes_at(int l) { return int64_t(1) << (2 * l); }
+
+// Number of core-kernel densities (Hadamard rank) for order k.
+inline int hadamard_rank(int k) {
+  switch (k) {
+    case 1: return 1;
+    case 2: return 4;
+    case 3: return 4;
+    case 4: return 9;
+    default: return 0;
+  }
+}
+
+inline int min_degree(int k) { return (k % 2 == 1) ? (k + 1) / 2 - 1 : k / 2; }
+inline int n_monomials(int d) { return (d + 1) * (d + 2) / 2; }
+inline double domain_half_width(int k) {
+  if (k == 2) return 0.25;
+  if (k % 2 == 1) return 0.5;
+  return 1.0;
+}
+// sign of Q_perp^T M Q_perp: +1 positive definite, -1 negative definite
+inline int definiteness_sign(int k) { return (k % 4 == 2 || k % 4 == 3) ? 1 : -1; }
+
+// ------------------------------------------------------------------ tree
+struct Tree {
+  int L = 2;        // leaf level; grid side G = 2^L
+  int G = 4;
+  double h = 0.25;  // domain [-h, h]^2 in normalised coordinates
+  int32_t *leaf_start = nullptr;  // G*G + 1, tree order ranges per leaf
+};
+
+// ------------------------------------------------------------------ FMM config
+struct LogTables {  // translation tables for one expansion order P
+  int P = 0;
+  double *Ht64 = nullptr;   // (P+1)^2 real, k-major: Ht[k*(P+1)+l]
+  float *Ht32 = nullptr;
+  double2 *M2M64 = nullptr; // 4 x (P+1)^2, [c][l][k]
+  double2 *L2L64 = nullptr; // 4 x (P+1)^2, [c][j][k]
+  float2 *M2M32 = nullptr;
+  float2 *L2L32 = nullptr;
+};
+
+struct ChebTables {  // Chebyshev interpolation tables for Q nodes per axis
+  int Q = 0;
+  double *nodes64 = nullptr;  // Q
+  double *S2c64 = nullptr;    // 2 x Q x Q : child node -> parent basis value
+  double *K64 = nullptr;      // 40 x Q^2 x Q^2 : M2L at unit half-width
+  float *nodes32 = nullptr;
+  float *S2c32 = nullptr;
+  float *K32 = nullptr;
+};
+
+// ------------------------------------------------------------------ plan
+struct Plan {
+  int64_t n = 0;
+  int k = 2, d = 1, S = 3, R = 4;
+  int precision = PHS_FP64;
+  int sign = 1;
+  bool core_log = true;
+  double c[2] = {0, 0};
+  double rho = 1;
+  Tree tree;
+  int p64 = 31, p32 = 15;  // log expansion order (terms beyond the constant)
+  int q64 = 16, q32 = 10;  // Chebyshev nodes per axis (distance kernel)
+
+  // tree-order node data
+  int32_t *order = nullptr;    // tree position -> caller index
+  int32_t *inv_order = nullptr;// caller index -> tree position
+  int32_t *leafkey = nullptr;
+  double *x = nullptr, *y = nullptr;   // normalised coordinates
+  float *ux = nullptr, *uy = nullptr;  // FP32 offsets from the leaf centre
+
+  // polynomial block
+  double *Q = nullptr;  // n x S column-major, tree order, orthonormal columns
+  std::vector<double> Rm;  // S x S upper triangular (row-major), B = Q R
+
+  // FMM workspace (sized for FP64 at the largest order in use)
+  void *mp = nullptr;   // multipole expansions levels 2..L
+  void *loc = nullptr;  // local expansions levels 2..L
+  size_t exp_bytes = 0;
+  LogTables lt64, lt32;  // tables for p64 (FP64) and p32 (FP32)
+  ChebTables ct64, ct32;
+
+  // vectors (tree order), n each
+  double *v_t = nullptr;    // density in tree order
+  double *v_y = nullptr;    // matvec output in tree order
+  double *wk[8] = {};       // PCG work vectors
+  double *red = nullptr;    // reduction partials
+  int red_cap = 0;
+  double *scal = nullptr;   // device scalars
+  double *hscal = nullptr;  // pinned host mirror
+  int32_t *iscratch = nullptr;  // sort scratch etc. (plan time)
+
+  // preconditioner
+  bool has_pc = false;
+  int m = 0;
+  double nu = 1, alpha = 0.35;
+  int pc_nugget_nodes = 0;      // nodes whose block needed a diagonal nugget
+  int32_t *pc_rank = nullptr;   // tree position -> rank
+  int32_t *pc_nbr = nullptr;    // n x m (tree positions, -1 padded), row per tree pos
+  double *pc_coef = nullptr;    // n x m  (-lambda / c)
+  double *pc_dinv = nullptr;    // n      (1 / c)
+  int32_t *pc_tstart = nullptr; // n + 1  transpose CSR
+  int32_t *pc_tidx = nullptr;   // n*m
+  double *pc_tcoef = nullptr;   // n*m
+
+  ~Plan();
+};
+
+// ------------------------------------------------------------------ launchers
+// tree.hip
+void minmax_xy(const double *xy, int64_t n, double *out4, double *partials,
+               int nblocks, hipStream_t s);
+void leaf_keys(const double *xy, int64_t n, double cx, double cy, double rho,
+               double h, int L, uint32_t *keys, int32_t *idx, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of key.
+// Temporary buffers: keys_tmp, vals_tmp (n each), hist (256*nblocks + scan ws).
+size_t radix_sort_scratch_ints(int64_t n);
+void radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, int bits,
+                    uint32_t *keys_tmp, int32_t *vals_tmp, int32_t *scratch,
+                    hipStream_t s);
+void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits,
+                    uint64_t *keys_tmp, int32_t *vals_tmp, int32_t *scratch,
+                    hipStream_t s);
+void leaf_ranges(const uint32_t *sorted_keys, int64_t n, int nleaves,
+                 int32_t *leaf_start, hipStream_t s);
+void build_tree_points(const double *xy, const int32_t *order,
+                       const uint32_t *keys_sorted, int64_t n, double cx,
+                       double cy, double rho, double h, int L, double *x,
+                       double *y, float *ux, float *uy, int32_t *leafkey,
+                       int32_t *inv_order, hipStream_t s);
+void count_duplicates(const double *x, const double *y,
+                      const int32_t *leaf_start, int nleaves, int32_t *flag,
+                      hipStream_t s);
+
+// vec.hip
+void gather_cols(const double *src_user, const int32_t *order, int64_t n,
+                 double *dst_tree, hipStream_t s);
+void scatter_cols(const double *src_tree, const int32_t *order, int64_t n,
+                  double *dst_user, hipStream_t s);
+void poly_block_tree(const double *x, const double *y, int64_t n, int d,
+                     double *B, hipStream_t s);
+// Partial sums for several dot products sum_i a_t[i]*b_t[i], t < nd.
+// out (device) receives nd results.  partials holds nblocks*nd doubles.
+int dot_blocks(int64_t n);
+void multi_dot(const double *const *a, const double *const *b, int nd,
+               int64_t n, double *partials, double *out, hipStream_t s);
+void gram(const double *B, int64_t n, int S, double *partials, double *out,
+          hipStream_t s);
+void apply_rinv(double *B, int64_t n, int S, const double *Rinv_dev,
+                hipStream_t s);
+void project(double *v, const double *Q, int64_t n, int S, double *partials,
+             double *scal, hipStream_t s);
+void axpby(double *y, const double *x, double a, double b, int64_t n,
+           hipStream_t s);
+void scale_copy(double *dst, const double *src, double a, int64_t n,
+                hipStream_t s);
+void pcg_update_wr(double *w, double *r, const double *p, const double *q,
+                   const double *scal, int64_t n, double *partials,
+                   double *out_rr, hipStream_t s);
+void pcg_update_p(double *p, const double *z, const double *scal, int64_t n,
+                  hipStream_t s);
+void fill(double *v, double a, int64_t n, hipStream_t s);
+void copy(double *dst, const double *src, int64_t n, hipStream_t s);
+
+// fmm_log.hip
+void build_log_tables(LogTables &t, int P);
+void free_log_tables(LogTables &t);
+size_t log_expansion_bytes(int L, int P, int ndens, bool fp64);
+void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user,
+                bool fp64, hipStream_t s);
+// Upward pass only (for evaluation at targets): fills pl.mp/pl.loc with
+// expansions of the densities V_r * w.
+void log_expansions(Plan &pl, const double *w_tree, hipStream_t s);
+
+// fmm_dist.hip
+void build_cheb_tables(ChebTables &t, int Q);
+void free_cheb_tables(ChebTables &t);
+size_t cheb_expansion_bytes(int L, int Q, int ndens, bool fp64);
+void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user,
+                 bool fp64, hipStream_t s);
+void dist_expansions(Plan &pl, const double *w_tree, hipStream_t s);
+
+void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
+                      const double *targets, int64_t m, double *out, hipStream_t s);
+void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,
+                       const double *targets, int64_t m, double *out, hipStream_t s);
+
+// vecchia.hip
+void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s);
+void vecchia_apply(Plan &pl, const double *r, double *z, double *tmp,
+                   hipStream_t s);
+void vecchia_free(Plan &pl);
+void vecchia_export(Plan &pl, int32_t *rank, int32_t *nbr, double *coef, double *diag,
+                    hipStream_t s);
+
+// api.hip
+void matvec_tree(Plan &pl, const double *t_tree, double *y_tree, int precision,
+                 hipStream_t s);
+
+}  // namespace phs

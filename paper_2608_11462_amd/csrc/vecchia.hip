@@ -1,0 +1,571 @@
+// Vecchia / Matern sparse inverse-Cholesky preconditioner (paper Sec. 2.2:
+// eqs. conditionals and vecchia_sumform, Fig. vecchia_chol; conditioning-set
+// sizes and random ordering of Sec. 3).
+//
+//  1. ordering: rank order = nodes sorted by (splitmix64(seed ^ i), i), i the
+//     caller index (stable LSD radix sort);
+//  2. conditioning sets: sigma(j) = the min(m, rank_j) predecessors with the
+//     smallest (d^2, rank), d^2 = dx*dx + dy*dy rounded exactly as written
+//     (no contraction) — found by ring search in uniform grids built over the
+//     rank prefixes [0, 2^t), so the predecessors of a node of rank in
+//     [2^(t-1), 2^t) fill at least half of the grid it searches;
+//  3. factor: per node, Cholesky of the (|sigma|+1)^2 Matern block with the
+//     node last; its last row gives L^{-1} k and the conditional standard
+//     deviation c, then lambda = L^{-T} (L^{-1} k); column j of U~ holds 1/c on
+//     the diagonal and -lambda/c at sigma(j);
+//  4. apply: z = U~ (U~^T r) as two gathers, the second through a transposed
+//     copy whose rows are sorted by column, so sums are in a fixed order.
+#include <cmath>
+
+#include "phs_internal.h"
+
+namespace phs {
+
+namespace {
+
+constexpr int kMaxM = 64;
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_rank_keys(int64_t n, uint64_t seed, uint64_t *keys, int32_t *vals) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = splitmix64(seed ^ (uint64_t)i);
+  vals[i] = (int32_t)i;
+}
+
+__global__ void k_rank_maps(const int32_t *perm, const int32_t *inv_order, int64_t n,
+                            const double *x, const double *y, int32_t *rank_tree,
+                            int32_t *pos_of_rank, double *xr, double *yr) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int p = inv_order[perm[t]];
+  pos_of_rank[t] = p;
+  rank_tree[p] = (int32_t)t;
+  xr[t] = x[p];
+  yr[t] = y[p];
+}
+
+__device__ __forceinline__ int grid_cell(double v, double h, int g) {
+#pragma clang fp contract(off)
+  double u = (v + h) * ((double)g / (2.0 * h));
+  int q = (int)floor(u);
+  return q < 0 ? 0 : (q >= g ? g - 1 : q);
+}
+
+// entry e of the concatenated rank prefixes -> (level << 20 | cell, rank)
+__global__ void k_grid_keys(const double *xr, const double *yr, int T,
+                            const int64_t *lvl_off, const int32_t *gbits, double h,
+                            int64_t total, uint32_t *keys, int32_t *vals) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int t = 0;
+  while (t < T && e >= lvl_off[t + 1]) ++t;
+  const int r = (int)(e - lvl_off[t]);
+  const int g = 1 << gbits[t];
+  const int cx = grid_cell(xr[r], h, g), cy = grid_cell(yr[r], h, g);
+  keys[e] = ((uint32_t)t << 20) | (uint32_t)(cy * g + cx);
+  vals[e] = r;
+}
+
+__global__ void k_cell_start(const uint32_t *keys, int64_t total, int T, const int32_t *gbits,
+                             const int64_t *cell_off, int64_t ncells_total, int32_t *start) {
+  int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= ncells_total) return;
+  int t = 0;
+  while (t < T && q >= cell_off[t + 1]) ++t;
+  const uint32_t c = (uint32_t)(q - cell_off[t]);
+  const uint32_t key = ((uint32_t)t << 20) | c;
+  int64_t lo = 0, hi = total;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  start[q] = (int32_t)lo;
+}
+
+__device__ __forceinline__ bool lessp(double da, int ra, double db, int rb) {
+  return da < db || (da == db && ra < rb);
+}
+
+// Ordered nearest predecessors; one thread per rank, lists in LDS.
+__global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, int64_t n,
+                                            int m, int T, double h, const int32_t *gbits,
+                                            const int64_t *cell_off, const int32_t *cell_start,
+                                            const int32_t *sorted_rank,
+                                            const int32_t *pos_of_rank, int32_t *nbr,
+                                            int32_t *cnt_out) {
+  __shared__ double d2s[kMaxM * 64];
+  __shared__ int rks[kMaxM * 64];
+  const int lane = threadIdx.x;
+  const int64_t t = blockIdx.x * (int64_t)64 + lane;
+  if (t >= n) return;
+  const int K = (int)(t < m ? t : m);
+  const int p = pos_of_rank[t];
+  if (K == 0) {
+    cnt_out[p] = 0;
+    for (int s = 0; s < m; ++s) nbr[(int64_t)s * n + p] = -1;
+    return;
+  }
+  int lv = 64 - __clzll((unsigned long long)t);  // smallest lv with 2^lv >= t+1
+  if (lv > T) lv = T;
+  const int gb = gbits[lv];
+  const int g = 1 << gb;
+  const double cw = 2.0 * h / g;
+  const double qx = xr[t], qy = yr[t];
+  const int cqx = grid_cell(qx, h, g), cqy = grid_cell(qy, h, g);
+  const int32_t *cs = cell_start + cell_off[lv];
+  int cnt = 0;
+  const int maxR = max(max(cqx, g - 1 - cqx), max(cqy, g - 1 - cqy));
+  for (int R = 0; R <= maxR; ++R) {
+    for (int cy = cqy - R; cy <= cqy + R; ++cy) {
+      if (cy < 0 || cy >= g) continue;
+      const bool edge_row = (cy == cqy - R) || (cy == cqy + R);
+      const int step = edge_row ? 1 : 2 * R;
+      for (int cx = cqx - R; cx <= cqx + R; cx += (step > 0 ? step : 1)) {
+        if (cx >= 0 && cx < g) {
+          const int c = cy * g + cx;
+          const int b = cs[c], e = cs[c + 1];
+          for (int q = b; q < e; ++q) {
+            const int r = sorted_rank[q];
+            if (r >= t) break;  // within a cell entries ascend by rank
+            double d2;
+            {
+              // each product rounded, then the sum: no fused multiply-add, so
+              // d^2 is symmetric in (dx, dy) and identical to the CPU reference
+#pragma clang fp contract(off)
+              const double dx = xr[r] - qx;
+              const double dy = yr[r] - qy;
+              d2 = dx * dx + dy * dy;
+            }
+            int pos;
+            if (cnt < K) {
+              pos = cnt++;
+            } else {
+              if (!lessp(d2, r, d2s[(K - 1) * 64 + lane], rks[(K - 1) * 64 + lane])) continue;
+              pos = K - 1;
+            }
+            while (pos > 0 && lessp(d2, r, d2s[(pos - 1) * 64 + lane], rks[(pos - 1) * 64 + lane])) {
+              d2s[pos * 64 + lane] = d2s[(pos - 1) * 64 + lane];
+              rks[pos * 64 + lane] = rks[(pos - 1) * 64 + lane];
+              --pos;
+            }
+            d2s[pos * 64 + lane] = d2;
+            rks[pos * 64 + lane] = r;
+          }
+        }
+        if (R == 0) break;
+      }
+    }
+    if (cnt == K && R >= 1) {
+      const double bound = (double)R * cw;
+      if (d2s[(K - 1) * 64 + lane] < bound * bound * (1.0 - 1e-12)) break;
+    }
+  }
+  cnt_out[p] = cnt;
+  for (int s = 0; s < m; ++s)
+    nbr[(int64_t)s * n + p] = s < cnt ? pos_of_rank[rks[s * 64 + lane]] : -1;
+}
+
+// ---------------------------------------------------------------- Matern
+constexpr double kEuler = 0.57721566490153286061;
+
+__device__ void bessel_k01(double x, double &K0, double &K1) {
+  if (x <= 2.0) {
+    // power series of I0, I1 and the logarithmic forms of K0, K1
+    const double q = 0.25 * x * x;
+    double t0 = 1.0, t1 = 1.0, I0 = 0.0, I1s = 0.0, S0 = 0.0, S1 = 0.0, H = 0.0;
+    for (int k = 0; k < 40; ++k) {
+      if (k > 0) {
+        t0 *= q / ((double)k * k);
+        t1 *= q / ((double)k * (k + 1));
+        H += 1.0 / k;
+      }
+      I0 += t0;
+      I1s += t1;
+      S0 += H * t0;
+      S1 += (-2.0 * kEuler + 2.0 * H + 1.0 / (k + 1)) * t1;
+      if (k > 2 && t0 < 1e-18 * I0) break;
+    }
+    const double lg = log(0.5 * x);
+    K0 = -(lg + kEuler) * I0 + S0;
+    K1 = 1.0 / x + lg * (0.5 * x) * I1s - 0.25 * x * S1;
+  } else {
+    // trapezoid rule on K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt, with
+    // e^{-x} factored out and a step shrinking like x^{-1/2}
+    const double hh = fmin(0.25, 0.6 / sqrt(x));
+    double s0 = 0.5, s1 = 0.5;
+    for (int i = 1; i < 400; ++i) {
+      const double tt = i * hh;
+      const double c = cosh(tt);
+      const double a = x * (c - 1.0);
+      const double e = exp(-a);
+      s0 += e;
+      s1 += e * c;
+      if (a > 42.0) break;
+    }
+    const double f = hh * exp(-x);
+    K0 = s0 * f;
+    K1 = s1 * f;
+  }
+}
+
+// normalised Matern correlation, value 1 at x = 0; nu2 = 2*nu in {1,2,3,4,5}
+__device__ double matern(int nu2, double x) {
+  if (x == 0.0) return 1.0;
+  switch (nu2) {
+    case 1: return exp(-x);
+    case 3: return (1.0 + x) * exp(-x);
+    case 5: return (1.0 + x + x * x / 3.0) * exp(-x);
+    case 2: {
+      double K0, K1;
+      bessel_k01(x, K0, K1);
+      return x * K1;
+    }
+    default: {  // nu = 2: x^2 K_2(x) / 2, K_2 = K_0 + 2 K_1 / x
+      double K0, K1;
+      bessel_k01(x, K0, K1);
+      return 0.5 * x * x * K0 + x * K1;
+    }
+  }
+}
+
+// One wavefront per node: factor the Matern block of sigma(j) u {j}.
+template <int MM>
+__global__ __launch_bounds__(64) void k_factor(const double *x, const double *y, int64_t n,
+                                               int m, const int32_t *nbr, const int32_t *cnt,
+                                               int nu2, double alpha, double *coef,
+                                               double *dinv, int32_t *nfail) {
+  constexpr int LD = MM + 1;
+  __shared__ double C[LD * LD];
+  __shared__ double px[LD], py[LD], vv[LD];
+  __shared__ int bad;
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int K = cnt[p];
+  const int N1 = K + 1;
+  for (int a = lane; a < K; a += 64) {
+    const int q = nbr[(int64_t)a * n + p];
+    px[a] = x[q];
+    py[a] = y[q];
+  }
+  if (lane == 0) {
+    px[K] = x[p];
+    py[K] = y[p];
+  }
+  __syncthreads();
+  double nug = 0.0;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    for (int e = lane; e < N1 * N1; e += 64) {
+      const int a = e / N1, b = e % N1;
+      if (b <= a) {
+        const double dx = px[a] - px[b], dy = py[a] - py[b];
+        double v = matern(nu2, alpha * sqrt(dx * dx + dy * dy));
+        if (a == b) v += nug;
+        C[a * LD + b] = v;
+      }
+    }
+    if (lane == 0) bad = 0;
+    __syncthreads();
+    for (int c = 0; c < N1; ++c) {
+      const double dg = C[c * LD + c];
+      if (!(dg > 0.0)) {
+        if (lane == 0) bad = 1;
+        break;
+      }
+      const double d = sqrt(dg);
+      __syncthreads();
+      for (int r = c + 1 + lane; r < N1; r += 64) C[r * LD + c] /= d;
+      if (lane == 0) C[c * LD + c] = d;
+      __syncthreads();
+      for (int r = c + 1 + lane; r < N1; r += 64) {
+        const double lrc = C[r * LD + c];
+        for (int s2 = c + 1; s2 <= r; ++s2) C[r * LD + s2] -= lrc * C[s2 * LD + c];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (!bad) break;
+    nug = (attempt == 0) ? 1e-12 : nug * 100.0;
+    if (lane == 0 && attempt == 0) atomicAdd(&nfail[0], 1);
+    __syncthreads();
+  }
+  if (bad) {
+    if (lane == 0) atomicAdd(&nfail[1], 1);
+    return;
+  }
+  // lambda = L_s^{-T} (row K of L); c = L[K][K]
+  const double cc = C[K * LD + K];
+  for (int a = lane; a < K; a += 64) vv[a] = C[K * LD + a];
+  __syncthreads();
+  for (int i = K - 1; i >= 0; --i) {
+    const double li = vv[i] / C[i * LD + i];
+    __syncthreads();
+    if (lane == 0) vv[i] = li;
+    for (int l = lane; l < i; l += 64) vv[l] -= C[i * LD + l] * li;
+    __syncthreads();
+  }
+  const double inv_c = 1.0 / cc;
+  for (int a = lane; a < m; a += 64)
+    coef[(int64_t)a * n + p] = a < K ? -vv[a] * inv_c : 0.0;
+  if (lane == 0) dinv[p] = inv_c;
+}
+
+// ---------------------------------------------------------------- transpose
+__global__ void k_tcount(const int32_t *nbr, int64_t n, int m, int32_t *count) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * m) return;
+  const int q = nbr[e];
+  if (q >= 0) atomicAdd(&count[q], 1);
+}
+
+__global__ void k_tfill(const int32_t *nbr, const double *coef, int64_t n, int m,
+                        const int32_t *tstart, int32_t *cursor, int32_t *tidx, double *tcoef) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * m) return;
+  const int q = nbr[e];
+  if (q < 0) return;
+  const int j = (int)(e % n);
+  const int pos = tstart[q] + atomicAdd(&cursor[q], 1);
+  tidx[pos] = j;
+  tcoef[pos] = coef[e];
+}
+
+// sort each transposed row by column index (fixed summation order)
+__global__ void k_tsort(const int32_t *tstart, int64_t n, int32_t *tidx, double *tcoef) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = tstart[i], e = tstart[i + 1];
+  for (int a = b + 1; a < e; ++a) {
+    const int key = tidx[a];
+    const double val = tcoef[a];
+    int q = a - 1;
+    while (q >= b && tidx[q] > key) {
+      tidx[q + 1] = tidx[q];
+      tcoef[q + 1] = tcoef[q];
+      --q;
+    }
+    tidx[q + 1] = key;
+    tcoef[q + 1] = val;
+  }
+}
+
+// ---------------------------------------------------------------- apply
+__global__ void k_apply_ut(const double *r, int64_t n, int m, const int32_t *nbr,
+                           const double *coef, const double *dinv, double *yv) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = dinv[j] * r[j];
+  for (int s = 0; s < m; ++s) {
+    const int q = nbr[(int64_t)s * n + j];
+    if (q < 0) break;
+    acc += coef[(int64_t)s * n + j] * r[q];
+  }
+  yv[j] = acc;
+}
+
+__global__ void k_apply_u(const double *yv, int64_t n, const int32_t *tstart,
+                          const int32_t *tidx, const double *tcoef, const double *dinv,
+                          double *z) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = dinv[i] * yv[i];
+  const int b = tstart[i], e = tstart[i + 1];
+  for (int a = b; a < e; ++a) acc += tcoef[a] * yv[tidx[a]];
+  z[i] = acc;
+}
+
+// export in caller order
+__global__ void k_export(int64_t n, int m, const int32_t *order, const int32_t *rank_tree,
+                         const int32_t *nbr, const double *coef, const double *dinv,
+                         int32_t *rank_u, int32_t *nbr_u, double *coef_u, double *diag_u) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int u = order[p];
+  rank_u[u] = rank_tree[p];
+  diag_u[u] = dinv[p];
+  for (int s = 0; s < m; ++s) {
+    const int q = nbr[(int64_t)s * n + p];
+    nbr_u[(int64_t)u * m + s] = q >= 0 ? order[q] : -1;
+    coef_u[(int64_t)u * m + s] = coef[(int64_t)s * n + p];
+  }
+}
+
+int nu_code(double nu) {
+  const double v[5] = {0.5, 1.0, 1.5, 2.0, 2.5};
+  for (int i = 0; i < 5; ++i)
+    if (std::fabs(nu - v[i]) < 1e-12) return i + 1;
+  return 0;
+}
+
+}  // namespace
+
+void scan_exclusive(int32_t *data, int64_t count, int32_t *ws, hipStream_t s);
+int64_t scan_ws_ints(int64_t count);
+
+void vecchia_free(Plan &pl) {
+  dfree(pl.pc_rank);
+  dfree(pl.pc_nbr);
+  dfree(pl.pc_coef);
+  dfree(pl.pc_dinv);
+  dfree(pl.pc_tstart);
+  dfree(pl.pc_tidx);
+  dfree(pl.pc_tcoef);
+  pl.pc_rank = pl.pc_nbr = pl.pc_tstart = pl.pc_tidx = nullptr;
+  pl.pc_coef = pl.pc_dinv = pl.pc_tcoef = nullptr;
+  pl.has_pc = false;
+}
+
+void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
+  const int64_t n = pl.n;
+  const int m = o.m > 0 ? o.m : (pl.k == 2 ? 30 : 50);
+  PHS_REQUIRE(m >= 1 && m <= kMaxM, PHS_ERR_INVALID_ARGUMENT,
+              "conditioning-set size must be 1..64");
+  const double nu = o.nu > 0 ? o.nu : 0.5 * pl.k;
+  const int nu2 = nu_code(nu);
+  PHS_REQUIRE(nu2 > 0, PHS_ERR_INVALID_ARGUMENT, "nu must be one of 0.5, 1, 1.5, 2, 2.5");
+  double alpha;
+  if (o.range > 0) {
+    PHS_REQUIRE(o.range_units == PHS_RANGE_NORMALIZED || o.range_units == PHS_RANGE_USER,
+                PHS_ERR_INVALID_ARGUMENT, "bad range units");
+    alpha = o.range_units == PHS_RANGE_USER ? 1.0 / (o.range * pl.rho) : 1.0 / o.range;
+  } else {
+    alpha = pl.k == 4 ? 2.0 : 0.35;
+  }
+  vecchia_free(pl);
+  pl.m = m;
+  pl.nu = nu;
+  pl.alpha = alpha;
+  const double h = pl.tree.h;
+  const int B = 256;
+  // 1. ordering
+  uint64_t *k64 = dmalloc<uint64_t>(n), *k64t = dmalloc<uint64_t>(n);
+  int32_t *perm = dmalloc<int32_t>(n), *vt = dmalloc<int32_t>(std::max<int64_t>(n, 1));
+  int T = 0;
+  while (((int64_t)1 << T) < n) ++T;
+  std::vector<int64_t> lvl_off(T + 2), cell_off(T + 2);
+  std::vector<int32_t> gb(T + 1);
+  lvl_off[0] = 0;
+  cell_off[0] = 0;
+  for (int t = 0; t <= T; ++t) {
+    const int64_t sz = std::min<int64_t>((int64_t)1 << t, n);
+    lvl_off[t + 1] = lvl_off[t] + sz;
+    gb[t] = std::min(10, std::max(0, (t - 2) / 2));
+    cell_off[t + 1] = cell_off[t] + ((int64_t)1 << (2 * gb[t])) + 1;
+  }
+  const int64_t total = lvl_off[T + 1];
+  const int64_t ncells = cell_off[T + 1];
+  int32_t *scr = dmalloc<int32_t>(radix_sort_scratch_ints(std::max(total, n)));
+  uint32_t *gk = dmalloc<uint32_t>(total), *gkt = dmalloc<uint32_t>(total);
+  int32_t *gv = dmalloc<int32_t>(total), *gvt = dmalloc<int32_t>(total);
+  int32_t *cstart = dmalloc<int32_t>(ncells);
+  int64_t *d_lvl = dmalloc<int64_t>(T + 2), *d_coff = dmalloc<int64_t>(T + 2);
+  int32_t *d_gb = dmalloc<int32_t>(T + 1);
+  double *xr = dmalloc<double>(n), *yr = dmalloc<double>(n);
+  int32_t *pos_of_rank = dmalloc<int32_t>(n), *cnt = dmalloc<int32_t>(n);
+  int32_t *nfail = dmalloc<int32_t>(2);
+  try {
+    PHS_LAUNCH("vecchia_rank_keys", s,
+               k_rank_keys<<<(n + B - 1) / B, B, 0, s>>>(n, o.seed, k64, perm));
+    radix_sort_u64(k64, perm, n, 64, k64t, vt, scr, s);
+    pl.pc_rank = dmalloc<int32_t>(n);
+    PHS_LAUNCH("vecchia_rank_maps", s,
+               k_rank_maps<<<(n + B - 1) / B, B, 0, s>>>(perm, pl.inv_order, n, pl.x, pl.y,
+                                                        pl.pc_rank, pos_of_rank, xr, yr));
+    // 2. rank-prefix grids
+    PHS_HIP(hipMemcpyAsync(d_lvl, lvl_off.data(), (T + 2) * 8, hipMemcpyHostToDevice, s));
+    PHS_HIP(hipMemcpyAsync(d_coff, cell_off.data(), (T + 2) * 8, hipMemcpyHostToDevice, s));
+    PHS_HIP(hipMemcpyAsync(d_gb, gb.data(), (T + 1) * 4, hipMemcpyHostToDevice, s));
+    PHS_LAUNCH("vecchia_grid_keys", s,
+               k_grid_keys<<<(total + B - 1) / B, B, 0, s>>>(xr, yr, T, d_lvl, d_gb, h, total,
+                                                            gk, gv));
+    radix_sort_u32(gk, gv, total, 25, gkt, gvt, scr, s);
+    PHS_LAUNCH("vecchia_cell_start", s,
+               k_cell_start<<<(ncells + B - 1) / B, B, 0, s>>>(gk, total, T, d_gb, d_coff,
+                                                              ncells, cstart));
+    // 3. ordered nearest predecessors
+    pl.pc_nbr = dmalloc<int32_t>((size_t)n * m);
+    PHS_LAUNCH("vecchia_knn", s,
+               k_knn<<<(n + 63) / 64, 64, 0, s>>>(xr, yr, n, m, T, h, d_gb, d_coff, cstart, gv,
+                                                  pos_of_rank, pl.pc_nbr, cnt));
+    // 4. factor
+    pl.pc_coef = dmalloc<double>((size_t)n * m);
+    pl.pc_dinv = dmalloc<double>(n);
+    PHS_HIP(hipMemsetAsync(nfail, 0, 8, s));
+    if (m <= 32)
+      PHS_LAUNCH("vecchia_factor", s,
+                 k_factor<32><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
+                                              pl.pc_coef, pl.pc_dinv, nfail));
+    else
+      PHS_LAUNCH("vecchia_factor", s,
+                 k_factor<kMaxM><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
+                                                 alpha, pl.pc_coef, pl.pc_dinv, nfail));
+    // 5. transpose
+    pl.pc_tstart = dmalloc<int32_t>(n + 1);
+    int32_t *cursor = cnt;  // reuse
+    PHS_HIP(hipMemsetAsync(pl.pc_tstart, 0, (n + 1) * 4, s));
+    PHS_LAUNCH("vecchia_tcount", s,
+               k_tcount<<<(n * m + B - 1) / B, B, 0, s>>>(pl.pc_nbr, n, m, pl.pc_tstart));
+    scan_exclusive(pl.pc_tstart, n + 1, scr, s);
+    int32_t nnz = 0;
+    PHS_HIP(hipMemcpyAsync(&nnz, pl.pc_tstart + n, 4, hipMemcpyDeviceToHost, s));
+    PHS_HIP(hipStreamSynchronize(s));
+    pl.pc_tidx = dmalloc<int32_t>(std::max(nnz, 1));
+    pl.pc_tcoef = dmalloc<double>(std::max(nnz, 1));
+    PHS_HIP(hipMemsetAsync(cursor, 0, n * 4, s));
+    PHS_LAUNCH("vecchia_tfill", s,
+               k_tfill<<<(n * m + B - 1) / B, B, 0, s>>>(pl.pc_nbr, pl.pc_coef, n, m,
+                                                        pl.pc_tstart, cursor, pl.pc_tidx,
+                                                        pl.pc_tcoef));
+    PHS_LAUNCH("vecchia_tsort", s,
+               k_tsort<<<(n + B - 1) / B, B, 0, s>>>(pl.pc_tstart, n, pl.pc_tidx, pl.pc_tcoef));
+    int32_t hfail[2] = {0, 0};
+    PHS_HIP(hipMemcpyAsync(hfail, nfail, 8, hipMemcpyDeviceToHost, s));
+    PHS_HIP(hipStreamSynchronize(s));
+    PHS_REQUIRE(hfail[1] == 0, PHS_ERR_INVALID_ARGUMENT,
+                "Matern block not positive definite even with a diagonal nugget");
+    pl.pc_nugget_nodes = hfail[0];
+    pl.has_pc = true;
+  } catch (...) {
+    vecchia_free(pl);
+    for (void *q : {(void *)k64, (void *)k64t, (void *)perm, (void *)vt, (void *)scr, (void *)gk,
+                    (void *)gkt, (void *)gv, (void *)gvt, (void *)cstart, (void *)d_lvl,
+                    (void *)d_coff, (void *)d_gb, (void *)xr, (void *)yr, (void *)pos_of_rank,
+                    (void *)cnt, (void *)nfail})
+      dfree(q);
+    throw;
+  }
+  for (void *q : {(void *)k64, (void *)k64t, (void *)perm, (void *)vt, (void *)scr, (void *)gk,
+                  (void *)gkt, (void *)gv, (void *)gvt, (void *)cstart, (void *)d_lvl,
+                  (void *)d_coff, (void *)d_gb, (void *)xr, (void *)yr, (void *)pos_of_rank,
+                  (void *)cnt, (void *)nfail})
+    dfree(q);
+}
+
+void vecchia_apply(Plan &pl, const double *r, double *z, double *tmp, hipStream_t s) {
+  const int64_t n = pl.n;
+  const int B = 256;
+  PHS_LAUNCH("precond_ut", s,
+             k_apply_ut<<<(n + B - 1) / B, B, 0, s>>>(r, n, pl.m, pl.pc_nbr, pl.pc_coef,
+                                                     pl.pc_dinv, tmp));
+  PHS_LAUNCH("precond_u", s,
+             k_apply_u<<<(n + B - 1) / B, B, 0, s>>>(tmp, n, pl.pc_tstart, pl.pc_tidx,
+                                                    pl.pc_tcoef, pl.pc_dinv, z));
+}
+
+void vecchia_export(Plan &pl, int32_t *rank, int32_t *nbr, double *coef, double *diag,
+                    hipStream_t s) {
+  const int64_t n = pl.n;
+  PHS_LAUNCH("precond_export", s,
+             k_export<<<(n + 255) / 256, 256, 0, s>>>(n, pl.m, pl.order, pl.pc_rank,
+                                                      pl.pc_nbr, pl.pc_coef, pl.pc_dinv, rank,
+                                                      nbr, coef, diag));
+}
+
+}  // namespace phs

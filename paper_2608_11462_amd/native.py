@@ -1,0 +1,248 @@
+"""Thin ctypes binding of libphs.so (argument marshalling only).
+
+Every step of the computation runs in the HIP library; PyTorch only provides
+device memory (tensors whose data pointers are handed to the C ABI) and the
+current HIP stream.  Importing this module does not load the library; the
+first call does, and raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from pathlib import Path
+
+import torch
+
+LIB_PATH = Path(__file__).resolve().parent / "libphs.so"
+
+PHS_FP64, PHS_MIXED = 0, 1
+PHS_RANGE_NORMALIZED, PHS_RANGE_USER = 0, 1
+
+STATUS = {
+    0: "PHS_OK", 1: "PHS_ERR_INVALID_ARGUMENT", 2: "PHS_ERR_DUPLICATE_POINTS",
+    3: "PHS_ERR_UNISOLVENT", 4: "PHS_ERR_NOT_CONVERGED", 5: "PHS_ERR_BREAKDOWN",
+    6: "PHS_ERR_OUT_OF_MEMORY", 7: "PHS_ERR_DEVICE", 8: "PHS_ERR_NOT_READY",
+}
+
+EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval",
+           "phs_plan_info", "phs_plan_tree", "phs_precond_export", "phs_precond_apply",
+           "phs_plan_destroy", "phs_last_error", "phs_profile_enable", "phs_profile_read")
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("k", C.c_int32), ("poly_degree", C.c_int32), ("precision", C.c_int32),
+                ("fmm_tol", C.c_double), ("leaf_size", C.c_int32),
+                ("expansion_order", C.c_int32)]
+
+
+class PrecondOpts(C.Structure):
+    _fields_ = [("m", C.c_int32), ("nu", C.c_double), ("range", C.c_double),
+                ("range_units", C.c_int32), ("seed", C.c_uint64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_refinements", C.c_int32),
+                ("rel_residual", C.c_double), ("t_solve", C.c_double)]
+
+
+class PHSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2608_11462_amd.build`")
+        L = C.CDLL(str(LIB_PATH))
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p
+        L.phs_plan.argtypes = [dp, i64, C.POINTER(PlanOpts), vp, C.POINTER(vp)]
+        L.phs_matvec.argtypes = [vp, dp, dp, i32, i32, vp]
+        L.phs_precond_build.argtypes = [vp, C.POINTER(PrecondOpts), vp]
+        L.phs_solve.argtypes = [vp, dp, i32, C.POINTER(SolveOpts), dp, dp,
+                                C.POINTER(SolveInfo), vp]
+        L.phs_eval.argtypes = [vp, dp, dp, i32, dp, i64, dp, vp]
+        L.phs_plan_info.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                    C.POINTER(i32)]
+        L.phs_plan_tree.argtypes = [vp, dp, dp, vp]
+        L.phs_precond_export.argtypes = [vp, dp, dp, dp, dp, vp]
+        L.phs_precond_apply.argtypes = [vp, dp, dp, vp]
+        L.phs_plan_destroy.argtypes = [vp]
+        L.phs_plan_destroy.restype = None
+        L.phs_last_error.restype = C.c_char_p
+        L.phs_profile_enable.argtypes = [i32]
+        L.phs_profile_enable.restype = None
+        L.phs_profile_read.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_double), i32]
+        L.phs_profile_read.restype = i32
+        for name in ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval",
+                     "phs_plan_info", "phs_plan_tree", "phs_precond_export",
+                     "phs_precond_apply"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow=()) -> int:
+    if status != 0 and status not in allow:
+        raise PHSError(status, lib().phs_last_error().decode())
+    return status
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str) -> C.c_void_p:
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _cols(t: torch.Tensor) -> torch.Tensor:
+    """n x nrhs tensor -> column-major storage (nrhs, n) contiguous."""
+    if t.dim() == 1:
+        return t.contiguous()
+    return t.t().contiguous()
+
+
+@dataclass
+class Info:
+    iters: int
+    outer_refinements: int
+    rel_residual: float
+    t_solve: float
+    status: str
+
+
+class Plan:
+    """A PHS interpolation plan over fixed nodes (device-resident)."""
+
+    def __init__(self, xy: torch.Tensor, k: int, degree: int = -1, precision: int = PHS_FP64,
+                 fmm_tol: float = 0.0, leaf_size: int = 0, expansion_order: int = 0):
+        xy = xy.contiguous()
+        _dev(xy, "xy")
+        if xy.dim() != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must be n x 2")
+        self.n = xy.shape[0]
+        self.k = k
+        opts = PlanOpts(k, degree, precision, fmm_tol, leaf_size, expansion_order)
+        h = C.c_void_p()
+        _check(lib().phs_plan(C.c_void_p(xy.data_ptr()), self.n, C.byref(opts), _stream(),
+                              C.byref(h)))
+        self._h = h
+        c = (C.c_double * 2)()
+        sc = C.c_double()
+        S, R, L, P = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().phs_plan_info(h, c, C.byref(sc), C.byref(S), C.byref(R), C.byref(L),
+                                   C.byref(P)))
+        self.center = (c[0], c[1])
+        self.scale = sc.value
+        self.S, self.R, self.leaf_level, self.order = S.value, R.value, L.value, P.value
+
+    # -- kernel matvec ---------------------------------------------------
+    def matvec(self, v: torch.Tensor, precision: int = PHS_FP64) -> torch.Tensor:
+        vc = _cols(v)
+        nrhs = 1 if v.dim() == 1 else v.shape[1]
+        y = torch.empty_like(vc)
+        _check(lib().phs_matvec(self._h, _dev(vc, "v"), _dev(y, "y"), nrhs, precision,
+                                _stream()))
+        return y if v.dim() == 1 else y.t()
+
+    # -- preconditioner --------------------------------------------------
+    def precond_build(self, m: int = 0, nu: float = 0.0, range_: float = 0.0,
+                      range_units: int = PHS_RANGE_NORMALIZED, seed: int = 0) -> None:
+        o = PrecondOpts(m, nu, range_, range_units, seed)
+        _check(lib().phs_precond_build(self._h, C.byref(o), _stream()))
+
+    def precond_export(self, m: int):
+        dev = torch.device("cuda")
+        rank = torch.empty(self.n, dtype=torch.int32, device=dev)
+        nbr = torch.empty(self.n * m, dtype=torch.int32, device=dev)
+        coef = torch.empty(self.n * m, dtype=torch.float64, device=dev)
+        diag = torch.empty(self.n, dtype=torch.float64, device=dev)
+        _check(lib().phs_precond_export(self._h, C.c_void_p(rank.data_ptr()),
+                                        C.c_void_p(nbr.data_ptr()), C.c_void_p(coef.data_ptr()),
+                                        C.c_void_p(diag.data_ptr()), _stream()))
+        return rank, nbr.view(self.n, m), coef.view(self.n, m), diag
+
+    def precond_apply(self, r: torch.Tensor) -> torch.Tensor:
+        r = r.contiguous()
+        z = torch.empty_like(r)
+        _check(lib().phs_precond_apply(self._h, _dev(r, "r"), _dev(z, "z"), _stream()))
+        return z
+
+    # -- solve / evaluate ---------------------------------------------------
+    def solve(self, f: torch.Tensor, rtol: float = 1e-8, maxit: int = 0, check_every: int = 0,
+              precision: int = -1, raise_on_error: bool = True):
+        fc = _cols(f)
+        nrhs = 1 if f.dim() == 1 else f.shape[1]
+        w = torch.empty_like(fc)
+        beta = torch.empty(nrhs * self.S, dtype=torch.float64, device=fc.device)
+        o = SolveOpts(rtol, maxit, check_every, precision)
+        inf = SolveInfo()
+        st = lib().phs_solve(self._h, _dev(fc, "f"), nrhs, C.byref(o), _dev(w, "w"),
+                             _dev(beta, "beta"), C.byref(inf), _stream())
+        if raise_on_error:
+            _check(st)
+        info = Info(inf.iters, inf.outer_refinements, inf.rel_residual, inf.t_solve,
+                    STATUS.get(st, str(st)))
+        if f.dim() == 1:
+            return w, beta, info
+        return w.view(nrhs, self.n).t(), beta.view(nrhs, self.S).t(), info
+
+    def eval(self, w: torch.Tensor, beta: torch.Tensor, targets: torch.Tensor) -> torch.Tensor:
+        wc, bc = _cols(w), _cols(beta)
+        nrhs = 1 if w.dim() == 1 else w.shape[1]
+        tg = targets.contiguous()
+        m = tg.shape[0]
+        out = torch.empty(nrhs * m, dtype=torch.float64, device=wc.device)
+        _check(lib().phs_eval(self._h, _dev(wc, "w"), _dev(bc, "beta"), nrhs, _dev(tg, "targets"),
+                              m, _dev(out, "out"), _stream()))
+        return out if w.dim() == 1 else out.view(nrhs, m).t()
+
+    def tree(self):
+        dev = torch.device("cuda")
+        order = torch.empty(self.n, dtype=torch.int32, device=dev)
+        leaf = torch.empty(self.n, dtype=torch.int32, device=dev)
+        _check(lib().phs_plan_tree(self._h, C.c_void_p(order.data_ptr()),
+                                   C.c_void_p(leaf.data_ptr()), _stream()))
+        return order, leaf
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().phs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile_enable(on: bool = True) -> None:
+    lib().phs_profile_enable(1 if on else 0)
+
+
+def profile_read(cap: int = 256) -> dict:
+    names = (C.c_char * 48 * cap)()
+    launches = (C.c_int64 * cap)()
+    ms = (C.c_double * cap)()
+    k = lib().phs_profile_read(C.cast(names, C.c_void_p), launches, ms, cap)
+    out = {}
+    for i in range(k):
+        out[bytes(names[i]).split(b"\0", 1)[0].decode()] = (launches[i], ms[i])
+    return out
