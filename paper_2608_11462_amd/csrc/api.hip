@@ -308,10 +308,11 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     PHS_REQUIRE(pl.p64 >= 4 && pl.p64 <= 63, PHS_ERR_INVALID_ARGUMENT,
                 "expansion order must be 4..63");
   } else {
-    pl.q64 = o->expansion_order > 0 ? o->expansion_order : (tol >= 1e-9 ? 12 : 16);
+    // Chebyshev nodes per axis: 12 -> ~6e-12, 16 -> ~1e-14 core relative error
+    pl.q64 = o->expansion_order > 0 ? o->expansion_order : (tol >= 1e-13 ? 12 : 16);
     pl.q32 = 8;
-    PHS_REQUIRE(pl.q64 >= 4 && pl.q64 <= 20, PHS_ERR_INVALID_ARGUMENT,
-                "Chebyshev order must be 4..20");
+    PHS_REQUIRE(pl.q64 == 8 || pl.q64 == 10 || pl.q64 == 12 || pl.q64 == 14 || pl.q64 == 16,
+                PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16");
   }
   // scratch used by the bounding box, reductions and scalars
   pl.red_cap = dot_blocks(n) * 32 + 4096;
@@ -336,7 +337,7 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     PHS_REQUIRE(half > 0.0, PHS_ERR_INVALID_ARGUMENT, "nodes have zero extent");
     pl.rho = pl.tree.h / half;
   }
-  int leaf_size = o->leaf_size > 0 ? o->leaf_size : (pl.core_log ? 40 : 24);
+  int leaf_size = o->leaf_size > 0 ? o->leaf_size : (pl.core_log ? 40 : 64);
   build_tree(pl, xy, leaf_size, s);
 
   // polynomial block and thin QR
@@ -429,6 +430,15 @@ PcgResult pcg(Plan &pl, double *w, double *r, double rtol_abs, int maxit, int ch
       const double *pa[1] = {p}, *pb[1] = {q};
       multi_dot(pa, pb, 1, n, pl.red, sc + 2, s);
     }
+    if (check_every == 1) {
+      // curvature check before the update so a breakdown step is never applied
+      PHS_HIP(hipMemcpyAsync(pl.hscal + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+      PHS_HIP(hipStreamSynchronize(s));
+      if (!(pl.hscal[2] > 0.0)) {
+        res.breakdown = true;
+        return res;
+      }
+    }
     pcg_update_wr(w, r, p, q, sc + 1, n, pl.red, sc + 3, s);
     res.iters = it;
     if (it % check_every == 0 || it == maxit) {
@@ -475,9 +485,11 @@ phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts 
     scale_copy(r, ft, (double)pl.sign, n, s);
     project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
     const double bn = std::sqrt(dot_host(pl, r, r, s));
+    const double fn = std::sqrt(dot_host(pl, ft, ft, s));
     const double tol_abs = rtol * bn;
     double rel = 0.0;
-    if (bn == 0.0) {
+    // data in span(B) to rounding level: the polynomial alone interpolates
+    if (bn <= 1e-13 * fn) {
       fill(w, 0.0, n, s);
     } else if (prec == PHS_FP64) {
       PcgResult pr = pcg(pl, w, r, tol_abs, maxit, check_every, PHS_FP64, z, p, q, tmp, s);
@@ -485,25 +497,47 @@ phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts 
       if (pr.breakdown) st = PHS_ERR_BREAKDOWN;
       else if (!pr.converged && st == PHS_OK) st = PHS_ERR_NOT_CONVERGED;
     } else {
-      // Mixed precision: inner PCG on FP32 matvecs, outer FP64 residual.
+      // Mixed precision: inner PCG on FP32 matvecs, outer FP64 residual
+      // (iterative refinement).  The FP32 operator carries the cancellation of
+      // the Hadamard far field, so on the smoothest modes it may lose
+      // definiteness: an inner solve stops at breakdown or stagnation, and if
+      // an outer step stops reducing the FP64 residual the remainder is solved
+      // with the FP64 operator.  The exit test is always on the FP64 residual.
       fill(w, 0.0, n, s);
       double rn = bn;
       int outer = 0, budget = maxit;
-      while (rn > tol_abs && outer < 20 && budget > 0) {
-        // inner solve of A dw = r to a relative accuracy the FP32 operator supports
-        const double inner_tol = std::max(tol_abs, 2e-5 * rn);
-        PcgResult pr = pcg(pl, dw, r, inner_tol, budget, check_every, PHS_MIXED, z, p, q, tmp, s);
+      bool fp64_finish = false;
+      while (rn > tol_abs && budget > 0) {
+        const double inner_tol = std::max(tol_abs, 1e-4 * rn);
+        const int inner_prec = fp64_finish ? PHS_FP64 : PHS_MIXED;
+        PcgResult pr = pcg(pl, dw, r, fp64_finish ? tol_abs : inner_tol,
+                           fp64_finish ? budget : std::min(budget, 60), check_every,
+                           inner_prec, z, p, q, tmp, s);
         total_iters += pr.iters;
         budget -= pr.iters;
+        if (pr.breakdown && pr.iters <= 1) {
+          if (fp64_finish) {
+            st = PHS_ERR_BREAKDOWN;
+            break;
+          }
+          fp64_finish = true;  // no usable FP32 step: restart this residual in FP64
+          matvec_tree(pl, w, q, PHS_FP64, s);
+          axpby(q, ft, 1.0, -1.0, n, s);
+          scale_copy(r, q, (double)pl.sign, n, s);
+          project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
+          continue;
+        }
         axpby(w, dw, 1.0, 1.0, n, s);
         // r = sign * Pi (f - M64 w)
         matvec_tree(pl, w, q, PHS_FP64, s);
         axpby(q, ft, 1.0, -1.0, n, s);  // q = f - M w
         scale_copy(r, q, (double)pl.sign, n, s);
         project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
-        rn = std::sqrt(dot_host(pl, r, r, s));
+        const double rn_new = std::sqrt(dot_host(pl, r, r, s));
         ++outer;
-        if (pr.breakdown) {
+        if (!(rn_new < 0.5 * rn)) fp64_finish = true;
+        rn = rn_new;
+        if (!std::isfinite(rn)) {
           st = PHS_ERR_BREAKDOWN;
           break;
         }

@@ -1,16 +1,739 @@
-// Distance-kernel FMM for odd k: not built yet; odd k is rejected at plan time.
-#include "phs_internal.h"
+// Distance-kernel FMM, core kernel |x - y|, used for odd k (paper eq.
+// matvec_hadamard with M = [r^(k-1)] o [r]; the paper names this core sum but
+// gives no expansion for it).
+//
+// The kernel is not harmonic, so instead of complex multipole series this unit
+// uses tensor Chebyshev interpolation on every box (a kernel-independent FMM):
+// a box of half-width w/2 carries Q x Q "equivalent densities" W at the
+// Chebyshev nodes xbar_a = cos((2a+1) pi / (2Q)) of its scaled square, and the
+// far field at the nodes of a target box is G_m = sum_s K(x_m, y_n) W_s[n].
+//   P2M  W[a][b]   = sum_j q_j S_a(y1_j) S_b(y2_j)       (S_a Lagrange basis)
+//   M2M  W_parent  = sum_children T_cx W_child T_cy^T,   T_s[a][a'] = S_a((xbar_a' + s)/2)
+//   M2L  G_target  = (w/2) sum_s K_D W_s, K_D[m][n] = |2D + xbar_m - xbar_n| at unit
+//        half-width (|x - y| is homogeneous of degree 1, so one set of 40
+//        matrices serves every level)
+//   L2L  G_child  += T_cx^T G_parent T_cy
+//   L2P  f(x)      = sum_ab S_a(x1) S_b(x2) G[a][b]
+// The near field (3x3 leaves) is direct phi(r) as in the log-kernel unit.
+//
+// Layout: per level, expansions [box][density][node] (node index a*Q + b).
+#include <cmath>
+#include <type_traits>
+
+#include "fmm_common.h"
+
 namespace phs {
-void build_cheb_tables(ChebTables &t, int Q) { t.Q = Q; }
-void free_cheb_tables(ChebTables &t) { t = ChebTables(); }
-size_t cheb_expansion_bytes(int, int, int, bool) { return 16; }
-void dist_matvec(Plan &, const double *, double *, double *, bool, hipStream_t) {
-  throw Error{PHS_ERR_INVALID_ARGUMENT, "odd k not built yet"};
+
+namespace {
+
+template <class T>
+using V2 = typename Vec2<T>::type;
+
+constexpr int kNoff = 40;
+
+__host__ __device__ inline int64_t cheb_level_base(int l, int QQ, int nd) {
+  return (int64_t)QQ * nd * (((int64_t)1 << (2 * l)) - 16) / 3;
 }
-void dist_expansions(Plan &, const double *, hipStream_t) {
-  throw Error{PHS_ERR_INVALID_ARGUMENT, "odd k not built yet"};
+
+// Lagrange basis at the Q Chebyshev nodes evaluated at x (|x| <= 1):
+// S_a(x) = (1 + 2 sum_{k>=1} T_k(x) T_k(xbar_a)) / Q.  Tk: table T_k(xbar_a), [k][a].
+template <class T, int Q>
+__device__ __forceinline__ void cheb_basis(T x, const T *__restrict__ Tk, T *S) {
+  T tk[Q];
+  tk[0] = T(1);
+  if (Q > 1) tk[1] = x;
+#pragma unroll
+  for (int k = 2; k < Q; ++k) tk[k] = T(2) * x * tk[k - 1] - tk[k - 2];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) s += tk[k] * Tk[k * Q + a];
+    S[a] = (T(1) + T(2) * s) * (T(1) / T(Q));
+  }
 }
-void dist_eval_targets(Plan &, const double *, const double *, const double *, int64_t, double *, hipStream_t) {
-  throw Error{PHS_ERR_INVALID_ARGUMENT, "odd k not built yet"};
+
+// ---------------------------------------------------------------- P2M
+template <class T, int K, int Q>
+__global__ __launch_bounds__(64) void k_cheb_p2m(const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 const float *__restrict__ ux,
+                                                 const float *__restrict__ uy,
+                                                 const double *__restrict__ t,
+                                                 const int32_t *__restrict__ start, int L,
+                                                 double h, const T *__restrict__ Tk,
+                                                 T *__restrict__ W) {
+  constexpr int R = Rank<K>::R;
+  constexpr int QQ = Q * Q;
+  constexpr int EPL = (QQ + 63) / 64;  // entries per lane
+  __shared__ T s1[64][Q], s2[64][Q], qd[64][R];
+  __shared__ T tk[Q * Q];
+  const int lane = threadIdx.x;
+  const int G = 1 << L;
+  const int leaf = blockIdx.x;
+  for (int i = lane; i < Q * Q; i += 64) tk[i] = Tk[i];
+  const int b = start[leaf], e = start[leaf + 1];
+  const double w = 2.0 * h / G;
+  const double inv_half = 2.0 / w;
+  const int ix = leaf % G, iy = leaf / G;
+  const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
+  T acc[EPL][R];
+#pragma unroll
+  for (int i = 0; i < EPL; ++i)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[i][r] = T(0);
+  __syncthreads();
+  for (int c0 = b; c0 < e; c0 += 64) {
+    const int np = min(64, e - c0);
+    if (lane < np) {
+      const int j = c0 + lane;
+      T u1, u2;
+      if constexpr (std::is_same<T, float>::value) {
+        u1 = ux[j] * (float)inv_half;
+        u2 = uy[j] * (float)inv_half;
+      } else {
+        u1 = (x[j] - cx) * inv_half;
+        u2 = (y[j] - cy) * inv_half;
+      }
+      T S[Q];
+      cheb_basis<T, Q>(u1, tk, S);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) s1[lane][a] = S[a];
+      cheb_basis<T, Q>(u2, tk, S);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) s2[lane][a] = S[a];
+      T v[R];
+      vfac<K, T>(x[j], y[j], v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) qd[lane][r] = v[r] * (T)t[j];
+    }
+    __syncthreads();
+    for (int p = 0; p < np; ++p) {
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) {
+        const int en = lane + 64 * i;
+        if (en < QQ) {
+          const T sab = s1[p][en / Q] * s2[p][en % Q];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[i][r] += qd[p][r] * sab;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < EPL; ++i) {
+    const int en = lane + 64 * i;
+    if (en < QQ)
+#pragma unroll
+      for (int r = 0; r < R; ++r) W[((int64_t)leaf * R + r) * QQ + en] = acc[i][r];
+  }
 }
+
+// ---------------------------------------------------------------- M2M / L2L
+// Block per (box, density), QQ threads.  Tpm: [2][Q][Q] with Tpm[s][a][a'] =
+// S_a((xbar_a' + (2s-1))/2).
+template <class T, int Q>
+__global__ void k_cheb_m2m(const T *__restrict__ Wc, T *__restrict__ Wp, int lp, int nd,
+                           const T *__restrict__ Tpm) {
+  constexpr int QQ = Q * Q;
+  __shared__ T tm[2 * QQ], wc[QQ], yy[QQ];
+  const int tid = threadIdx.x;
+  const int Gp = 1 << lp, Gc = 2 * Gp;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int bx = box % Gp, by = box / Gp;
+  for (int i = tid; i < 2 * QQ; i += blockDim.x) tm[i] = Tpm[i];
+  const int a = tid / Q, bb = tid % Q;
+  T acc = T(0);
+  for (int c = 0; c < 4; ++c) {
+    const int cxx = c & 1, cyy = c >> 1;
+    const int child = (2 * by + cyy) * Gc + 2 * bx + cxx;
+    __syncthreads();
+    if (tid < QQ) wc[tid] = Wc[((int64_t)child * nd + r) * QQ + tid];
+    __syncthreads();
+    // Y[a'][b] = sum_b' W[a'][b'] T_cy[b][b']
+    if (tid < QQ) {
+      T s = T(0);
+      const T *ty = tm + cyy * QQ + bb * Q;
+#pragma unroll
+      for (int q2 = 0; q2 < Q; ++q2) s += wc[a * Q + q2] * ty[q2];
+      yy[tid] = s;
+    }
+    __syncthreads();
+    if (tid < QQ) {
+      const T *tx = tm + cxx * QQ + a * Q;
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1) acc += tx[q1] * yy[q1 * Q + bb];
+    }
+  }
+  if (tid < QQ) Wp[((int64_t)box * nd + r) * QQ + tid] = acc;
 }
+
+template <class T, int Q>
+__global__ void k_cheb_l2l(const T *__restrict__ Gp, T *__restrict__ Gc, int lc, int nd,
+                           const T *__restrict__ Tpm) {
+  constexpr int QQ = Q * Q;
+  __shared__ T tm[2 * QQ], gp[QQ], yy[QQ];
+  const int tid = threadIdx.x;
+  const int G = 1 << lc;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int bx = box % G, by = box / G;
+  const int cxx = bx & 1, cyy = by & 1;
+  const int parent = (by >> 1) * (G / 2) + (bx >> 1);
+  for (int i = tid; i < 2 * QQ; i += blockDim.x) tm[i] = Tpm[i];
+  if (tid < QQ) gp[tid] = Gp[((int64_t)parent * nd + r) * QQ + tid];
+  __syncthreads();
+  const int a = tid / Q, bb = tid % Q;
+  // Y[a'][b] = sum_b' G[a'][b'] T_cy[b'][b]
+  if (tid < QQ) {
+    T s = T(0);
+#pragma unroll
+    for (int q2 = 0; q2 < Q; ++q2) s += gp[a * Q + q2] * tm[cyy * QQ + q2 * Q + bb];
+    yy[tid] = s;
+  }
+  __syncthreads();
+  if (tid < QQ) {
+    T s = T(0);
+#pragma unroll
+    for (int q1 = 0; q1 < Q; ++q1) s += tm[cxx * QQ + q1 * Q + a] * yy[q1 * Q + bb];
+    T *dst = &Gc[((int64_t)box * nd + r) * QQ + tid];
+    *dst += s;
+  }
+}
+
+// ---------------------------------------------------------------- M2L
+// Tiled GEMM: a block owns all QQ rows of a tile of 64 (box, density)
+// columns of one level and accumulates sum_D K_D W_{src(D)} over the 40
+// offsets in a fixed order.  Boxes are enumerated by parity class so a tile
+// mostly shares one interaction-list pattern.
+constexpr int kCols = 64, kKc = 16;
+
+template <class T, int QQ>
+__global__ __launch_bounds__(256) void k_cheb_m2l(const T *__restrict__ Wall,
+                                                  T *__restrict__ Gall, int L, int nd,
+                                                  const T *__restrict__ Kd, double h) {
+  constexpr int RPT = (QQ + 15) / 16;  // rows per thread
+  constexpr int AST = kKc + 1;         // padded row stride of the A tile
+  __shared__ T As[QQ * AST];
+  __shared__ T Bs[kKc * kCols];
+  __shared__ int src_box[kCols];
+  __shared__ int any_valid;
+  const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+  // locate level and tile
+  int64_t tcol = (int64_t)blockIdx.x * kCols;
+  int l = 2;
+  int64_t off = 0, base = 0;
+  while (l <= L) {
+    const int64_t cols_l = ((int64_t)1 << (2 * l)) * nd;
+    const int64_t tiles_l = (cols_l + kCols - 1) / kCols;
+    if (tcol < off + tiles_l * kCols) break;
+    off += tiles_l * kCols;
+    base += cols_l * QQ;
+    ++l;
+  }
+  if (l > L) return;
+  const int G = 1 << l;
+  const int64_t nb = (int64_t)G * G;
+  const int64_t col0 = tcol - off;
+  const T *Wl = Wall + base;
+  T *Gl = Gall + base;
+  const T half_w = (T)(h / G);  // (w/2)
+  // my columns: c = tx + 16 j
+  T acc[RPT][4];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  // target box for column index (parity-class order)
+  auto tgt_of = [&](int64_t cidx, int &ix, int &iy, int &r) -> bool {
+    if (cidx >= nb * nd) return false;
+    const int64_t bi = cidx / nd;
+    r = (int)(cidx % nd);
+    const int64_t quarter = nb / 4;
+    const int cls = (int)(bi / quarter);
+    const int64_t rem = bi % quarter;
+    const int hf = G / 2;
+    ix = 2 * (int)(rem % hf) + (cls & 1);
+    iy = 2 * (int)(rem / hf) + (cls >> 1);
+    return true;
+  };
+  int oi = 0;
+  for (int oy = -3; oy <= 3; ++oy)
+    for (int ox = -3; ox <= 3; ++ox) {
+      if (abs(ox) <= 1 && abs(oy) <= 1) continue;
+      const int d_idx = oi++;
+      __syncthreads();
+      if (tid == 0) any_valid = 0;
+      __syncthreads();
+      if (tid < kCols) {
+        int ix, iy, r;
+        int sb = -1;
+        if (tgt_of(col0 + tid, ix, iy, r)) {
+          const int jx = ix + ox, jy = iy + oy;
+          if (jx >= 0 && jy >= 0 && jx < G && jy < G && abs((jx >> 1) - (ix >> 1)) <= 1 &&
+              abs((jy >> 1) - (iy >> 1)) <= 1)
+            sb = (jy * G + jx) * nd + r;
+        }
+        src_box[tid] = sb;
+        if (sb >= 0) any_valid = 1;
+      }
+      __syncthreads();
+      if (!any_valid) continue;
+      const T *KD = Kd + (int64_t)d_idx * QQ * QQ;
+      for (int k0 = 0; k0 < QQ; k0 += kKc) {
+        // A tile: KD[m][k0..k0+kKc)
+        for (int e = tid; e < QQ * kKc; e += 256) {
+          const int m = e / kKc, kk = e % kKc;
+          As[m * AST + kk] = (k0 + kk < QQ) ? KD[(int64_t)m * QQ + k0 + kk] : T(0);
+        }
+        // B tile: W[src][k0..k0+kKc) per column
+        for (int e = tid; e < kKc * kCols; e += 256) {
+          const int c = e / kKc, kk = e % kKc;
+          const int sb = src_box[c];
+          Bs[kk * kCols + c] = (sb >= 0 && k0 + kk < QQ) ? Wl[(int64_t)sb * QQ + k0 + kk] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kKc; ++kk) {
+          T bv[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bv[j] = Bs[kk * kCols + tx + 16 * j];
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int m = ty + 16 * i;
+            if (m < QQ) {
+              const T av = As[m * AST + kk];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[i][j] += av * bv[j];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  // store
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int ix, iy, r;
+    if (!tgt_of(col0 + tx + 16 * j, ix, iy, r)) continue;
+    const int64_t tb = ((int64_t)(iy * G + ix) * nd + r) * QQ;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int m = ty + 16 * i;
+      if (m < QQ) Gl[tb + m] = half_w * acc[i][j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- leaf
+template <class T, int K, int Q>
+__global__ __launch_bounds__(64) void k_cheb_leaf_eval(
+    const double *__restrict__ x, const double *__restrict__ y,
+    const float *__restrict__ ux, const float *__restrict__ uy,
+    const double *__restrict__ t, const int32_t *__restrict__ start, int L, double h,
+    const T *__restrict__ Tk, const T *__restrict__ Gleaf, double *__restrict__ ytree,
+    double *__restrict__ yuser, const int32_t *__restrict__ order) {
+  constexpr int R = Rank<K>::R;
+  constexpr int QQ = Q * Q;
+  __shared__ T tk[QQ];
+  const int G = 1 << L;
+  const int leaf = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < QQ; i += 64) tk[i] = Tk[i];
+  __syncthreads();
+  const int b = start[leaf], e = start[leaf + 1];
+  if (b == e) return;
+  const int ix = leaf % G, iy = leaf / G;
+  const double w = 2.0 * h / G, inv_half = 2.0 / w;
+  const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
+  const int r0 = iy > 0 ? iy - 1 : 0, r1 = iy + 1 < G ? iy + 1 : G - 1;
+  const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
+  const T *Gl = Gleaf + (int64_t)leaf * R * QQ;
+  for (int i0 = b; i0 < e; i0 += 64) {
+    const int i = i0 + lane;
+    const bool act = i < e;
+    const int ii = act ? i : b;
+    const double xi = x[ii], yi = y[ii];
+    T far = T(0);
+    {
+      T u1, u2;
+      if constexpr (std::is_same<T, float>::value) {
+        u1 = ux[ii] * (float)inv_half;
+        u2 = uy[ii] * (float)inv_half;
+      } else {
+        u1 = (xi - cx) * inv_half;
+        u2 = (yi - cy) * inv_half;
+      }
+      T S1[Q], S2[Q];
+      cheb_basis<T, Q>(u1, tk, S1);
+      cheb_basis<T, Q>(u2, tk, S2);
+      T u[R];
+      ufac<K, T>(xi, yi, u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T *g = Gl + r * QQ;
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+          T sa = T(0);
+#pragma unroll
+          for (int bb = 0; bb < Q; ++bb) sa += S2[bb] * g[a * Q + bb];
+          s += S1[a] * sa;
+        }
+        far += u[r] * s;
+      }
+    }
+    T nearv = T(0);
+    if constexpr (std::is_same<T, double>::value) {
+      for (int row = r0; row <= r1; ++row) {
+        const int js = start[row * G + c0], je = start[row * G + c1 + 1];
+#pragma unroll 4
+        for (int j = js; j < je; ++j) {
+          const double dx = xi - x[j], dy = yi - y[j];
+          nearv += phi_r2<K>(dx * dx + dy * dy) * t[j];
+        }
+      }
+    } else {
+      const float uxi = ux[ii], uyi = uy[ii];
+      for (int row = r0; row <= r1; ++row) {
+        const float offy = (float)((iy - row) * w);
+        for (int col = c0; col <= c1; ++col) {
+          const float offx = (float)((ix - col) * w);
+          const int js = start[row * G + col], je = start[row * G + col + 1];
+#pragma unroll 4
+          for (int j = js; j < je; ++j) {
+            const float dx = (uxi - ux[j]) + offx, dy = (uyi - uy[j]) + offy;
+            nearv += phi_r2f<K>(dx * dx + dy * dy) * (float)t[j];
+          }
+        }
+      }
+    }
+    if (act) {
+      const double out = (double)far + (double)nearv;
+      if (ytree) ytree[i] = out;
+      if (yuser) yuser[order[i]] = out;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- targets
+template <int K, int Q>
+__global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, double cxn,
+                                    double cyn, double rho, const double *__restrict__ x,
+                                    const double *__restrict__ y,
+                                    const double *__restrict__ wt,
+                                    const int32_t *__restrict__ start, int L, double h,
+                                    const double *__restrict__ Tk,
+                                    const double *__restrict__ nodes,
+                                    const double *__restrict__ Wall,
+                                    const double *__restrict__ Gleaf,
+                                    const double *__restrict__ beta, int d,
+                                    double *__restrict__ out) {
+  constexpr int R = Rank<K>::R;
+  constexpr int QQ = Q * Q;
+  const int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (it >= m) return;
+  const double xi = (tg[2 * it] - cxn) * rho, yi = (tg[2 * it + 1] - cyn) * rho;
+  double poly = 0.0;
+  {
+    double px[8], py[8];
+    px[0] = py[0] = 1.0;
+    for (int q = 1; q <= d; ++q) {
+      px[q] = px[q - 1] * xi;
+      py[q] = py[q - 1] * yi;
+    }
+    int col = 0;
+    for (int tdeg = 0; tdeg <= d; ++tdeg)
+      for (int a = tdeg; a >= 0; --a) poly += beta[col++] * px[a] * py[tdeg - a];
+  }
+  double u[R];
+  ufac<K, double>(xi, yi, u);
+  const int G = 1 << L;
+  double far = 0.0, nearv = 0.0;
+  const bool inside = fabs(xi) <= h && fabs(yi) <= h;
+  if (inside) {
+    const double scale = G / (2.0 * h);
+    int ix = (int)floor((xi + h) * scale), iy = (int)floor((yi + h) * scale);
+    ix = ix < 0 ? 0 : (ix >= G ? G - 1 : ix);
+    iy = iy < 0 ? 0 : (iy >= G ? G - 1 : iy);
+    const int leaf = iy * G + ix;
+    const double w = 2.0 * h / G;
+    const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
+    double S1[Q], S2[Q];
+    cheb_basis<double, Q>((xi - cx) * (2.0 / w), Tk, S1);
+    cheb_basis<double, Q>((yi - cy) * (2.0 / w), Tk, S2);
+    for (int r = 0; r < R; ++r) {
+      const double *g = Gleaf + ((int64_t)leaf * R + r) * QQ;
+      double s = 0.0;
+      for (int a = 0; a < Q; ++a) {
+        double sa = 0.0;
+        for (int bb = 0; bb < Q; ++bb) sa += S2[bb] * g[a * Q + bb];
+        s += S1[a] * sa;
+      }
+      far += u[r] * s;
+    }
+    const int r0 = iy > 0 ? iy - 1 : 0, r1 = iy + 1 < G ? iy + 1 : G - 1;
+    const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
+    for (int row = r0; row <= r1; ++row) {
+      const int js = start[row * G + c0], je = start[row * G + c1 + 1];
+      for (int j = js; j < je; ++j) {
+        const double dx = xi - x[j], dy = yi - y[j];
+        nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
+      }
+    }
+  } else {
+    int stk_l[64];
+    int stk_b[64];
+    int sp = 0;
+    for (int b0 = 0; b0 < 16; ++b0) {
+      stk_l[sp] = 2;
+      stk_b[sp] = b0;
+      ++sp;
+    }
+    while (sp > 0) {
+      --sp;
+      const int l = stk_l[sp], box = stk_b[sp];
+      const int Gl = 1 << l;
+      const double wl = 2.0 * h / Gl;
+      const int bx = box % Gl, by = box / Gl;
+      const double ccx = -h + (bx + 0.5) * wl, ccy = -h + (by + 0.5) * wl;
+      const double ddx = xi - ccx, ddy = yi - ccy;
+      if (ddx * ddx + ddy * ddy >= (2.5 * wl) * (2.5 * wl)) {
+        // far: equivalent densities at the box's Chebyshev nodes
+        const double *Wl = Wall + cheb_level_base(l, QQ, R);
+        for (int a = 0; a < Q; ++a)
+          for (int bb = 0; bb < Q; ++bb) {
+            const double px = ccx + 0.5 * wl * nodes[a], py = ccy + 0.5 * wl * nodes[bb];
+            const double dx = xi - px, dy = yi - py;
+            const double kv = sqrt(dx * dx + dy * dy);
+            for (int r = 0; r < R; ++r)
+              far += u[r] * kv * Wl[((int64_t)box * R + r) * QQ + a * Q + bb];
+          }
+      } else if (l == L) {
+        const int js = start[box], je = start[box + 1];
+        for (int j = js; j < je; ++j) {
+          const double dx = xi - x[j], dy = yi - y[j];
+          nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
+        }
+      } else {
+        for (int c = 0; c < 4; ++c) {
+          stk_l[sp] = l + 1;
+          stk_b[sp] = (2 * by + (c >> 1)) * (2 * Gl) + 2 * bx + (c & 1);
+          ++sp;
+        }
+      }
+    }
+  }
+  out[it] = poly + far + nearv;
+}
+
+// ---------------------------------------------------------------- host
+template <class T, int Q>
+void far_field_q(Plan &pl, const double *t, hipStream_t s) {
+  constexpr int QQ = Q * Q;
+  const bool fp64 = std::is_same<T, double>::value;
+  const ChebTables &ct = fp64 ? pl.ct64 : pl.ct32;
+  const T *Tk = fp64 ? (const T *)ct.nodes64 + Q : (const T *)ct.nodes32 + Q;
+  const T *Tpm = fp64 ? (const T *)ct.S2c64 : (const T *)ct.S2c32;
+  const T *Kd = fp64 ? (const T *)ct.K64 : (const T *)ct.K32;
+  const int nd = pl.R, L = pl.tree.L;
+  const double h = pl.tree.h;
+  T *W = (T *)pl.mp;
+  T *Gx = (T *)pl.loc;
+  const int64_t nleaf = boxes_at(L);
+  T *WL = W + cheb_level_base(L, QQ, nd);
+  if (pl.k == 1)
+    PHS_LAUNCH("cheb_p2m", s, k_cheb_p2m<T, 1, Q><<<nleaf, 64, 0, s>>>(
+        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, h, Tk, WL));
+  else
+    PHS_LAUNCH("cheb_p2m", s, k_cheb_p2m<T, 3, Q><<<nleaf, 64, 0, s>>>(
+        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, h, Tk, WL));
+  const int thr = QQ <= 64 ? 64 : (QQ <= 128 ? 128 : 256);
+  for (int lp = L - 1; lp >= 2; --lp) {
+    dim3 grid((unsigned)boxes_at(lp), (unsigned)nd);
+    PHS_LAUNCH("cheb_m2m", s, k_cheb_m2m<T, Q><<<grid, thr, 0, s>>>(
+        W + cheb_level_base(lp + 1, QQ, nd), W + cheb_level_base(lp, QQ, nd), lp, nd, Tpm));
+  }
+  {
+    int64_t tiles = 0;
+    for (int l = 2; l <= L; ++l) tiles += (boxes_at(l) * nd + kCols - 1) / kCols;
+    PHS_LAUNCH("cheb_m2l", s, k_cheb_m2l<T, QQ><<<tiles, 256, 0, s>>>(W, Gx, L, nd, Kd, h));
+  }
+  for (int lc = 3; lc <= L; ++lc) {
+    dim3 grid((unsigned)boxes_at(lc), (unsigned)nd);
+    PHS_LAUNCH("cheb_l2l", s, k_cheb_l2l<T, Q><<<grid, thr, 0, s>>>(
+        Gx + cheb_level_base(lc - 1, QQ, nd), Gx + cheb_level_base(lc, QQ, nd), lc, nd, Tpm));
+  }
+}
+
+template <class T, int Q>
+void leaf_q(Plan &pl, const double *t, double *yt, double *yu, hipStream_t s) {
+  constexpr int QQ = Q * Q;
+  const bool fp64 = std::is_same<T, double>::value;
+  const ChebTables &ct = fp64 ? pl.ct64 : pl.ct32;
+  const T *Tk = fp64 ? (const T *)ct.nodes64 + Q : (const T *)ct.nodes32 + Q;
+  const int L = pl.tree.L;
+  const T *GL = (const T *)pl.loc + cheb_level_base(L, QQ, pl.R);
+  const int64_t nleaf = boxes_at(L);
+  if (pl.k == 1)
+    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, 1, Q><<<nleaf, 64, 0, s>>>(
+        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
+        pl.order));
+  else
+    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, 3, Q><<<nleaf, 64, 0, s>>>(
+        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
+        pl.order));
+}
+
+template <class T>
+void run_q(Plan &pl, const double *t, double *yt, double *yu, bool leaf, hipStream_t s) {
+  const int Q = std::is_same<T, double>::value ? pl.q64 : pl.q32;
+  switch (Q) {
+    case 8:
+      far_field_q<T, 8>(pl, t, s);
+      if (leaf) leaf_q<T, 8>(pl, t, yt, yu, s);
+      break;
+    case 10:
+      far_field_q<T, 10>(pl, t, s);
+      if (leaf) leaf_q<T, 10>(pl, t, yt, yu, s);
+      break;
+    case 12:
+      far_field_q<T, 12>(pl, t, s);
+      if (leaf) leaf_q<T, 12>(pl, t, yt, yu, s);
+      break;
+    case 14:
+      far_field_q<T, 14>(pl, t, s);
+      if (leaf) leaf_q<T, 14>(pl, t, yt, yu, s);
+      break;
+    case 16:
+      far_field_q<T, 16>(pl, t, s);
+      if (leaf) leaf_q<T, 16>(pl, t, yt, yu, s);
+      break;
+    default:
+      throw Error{PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16"};
+  }
+}
+
+template <int Q>
+void eval_q(Plan &pl, const double *w_tree, const double *beta, const double *targets,
+            int64_t m, double *out, hipStream_t s) {
+  constexpr int QQ = Q * Q;
+  const int L = pl.tree.L;
+  const double *Tk = pl.ct64.nodes64 + Q;
+  const double *W = (const double *)pl.mp;
+  const double *GL = (const double *)pl.loc + cheb_level_base(L, QQ, pl.R);
+  const int64_t nb = (m + 127) / 128;
+  if (pl.k == 1)
+    PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<1, Q><<<nb, 128, 0, s>>>(
+        targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
+        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out));
+  else
+    PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<3, Q><<<nb, 128, 0, s>>>(
+        targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
+        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out));
+}
+
+std::vector<double> cheb_nodes(int Q) {
+  std::vector<double> xm(Q);
+  for (int a = 0; a < Q; ++a) xm[a] = std::cos((2 * a + 1) * M_PI / (2.0 * Q));
+  return xm;
+}
+
+double basis_host(int Q, const std::vector<double> &xm, int a, double x) {
+  double s = 1.0;
+  double tkm = 1.0, tk = x;
+  for (int k = 1; k < Q; ++k) {
+    s += 2.0 * tk * std::cos(k * std::acos(xm[a]));
+    const double nx = 2.0 * x * tk - tkm;
+    tkm = tk;
+    tk = nx;
+  }
+  return s / Q;
+}
+
+template <class T>
+T *upload(const std::vector<double> &v) {
+  std::vector<T> c(v.begin(), v.end());
+  T *d = dmalloc<T>(c.size());
+  PHS_HIP(hipMemcpy(d, c.data(), c.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+}  // namespace
+
+void build_cheb_tables(ChebTables &t, int Q) {
+  free_cheb_tables(t);
+  t.Q = Q;
+  const int QQ = Q * Q;
+  const std::vector<double> xm = cheb_nodes(Q);
+  // nodes followed by T_k(xbar_a) [k][a]
+  std::vector<double> nt(Q + QQ);
+  for (int a = 0; a < Q; ++a) nt[a] = xm[a];
+  for (int k = 0; k < Q; ++k)
+    for (int a = 0; a < Q; ++a) nt[Q + k * Q + a] = std::cos(k * std::acos(xm[a]));
+  // Tpm[s][a][a'] = S_a((xbar_a' + (2s - 1))/2)
+  std::vector<double> tpm(2 * QQ);
+  for (int sgn = 0; sgn < 2; ++sgn)
+    for (int a = 0; a < Q; ++a)
+      for (int ap = 0; ap < Q; ++ap)
+        tpm[sgn * QQ + a * Q + ap] = basis_host(Q, xm, a, (xm[ap] + (2 * sgn - 1)) * 0.5);
+  // K_D at unit half-width, offsets in the M2L loop order (D = -o)
+  std::vector<double> K((size_t)kNoff * QQ * QQ);
+  int oi = 0;
+  for (int oy = -3; oy <= 3; ++oy)
+    for (int ox = -3; ox <= 3; ++ox) {
+      if (std::abs(ox) <= 1 && std::abs(oy) <= 1) continue;
+      const double Dx = -ox, Dy = -oy;
+      for (int m = 0; m < QQ; ++m)
+        for (int nn = 0; nn < QQ; ++nn) {
+          const double dx = 2.0 * Dx + xm[m / Q] - xm[nn / Q];
+          const double dy = 2.0 * Dy + xm[m % Q] - xm[nn % Q];
+          K[((size_t)oi * QQ + m) * QQ + nn] = std::sqrt(dx * dx + dy * dy);
+        }
+      ++oi;
+    }
+  t.nodes64 = upload<double>(nt);
+  t.nodes32 = upload<float>(nt);
+  t.S2c64 = upload<double>(tpm);
+  t.S2c32 = upload<float>(tpm);
+  t.K64 = upload<double>(K);
+  t.K32 = upload<float>(K);
+}
+
+void free_cheb_tables(ChebTables &t) {
+  dfree(t.nodes64);
+  dfree(t.nodes32);
+  dfree(t.S2c64);
+  dfree(t.S2c32);
+  dfree(t.K64);
+  dfree(t.K32);
+  t = ChebTables();
+}
+
+size_t cheb_expansion_bytes(int L, int Q, int nd, bool fp64) {
+  return (size_t)cheb_level_base(L + 1, Q * Q, nd) * (fp64 ? 8 : 4);
+}
+
+void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, bool fp64,
+                 hipStream_t s) {
+  if (fp64) run_q<double>(pl, t_tree, y_tree, y_user, true, s);
+  else run_q<float>(pl, t_tree, y_tree, y_user, true, s);
+}
+
+void dist_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
+  run_q<double>(pl, w_tree, nullptr, nullptr, false, s);
+}
+
+void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,
+                       const double *targets, int64_t m, double *out, hipStream_t s) {
+  switch (pl.q64) {
+    case 8: eval_q<8>(pl, w_tree, beta, targets, m, out, s); break;
+    case 10: eval_q<10>(pl, w_tree, beta, targets, m, out, s); break;
+    case 12: eval_q<12>(pl, w_tree, beta, targets, m, out, s); break;
+    case 14: eval_q<14>(pl, w_tree, beta, targets, m, out, s); break;
+    case 16: eval_q<16>(pl, w_tree, beta, targets, m, out, s); break;
+    default: throw Error{PHS_ERR_INVALID_ARGUMENT, "bad Chebyshev order"};
+  }
+}
+
+}  // namespace phs

@@ -30,7 +30,7 @@ def _plan(pr, k=None, degree=None, **kw):
                   degree if degree is not None else pr.degree, **kw)
 
 
-@pytest.mark.parametrize("k", [2, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_normalisation_and_tree_bit_exact(small, k):
     pl = _plan(small, k=k, degree=-1)
     c, rho, xi = D.normalize(small.xy, k)
@@ -42,7 +42,7 @@ def test_normalisation_and_tree_bit_exact(small, k):
     np.testing.assert_array_equal(host(leaf), keys_ref)
 
 
-@pytest.mark.parametrize("k", [2, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_matvec_fp64_parity(small, k):
     pl = _plan(small, k=k, degree=-1)
     c, rho, xi = D.normalize(small.xy, k)
@@ -62,7 +62,7 @@ def test_matvec_fp64_parity(small, k):
     assert e2 <= 1e-10
 
 
-@pytest.mark.parametrize("k", [2, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_matvec_mixed_reported(small, k):
     pl = _plan(small, k=k, degree=-1)
     c, rho, xi = D.normalize(small.xy, k)
