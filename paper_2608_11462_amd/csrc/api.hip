@@ -13,6 +13,8 @@
 
 namespace phs {
 
+void fill_log_table(double *tab);
+
 void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                       const double *targets, int64_t m, double *out, hipStream_t s);
 void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,
@@ -102,6 +104,8 @@ Plan::~Plan() {
   dfree(y);
   dfree(ux);
   dfree(uy);
+  dfree(xy2);
+  dfree(logtab);
   dfree(Q);
   dfree(mp);
   dfree(loc);
@@ -256,8 +260,9 @@ void build_tree(Plan &pl, const double *xy, int leaf_size, hipStream_t s) {
     pl.y = dmalloc<double>(n);
     pl.ux = dmalloc<float>(n);
     pl.uy = dmalloc<float>(n);
+    pl.xy2 = dmalloc<double2>(n);
     build_tree_points(xy, pl.order, keys, n, pl.c[0], pl.c[1], pl.rho, pl.tree.h, pl.tree.L,
-                      pl.x, pl.y, pl.ux, pl.uy, pl.leafkey, pl.inv_order, s);
+                      pl.x, pl.y, pl.ux, pl.uy, pl.xy2, pl.leafkey, pl.inv_order, s);
     int32_t *flag = scr;
     PHS_HIP(hipMemsetAsync(flag, 0, 4, s));
     count_duplicates(pl.x, pl.y, pl.tree.leaf_start, pl.tree.G * pl.tree.G, flag, s);
@@ -359,6 +364,12 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
                   cheb_expansion_bytes(pl.tree.L, pl.q32, pl.R, false));
   }
   pl.exp_bytes = eb;
+  {
+    std::vector<double> tab(256);
+    fill_log_table(tab.data());
+    pl.logtab = dmalloc<double>(256);
+    PHS_HIP(hipMemcpy(pl.logtab, tab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
+  }
   pl.mp = dmalloc<char>(eb);
   pl.loc = dmalloc<char>(eb);
   pl.v_t = dmalloc<double>(n);

@@ -119,15 +119,89 @@ __device__ __forceinline__ double phi_r2(double r2) {
   else return 0.5 * r2 * r2 * log(r2);
 }
 
+// phi(r) from r^2 in FP32 without the constant factor: r^2 log2(r^2) (k=2),
+// r^4 log2(r^2) (k=4), r (k=1), r^3 (k=3); multiply the sum by
+// phi_scale_f<K>() (0.5 ln 2 for even k).  r = 0 gives 0 (clamped r^2 for
+// even k).
 template <int K>
 __device__ __forceinline__ float phi_r2f(float r2) {
-  // 0.5 * ln 2: log(r^2)/2 = log2(r^2) * ln2 / 2
-  constexpr float kHalfLn2 = 0.34657359027997264f;
-  if (r2 == 0.0f) return 0.0f;
   if constexpr (K == 1) return __fsqrt_rn(r2);
-  else if constexpr (K == 2) return kHalfLn2 * r2 * __log2f(r2);
   else if constexpr (K == 3) return r2 * __fsqrt_rn(r2);
-  else return kHalfLn2 * r2 * r2 * __log2f(r2);
+  else {
+    r2 = fmaxf(r2, 1e-30f);
+    const float v = r2 * __log2f(r2);
+    return K == 4 ? v * r2 : v;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ float phi_scale_f() {
+  return (K % 2 == 0) ? 0.34657359027997264f : 1.0f;  // 0.5 * ln 2
+}
+
+// ---------------------------------------------------------------- near field
+// Natural logarithm of a positive normal double by table-driven range
+// reduction (Tang's method): x = m 2^e, m in [1, 2), c_j = 1 + j/128 from the
+// top seven mantissa bits, r = (m - c_j) * (1/c_j) (m - c_j is exact), and
+// log x = e ln2 + log c_j + log1p(r) with a degree-7 series for |r| < 1/128.
+// tab: 1/c_j for j < 128, then log c_j.  Error: about one ulp of |log x|.
+constexpr double kLn2Hi = 6.93147180369123816490e-01;  // 0x1.62e42fefa3800p-1
+constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln2 - kLn2Hi
+
+__device__ __forceinline__ double tang_log(double x, const double *__restrict__ tab) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t hi = (uint32_t)(b >> 32), lo = (uint32_t)b;
+  const int e = (int)(hi >> 20) - 1023;
+  const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FF00000u), (int)lo);
+  const int j = (int)((hi >> 13) & 127u);
+  const double c = fma((double)j, 0.0078125, 1.0);
+  const double r = (m - c) * tab[j];
+  double p = 1.0 / 7.0;
+  p = fma(p, r, -1.0 / 6.0);
+  p = fma(p, r, 1.0 / 5.0);
+  p = fma(p, r, -0.25);
+  p = fma(p, r, 1.0 / 3.0);
+  p = fma(p, r, -0.5);
+  const double l1p = fma(r * r, p, r);
+  const double ed = (double)e;
+  return fma(ed, kLn2Hi, tab[128 + j]) + fma(ed, kLn2Lo, l1p);
+}
+
+// Host: fill the 256-entry table used by tang_log.
+void fill_log_table(double *tab);
+
+// sum_j phi(|x_i - y_j|) t_j over a contiguous source range, FP64.  For even
+// k the r = 0 term is removed by clamping r^2 to 1e-300 (phi is then ~1e-298,
+// below the rounding of any sum of O(1) terms).  Returns the sum without the
+// factor 1/2 of phi = r^k log r = (1/2) r^k log r^2 for even k.
+template <int K>
+__device__ __forceinline__ double near_range(double xi, double yi,
+                                             const double2 *__restrict__ xy2,
+                                             const double *__restrict__ t, int js, int je,
+                                             const double *__restrict__ tab) {
+  double acc = 0.0;
+#pragma unroll 4
+  for (int j = js; j < je; ++j) {
+    const double2 s = xy2[j];
+    const double dx = xi - s.x, dy = yi - s.y;
+    double r2 = fma(dy, dy, dx * dx);
+    if constexpr (K == 1) {
+      acc = fma(sqrt(r2), t[j], acc);
+    } else if constexpr (K == 3) {
+      acc = fma(r2 * sqrt(r2), t[j], acc);
+    } else {
+      r2 = fmax(r2, 1e-300);
+      double ph = r2 * tang_log(r2, tab);
+      if constexpr (K == 4) ph *= r2;
+      acc = fma(ph, t[j], acc);
+    }
+  }
+  return acc;
+}
+
+template <int K>
+__device__ __forceinline__ double near_scale() {
+  return (K % 2 == 0) ? 0.5 : 1.0;
 }
 
 }  // namespace phs

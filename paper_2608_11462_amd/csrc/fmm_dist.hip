@@ -332,7 +332,8 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
     const float *__restrict__ ux, const float *__restrict__ uy,
     const double *__restrict__ t, const int32_t *__restrict__ start, int L, double h,
     const T *__restrict__ Tk, const T *__restrict__ Gleaf, double *__restrict__ ytree,
-    double *__restrict__ yuser, const int32_t *__restrict__ order) {
+    double *__restrict__ yuser, const int32_t *__restrict__ order,
+    const double2 *__restrict__ xy2, const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
   constexpr int QQ = Q * Q;
   __shared__ T tk[QQ];
@@ -387,12 +388,9 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
     if constexpr (std::is_same<T, double>::value) {
       for (int row = r0; row <= r1; ++row) {
         const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-#pragma unroll 4
-        for (int j = js; j < je; ++j) {
-          const double dx = xi - x[j], dy = yi - y[j];
-          nearv += phi_r2<K>(dx * dx + dy * dy) * t[j];
-        }
+        nearv += near_range<K>(xi, yi, xy2, t, js, je, logtab);
       }
+      nearv *= near_scale<K>();
     } else {
       const float uxi = ux[ii], uyi = uy[ii];
       for (int row = r0; row <= r1; ++row) {
@@ -407,6 +405,7 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
           }
         }
       }
+      nearv *= phi_scale_f<K>();
     }
     if (act) {
       const double out = (double)far + (double)nearv;
@@ -428,7 +427,9 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
                                     const double *__restrict__ Wall,
                                     const double *__restrict__ Gleaf,
                                     const double *__restrict__ beta, int d,
-                                    double *__restrict__ out) {
+                                    double *__restrict__ out,
+                                    const double2 *__restrict__ xy2,
+                                    const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
   constexpr int QQ = Q * Q;
   const int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -476,10 +477,7 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
     const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
     for (int row = r0; row <= r1; ++row) {
       const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-      for (int j = js; j < je; ++j) {
-        const double dx = xi - x[j], dy = yi - y[j];
-        nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
-      }
+      nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
     }
   } else {
     int stk_l[64];
@@ -511,10 +509,7 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
           }
       } else if (l == L) {
         const int js = start[box], je = start[box + 1];
-        for (int j = js; j < je; ++j) {
-          const double dx = xi - x[j], dy = yi - y[j];
-          nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
-        }
+        nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
       } else {
         for (int c = 0; c < 4; ++c) {
           stk_l[sp] = l + 1;
@@ -578,11 +573,11 @@ void leaf_q(Plan &pl, const double *t, double *yt, double *yu, hipStream_t s) {
   if (pl.k == 1)
     PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, 1, Q><<<nleaf, 64, 0, s>>>(
         pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
-        pl.order));
+        pl.order, pl.xy2, pl.logtab));
   else
     PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, 3, Q><<<nleaf, 64, 0, s>>>(
         pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
-        pl.order));
+        pl.order, pl.xy2, pl.logtab));
 }
 
 template <class T>
@@ -626,11 +621,11 @@ void eval_q(Plan &pl, const double *w_tree, const double *beta, const double *ta
   if (pl.k == 1)
     PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<1, Q><<<nb, 128, 0, s>>>(
         targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
-        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out));
+        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
   else
     PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<3, Q><<<nb, 128, 0, s>>>(
         targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
-        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out));
+        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
 }
 
 std::vector<double> cheb_nodes(int Q) {

@@ -216,12 +216,18 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
     const float *__restrict__ ux, const float *__restrict__ uy,
     const double *__restrict__ t, const int32_t *__restrict__ start, int L, double h,
     int P, const V2<T> *__restrict__ Bleaf, double *__restrict__ ytree,
-    double *__restrict__ yuser, const int32_t *__restrict__ order) {
+    double *__restrict__ yuser, const int32_t *__restrict__ order,
+    const double2 *__restrict__ xy2, const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
+  __shared__ double tab[256];
   const int G = 1 << L;
   const int nleaf = G * G;
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
+  if constexpr (std::is_same<T, double>::value && K % 2 == 0) {
+    for (int i = lane; i < 256; i += 64) tab[i] = logtab[i];
+    __syncthreads();
+  }
   const int b = start[leaf], e = start[leaf + 1];
   if (b == e) return;
   const int ix = leaf % G, iy = leaf / G;
@@ -259,12 +265,9 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
     if constexpr (std::is_same<T, double>::value) {
       for (int row = r0; row <= r1; ++row) {
         const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-#pragma unroll 4
-        for (int j = js; j < je; ++j) {
-          const double dx = xi - x[j], dy = yi - y[j];
-          nearv += phi_r2<K>(dx * dx + dy * dy) * t[j];
-        }
+        nearv += near_range<K>(xi, yi, xy2, t, js, je, tab);
       }
+      nearv *= near_scale<K>();
     } else {
       const float uxi = ux[ii], uyi = uy[ii];
       for (int row = r0; row <= r1; ++row) {
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
           }
         }
       }
+      nearv *= phi_scale_f<K>();
     }
     if (act) {
       const double out = (double)far + (double)nearv;
@@ -301,7 +305,8 @@ __global__ void k_eval_targets(const double *__restrict__ tg, int64_t m, double 
                                const double2 *__restrict__ Aall,
                                const double2 *__restrict__ Bleaf,
                                const double *__restrict__ beta, int d,
-                               double *__restrict__ out) {
+                               double *__restrict__ out, const double2 *__restrict__ xy2,
+                               const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
   const int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (it >= m) return;
@@ -344,10 +349,7 @@ __global__ void k_eval_targets(const double *__restrict__ tg, int64_t m, double 
     const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
     for (int row = r0; row <= r1; ++row) {
       const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-      for (int j = js; j < je; ++j) {
-        const double dx = xi - x[j], dy = yi - y[j];
-        nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
-      }
+      nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
     }
   } else {
     // explicit-stack descent from level 2
@@ -385,10 +387,7 @@ __global__ void k_eval_targets(const double *__restrict__ tg, int64_t m, double 
         }
       } else if (l == L) {
         const int js = start[box], je = start[box + 1];
-        for (int j = js; j < je; ++j) {
-          const double dx = xi - x[j], dy = yi - y[j];
-          nearv += phi_r2<K>(dx * dx + dy * dy) * wt[j];
-        }
+        nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
       } else {
         for (int c = 0; c < 4; ++c) {
           stk_l[sp] = l + 1;
@@ -475,12 +474,14 @@ void leaf_pass(Plan &pl, const double *t, double *y_tree, double *y_user, hipStr
     PHS_LAUNCH("leaf_eval", s,
                k_leaf_eval<T, 2><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
                                                       pl.tree.leaf_start, L, pl.tree.h, P,
-                                                      BL, y_tree, y_user, pl.order));
+                                                      BL, y_tree, y_user, pl.order, pl.xy2,
+                                                      pl.logtab));
   else
     PHS_LAUNCH("leaf_eval", s,
                k_leaf_eval<T, 4><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
                                                       pl.tree.leaf_start, L, pl.tree.h, P,
-                                                      BL, y_tree, y_user, pl.order));
+                                                      BL, y_tree, y_user, pl.order, pl.xy2,
+                                                      pl.logtab));
 }
 
 }  // namespace
@@ -566,6 +567,13 @@ void free_log_tables(LogTables &t) {
   t = LogTables();
 }
 
+void fill_log_table(double *tab) {
+  for (int j = 0; j < 128; ++j) {
+    tab[j] = 1.0 / (1.0 + j / 128.0);
+    tab[128 + j] = std::log1p(j / 128.0);
+  }
+}
+
 size_t log_expansion_bytes(int L, int P, int nd, bool fp64) {
   return (size_t)level_base(L + 1, P, nd) * (fp64 ? 16 : 8);
 }
@@ -596,13 +604,13 @@ void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                k_eval_targets<2><<<nb, 128, 0, s>>>(targets, m, pl.c[0], pl.c[1], pl.rho,
                                                     pl.x, pl.y, w_tree, pl.tree.leaf_start,
                                                     L, pl.tree.h, P, A, BL, beta, pl.d,
-                                                    out));
+                                                    out, pl.xy2, pl.logtab));
   else
     PHS_LAUNCH("eval_targets", s,
                k_eval_targets<4><<<nb, 128, 0, s>>>(targets, m, pl.c[0], pl.c[1], pl.rho,
                                                     pl.x, pl.y, w_tree, pl.tree.leaf_start,
                                                     L, pl.tree.h, P, A, BL, beta, pl.d,
-                                                    out));
+                                                    out, pl.xy2, pl.logtab));
 }
 
 }  // namespace phs

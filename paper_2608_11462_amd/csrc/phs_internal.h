@@ -147,6 +147,8 @@ struct Plan {
   int32_t *leafkey = nullptr;
   double *x = nullptr, *y = nullptr;   // normalised coordinates
   float *ux = nullptr, *uy = nullptr;  // FP32 offsets from the leaf centre
+  double2 *xy2 = nullptr;              // packed (x, y), source records of the near field
+  double *logtab = nullptr;            // 256-entry table of the near-field logarithm
 
   // polynomial block
   double *Q = nullptr;  // n x S column-major, tree order, orthonormal columns
@@ -205,7 +207,7 @@ void leaf_ranges(const uint32_t *sorted_keys, int64_t n, int nleaves,
 void build_tree_points(const double *xy, const int32_t *order,
                        const uint32_t *keys_sorted, int64_t n, double cx,
                        double cy, double rho, double h, int L, double *x,
-                       double *y, float *ux, float *uy, int32_t *leafkey,
+                       double *y, float *ux, float *uy, double2 *xy2, int32_t *leafkey,
                        int32_t *inv_order, hipStream_t s);
 void count_duplicates(const double *x, const double *y,
                       const int32_t *leaf_start, int nleaves, int32_t *flag,

@@ -201,7 +201,7 @@ __global__ void k_tree_points(const double *__restrict__ xy,
                               double cx, double cy, double rho, double h, int L,
                               double *__restrict__ x, double *__restrict__ y,
                               float *__restrict__ ux, float *__restrict__ uy,
-                              int32_t *__restrict__ leafkey,
+                              double2 *__restrict__ xy2, int32_t *__restrict__ leafkey,
                               int32_t *__restrict__ inv) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -210,6 +210,7 @@ __global__ void k_tree_points(const double *__restrict__ xy,
   double yi = (xy[2 * (int64_t)u + 1] - cy) * rho;
   x[i] = xi;
   y[i] = yi;
+  xy2[i] = make_double2(xi, yi);
   const int G = 1 << L;
   uint32_t key = keys[i];
   int ix = (int)(key % (uint32_t)G), iy = (int)(key / (uint32_t)G);
@@ -346,12 +347,12 @@ void leaf_ranges(const uint32_t *sorted_keys, int64_t n, int nleaves,
 void build_tree_points(const double *xy, const int32_t *order,
                        const uint32_t *keys_sorted, int64_t n, double cx,
                        double cy, double rho, double h, int L, double *x,
-                       double *y, float *ux, float *uy, int32_t *leafkey,
+                       double *y, float *ux, float *uy, double2 *xy2, int32_t *leafkey,
                        int32_t *inv_order, hipStream_t s) {
   int64_t nb = (n + kBlock - 1) / kBlock;
   PHS_LAUNCH("tree_points", s,
              k_tree_points<<<nb, kBlock, 0, s>>>(xy, order, keys_sorted, n, cx, cy,
-                                                 rho, h, L, x, y, ux, uy, leafkey,
+                                                 rho, h, L, x, y, ux, uy, xy2, leafkey,
                                                  inv_order));
 }
 
