@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "near32"], default="fp64")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -133,7 +133,7 @@ def main():
     from paper_2608_11462_amd import native as N
     from paper_2608_11462_amd import workloads as W
 
-    prec = N.PHS_FP64 if args.precision == "fp64" else N.PHS_MIXED
+    prec = {"fp64": N.PHS_FP64, "mixed": N.PHS_MIXED, "near32": N.PHS_NEAR32}[args.precision]
     pr = W.large_tps(n=args.n)
     dev = torch.device("cuda")
     xy = torch.as_tensor(pr.xy, device=dev)
@@ -189,7 +189,7 @@ def main():
     pl = N.Plan(xy, 2, 1)
     v = torch.as_tensor(W.rng_for(17).standard_normal(n), device=dev)
     mv = {}
-    for name, p in (("fp64", N.PHS_FP64), ("mixed", N.PHS_MIXED)):
+    for name, p in (("fp64", N.PHS_FP64), ("mixed", N.PHS_MIXED), ("near32", N.PHS_NEAR32)):
         for _ in range(2):
             pl.matvec(v, p)
         torch.cuda.synchronize()
@@ -201,30 +201,43 @@ def main():
         mv[name] = n / ((time.perf_counter() - t) / reps) / 1e6
     pl.close()
 
-    # roofline of the dominant kernel (HIP-event durations from the timed region)
-    roof = None
+    # rooflines from the HIP-event durations of the timed region
+    roofs = {}
     if prof:
-        dom = max(prof.items(), key=lambda kv: kv[1][1])
-        kname, (launches, total_ms) = dom
-        avg_s = total_ms / launches / 1e3
         leaf = last["leaf"].cpu().numpy()
         pairs, m2l_pairs = tree_work(leaf, last["L"], n)
-        P, R = last["P"], last["R"]
-        if prec == N.PHS_MIXED:
-            P = 15
-        flops = None
-        if kname == "leaf_eval":
-            flops = pairs * FLOP_PAIR + n * R * (8 * P + 2)
-        elif kname == "m2l":
-            flops = m2l_pairs * R * (4 * (P + 1) ** 2 + 12 * (P + 1))
-        if flops is not None:
-            ach = flops / avg_s / 1e12
-            peak = FP64_PEAK_TFLOPS if prec == N.PHS_FP64 else FP32_PEAK_TFLOPS
-            roof = {"kernel": kname, "bound": "alu", "achieved": round(ach, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-                    "traffic": stored_traffic(kname, "large_tps"),
-                    "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
-                    "algorithmic_flops_per_launch": flops}
+        P, R, m = last["P"], last["R"], 30
+        far32 = prec == N.PHS_MIXED
+        near32 = prec in (N.PHS_MIXED, N.PHS_NEAR32)
+        Pf = 15 if far32 else P
+        nnz = n * m - m * (m + 1) // 2
+        models = {
+            # kernel: (work per launch, unit, peak, bound)
+            "leaf_eval": (pairs * FLOP_PAIR + n * R * (8 * Pf + 2), "TFLOP/s",
+                          FP32_PEAK_TFLOPS if near32 else FP64_PEAK_TFLOPS, "alu"),
+            "m2l": (m2l_pairs * R * (4 * (Pf + 1) ** 2 + 12 * (Pf + 1)), "TFLOP/s",
+                    FP32_PEAK_TFLOPS if far32 else FP64_PEAK_TFLOPS, "alu"),
+            "vecchia_factor": (n * (2 * (m + 1) ** 3 / 3 + 2 * m * m
+                                    + 20 * (m + 1) * (m + 2) / 2), "TFLOP/s",
+                               FP64_PEAK_TFLOPS, "alu"),
+            # bytes: factor entries (index + value) and three n-vectors
+            "precond_u": (nnz * 12 + n * 28, "GB/s", 8000.0, "hbm"),
+            "precond_ut": (nnz * 12 + n * 24, "GB/s", 8000.0, "hbm"),
+        }
+        for kname, (work, unit, peak, bound) in models.items():
+            if kname not in prof:
+                continue
+            launches, total_ms = prof[kname]
+            avg_s = total_ms / launches / 1e3
+            scale = 1e12 if unit == "TFLOP/s" else 1e9
+            ach = work / avg_s / scale
+            src = "vecchia.hip" if kname.startswith(("vecchia", "precond")) else "fmm_log.hip"
+            roofs[kname] = {"kernel": kname, "bound": bound, "achieved": round(ach, 3),
+                            "peak": peak, "unit": unit, "frac": round(ach / peak, 4),
+                            "traffic": stored_traffic(kname, "large_tps"),
+                            "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
+                            "work_per_launch": work, "total_ms": round(total_ms, 3)}
+    roof = max(roofs.values(), key=lambda r: r["total_ms"]) if roofs else None
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 3)}
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]}
 
@@ -235,7 +248,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == N.PHS_FP64 else "f32 FMM / f64 Krylov",
+        "dtype": {N.PHS_FP64: "f64", N.PHS_MIXED: "f32 FMM / f64 Krylov",
+                  N.PHS_NEAR32: "f64 far field, f32 near field / f64 Krylov"}[prec],
         "data": "synthetic",
         "config": {"workload": "large_tps", "n": n, "k": 2, "poly_degree": 1,
                    "field": "16-mode random Fourier, |kappa|<=8", "targets": int(tg.shape[0]),
@@ -249,6 +263,8 @@ def main():
         "matvec_mpts_s": {k: round(v, 2) for k, v in mv.items()},
         "serve_p50_ms": None, "serve_p99_ms": None,
         "roofline": roof,
+        "rooflines": {k: {kk: v[kk] for kk in ("achieved", "unit", "frac", "avg_launch_ms")}
+                      for k, v in roofs.items()},
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:

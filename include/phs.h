@@ -63,7 +63,12 @@ typedef enum {
   PHS_ERR_NOT_READY = 8         /* phs_solve before phs_precond_build, ... */
 } phs_status;
 
-enum { PHS_FP64 = 0, PHS_MIXED = 1 };             /* matvec precision */
+/* Matvec precision.  PHS_FP64: everything in FP64.  PHS_MIXED: far field
+ * (FMM expansions) and near field in FP32.  PHS_NEAR32: far field in FP64,
+ * near-field pairs in FP32 (coordinates relative to the leaf centre).  In
+ * phs_solve the two mixed modes run inside FP64 residual refinement: the exit
+ * test is always on the FP64 residual. */
+enum { PHS_FP64 = 0, PHS_MIXED = 1, PHS_NEAR32 = 2 };
 enum { PHS_RANGE_NORMALIZED = 0, PHS_RANGE_USER = 1 };
 
 typedef struct phs_plan_s *phs_plan_t; /* opaque; owns all device state */
@@ -74,8 +79,7 @@ typedef struct {
   int32_t poly_degree;     /* total degree d of B; -1 => minimal for k
                               (k odd: ceil(k/2)-1, k even: k/2); must be >= it */
   int32_t precision;       /* default matvec precision used by phs_solve:
-                              PHS_FP64, or PHS_MIXED (FP32 far field and near
-                              field inside FP64 residual refinement) */
+                              PHS_FP64, PHS_MIXED or PHS_NEAR32 */
   double fmm_tol;          /* target relative accuracy of the core FMM;
                               0 => 1e-12 (FP64) */
   int32_t leaf_size;       /* mean points per leaf box; 0 => automatic */
@@ -85,7 +89,7 @@ typedef struct {
 
 /* Preconditioner options (Sec. 2.2; conditioning-set sizes of Sec. 3). */
 typedef struct {
-  int32_t m;           /* conditioning-set size |sigma(j)|; 0 => 30 (k=2), 50 */
+  int32_t m;           /* conditioning-set size |sigma(j)|, 1..63; 0 => 30 (k=2), 50 */
   double nu;           /* Matern smoothness; <= 0 => k/2. Supported: 0.5, 1,
                           1.5, 2, 2.5 */
   double range;        /* Matern range l = 1/alpha; <= 0 => alpha 0.35
@@ -100,7 +104,7 @@ typedef struct {
   double rtol;         /* 0 => 1e-8 */
   int32_t maxit;       /* 0 => 500 */
   int32_t check_every; /* host convergence check period; 0 => 1 */
-  int32_t precision;   /* -1 => plan default; PHS_FP64 or PHS_MIXED */
+  int32_t precision;   /* -1 => plan default; PHS_FP64, PHS_MIXED, PHS_NEAR32 */
 } phs_solve_opts;
 
 typedef struct {
@@ -119,7 +123,8 @@ phs_status phs_plan(const double *xy, int64_t n, const phs_plan_opts *opts,
                     void *stream, phs_plan_t *out);
 
 /* y = M v for the kernel block M only (eq. matvec_hadamard; Sec. 2.1 FMM).
- * v, y: device, n x nrhs.  precision: PHS_FP64 or PHS_MIXED.  Asynchronous. */
+ * v, y: device, n x nrhs.  precision: PHS_FP64, PHS_MIXED or PHS_NEAR32.
+ * Asynchronous. */
 phs_status phs_matvec(phs_plan_t plan, const double *v, double *y, int32_t nrhs,
                       int32_t precision, void *stream);
 

@@ -298,7 +298,8 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
   pl.S = n_monomials(pl.d);
   PHS_REQUIRE(n >= pl.S && n < (int64_t(1) << 30), PHS_ERR_INVALID_ARGUMENT,
               "n must be >= number of polynomial terms and < 2^30");
-  PHS_REQUIRE(o->precision == PHS_FP64 || o->precision == PHS_MIXED,
+  PHS_REQUIRE(o->precision == PHS_FP64 || o->precision == PHS_MIXED ||
+                  o->precision == PHS_NEAR32,
               PHS_ERR_INVALID_ARGUMENT, "bad precision");
   pl.n = n;
   pl.R = hadamard_rank(pl.k);
@@ -382,9 +383,8 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
 
 void matvec_tree(Plan &pl, const double *t_tree, double *y_tree, int precision,
                  hipStream_t s) {
-  const bool fp64 = precision == PHS_FP64;
-  if (pl.core_log) log_matvec(pl, t_tree, y_tree, nullptr, fp64, s);
-  else dist_matvec(pl, t_tree, y_tree, nullptr, fp64, s);
+  if (pl.core_log) log_matvec(pl, t_tree, y_tree, nullptr, precision, s);
+  else dist_matvec(pl, t_tree, y_tree, nullptr, precision, s);
 }
 
 namespace {
@@ -483,8 +483,8 @@ phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts 
   const int maxit = (o && o->maxit > 0) ? o->maxit : 500;
   const int check_every = (o && o->check_every > 0) ? o->check_every : 1;
   const int prec = (o && o->precision >= 0) ? o->precision : pl.precision;
-  PHS_REQUIRE(prec == PHS_FP64 || prec == PHS_MIXED, PHS_ERR_INVALID_ARGUMENT,
-              "bad precision");
+  PHS_REQUIRE(prec == PHS_FP64 || prec == PHS_MIXED || prec == PHS_NEAR32,
+              PHS_ERR_INVALID_ARGUMENT, "bad precision");
   double *ft = pl.wk[0], *r = pl.wk[1], *w = pl.wk[2], *z = pl.wk[3], *p = pl.wk[4],
          *q = pl.wk[5], *tmp = pl.wk[6], *dw = pl.wk[7];
   int total_iters = 0, total_outer = 0;
@@ -519,10 +519,14 @@ phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts 
       int outer = 0, budget = maxit;
       bool fp64_finish = false;
       while (rn > tol_abs && budget > 0) {
-        const double inner_tol = std::max(tol_abs, 1e-4 * rn);
-        const int inner_prec = fp64_finish ? PHS_FP64 : PHS_MIXED;
+        // FP32 far field: small steps (its error is relative to ||M||); FP32
+        // near field only: the operator is accurate enough to go to rtol at once
+        const double inner_tol =
+            prec == PHS_NEAR32 ? 0.5 * tol_abs : std::max(tol_abs, 1e-4 * rn);
+        const int inner_prec = fp64_finish ? PHS_FP64 : prec;
         PcgResult pr = pcg(pl, dw, r, fp64_finish ? tol_abs : inner_tol,
-                           fp64_finish ? budget : std::min(budget, 60), check_every,
+                           (fp64_finish || prec == PHS_NEAR32) ? budget : std::min(budget, 60),
+                           check_every,
                            inner_prec, z, p, q, tmp, s);
         total_iters += pr.iters;
         budget -= pr.iters;
@@ -652,15 +656,14 @@ phs_status phs_matvec(phs_plan_t plan, const double *v, double *y, int32_t nrhs,
                       int32_t precision, void *stream) {
   return guarded([&] {
     PHS_REQUIRE(plan && v && y && nrhs >= 1, PHS_ERR_INVALID_ARGUMENT, "bad matvec arguments");
-    PHS_REQUIRE(precision == PHS_FP64 || precision == PHS_MIXED, PHS_ERR_INVALID_ARGUMENT,
-                "bad precision");
+    PHS_REQUIRE(precision == PHS_FP64 || precision == PHS_MIXED || precision == PHS_NEAR32,
+                PHS_ERR_INVALID_ARGUMENT, "bad precision");
     Plan &pl = plan->pl;
     hipStream_t s = S(stream);
     for (int c = 0; c < nrhs; ++c) {
       gather_cols(v + (int64_t)c * pl.n, pl.order, pl.n, pl.v_t, s);
-      const bool fp64 = precision == PHS_FP64;
-      if (pl.core_log) log_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, fp64, s);
-      else dist_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, fp64, s);
+      if (pl.core_log) log_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, precision, s);
+      else dist_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, precision, s);
     }
     return PHS_OK;
   });

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_cheb_m2l(const T *__restrict__ Wall,
 }
 
 // ---------------------------------------------------------------- leaf
-template <class T, int K, int Q>
+template <class T, class TN, int K, int Q>
 __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
     const double *__restrict__ x, const double *__restrict__ y,
     const float *__restrict__ ux, const float *__restrict__ uy,
@@ -384,8 +384,8 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
         far += u[r] * s;
       }
     }
-    T nearv = T(0);
-    if constexpr (std::is_same<T, double>::value) {
+    TN nearv = TN(0);
+    if constexpr (std::is_same<TN, double>::value) {
       for (int row = r0; row <= r1; ++row) {
         const int js = start[row * G + c0], je = start[row * G + c1 + 1];
         nearv += near_range<K>(xi, yi, xy2, t, js, je, logtab);
@@ -561,7 +561,7 @@ void far_field_q(Plan &pl, const double *t, hipStream_t s) {
   }
 }
 
-template <class T, int Q>
+template <class T, class TN, int Q>
 void leaf_q(Plan &pl, const double *t, double *yt, double *yu, hipStream_t s) {
   constexpr int QQ = Q * Q;
   const bool fp64 = std::is_same<T, double>::value;
@@ -571,38 +571,38 @@ void leaf_q(Plan &pl, const double *t, double *yt, double *yu, hipStream_t s) {
   const T *GL = (const T *)pl.loc + cheb_level_base(L, QQ, pl.R);
   const int64_t nleaf = boxes_at(L);
   if (pl.k == 1)
-    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, 1, Q><<<nleaf, 64, 0, s>>>(
+    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, TN, 1, Q><<<nleaf, 64, 0, s>>>(
         pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
         pl.order, pl.xy2, pl.logtab));
   else
-    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, 3, Q><<<nleaf, 64, 0, s>>>(
+    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, TN, 3, Q><<<nleaf, 64, 0, s>>>(
         pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
         pl.order, pl.xy2, pl.logtab));
 }
 
-template <class T>
+template <class T, class TN>
 void run_q(Plan &pl, const double *t, double *yt, double *yu, bool leaf, hipStream_t s) {
   const int Q = std::is_same<T, double>::value ? pl.q64 : pl.q32;
   switch (Q) {
     case 8:
       far_field_q<T, 8>(pl, t, s);
-      if (leaf) leaf_q<T, 8>(pl, t, yt, yu, s);
+      if (leaf) leaf_q<T, TN, 8>(pl, t, yt, yu, s);
       break;
     case 10:
       far_field_q<T, 10>(pl, t, s);
-      if (leaf) leaf_q<T, 10>(pl, t, yt, yu, s);
+      if (leaf) leaf_q<T, TN, 10>(pl, t, yt, yu, s);
       break;
     case 12:
       far_field_q<T, 12>(pl, t, s);
-      if (leaf) leaf_q<T, 12>(pl, t, yt, yu, s);
+      if (leaf) leaf_q<T, TN, 12>(pl, t, yt, yu, s);
       break;
     case 14:
       far_field_q<T, 14>(pl, t, s);
-      if (leaf) leaf_q<T, 14>(pl, t, yt, yu, s);
+      if (leaf) leaf_q<T, TN, 14>(pl, t, yt, yu, s);
       break;
     case 16:
       far_field_q<T, 16>(pl, t, s);
-      if (leaf) leaf_q<T, 16>(pl, t, yt, yu, s);
+      if (leaf) leaf_q<T, TN, 16>(pl, t, yt, yu, s);
       break;
     default:
       throw Error{PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16"};
@@ -709,14 +709,15 @@ size_t cheb_expansion_bytes(int L, int Q, int nd, bool fp64) {
   return (size_t)cheb_level_base(L + 1, Q * Q, nd) * (fp64 ? 8 : 4);
 }
 
-void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, bool fp64,
+void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, int precision,
                  hipStream_t s) {
-  if (fp64) run_q<double>(pl, t_tree, y_tree, y_user, true, s);
-  else run_q<float>(pl, t_tree, y_tree, y_user, true, s);
+  if (precision == PHS_MIXED) run_q<float, float>(pl, t_tree, y_tree, y_user, true, s);
+  else if (precision == PHS_NEAR32) run_q<double, float>(pl, t_tree, y_tree, y_user, true, s);
+  else run_q<double, double>(pl, t_tree, y_tree, y_user, true, s);
 }
 
 void dist_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
-  run_q<double>(pl, w_tree, nullptr, nullptr, false, s);
+  run_q<double, double>(pl, w_tree, nullptr, nullptr, false, s);
 }
 
 void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,

@@ -210,7 +210,7 @@ __global__ void k_l2l(const V2<T> *__restrict__ Bp, V2<T> *__restrict__ Bc, int 
 // One wavefront per leaf: each lane one target node.  Far field by Horner on
 // the leaf's incoming expansions (L2P) combined with U_r; near field by
 // direct phi over the 3x3 neighbouring leaves (step 2: direct evaluation).
-template <class T, int K>
+template <class T, class TN, int K>
 __global__ __launch_bounds__(64) void k_leaf_eval(
     const double *__restrict__ x, const double *__restrict__ y,
     const float *__restrict__ ux, const float *__restrict__ uy,
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
   const int nleaf = G * G;
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
-  if constexpr (std::is_same<T, double>::value && K % 2 == 0) {
+  if constexpr (std::is_same<TN, double>::value && K % 2 == 0) {
     for (int i = lane; i < 256; i += 64) tab[i] = logtab[i];
     __syncthreads();
   }
@@ -261,8 +261,8 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       }
     }
     // near field
-    T nearv = T(0);
-    if constexpr (std::is_same<T, double>::value) {
+    TN nearv = TN(0);
+    if constexpr (std::is_same<TN, double>::value) {
       for (int row = r0; row <= r1; ++row) {
         const int js = start[row * G + c0], je = start[row * G + c1 + 1];
         nearv += near_range<K>(xi, yi, xy2, t, js, je, tab);
@@ -463,7 +463,7 @@ void far_field(Plan &pl, const double *t, hipStream_t s) {
   }
 }
 
-template <class T>
+template <class T, class TN>
 void leaf_pass(Plan &pl, const double *t, double *y_tree, double *y_user, hipStream_t s) {
   const bool fp64 = std::is_same<T, double>::value;
   const int P = fp64 ? pl.p64 : pl.p32;
@@ -472,13 +472,13 @@ void leaf_pass(Plan &pl, const double *t, double *y_tree, double *y_user, hipStr
   const int64_t nleaf = boxes_at(L);
   if (pl.k == 2)
     PHS_LAUNCH("leaf_eval", s,
-               k_leaf_eval<T, 2><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
+               k_leaf_eval<T, TN, 2><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
                                                       pl.tree.leaf_start, L, pl.tree.h, P,
                                                       BL, y_tree, y_user, pl.order, pl.xy2,
                                                       pl.logtab));
   else
     PHS_LAUNCH("leaf_eval", s,
-               k_leaf_eval<T, 4><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
+               k_leaf_eval<T, TN, 4><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
                                                       pl.tree.leaf_start, L, pl.tree.h, P,
                                                       BL, y_tree, y_user, pl.order, pl.xy2,
                                                       pl.logtab));
@@ -578,14 +578,15 @@ size_t log_expansion_bytes(int L, int P, int nd, bool fp64) {
   return (size_t)level_base(L + 1, P, nd) * (fp64 ? 16 : 8);
 }
 
-void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, bool fp64,
+void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, int precision,
                 hipStream_t s) {
-  if (fp64) {
-    far_field<double>(pl, t_tree, s);
-    leaf_pass<double>(pl, t_tree, y_tree, y_user, s);
-  } else {
+  if (precision == PHS_MIXED) {
     far_field<float>(pl, t_tree, s);
-    leaf_pass<float>(pl, t_tree, y_tree, y_user, s);
+    leaf_pass<float, float>(pl, t_tree, y_tree, y_user, s);
+  } else {
+    far_field<double>(pl, t_tree, s);
+    if (precision == PHS_NEAR32) leaf_pass<double, float>(pl, t_tree, y_tree, y_user, s);
+    else leaf_pass<double, double>(pl, t_tree, y_tree, y_user, s);
   }
 }
 

@@ -248,7 +248,7 @@ void build_log_tables(LogTables &t, int P);
 void free_log_tables(LogTables &t);
 size_t log_expansion_bytes(int L, int P, int ndens, bool fp64);
 void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user,
-                bool fp64, hipStream_t s);
+                int precision, hipStream_t s);
 // Upward pass only (for evaluation at targets): fills pl.mp/pl.loc with
 // expansions of the densities V_r * w.
 void log_expansions(Plan &pl, const double *w_tree, hipStream_t s);
@@ -258,7 +258,7 @@ void build_cheb_tables(ChebTables &t, int Q);
 void free_cheb_tables(ChebTables &t);
 size_t cheb_expansion_bytes(int L, int Q, int ndens, bool fp64);
 void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user,
-                 bool fp64, hipStream_t s);
+                 int precision, hipStream_t s);
 void dist_expansions(Plan &pl, const double *w_tree, hipStream_t s);
 
 void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,

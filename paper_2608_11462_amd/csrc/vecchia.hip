@@ -23,7 +23,7 @@ namespace phs {
 
 namespace {
 
-constexpr int kMaxM = 64;
+constexpr int kMaxM = 63;  // the augmented block (|sigma| + 1) fits one wavefront
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
@@ -101,8 +101,8 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
                                             const int32_t *sorted_rank,
                                             const int32_t *pos_of_rank, int32_t *nbr,
                                             int32_t *cnt_out) {
-  __shared__ double d2s[kMaxM * 64];
-  __shared__ int rks[kMaxM * 64];
+  __shared__ double d2s[64 * 64];
+  __shared__ int rks[64 * 64];
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x * (int64_t)64 + lane;
   if (t >= n) return;
@@ -236,19 +236,29 @@ __device__ double matern(int nu2, double x) {
   }
 }
 
-// One wavefront per node: factor the Matern block of sigma(j) u {j}.
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// One wavefront per node: Cholesky of the Matern block of sigma(j) u {j}
+// (node last).  The block is formed in LDS with its entries spread evenly
+// over the lanes; then lane r holds row r in registers and the factorisation
+// broadcasts column entries with readlane.  Row |sigma| of the factor is
+// (L_s^{-1} k, c); lambda = L_s^{-T} L_s^{-1} k by a back substitution whose
+// sums are wave reductions in a fixed order.
 template <int MM>
 __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y, int64_t n,
                                                int m, const int32_t *nbr, const int32_t *cnt,
                                                int nu2, double alpha, double *coef,
                                                double *dinv, int32_t *nfail) {
   constexpr int LD = MM + 1;
-  __shared__ double C[LD * LD];
-  __shared__ double px[LD], py[LD], vv[LD];
-  __shared__ int bad;
+  __shared__ double C[MM * LD];
+  __shared__ double px[MM], py[MM];
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
-  const int K = cnt[p];
+  const int K = __builtin_amdgcn_readfirstlane(cnt[p]);
   const int N1 = K + 1;
   for (int a = lane; a < K; a += 64) {
     const int q = nbr[(int64_t)a * n + p];
@@ -260,100 +270,106 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
     py[K] = y[p];
   }
   __syncthreads();
-  double nug = 0.0;
-  for (int attempt = 0; attempt < 4; ++attempt) {
-    for (int e = lane; e < N1 * N1; e += 64) {
-      const int a = e / N1, b = e % N1;
-      if (b <= a) {
-        const double dx = px[a] - px[b], dy = py[a] - py[b];
-        double v = matern(nu2, alpha * sqrt(dx * dx + dy * dy));
-        if (a == b) v += nug;
-        C[a * LD + b] = v;
-      }
+  for (int e = lane; e < N1 * N1; e += 64) {
+    const int a = e / N1, b = e % N1;
+    if (b <= a) {
+      const double dx = px[a] - px[b], dy = py[a] - py[b];
+      C[a * LD + b] = matern(nu2, alpha * sqrt(dx * dx + dy * dy));
     }
-    if (lane == 0) bad = 0;
-    __syncthreads();
-    for (int c = 0; c < N1; ++c) {
-      const double dg = C[c * LD + c];
-      if (!(dg > 0.0)) {
-        if (lane == 0) bad = 1;
-        break;
-      }
-      const double d = sqrt(dg);
-      __syncthreads();
-      for (int r = c + 1 + lane; r < N1; r += 64) C[r * LD + c] /= d;
-      if (lane == 0) C[c * LD + c] = d;
-      __syncthreads();
-      for (int r = c + 1 + lane; r < N1; r += 64) {
-        const double lrc = C[r * LD + c];
-        for (int s2 = c + 1; s2 <= r; ++s2) C[r * LD + s2] -= lrc * C[s2 * LD + c];
-      }
-      __syncthreads();
-    }
-    __syncthreads();
-    if (!bad) break;
-    nug = (attempt == 0) ? 1e-12 : nug * 100.0;
-    if (lane == 0 && attempt == 0) atomicAdd(&nfail[0], 1);
-    __syncthreads();
   }
-  if (bad) {
+  __syncthreads();
+  double nug = 0.0;
+  double a[MM];
+  bool ok = false;
+  for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+    // load row `lane` (lower triangle), identity beyond the block
+#pragma unroll
+    for (int s2 = 0; s2 < MM; ++s2) {
+      double v = 0.0;
+      if (lane < N1 && s2 <= lane) v = C[lane * LD + s2] + (s2 == lane ? nug : 0.0);
+      else if (s2 == lane) v = 1.0;
+      a[s2] = v;
+    }
+    ok = true;
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+      if (c < N1) {
+        const double piv = bcast(a[c], c);
+        if (!(piv > 0.0)) {
+          ok = false;
+          break;
+        }
+        const double d = sqrt(piv);
+        const double inv = 1.0 / d;
+        if (lane == c) a[c] = d;
+        if (lane > c) a[c] *= inv;
+        const double lrc = a[c];
+#pragma unroll
+        for (int s2 = c + 1; s2 < MM; ++s2) {
+          if (s2 < N1) {
+            const double lsc = bcast(a[c], s2);
+            if (lane >= s2) a[s2] = fma(-lrc, lsc, a[s2]);
+          }
+        }
+      }
+    }
+    if (!ok) {
+      nug = (attempt == 0) ? 1e-12 : nug * 100.0;
+      if (lane == 0 && attempt == 0) atomicAdd(&nfail[0], 1);
+    }
+  }
+  if (!ok) {
     if (lane == 0) atomicAdd(&nfail[1], 1);
     return;
   }
-  // lambda = L_s^{-T} (row K of L); c = L[K][K]
-  const double cc = C[K * LD + K];
-  for (int a = lane; a < K; a += 64) vv[a] = C[K * LD + a];
-  __syncthreads();
-  for (int i = K - 1; i >= 0; --i) {
-    const double li = vv[i] / C[i * LD + i];
-    __syncthreads();
-    if (lane == 0) vv[i] = li;
-    for (int l = lane; l < i; l += 64) vv[l] -= C[i * LD + l] * li;
-    __syncthreads();
+  // u = row K (L_s^{-1} k), c = L[K][K]; lane i keeps u_i
+  double u_i = 0.0, cc = 1.0, lii = 1.0;
+#pragma unroll
+  for (int i = 0; i < MM; ++i) {
+    if (i < K) {
+      const double v = bcast(a[i], K);
+      if (lane == i) u_i = v;
+    }
+    if (i == K) cc = bcast(a[i], K);
+    if (lane == i) lii = a[i];
+  }
+  // back substitution: lambda_i = (u_i - sum_{l>i} L[l][i] lambda_l) / L[i][i]
+  double lam = 0.0;  // lambda of this lane's index
+#pragma unroll
+  for (int i = MM - 1; i >= 0; --i) {
+    if (i < K) {
+      double t = (lane > i && lane < K) ? a[i] * lam : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+      if (lane == i) lam = (u_i - t) / lii;
+    }
   }
   const double inv_c = 1.0 / cc;
-  for (int a = lane; a < m; a += 64)
-    coef[(int64_t)a * n + p] = a < K ? -vv[a] * inv_c : 0.0;
+  if (lane < m) coef[(int64_t)lane * n + p] = lane < K ? -lam * inv_c : 0.0;
   if (lane == 0) dinv[p] = inv_c;
 }
 
 // ---------------------------------------------------------------- transpose
-__global__ void k_tcount(const int32_t *nbr, int64_t n, int m, int32_t *count) {
+// Row-major enumeration e = j*m + s of the factor's entries, keyed by the row
+// q = nbr[s][j]; a stable sort by q then lists each row's entries by
+// ascending column j (each (q, j) pair occurs once).
+__global__ void k_tkeys(const int32_t *nbr, int64_t n, int m, uint32_t *keys, int32_t *vals) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n * m) return;
-  const int q = nbr[e];
-  if (q >= 0) atomicAdd(&count[q], 1);
+  const int64_t j = e / m, s = e % m;
+  const int q = nbr[s * n + j];
+  keys[e] = q < 0 ? (uint32_t)n : (uint32_t)q;
+  vals[e] = (int32_t)e;
 }
 
-__global__ void k_tfill(const int32_t *nbr, const double *coef, int64_t n, int m,
-                        const int32_t *tstart, int32_t *cursor, int32_t *tidx, double *tcoef) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n * m) return;
-  const int q = nbr[e];
-  if (q < 0) return;
-  const int j = (int)(e % n);
-  const int pos = tstart[q] + atomicAdd(&cursor[q], 1);
-  tidx[pos] = j;
-  tcoef[pos] = coef[e];
-}
-
-// sort each transposed row by column index (fixed summation order)
-__global__ void k_tsort(const int32_t *tstart, int64_t n, int32_t *tidx, double *tcoef) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int b = tstart[i], e = tstart[i + 1];
-  for (int a = b + 1; a < e; ++a) {
-    const int key = tidx[a];
-    const double val = tcoef[a];
-    int q = a - 1;
-    while (q >= b && tidx[q] > key) {
-      tidx[q + 1] = tidx[q];
-      tcoef[q + 1] = tcoef[q];
-      --q;
-    }
-    tidx[q + 1] = key;
-    tcoef[q + 1] = val;
-  }
+__global__ void k_tfill(const int32_t *vals, int64_t nnz, int64_t n, int m, const double *coef,
+                        int32_t *tidx, double *tcoef) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int64_t e = vals[p];
+  const int64_t j = e / m, s = e % m;
+  tidx[p] = (int32_t)j;
+  tcoef[p] = coef[s * n + j];
 }
 
 // ---------------------------------------------------------------- apply
@@ -370,15 +386,21 @@ __global__ void k_apply_ut(const double *r, int64_t n, int m, const int32_t *nbr
   yv[j] = acc;
 }
 
-__global__ void k_apply_u(const double *yv, int64_t n, const int32_t *tstart,
-                          const int32_t *tidx, const double *tcoef, const double *dinv,
-                          double *z) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Row gather of the transposed factor, 32 lanes per row: lanes stride over the
+// row's entries (coalesced) and a fixed butterfly sums the partial sums.
+__global__ __launch_bounds__(256) void k_apply_u(const double *yv, int64_t n,
+                                                 const int32_t *tstart, const int32_t *tidx,
+                                                 const double *tcoef, const double *dinv,
+                                                 double *z) {
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 5;
+  const int g = threadIdx.x & 31;
   if (i >= n) return;
-  double acc = dinv[i] * yv[i];
   const int b = tstart[i], e = tstart[i + 1];
-  for (int a = b; a < e; ++a) acc += tcoef[a] * yv[tidx[a]];
-  z[i] = acc;
+  double acc = 0.0;
+  for (int a = b + g; a < e; a += 32) acc += tcoef[a] * yv[tidx[a]];
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+  if (g == 0) z[i] = dinv[i] * yv[i] + acc;
 }
 
 // export in caller order
@@ -426,7 +448,7 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
   const int64_t n = pl.n;
   const int m = o.m > 0 ? o.m : (pl.k == 2 ? 30 : 50);
   PHS_REQUIRE(m >= 1 && m <= kMaxM, PHS_ERR_INVALID_ARGUMENT,
-              "conditioning-set size must be 1..64");
+              "conditioning-set size must be 1..63");
   const double nu = o.nu > 0 ? o.nu : 0.5 * pl.k;
   const int nu2 = nu_code(nu);
   PHS_REQUIRE(nu2 > 0, PHS_ERR_INVALID_ARGUMENT, "nu must be one of 0.5, 1, 1.5, 2, 2.5");
@@ -498,33 +520,38 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     pl.pc_coef = dmalloc<double>((size_t)n * m);
     pl.pc_dinv = dmalloc<double>(n);
     PHS_HIP(hipMemsetAsync(nfail, 0, 8, s));
-    if (m <= 32)
+    if (m <= 31)
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<32><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
                                               pl.pc_coef, pl.pc_dinv, nfail));
     else
       PHS_LAUNCH("vecchia_factor", s,
-                 k_factor<kMaxM><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
+                 k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
                                                  alpha, pl.pc_coef, pl.pc_dinv, nfail));
-    // 5. transpose
-    pl.pc_tstart = dmalloc<int32_t>(n + 1);
-    int32_t *cursor = cnt;  // reuse
-    PHS_HIP(hipMemsetAsync(pl.pc_tstart, 0, (n + 1) * 4, s));
-    PHS_LAUNCH("vecchia_tcount", s,
-               k_tcount<<<(n * m + B - 1) / B, B, 0, s>>>(pl.pc_nbr, n, m, pl.pc_tstart));
-    scan_exclusive(pl.pc_tstart, n + 1, scr, s);
-    int32_t nnz = 0;
-    PHS_HIP(hipMemcpyAsync(&nnz, pl.pc_tstart + n, 4, hipMemcpyDeviceToHost, s));
-    PHS_HIP(hipStreamSynchronize(s));
-    pl.pc_tidx = dmalloc<int32_t>(std::max(nnz, 1));
-    pl.pc_tcoef = dmalloc<double>(std::max(nnz, 1));
-    PHS_HIP(hipMemsetAsync(cursor, 0, n * 4, s));
-    PHS_LAUNCH("vecchia_tfill", s,
-               k_tfill<<<(n * m + B - 1) / B, B, 0, s>>>(pl.pc_nbr, pl.pc_coef, n, m,
-                                                        pl.pc_tstart, cursor, pl.pc_tidx,
-                                                        pl.pc_tcoef));
-    PHS_LAUNCH("vecchia_tsort", s,
-               k_tsort<<<(n + B - 1) / B, B, 0, s>>>(pl.pc_tstart, n, pl.pc_tidx, pl.pc_tcoef));
+    // 5. transpose: stable radix sort of the entries by row
+    {
+      const int64_t N = n * m;
+      uint32_t *tk = dmalloc<uint32_t>(N), *tkt = dmalloc<uint32_t>(N);
+      int32_t *tv = dmalloc<int32_t>(N), *tvt = dmalloc<int32_t>(N);
+      int32_t *tscr = dmalloc<int32_t>(radix_sort_scratch_ints(N));
+      int bits = 1;
+      while (((int64_t)1 << bits) <= n) ++bits;
+      PHS_LAUNCH("vecchia_tkeys", s,
+                 k_tkeys<<<(N + B - 1) / B, B, 0, s>>>(pl.pc_nbr, n, m, tk, tv));
+      radix_sort_u32(tk, tv, N, bits, tkt, tvt, tscr, s);
+      pl.pc_tstart = dmalloc<int32_t>(n + 1);
+      leaf_ranges(tk, N, (int)n, pl.pc_tstart, s);
+      int32_t nnz = 0;
+      PHS_HIP(hipMemcpyAsync(&nnz, pl.pc_tstart + n, 4, hipMemcpyDeviceToHost, s));
+      PHS_HIP(hipStreamSynchronize(s));
+      pl.pc_tidx = dmalloc<int32_t>(std::max(nnz, 1));
+      pl.pc_tcoef = dmalloc<double>(std::max(nnz, 1));
+      if (nnz > 0)
+        PHS_LAUNCH("vecchia_tfill", s,
+                   k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(tv, nnz, n, m, pl.pc_coef,
+                                                          pl.pc_tidx, pl.pc_tcoef));
+      for (void *q : {(void *)tk, (void *)tkt, (void *)tv, (void *)tvt, (void *)tscr}) dfree(q);
+    }
     int32_t hfail[2] = {0, 0};
     PHS_HIP(hipMemcpyAsync(hfail, nfail, 8, hipMemcpyDeviceToHost, s));
     PHS_HIP(hipStreamSynchronize(s));
@@ -555,8 +582,8 @@ void vecchia_apply(Plan &pl, const double *r, double *z, double *tmp, hipStream_
              k_apply_ut<<<(n + B - 1) / B, B, 0, s>>>(r, n, pl.m, pl.pc_nbr, pl.pc_coef,
                                                      pl.pc_dinv, tmp));
   PHS_LAUNCH("precond_u", s,
-             k_apply_u<<<(n + B - 1) / B, B, 0, s>>>(tmp, n, pl.pc_tstart, pl.pc_tidx,
-                                                    pl.pc_tcoef, pl.pc_dinv, z));
+             k_apply_u<<<(n * 32 + B - 1) / B, B, 0, s>>>(tmp, n, pl.pc_tstart, pl.pc_tidx,
+                                                         pl.pc_tcoef, pl.pc_dinv, z));
 }
 
 void vecchia_export(Plan &pl, int32_t *rank, int32_t *nbr, double *coef, double *diag,

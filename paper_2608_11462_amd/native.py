@@ -15,7 +15,7 @@ import torch
 
 LIB_PATH = Path(__file__).resolve().parent / "libphs.so"
 
-PHS_FP64, PHS_MIXED = 0, 1
+PHS_FP64, PHS_MIXED, PHS_NEAR32 = 0, 1, 2
 PHS_RANGE_NORMALIZED, PHS_RANGE_USER = 0, 1
 
 STATUS = {

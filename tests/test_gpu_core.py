@@ -73,6 +73,19 @@ def test_matvec_mixed_reported(small, k):
     assert e <= 1e-4
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_matvec_near32(small, k):
+    """FP64 far field with an FP32 near field: the near-field entries are small,
+    so the matvec stays close to FP64 accuracy."""
+    pl = _plan(small, k=k, degree=-1)
+    c, rho, xi = D.normalize(small.xy, k)
+    v = W.rng_for(300 + k).standard_normal(small.n)
+    y_ref = D.matvec_dense(k, xi, v)
+    e = rel(host(pl.matvec(dev(v), precision=N.PHS_NEAR32)), y_ref)
+    print(f"k={k} near32 matvec rel err {e:.3e}")
+    assert e <= 1e-6
+
+
 def test_matvec_multi_rhs(small):
     pl = _plan(small)
     c, rho, xi = D.normalize(small.xy, 2)

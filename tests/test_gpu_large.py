@@ -67,3 +67,7 @@ def test_large_tps_full_fp64():
 
 def test_large_tps_full_mixed():
     _run(W.large_tps(), 30, 1.0, 128, 512, precision=N.PHS_MIXED)
+
+
+def test_large_tps_full_near32():
+    _run(W.large_tps(), 30, 1.0, 128, 512, precision=N.PHS_NEAR32)
