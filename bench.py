@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    # one elementwise kernel reading 1 GiB and writing 1 GiB before the steps:
+    # the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters
+    ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
 
@@ -140,6 +143,12 @@ def main():
     f = torch.as_tensor(pr.f, device=dev)
     tg = torch.as_tensor(pr.targets, device=dev)
     torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.mul(src, 2.0)
+        torch.cuda.synchronize()
+        del src, dst
 
     phases = {"plan": 0.0, "precond": 0.0, "solve": 0.0, "eval": 0.0}
     last = {}
