@@ -8,6 +8,16 @@
 
 namespace phs {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8).  xcd_remap gives XCD x the contiguous logical range
+// [x*q + min(x, r), ...) of the nb workgroups (q = nb / 8, r = nb % 8), so
+// neighbouring boxes share one XCD's L2.  A bijection on [0, nb).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7;
+  const int64_t x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <class T>
 struct C2 {
   T re, im;

@@ -338,7 +338,7 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
   constexpr int QQ = Q * Q;
   __shared__ T tk[QQ];
   const int G = 1 << L;
-  const int leaf = blockIdx.x;
+  const int leaf = (int)xcd_remap(blockIdx.x, (int64_t)G * G);
   const int lane = threadIdx.x;
   for (int i = lane; i < QQ; i += 64) tk[i] = Tk[i];
   __syncthreads();

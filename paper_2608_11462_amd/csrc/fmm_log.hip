@@ -112,10 +112,13 @@ template <class T, int LCH>
 __global__ __launch_bounds__(256) void k_m2l(const V2<T> *__restrict__ A,
                                              V2<T> *__restrict__ B, int L, int P,
                                              int nd, const T *__restrict__ Ht,
-                                             double h) {
-  const int l0 = blockIdx.y * LCH;
-  const int r = blockIdx.z;
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+                                             double h, int nchunks, int64_t ntiles) {
+  // logical workgroup: chunk fastest, then density, then tile of 256 boxes
+  const int64_t lb = xcd_remap(blockIdx.x, (int64_t)nchunks * nd * ntiles);
+  const int l0 = (int)(lb % nchunks) * LCH;
+  const int r = (int)((lb / nchunks) % nd);
+  const int64_t tile = lb / ((int64_t)nchunks * nd);
+  int64_t t = tile * 256 + threadIdx.x;
   int l = 2;
   int64_t off = 0, base = 0;
   while (l <= L && t >= off + ((int64_t)1 << (2 * l))) {
@@ -127,12 +130,15 @@ __global__ __launch_bounds__(256) void k_m2l(const V2<T> *__restrict__ A,
   const int G = 1 << l;
   const int64_t nb = (int64_t)G * G;
   const int64_t ti = t - off;
-  const int64_t quarter = nb / 4;
-  const int cls = (int)(ti / quarter);
-  const int64_t rem = ti % quarter;
+  // boxes by strips of two rows: within a strip the four parity classes, each
+  // a run of G/2 boxes with one interaction-list pattern
   const int half = G / 2;
-  const int ix = 2 * (int)(rem % half) + (cls & 1);
-  const int iy = 2 * (int)(rem / half) + (cls >> 1);
+  const int aa = (int)(ti % half);
+  const int64_t rest = ti / half;
+  const int cls = (int)(rest & 3);
+  const int brow = (int)(rest >> 2);
+  const int ix = 2 * aa + (cls & 1);
+  const int iy = 2 * brow + (cls >> 1);
   const V2<T> *Al = A + base;
   V2<T> *Bl = B + base;
   const T logw = (T)log(2.0 * h / G);
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
   __shared__ double tab[256];
   const int G = 1 << L;
   const int nleaf = G * G;
-  const int leaf = blockIdx.x;
+  const int leaf = (int)xcd_remap(blockIdx.x, nleaf);
   const int lane = threadIdx.x;
   if constexpr (std::is_same<TN, double>::value && K % 2 == 0) {
     for (int i = lane; i < 256; i += 64) tab[i] = logtab[i];
@@ -448,10 +454,27 @@ void far_field(Plan &pl, const double *t, hipStream_t s) {
   {
     int64_t tot = 0;
     for (int l = 2; l <= L; ++l) tot += boxes_at(l);
-    constexpr int LCH = 16;
-    dim3 grid((unsigned)((tot + 255) / 256), (unsigned)((P + 1 + LCH - 1) / LCH),
-              (unsigned)nd);
-    PHS_LAUNCH("m2l", s, k_m2l<T, LCH><<<grid, 256, 0, s>>>(A, B, L, P, nd, Ht, h));
+    // chunk of LCH output coefficients: the widest of 16/14/12 that divides
+    // P+1, else 8 (the last chunk then stores only its first coefficients)
+    const int64_t ntiles = (tot + 255) / 256;
+    const int lch = ((P + 1) % 16 == 0) ? 16 : ((P + 1) % 14 == 0) ? 14
+                    : ((P + 1) % 12 == 0) ? 12 : 8;
+    const int nchunks = (P + 1 + lch - 1) / lch;
+    const unsigned nblk = (unsigned)(ntiles * nchunks * nd);
+    switch (lch) {
+    case 16:
+      PHS_LAUNCH("m2l", s, k_m2l<T, 16><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      break;
+    case 14:
+      PHS_LAUNCH("m2l", s, k_m2l<T, 14><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      break;
+    case 12:
+      PHS_LAUNCH("m2l", s, k_m2l<T, 12><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      break;
+    default:
+      PHS_LAUNCH("m2l", s, k_m2l<T, 8><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      break;
+    }
   }
   // downward pass
   for (int lc = 3; lc <= L; ++lc) {

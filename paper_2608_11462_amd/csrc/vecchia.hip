@@ -17,7 +17,7 @@
 //     copy whose rows are sorted by column, so sums are in a fixed order.
 #include <cmath>
 
-#include "phs_internal.h"
+#include "fmm_common.h"
 
 namespace phs {
 
@@ -73,6 +73,15 @@ __global__ void k_grid_keys(const double *xr, const double *yr, int T,
   vals[e] = r;
 }
 
+// coordinates of the grid entries in their sorted (cell) order
+__global__ void k_grid_coords(const int32_t *sorted_rank, const double *xr, const double *yr,
+                              int64_t total, double2 *gxy) {
+  int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= total) return;
+  const int r = sorted_rank[q];
+  gxy[q] = make_double2(xr[r], yr[r]);
+}
+
 __global__ void k_cell_start(const uint32_t *keys, int64_t total, int T, const int32_t *gbits,
                              const int64_t *cell_off, int64_t ncells_total, int32_t *start) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -99,6 +108,7 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
                                             int m, int T, double h, const int32_t *gbits,
                                             const int64_t *cell_off, const int32_t *cell_start,
                                             const int32_t *sorted_rank,
+                                            const double2 *__restrict__ gxy,
                                             const int32_t *pos_of_rank, int32_t *nbr,
                                             int32_t *cnt_out) {
   __shared__ double d2s[64 * 64];
@@ -110,7 +120,7 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
   const int p = pos_of_rank[t];
   if (K == 0) {
     cnt_out[p] = 0;
-    for (int s = 0; s < m; ++s) nbr[(int64_t)s * n + p] = -1;
+    for (int s = 0; s < m; ++s) nbr[(int64_t)p * m + s] = -1;
     return;
   }
   int lv = 64 - __clzll((unsigned long long)t);  // smallest lv with 2^lv >= t+1
@@ -122,6 +132,9 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
   const int cqx = grid_cell(qx, h, g), cqy = grid_cell(qy, h, g);
   const int32_t *cs = cell_start + cell_off[lv];
   int cnt = 0;
+  // worst kept candidate (the list's last entry), cached in registers
+  double wd2 = INFINITY;
+  int wrk = 0x7fffffff;
   const int maxR = max(max(cqx, g - 1 - cqx), max(cqy, g - 1 - cqy));
   for (int R = 0; R <= maxR; ++R) {
     for (int cy = cqy - R; cy <= cqy + R; ++cy) {
@@ -130,34 +143,50 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
       const int step = edge_row ? 1 : 2 * R;
       for (int cx = cqx - R; cx <= cqx + R; cx += (step > 0 ? step : 1)) {
         if (cx >= 0 && cx < g) {
-          const int c = cy * g + cx;
-          const int b = cs[c], e = cs[c + 1];
-          for (int q = b; q < e; ++q) {
-            const int r = sorted_rank[q];
-            if (r >= t) break;  // within a cell entries ascend by rank
-            double d2;
-            {
-              // each product rounded, then the sum: no fused multiply-add, so
-              // d^2 is symmetric in (dx, dy) and identical to the CPU reference
+          bool visit = true;
+          if (cnt == K) {
+            // skip a cell that cannot hold a point closer than the worst kept
+            // one (strictly; a tie at equal d^2 could still win on rank)
+            const double lo_x = -h + cx * cw, lo_y = -h + cy * cw;
+            const double ex = fmax(fmax(lo_x - qx, qx - (lo_x + cw)), 0.0);
+            const double ey = fmax(fmax(lo_y - qy, qy - (lo_y + cw)), 0.0);
+            visit = (ex * ex + ey * ey) * (1.0 - 1e-12) <= wd2;
+          }
+          if (visit) {
+            const int c = cy * g + cx;
+            const int b = cs[c], e = cs[c + 1];
+            for (int q = b; q < e; ++q) {
+              const int r = sorted_rank[q];
+              if (r >= t) break;  // within a cell entries ascend by rank
+              double d2;
+              {
+                // each product rounded, then the sum: no fused multiply-add, so
+                // d^2 is symmetric in (dx, dy) and identical to the CPU reference
 #pragma clang fp contract(off)
-              const double dx = xr[r] - qx;
-              const double dy = yr[r] - qy;
-              d2 = dx * dx + dy * dy;
+                const double2 cxy = gxy[q];
+                const double dx = cxy.x - qx;
+                const double dy = cxy.y - qy;
+                d2 = dx * dx + dy * dy;
+              }
+              int pos;
+              if (cnt < K) {
+                pos = cnt++;
+              } else {
+                if (!lessp(d2, r, wd2, wrk)) continue;
+                pos = K - 1;
+              }
+              while (pos > 0 && lessp(d2, r, d2s[(pos - 1) * 64 + lane], rks[(pos - 1) * 64 + lane])) {
+                d2s[pos * 64 + lane] = d2s[(pos - 1) * 64 + lane];
+                rks[pos * 64 + lane] = rks[(pos - 1) * 64 + lane];
+                --pos;
+              }
+              d2s[pos * 64 + lane] = d2;
+              rks[pos * 64 + lane] = r;
+              if (cnt == K) {
+                wd2 = d2s[(K - 1) * 64 + lane];
+                wrk = rks[(K - 1) * 64 + lane];
+              }
             }
-            int pos;
-            if (cnt < K) {
-              pos = cnt++;
-            } else {
-              if (!lessp(d2, r, d2s[(K - 1) * 64 + lane], rks[(K - 1) * 64 + lane])) continue;
-              pos = K - 1;
-            }
-            while (pos > 0 && lessp(d2, r, d2s[(pos - 1) * 64 + lane], rks[(pos - 1) * 64 + lane])) {
-              d2s[pos * 64 + lane] = d2s[(pos - 1) * 64 + lane];
-              rks[pos * 64 + lane] = rks[(pos - 1) * 64 + lane];
-              --pos;
-            }
-            d2s[pos * 64 + lane] = d2;
-            rks[pos * 64 + lane] = r;
           }
         }
         if (R == 0) break;
@@ -165,12 +194,12 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
     }
     if (cnt == K && R >= 1) {
       const double bound = (double)R * cw;
-      if (d2s[(K - 1) * 64 + lane] < bound * bound * (1.0 - 1e-12)) break;
+      if (wd2 < bound * bound * (1.0 - 1e-12)) break;
     }
   }
   cnt_out[p] = cnt;
   for (int s = 0; s < m; ++s)
-    nbr[(int64_t)s * n + p] = s < cnt ? pos_of_rank[rks[s * 64 + lane]] : -1;
+    nbr[(int64_t)p * m + s] = s < cnt ? pos_of_rank[rks[s * 64 + lane]] : -1;
 }
 
 // ---------------------------------------------------------------- Matern
@@ -216,6 +245,44 @@ __device__ void bessel_k01(double x, double &K0, double &K1) {
   }
 }
 
+// Power-series coefficients for q = x^2/4 <= 1 (x <= 2), kSerTerms each:
+// ser[0][k] = 1/(k!)^2,                     I0(x) = sum ser0 q^k
+// ser[1][k] = H_k/(k!)^2,                   K0 = -(log(x/2)+gamma) I0 + sum ser1 q^k
+// ser[2][k] = 1/(k!(k+1)!),                 I1(x) = (x/2) sum ser2 q^k
+// ser[3][k] = (2H_k + 1/(k+1) - 2 gamma)/(k!(k+1)!),
+//                                           x K1 = 1 + 2q log(x/2) I1s - q sum ser3 q^k
+// (H_k the harmonic numbers; the logarithmic series of K0 and K1).
+constexpr int kSerTerms = 16;
+
+__device__ __forceinline__ double horner(const double *c, double q) {
+  double v = c[kSerTerms - 1];
+#pragma unroll
+  for (int k = kSerTerms - 2; k >= 0; --k) v = fma(v, q, c[k]);
+  return v;
+}
+
+// normalised Matern correlation for the factor kernel: division-free series
+// and the table-driven logarithm for x <= 2, the trapezoid rule beyond.
+__device__ double matern_fast(int nu2, double x, const double *__restrict__ ser,
+                              const double *__restrict__ logtab) {
+  if (x == 0.0) return 1.0;
+  if (nu2 == 1) return exp(-x);
+  if (nu2 == 3) return (1.0 + x) * exp(-x);
+  if (nu2 == 5) return (1.0 + x + x * x * (1.0 / 3.0)) * exp(-x);
+  if (x > 2.0) {
+    double K0, K1;
+    bessel_k01(x, K0, K1);
+    return nu2 == 2 ? x * K1 : 0.5 * x * x * K0 + x * K1;
+  }
+  const double q = 0.25 * x * x;
+  const double lg = tang_log(0.5 * x, logtab);
+  const double xk1 = 1.0 + 2.0 * q * lg * horner(ser + 2 * kSerTerms, q) -
+                     q * horner(ser + 3 * kSerTerms, q);
+  if (nu2 == 2) return xk1;
+  const double k0 = -(lg + kEuler) * horner(ser, q) + horner(ser + kSerTerms, q);
+  return 2.0 * q * k0 + xk1;
+}
+
 // normalised Matern correlation, value 1 at x = 0; nu2 = 2*nu in {1,2,3,4,5}
 __device__ double matern(int nu2, double x) {
   if (x == 0.0) return 1.0;
@@ -242,26 +309,33 @@ __device__ __forceinline__ double bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// (a, b), b <= a, of the e-th entry of a lower triangle enumerated row by row
+__device__ __forceinline__ void tri_index(int e, int &a, int &b) {
+  a = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+  while (a * (a + 1) / 2 > e) --a;
+  while ((a + 1) * (a + 2) / 2 <= e) ++a;
+  b = e - a * (a + 1) / 2;
+}
+
 // One wavefront per node: Cholesky of the Matern block of sigma(j) u {j}
-// (node last).  The block is formed in LDS with its entries spread evenly
-// over the lanes; then lane r holds row r in registers and the factorisation
-// broadcasts column entries with readlane.  Row |sigma| of the factor is
-// (L_s^{-1} k, c); lambda = L_s^{-T} L_s^{-1} k by a back substitution whose
-// sums are wave reductions in a fixed order.
+// (node last), right-looking in LDS with every step's trailing update spread
+// over all 64 lanes.  Row |sigma| of the factor is (L_s^{-1} k, c), and
+// lambda = L_s^{-T} (L_s^{-1} k) by a column-oriented back substitution.
 template <int MM>
 __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y, int64_t n,
                                                int m, const int32_t *nbr, const int32_t *cnt,
                                                int nu2, double alpha, double *coef,
-                                               double *dinv, int32_t *nfail) {
+                                               double *dinv, int32_t *nfail,
+                                               const double *ser, const double *logtab) {
   constexpr int LD = MM + 1;
   __shared__ double C[MM * LD];
-  __shared__ double px[MM], py[MM];
+  __shared__ double px[MM], py[MM], vv[MM];
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
-  const int K = __builtin_amdgcn_readfirstlane(cnt[p]);
+  const int K = cnt[p];
   const int N1 = K + 1;
   for (int a = lane; a < K; a += 64) {
-    const int q = nbr[(int64_t)a * n + p];
+    const int q = nbr[(int64_t)p * m + a];
     px[a] = x[q];
     py[a] = y[q];
   }
@@ -270,49 +344,44 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
     py[K] = y[p];
   }
   __syncthreads();
-  for (int e = lane; e < N1 * N1; e += 64) {
-    const int a = e / N1, b = e % N1;
-    if (b <= a) {
-      const double dx = px[a] - px[b], dy = py[a] - py[b];
-      C[a * LD + b] = matern(nu2, alpha * sqrt(dx * dx + dy * dy));
-    }
-  }
-  __syncthreads();
-  double nug = 0.0;
-  double a[MM];
+  const int ntri = N1 * (N1 + 1) / 2;
   bool ok = false;
+  double nug = 0.0;
   for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
-    // load row `lane` (lower triangle), identity beyond the block
-#pragma unroll
-    for (int s2 = 0; s2 < MM; ++s2) {
-      double v = 0.0;
-      if (lane < N1 && s2 <= lane) v = C[lane * LD + s2] + (s2 == lane ? nug : 0.0);
-      else if (s2 == lane) v = 1.0;
-      a[s2] = v;
-    }
-    ok = true;
-#pragma unroll
-    for (int c = 0; c < MM; ++c) {
-      if (c < N1) {
-        const double piv = bcast(a[c], c);
-        if (!(piv > 0.0)) {
-          ok = false;
-          break;
-        }
-        const double d = sqrt(piv);
-        const double inv = 1.0 / d;
-        if (lane == c) a[c] = d;
-        if (lane > c) a[c] *= inv;
-        const double lrc = a[c];
-#pragma unroll
-        for (int s2 = c + 1; s2 < MM; ++s2) {
-          if (s2 < N1) {
-            const double lsc = bcast(a[c], s2);
-            if (lane >= s2) a[s2] = fma(-lrc, lsc, a[s2]);
-          }
-        }
+    for (int e = lane; e < ntri; e += 64) {
+      int a, b;
+      tri_index(e, a, b);
+      double v = 1.0 + nug;
+      if (b != a) {
+        const double dx = px[a] - px[b], dy = py[a] - py[b];
+        v = matern_fast(nu2, alpha * sqrt(dx * dx + dy * dy), ser, logtab);
       }
+      C[a * LD + b] = v;
     }
+    __syncthreads();
+    ok = true;
+    for (int c = 0; c < N1; ++c) {
+      const double dg = C[c * LD + c];
+      if (!(dg > 0.0)) {
+        ok = false;
+        break;
+      }
+      const double d = sqrt(dg);
+      const double inv = 1.0 / d;
+      for (int r = c + 1 + lane; r < N1; r += 64) C[r * LD + c] *= inv;
+      __syncthreads();
+      if (lane == 0) C[c * LD + c] = d;
+      const int Mp = N1 - c - 1;
+      const int np = Mp * (Mp + 1) / 2;
+      for (int e = lane; e < np; e += 64) {
+        int a, b;
+        tri_index(e, a, b);
+        const int r = c + 1 + a, s2 = c + 1 + b;
+        C[r * LD + s2] = fma(-C[r * LD + c], C[s2 * LD + c], C[r * LD + s2]);
+      }
+      __syncthreads();
+    }
+    __syncthreads();
     if (!ok) {
       nug = (attempt == 0) ? 1e-12 : nug * 100.0;
       if (lane == 0 && attempt == 0) atomicAdd(&nfail[0], 1);
@@ -322,42 +391,30 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
     if (lane == 0) atomicAdd(&nfail[1], 1);
     return;
   }
-  // u = row K (L_s^{-1} k), c = L[K][K]; lane i keeps u_i
-  double u_i = 0.0, cc = 1.0, lii = 1.0;
-#pragma unroll
-  for (int i = 0; i < MM; ++i) {
-    if (i < K) {
-      const double v = bcast(a[i], K);
-      if (lane == i) u_i = v;
-    }
-    if (i == K) cc = bcast(a[i], K);
-    if (lane == i) lii = a[i];
-  }
-  // back substitution: lambda_i = (u_i - sum_{l>i} L[l][i] lambda_l) / L[i][i]
-  double lam = 0.0;  // lambda of this lane's index
-#pragma unroll
-  for (int i = MM - 1; i >= 0; --i) {
-    if (i < K) {
-      double t = (lane > i && lane < K) ? a[i] * lam : 0.0;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-      if (lane == i) lam = (u_i - t) / lii;
-    }
+  for (int a = lane; a < K; a += 64) vv[a] = C[K * LD + a];
+  const double cc = C[K * LD + K];
+  __syncthreads();
+  // column-oriented back substitution with L_s^T (one wavefront: the reads of
+  // vv[i] precede lane 0's write in program order)
+  for (int i = K - 1; i >= 0; --i) {
+    const double li = vv[i] / C[i * LD + i];
+    for (int l = lane; l < i; l += 64) vv[l] = fma(-C[i * LD + l], li, vv[l]);
+    if (lane == 0) vv[i] = li;
+    __syncthreads();
   }
   const double inv_c = 1.0 / cc;
-  if (lane < m) coef[(int64_t)lane * n + p] = lane < K ? -lam * inv_c : 0.0;
+  for (int a = lane; a < m; a += 64) coef[(int64_t)p * m + a] = a < K ? -vv[a] * inv_c : 0.0;
   if (lane == 0) dinv[p] = inv_c;
 }
 
 // ---------------------------------------------------------------- transpose
-// Row-major enumeration e = j*m + s of the factor's entries, keyed by the row
-// q = nbr[s][j]; a stable sort by q then lists each row's entries by
-// ascending column j (each (q, j) pair occurs once).
+// Node-major entries e = j*m + s of the factor, keyed by the row q = nbr[j][s];
+// a stable sort by q then lists each row's entries by ascending column j
+// (each (q, j) pair occurs once).
 __global__ void k_tkeys(const int32_t *nbr, int64_t n, int m, uint32_t *keys, int32_t *vals) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n * m) return;
-  const int64_t j = e / m, s = e % m;
-  const int q = nbr[s * n + j];
+  const int q = nbr[e];
   keys[e] = q < 0 ? (uint32_t)n : (uint32_t)q;
   vals[e] = (int32_t)e;
 }
@@ -367,23 +424,27 @@ __global__ void k_tfill(const int32_t *vals, int64_t nnz, int64_t n, int m, cons
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= nnz) return;
   const int64_t e = vals[p];
-  const int64_t j = e / m, s = e % m;
-  tidx[p] = (int32_t)j;
-  tcoef[p] = coef[s * n + j];
+  tidx[p] = (int32_t)(e / m);
+  tcoef[p] = coef[e];
 }
 
 // ---------------------------------------------------------------- apply
-__global__ void k_apply_ut(const double *r, int64_t n, int m, const int32_t *nbr,
-                           const double *coef, const double *dinv, double *yv) {
-  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// y = U~^T r: row j of U~^T holds 1/c_j at j and -lambda/c_j at sigma(j);
+// 32 lanes per row read the node-major entries coalesced.
+__global__ __launch_bounds__(256) void k_apply_ut(const double *r, int64_t n, int m,
+                                                  const int32_t *nbr, const double *coef,
+                                                  const double *dinv, double *yv) {
+  const int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 5;
+  const int g = threadIdx.x & 31;
   if (j >= n) return;
-  double acc = dinv[j] * r[j];
-  for (int s = 0; s < m; ++s) {
-    const int q = nbr[(int64_t)s * n + j];
-    if (q < 0) break;
-    acc += coef[(int64_t)s * n + j] * r[q];
+  double acc = 0.0;
+  for (int s2 = g; s2 < m; s2 += 32) {
+    const int q = nbr[j * m + s2];
+    if (q >= 0) acc += coef[j * m + s2] * r[q];
   }
-  yv[j] = acc;
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+  if (g == 0) yv[j] = dinv[j] * r[j] + acc;
 }
 
 // Row gather of the transposed factor, 32 lanes per row: lanes stride over the
@@ -413,9 +474,9 @@ __global__ void k_export(int64_t n, int m, const int32_t *order, const int32_t *
   rank_u[u] = rank_tree[p];
   diag_u[u] = dinv[p];
   for (int s = 0; s < m; ++s) {
-    const int q = nbr[(int64_t)s * n + p];
+    const int q = nbr[(int64_t)p * m + s];
     nbr_u[(int64_t)u * m + s] = q >= 0 ? order[q] : -1;
-    coef_u[(int64_t)u * m + s] = coef[(int64_t)s * n + p];
+    coef_u[(int64_t)u * m + s] = coef[(int64_t)p * m + s];
   }
 }
 
@@ -508,6 +569,9 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
                k_grid_keys<<<(total + B - 1) / B, B, 0, s>>>(xr, yr, T, d_lvl, d_gb, h, total,
                                                             gk, gv));
     radix_sort_u32(gk, gv, total, 25, gkt, gvt, scr, s);
+    double2 *gxy = dmalloc<double2>(total);
+    PHS_LAUNCH("vecchia_grid_coords", s,
+               k_grid_coords<<<(total + B - 1) / B, B, 0, s>>>(gv, xr, yr, total, gxy));
     PHS_LAUNCH("vecchia_cell_start", s,
                k_cell_start<<<(ncells + B - 1) / B, B, 0, s>>>(gk, total, T, d_gb, d_coff,
                                                               ncells, cstart));
@@ -515,7 +579,27 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     pl.pc_nbr = dmalloc<int32_t>((size_t)n * m);
     PHS_LAUNCH("vecchia_knn", s,
                k_knn<<<(n + 63) / 64, 64, 0, s>>>(xr, yr, n, m, T, h, d_gb, d_coff, cstart, gv,
-                                                  pos_of_rank, pl.pc_nbr, cnt));
+                                                  gxy, pos_of_rank, pl.pc_nbr, cnt));
+    dfree(gxy);
+    // series coefficients of the Bessel functions (host, exact rationals in FP64)
+    double *ser = dmalloc<double>(4 * kSerTerms);
+    {
+      std::vector<double> hs(4 * kSerTerms);
+      double fk = 1.0, fk1 = 1.0, H = 0.0;  // k!, (k+1)!, H_k
+      for (int k = 0; k < kSerTerms; ++k) {
+        if (k > 0) {
+          fk *= k;
+          H += 1.0 / k;
+        }
+        fk1 = fk * (k + 1);
+        hs[k] = 1.0 / (fk * fk);
+        hs[kSerTerms + k] = H / (fk * fk);
+        hs[2 * kSerTerms + k] = 1.0 / (fk * fk1);
+        hs[3 * kSerTerms + k] = (2.0 * H + 1.0 / (k + 1) - 2.0 * kEuler) / (fk * fk1);
+      }
+      PHS_HIP(hipMemcpyAsync(ser, hs.data(), hs.size() * 8, hipMemcpyHostToDevice, s));
+      PHS_HIP(hipStreamSynchronize(s));
+    }
     // 4. factor
     pl.pc_coef = dmalloc<double>((size_t)n * m);
     pl.pc_dinv = dmalloc<double>(n);
@@ -523,11 +607,13 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     if (m <= 31)
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<32><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
-                                              pl.pc_coef, pl.pc_dinv, nfail));
+                                              pl.pc_coef, pl.pc_dinv, nfail, ser, pl.logtab));
     else
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
-                                                 alpha, pl.pc_coef, pl.pc_dinv, nfail));
+                                                 alpha, pl.pc_coef, pl.pc_dinv, nfail, ser,
+                                                 pl.logtab));
+    dfree(ser);
     // 5. transpose: stable radix sort of the entries by row
     {
       const int64_t N = n * m;
@@ -579,8 +665,8 @@ void vecchia_apply(Plan &pl, const double *r, double *z, double *tmp, hipStream_
   const int64_t n = pl.n;
   const int B = 256;
   PHS_LAUNCH("precond_ut", s,
-             k_apply_ut<<<(n + B - 1) / B, B, 0, s>>>(r, n, pl.m, pl.pc_nbr, pl.pc_coef,
-                                                     pl.pc_dinv, tmp));
+             k_apply_ut<<<(n * 32 + B - 1) / B, B, 0, s>>>(r, n, pl.m, pl.pc_nbr, pl.pc_coef,
+                                                          pl.pc_dinv, tmp));
   PHS_LAUNCH("precond_u", s,
              k_apply_u<<<(n * 32 + B - 1) / B, B, 0, s>>>(tmp, n, pl.pc_tstart, pl.pc_tidx,
                                                          pl.pc_tcoef, pl.pc_dinv, z));
