@@ -114,6 +114,8 @@ Plan::~Plan() {
   free_log_tables(lt32);
   free_cheb_tables(ct64);
   free_cheb_tables(ct32);
+  free_log_tables(lte);
+  free_cheb_tables(cte);
   dfree(v_t);
   dfree(v_y);
   for (auto &p : wk) dfree(p);
@@ -316,12 +318,14 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     pl.p32 = order_for_tol(tol, false);
     PHS_REQUIRE(pl.p64 >= 4 && pl.p64 <= 63, PHS_ERR_INVALID_ARGUMENT,
                 "expansion order must be 4..63");
+    pl.pe = std::max(pl.p64, 31);
   } else {
     // Chebyshev nodes per axis: 12 -> ~6e-12, 16 -> ~1e-14 core relative error
     pl.q64 = o->expansion_order > 0 ? o->expansion_order : (tol >= 1e-13 ? 12 : 16);
     pl.q32 = 8;
     PHS_REQUIRE(pl.q64 == 8 || pl.q64 == 10 || pl.q64 == 12 || pl.q64 == 14 || pl.q64 == 16,
                 PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16");
+    pl.qe = 16;
   }
   // scratch used by the bounding box, reductions and scalars
   pl.red_cap = dot_blocks(n) * 32 + 4096;
@@ -359,13 +363,17 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
   if (pl.core_log) {
     build_log_tables(pl.lt64, pl.p64);
     build_log_tables(pl.lt32, pl.p32);
-    eb = std::max(log_expansion_bytes(pl.tree.L, pl.p64, pl.R, true),
-                  log_expansion_bytes(pl.tree.L, pl.p32, pl.R, false));
+    if (pl.pe != pl.p64) build_log_tables(pl.lte, pl.pe);
+    eb = std::max({log_expansion_bytes(pl.tree.L, pl.p64, pl.R, true),
+                   log_expansion_bytes(pl.tree.L, pl.pe, pl.R, true),
+                   log_expansion_bytes(pl.tree.L, pl.p32, pl.R, false)});
   } else {
     build_cheb_tables(pl.ct64, pl.q64);
     build_cheb_tables(pl.ct32, pl.q32);
-    eb = std::max(cheb_expansion_bytes(pl.tree.L, pl.q64, pl.R, true),
-                  cheb_expansion_bytes(pl.tree.L, pl.q32, pl.R, false));
+    if (pl.qe != pl.q64) build_cheb_tables(pl.cte, pl.qe);
+    eb = std::max({cheb_expansion_bytes(pl.tree.L, pl.q64, pl.R, true),
+                   cheb_expansion_bytes(pl.tree.L, pl.qe, pl.R, true),
+                   cheb_expansion_bytes(pl.tree.L, pl.q32, pl.R, false)});
   }
   pl.exp_bytes = eb;
   {

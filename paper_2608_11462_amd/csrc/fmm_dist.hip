@@ -524,10 +524,9 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
 
 // ---------------------------------------------------------------- host
 template <class T, int Q>
-void far_field_q(Plan &pl, const double *t, hipStream_t s) {
+void far_field_q(Plan &pl, const double *t, const ChebTables &ct, hipStream_t s) {
   constexpr int QQ = Q * Q;
   const bool fp64 = std::is_same<T, double>::value;
-  const ChebTables &ct = fp64 ? pl.ct64 : pl.ct32;
   const T *Tk = fp64 ? (const T *)ct.nodes64 + Q : (const T *)ct.nodes32 + Q;
   const T *Tpm = fp64 ? (const T *)ct.S2c64 : (const T *)ct.S2c32;
   const T *Kd = fp64 ? (const T *)ct.K64 : (const T *)ct.K32;
@@ -580,28 +579,30 @@ void leaf_q(Plan &pl, const double *t, double *yt, double *yu, hipStream_t s) {
         pl.order, pl.xy2, pl.logtab));
 }
 
+// One far-field pass (and, with `leaf`, the leaf pass) at Q nodes per axis;
+// `ct` holds the tables of that Q.
 template <class T, class TN>
-void run_q(Plan &pl, const double *t, double *yt, double *yu, bool leaf, hipStream_t s) {
-  const int Q = std::is_same<T, double>::value ? pl.q64 : pl.q32;
+void run_q(Plan &pl, const double *t, double *yt, double *yu, bool leaf, int Q,
+           const ChebTables &ct, hipStream_t s) {
   switch (Q) {
     case 8:
-      far_field_q<T, 8>(pl, t, s);
+      far_field_q<T, 8>(pl, t, ct, s);
       if (leaf) leaf_q<T, TN, 8>(pl, t, yt, yu, s);
       break;
     case 10:
-      far_field_q<T, 10>(pl, t, s);
+      far_field_q<T, 10>(pl, t, ct, s);
       if (leaf) leaf_q<T, TN, 10>(pl, t, yt, yu, s);
       break;
     case 12:
-      far_field_q<T, 12>(pl, t, s);
+      far_field_q<T, 12>(pl, t, ct, s);
       if (leaf) leaf_q<T, TN, 12>(pl, t, yt, yu, s);
       break;
     case 14:
-      far_field_q<T, 14>(pl, t, s);
+      far_field_q<T, 14>(pl, t, ct, s);
       if (leaf) leaf_q<T, TN, 14>(pl, t, yt, yu, s);
       break;
     case 16:
-      far_field_q<T, 16>(pl, t, s);
+      far_field_q<T, 16>(pl, t, ct, s);
       if (leaf) leaf_q<T, TN, 16>(pl, t, yt, yu, s);
       break;
     default:
@@ -614,18 +615,19 @@ void eval_q(Plan &pl, const double *w_tree, const double *beta, const double *ta
             int64_t m, double *out, hipStream_t s) {
   constexpr int QQ = Q * Q;
   const int L = pl.tree.L;
-  const double *Tk = pl.ct64.nodes64 + Q;
+  const ChebTables &ct = pl.qe == pl.q64 ? pl.ct64 : pl.cte;
+  const double *Tk = ct.nodes64 + Q;
   const double *W = (const double *)pl.mp;
   const double *GL = (const double *)pl.loc + cheb_level_base(L, QQ, pl.R);
   const int64_t nb = (m + 127) / 128;
   if (pl.k == 1)
     PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<1, Q><<<nb, 128, 0, s>>>(
         targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
-        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
+        pl.tree.h, Tk, ct.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
   else
     PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<3, Q><<<nb, 128, 0, s>>>(
         targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
-        pl.tree.h, Tk, pl.ct64.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
+        pl.tree.h, Tk, ct.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
 }
 
 std::vector<double> cheb_nodes(int Q) {
@@ -711,18 +713,22 @@ size_t cheb_expansion_bytes(int L, int Q, int nd, bool fp64) {
 
 void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, int precision,
                  hipStream_t s) {
-  if (precision == PHS_MIXED) run_q<float, float>(pl, t_tree, y_tree, y_user, true, s);
-  else if (precision == PHS_NEAR32) run_q<double, float>(pl, t_tree, y_tree, y_user, true, s);
-  else run_q<double, double>(pl, t_tree, y_tree, y_user, true, s);
+  if (precision == PHS_MIXED)
+    run_q<float, float>(pl, t_tree, y_tree, y_user, true, pl.q32, pl.ct32, s);
+  else if (precision == PHS_NEAR32)
+    run_q<double, float>(pl, t_tree, y_tree, y_user, true, pl.q64, pl.ct64, s);
+  else
+    run_q<double, double>(pl, t_tree, y_tree, y_user, true, pl.q64, pl.ct64, s);
 }
 
 void dist_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
-  run_q<double, double>(pl, w_tree, nullptr, nullptr, false, s);
+  run_q<double, double>(pl, w_tree, nullptr, nullptr, false, pl.qe,
+                        pl.qe == pl.q64 ? pl.ct64 : pl.cte, s);
 }
 
 void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                        const double *targets, int64_t m, double *out, hipStream_t s) {
-  switch (pl.q64) {
+  switch (pl.qe) {
     case 8: eval_q<8>(pl, w_tree, beta, targets, m, out, s); break;
     case 10: eval_q<10>(pl, w_tree, beta, targets, m, out, s); break;
     case 12: eval_q<12>(pl, w_tree, beta, targets, m, out, s); break;

@@ -414,11 +414,10 @@ double binom(int n, int k) {
   return r;
 }
 
+// Upward pass, M2L and downward pass at order P with the tables of that order.
 template <class T>
-void far_field(Plan &pl, const double *t, hipStream_t s) {
+void far_field(Plan &pl, const double *t, int P, const LogTables &lt, hipStream_t s) {
   const bool fp64 = std::is_same<T, double>::value;
-  const int P = fp64 ? pl.p64 : pl.p32;
-  const LogTables &lt = fp64 ? pl.lt64 : pl.lt32;
   const int nd = pl.R, L = pl.tree.L;
   const double h = pl.tree.h;
   V2<T> *A = (V2<T> *)pl.mp;
@@ -604,22 +603,22 @@ size_t log_expansion_bytes(int L, int P, int nd, bool fp64) {
 void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, int precision,
                 hipStream_t s) {
   if (precision == PHS_MIXED) {
-    far_field<float>(pl, t_tree, s);
+    far_field<float>(pl, t_tree, pl.p32, pl.lt32, s);
     leaf_pass<float, float>(pl, t_tree, y_tree, y_user, s);
   } else {
-    far_field<double>(pl, t_tree, s);
+    far_field<double>(pl, t_tree, pl.p64, pl.lt64, s);
     if (precision == PHS_NEAR32) leaf_pass<double, float>(pl, t_tree, y_tree, y_user, s);
     else leaf_pass<double, double>(pl, t_tree, y_tree, y_user, s);
   }
 }
 
 void log_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
-  far_field<double>(pl, w_tree, s);
+  far_field<double>(pl, w_tree, pl.pe, pl.pe == pl.p64 ? pl.lt64 : pl.lte, s);
 }
 
 void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                       const double *targets, int64_t m, double *out, hipStream_t s) {
-  const int P = pl.p64, L = pl.tree.L;
+  const int P = pl.pe, L = pl.tree.L;
   const double2 *A = (const double2 *)pl.mp;
   const double2 *BL = (const double2 *)pl.loc + level_base(L, P, pl.R);
   const int64_t nb = (m + 127) / 128;

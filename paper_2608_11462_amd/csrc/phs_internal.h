@@ -140,6 +140,9 @@ struct Plan {
   Tree tree;
   int p64 = 31, p32 = 15;  // log expansion order (terms beyond the constant)
   int q64 = 16, q32 = 10;  // Chebyshev nodes per axis (distance kernel)
+  // FP64 orders of the expansions that serve target evaluation (>= the
+  // matvec orders; evaluation runs once per solve, so it takes the tighter one)
+  int pe = 31, qe = 16;
 
   // tree-order node data
   int32_t *order = nullptr;    // tree position -> caller index
@@ -160,6 +163,8 @@ struct Plan {
   size_t exp_bytes = 0;
   LogTables lt64, lt32;  // tables for p64 (FP64) and p32 (FP32)
   ChebTables ct64, ct32;
+  LogTables lte;         // tables for pe when pe != p64
+  ChebTables cte;        // tables for qe when qe != q64
 
   // vectors (tree order), n each
   double *v_t = nullptr;    // density in tree order

@@ -7,11 +7,11 @@
   alpha = 0.35 (the benchmark configuration).
 Gates: matvec 1e-10 relative on sampled rows (FP64); node residual
 RMS(f - M w - B beta)/RMS(f) <= 1e-8 on sampled nodes after a 1e-8 solve;
-evaluation at sampled targets (4096 in the FP64 benchmark case) <= 1e-9
-relative to direct summation with the same (w, beta), ten times inside the
-1e-8 interpolant bar.  The interpolant is a sum of large alternating
-w_j phi terms, so an FMM error of ~2e-14 relative to sum |w_j phi| shows up
-as ~1e-10 relative to max |s|.
+evaluation at sampled targets (4096 in the FP64 benchmark case) <= 1e-10
+relative to direct summation with the same (w, beta).  The interpolant is a
+sum of large alternating w_j phi terms (an FMM error of ~2e-14 relative to
+sum |w_j phi| shows up as ~1e-10 relative to max |s|), which is why target
+evaluation uses the tighter FP64 expansion order of the plan.
 """
 import numpy as np
 import pytest
@@ -53,7 +53,7 @@ def _run(pr, m, nu, rows, ntg, precision=N.PHS_FP64):
     assert e_mv <= 1e-10
     assert info.rel_residual <= 1e-8
     assert e_res <= 1e-8
-    assert e_ev <= 1e-9
+    assert e_ev <= 1e-10
     return info
 
 
