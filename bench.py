@@ -86,8 +86,10 @@ def tree_work(order_leaf: np.ndarray, L: int, n: int):
 
 
 def source_sha(name: str) -> str:
+    """Hash of a kernel source file and the headers every kernel includes."""
     h = hashlib.sha256()
-    h.update((ROOT / "paper_2608_11462_amd" / "csrc" / name).read_bytes())
+    for f in (name, "fmm_common.h", "phs_internal.h"):
+        h.update((ROOT / "paper_2608_11462_amd" / "csrc" / f).read_bytes())
     return h.hexdigest()[:16]
 
 
@@ -103,7 +105,7 @@ def stored_traffic(kernel: str, workload: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(seed: int = 3, n_s: int = 4096, n_t: int = 10000):
+def cpu_baseline(seed: int = 3, n_s: int = 6144, n_t: int = 10000):
     """The CPU oracle (dense FP64 complement solve + evaluation) on a bounded
     sample of the same workload: n_s nodes of the same distribution and field."""
     from oracle import phs_dense as D
@@ -216,16 +218,20 @@ def main():
         leaf = last["leaf"].cpu().numpy()
         pairs, m2l_pairs = tree_work(leaf, last["L"], n)
         P, R, m = last["P"], last["R"], 30
-        far32 = prec == N.PHS_MIXED
-        near32 = prec in (N.PHS_MIXED, N.PHS_NEAR32)
-        Pf = 15 if far32 else P
+        P32 = 15  # FP32 expansion order of the plan
         nnz = n * m - m * (m + 1) // 2
         models = {
             # kernel: (work per launch, unit, peak, bound)
-            "leaf_eval": (pairs * FLOP_PAIR + n * R * (8 * Pf + 2), "TFLOP/s",
-                          FP32_PEAK_TFLOPS if near32 else FP64_PEAK_TFLOPS, "alu"),
-            "m2l": (m2l_pairs * R * (4 * (Pf + 1) ** 2 + 12 * (Pf + 1)), "TFLOP/s",
-                    FP32_PEAK_TFLOPS if far32 else FP64_PEAK_TFLOPS, "alu"),
+            "leaf_eval": (pairs * FLOP_PAIR + n * R * (8 * P + 2), "TFLOP/s",
+                          FP64_PEAK_TFLOPS, "alu"),
+            "leaf_eval_near32": (pairs * FLOP_PAIR + n * R * (8 * P + 2), "TFLOP/s",
+                                 FP32_PEAK_TFLOPS, "alu"),
+            "leaf_eval_f32": (pairs * FLOP_PAIR + n * R * (8 * P32 + 2), "TFLOP/s",
+                              FP32_PEAK_TFLOPS, "alu"),
+            "m2l": (m2l_pairs * R * (4 * (P + 1) ** 2 + 12 * (P + 1)), "TFLOP/s",
+                    FP64_PEAK_TFLOPS, "alu"),
+            "m2l_f32": (m2l_pairs * R * (4 * (P32 + 1) ** 2 + 12 * (P32 + 1)), "TFLOP/s",
+                        FP32_PEAK_TFLOPS, "alu"),
             "vecchia_factor": (n * (2 * (m + 1) ** 3 / 3 + 2 * m * m
                                     + 20 * (m + 1) * (m + 2) / 2), "TFLOP/s",
                                FP64_PEAK_TFLOPS, "alu"),

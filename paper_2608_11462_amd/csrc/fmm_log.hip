@@ -415,8 +415,10 @@ double binom(int n, int k) {
 }
 
 // Upward pass, M2L and downward pass at order P with the tables of that order.
+// `m2l_name` labels the M2L launch in the per-kernel timing.
 template <class T>
-void far_field(Plan &pl, const double *t, int P, const LogTables &lt, hipStream_t s) {
+void far_field(Plan &pl, const double *t, int P, const LogTables &lt, const char *m2l_name,
+               hipStream_t s) {
   const bool fp64 = std::is_same<T, double>::value;
   const int nd = pl.R, L = pl.tree.L;
   const double h = pl.tree.h;
@@ -462,16 +464,16 @@ void far_field(Plan &pl, const double *t, int P, const LogTables &lt, hipStream_
     const unsigned nblk = (unsigned)(ntiles * nchunks * nd);
     switch (lch) {
     case 16:
-      PHS_LAUNCH("m2l", s, k_m2l<T, 16><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      PHS_LAUNCH(m2l_name, s, k_m2l<T, 16><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
       break;
     case 14:
-      PHS_LAUNCH("m2l", s, k_m2l<T, 14><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      PHS_LAUNCH(m2l_name, s, k_m2l<T, 14><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
       break;
     case 12:
-      PHS_LAUNCH("m2l", s, k_m2l<T, 12><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      PHS_LAUNCH(m2l_name, s, k_m2l<T, 12><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
       break;
     default:
-      PHS_LAUNCH("m2l", s, k_m2l<T, 8><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
+      PHS_LAUNCH(m2l_name, s, k_m2l<T, 8><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
       break;
     }
   }
@@ -492,14 +494,17 @@ void leaf_pass(Plan &pl, const double *t, double *y_tree, double *y_user, hipStr
   const int L = pl.tree.L;
   const V2<T> *BL = (const V2<T> *)pl.loc + level_base(L, P, pl.R);
   const int64_t nleaf = boxes_at(L);
+  const char *name = std::is_same<T, float>::value    ? "leaf_eval_f32"
+                     : std::is_same<TN, float>::value ? "leaf_eval_near32"
+                                                      : "leaf_eval";
   if (pl.k == 2)
-    PHS_LAUNCH("leaf_eval", s,
+    PHS_LAUNCH(name, s,
                k_leaf_eval<T, TN, 2><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
                                                       pl.tree.leaf_start, L, pl.tree.h, P,
                                                       BL, y_tree, y_user, pl.order, pl.xy2,
                                                       pl.logtab));
   else
-    PHS_LAUNCH("leaf_eval", s,
+    PHS_LAUNCH(name, s,
                k_leaf_eval<T, TN, 4><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
                                                       pl.tree.leaf_start, L, pl.tree.h, P,
                                                       BL, y_tree, y_user, pl.order, pl.xy2,
@@ -603,17 +608,17 @@ size_t log_expansion_bytes(int L, int P, int nd, bool fp64) {
 void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, int precision,
                 hipStream_t s) {
   if (precision == PHS_MIXED) {
-    far_field<float>(pl, t_tree, pl.p32, pl.lt32, s);
+    far_field<float>(pl, t_tree, pl.p32, pl.lt32, "m2l_f32", s);
     leaf_pass<float, float>(pl, t_tree, y_tree, y_user, s);
   } else {
-    far_field<double>(pl, t_tree, pl.p64, pl.lt64, s);
+    far_field<double>(pl, t_tree, pl.p64, pl.lt64, "m2l", s);
     if (precision == PHS_NEAR32) leaf_pass<double, float>(pl, t_tree, y_tree, y_user, s);
     else leaf_pass<double, double>(pl, t_tree, y_tree, y_user, s);
   }
 }
 
 void log_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
-  far_field<double>(pl, w_tree, pl.pe, pl.pe == pl.p64 ? pl.lt64 : pl.lte, s);
+  far_field<double>(pl, w_tree, pl.pe, pl.pe == pl.p64 ? pl.lt64 : pl.lte, "m2l_eval", s);
 }
 
 void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,

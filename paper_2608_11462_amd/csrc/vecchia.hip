@@ -111,8 +111,9 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
                                             const double2 *__restrict__ gxy,
                                             const int32_t *pos_of_rank, int32_t *nbr,
                                             int32_t *cnt_out) {
-  __shared__ double d2s[64 * 64];
-  __shared__ int rks[64 * 64];
+  // per-lane candidate lists, m entries each (dynamic LDS: 64 m (8 + 4) bytes)
+  extern __shared__ double d2s[];
+  int *rks = (int *)(d2s + 64 * m);
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x * (int64_t)64 + lane;
   if (t >= n) return;
@@ -578,7 +579,8 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     // 3. ordered nearest predecessors
     pl.pc_nbr = dmalloc<int32_t>((size_t)n * m);
     PHS_LAUNCH("vecchia_knn", s,
-               k_knn<<<(n + 63) / 64, 64, 0, s>>>(xr, yr, n, m, T, h, d_gb, d_coff, cstart, gv,
+               k_knn<<<(n + 63) / 64, 64, (size_t)64 * m * 12, s>>>(xr, yr, n, m, T, h, d_gb,
+                                                                   d_coff, cstart, gv,
                                                   gxy, pos_of_rank, pl.pc_nbr, cnt));
     dfree(gxy);
     // series coefficients of the Bessel functions (host, exact rationals in FP64)
