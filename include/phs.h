@@ -178,6 +178,40 @@ phs_status phs_precond_apply(phs_plan_t plan, const double *r, double *z,
 
 void phs_plan_destroy(phs_plan_t plan);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent interpolation problems, and several right-hand sides per
+ * point set, solved together.  Each (plan, right-hand side) pair is one
+ * system with its own PCG vectors and FMM workspace; every step of the solve
+ * (each FMM stage, the preconditioner apply, each vector update and
+ * reduction) is one launch over all systems still iterating, and a system
+ * runs exactly the arithmetic it runs alone (results are bitwise equal to
+ * phs_solve on that plan).  Problems of different n, order k and polynomial
+ * degree can share a batch; all even-k plans must use the same expansion
+ * orders, and so must all odd-k plans (the default fmm_tol gives that). */
+typedef struct phs_batch_s *phs_batch_t;
+
+/* plans: host array of nplans plan handles, which must outlive the batch (a
+ * preconditioner built or rebuilt later is picked up by phs_batch_solve).
+ * nrhs: host array, right-hand sides per plan (>= 1).  Allocates the
+ * workspace of every system; synchronises `stream`.  Errors:
+ * INVALID_ARGUMENT (bad counts, mismatched expansion orders), OUT_OF_MEMORY. */
+phs_status phs_batch_create(const phs_plan_t *plans, int32_t nplans, const int32_t *nrhs,
+                            void *stream, phs_batch_t *out);
+
+/* Solve all problems: f[i], w[i] are device n_i x nrhs_i column-major arrays of
+ * plan i (caller order), beta[i] device S_i x nrhs_i; f, w, beta are host
+ * arrays of nplans device pointers.  opts as for phs_solve (its precision
+ * applies to every system; -1 takes the first plan's default).  info: host
+ * array of nplans (may be NULL), filled per plan as by phs_solve, t_solve
+ * being the whole batch's time.  Returns the first non-OK status of any
+ * system (others still hold their results).  Allocates nothing;
+ * synchronises `stream` once per PCG iteration. */
+phs_status phs_batch_solve(phs_batch_t batch, const double *const *f, double *const *w,
+                           double *const *beta, const phs_solve_opts *opts,
+                           phs_solve_info *info, void *stream);
+
+void phs_batch_destroy(phs_batch_t batch);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *phs_last_error(void);
 

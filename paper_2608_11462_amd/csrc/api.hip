@@ -97,6 +97,9 @@ void prof_end(hipStream_t s) {
 
 // ------------------------------------------------------------------ plan
 Plan::~Plan() {
+  delete self;
+  self = nullptr;
+  sw.release();
   dfree(order);
   dfree(inv_order);
   dfree(leafkey);
@@ -107,8 +110,6 @@ Plan::~Plan() {
   dfree(xy2);
   dfree(logtab);
   dfree(Q);
-  dfree(mp);
-  dfree(loc);
   dfree(tree.leaf_start);
   free_log_tables(lt64);
   free_log_tables(lt32);
@@ -116,9 +117,6 @@ Plan::~Plan() {
   free_cheb_tables(ct32);
   free_log_tables(lte);
   free_cheb_tables(cte);
-  dfree(v_t);
-  dfree(v_y);
-  for (auto &p : wk) dfree(p);
   dfree(red);
   dfree(scal);
   if (hscal) (void)hipHostFree(hscal);
@@ -382,112 +380,18 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     pl.logtab = dmalloc<double>(256);
     PHS_HIP(hipMemcpy(pl.logtab, tab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
   }
-  pl.mp = dmalloc<char>(eb);
-  pl.loc = dmalloc<char>(eb);
-  pl.v_t = dmalloc<double>(n);
-  pl.v_y = dmalloc<double>(n);
-  for (auto &p : pl.wk) p = dmalloc<double>(n);
+  alloc_syswork(pl.sw, pl);
+  pl.self = new Forest();
+  build_forest(*pl.self, {&pl}, {&pl.sw}, s);
   PHS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
 
-void matvec_tree(Plan &pl, const double *t_tree, double *y_tree, int precision,
-                 hipStream_t s) {
-  if (pl.core_log) log_matvec(pl, t_tree, y_tree, nullptr, precision, s);
-  else dist_matvec(pl, t_tree, y_tree, nullptr, precision, s);
-}
-
 namespace {
 
-// z = Pi U U^T r (or r without a preconditioner).  r is a residual of the
-// projected system and already lies in range(Pi); r is not modified.
-void precond_tree(Plan &pl, const double *r, double *z, double *tmp, hipStream_t s) {
-  (void)tmp;
-  if (pl.has_pc) {
-    vecchia_apply(pl, r, z, pl.v_y, s);
-    project(z, pl.Q, pl.n, pl.S, pl.red, pl.scal + 8, s);
-  } else {
-    copy(z, r, pl.n, s);
-  }
-}
-
-double dot_host(Plan &pl, const double *a, const double *b, hipStream_t s) {
-  const double *pa[1] = {a}, *pb[1] = {b};
-  multi_dot(pa, pb, 1, pl.n, pl.red, pl.scal + 16, s);
-  PHS_HIP(hipMemcpyAsync(pl.hscal + 16, pl.scal + 16, 8, hipMemcpyDeviceToHost, s));
-  PHS_HIP(hipStreamSynchronize(s));
-  return pl.hscal[16];
-}
-
-// q = sign * Pi M p
-void apply_op(Plan &pl, const double *p, double *q, int precision, hipStream_t s) {
-  matvec_tree(pl, p, q, precision, s);
-  project(q, pl.Q, pl.n, pl.S, pl.red, pl.scal + 8, s);
-  if (pl.sign < 0) scale_copy(q, q, -1.0, pl.n, s);
-}
-
-struct PcgResult {
-  int iters = 0;
-  bool converged = false;
-  bool breakdown = false;
-};
-
-// PCG on sign * Pi M Pi w = b with b in range(Pi), starting from w = 0.
-// w, r (in: b, out: residual), and three work vectors.
-PcgResult pcg(Plan &pl, double *w, double *r, double rtol_abs, int maxit, int check_every,
-              int precision, double *z, double *p, double *q, double *tmp, hipStream_t s) {
-  const int64_t n = pl.n;
-  PcgResult res;
-  fill(w, 0.0, n, s);
-  double *sc = pl.scal;  // [0] rho_new, [1] rho, [2] pq, [3] rr
-  precond_tree(pl, r, z, tmp, s);
-  {
-    const double *pa[1] = {r}, *pb[1] = {z};
-    multi_dot(pa, pb, 1, n, pl.red, sc + 1, s);
-  }
-  copy(p, z, n, s);
-  for (int it = 1; it <= maxit; ++it) {
-    apply_op(pl, p, q, precision, s);
-    {
-      const double *pa[1] = {p}, *pb[1] = {q};
-      multi_dot(pa, pb, 1, n, pl.red, sc + 2, s);
-    }
-    if (check_every == 1 && precision != PHS_FP64) {
-      // curvature check before the update so a breakdown step of an inexact
-      // (FP32) operator is never applied
-      PHS_HIP(hipMemcpyAsync(pl.hscal + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-      PHS_HIP(hipStreamSynchronize(s));
-      if (!(pl.hscal[2] > 0.0)) {
-        res.breakdown = true;
-        return res;
-      }
-    }
-    pcg_update_wr(w, r, p, q, sc + 1, n, pl.red, sc + 3, s);
-    res.iters = it;
-    if (it % check_every == 0 || it == maxit) {
-      PHS_HIP(hipMemcpyAsync(pl.hscal, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-      PHS_HIP(hipStreamSynchronize(s));
-      if (!(pl.hscal[2] > 0.0)) {
-        res.breakdown = true;
-        return res;
-      }
-      if (std::sqrt(pl.hscal[3]) <= rtol_abs) {
-        res.converged = true;
-        return res;
-      }
-    }
-    precond_tree(pl, r, z, tmp, s);
-    {
-      const double *pa[1] = {r}, *pb[1] = {z};
-      multi_dot(pa, pb, 1, n, pl.red, sc + 0, s);
-    }
-    pcg_update_p(p, z, sc, n, s);
-    PHS_HIP(hipMemcpyAsync(sc + 1, sc + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
-  }
-  return res;
-}
-
+// One column at a time through the plan's own forest (one system), so a
+// column's arithmetic is that of the same system in a batch.
 phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts *o,
                       double *w_out, double *beta_out, phs_solve_info *info, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -498,108 +402,21 @@ phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts 
   const int prec = (o && o->precision >= 0) ? o->precision : pl.precision;
   PHS_REQUIRE(prec == PHS_FP64 || prec == PHS_MIXED || prec == PHS_NEAR32,
               PHS_ERR_INVALID_ARGUMENT, "bad precision");
-  double *ft = pl.wk[0], *r = pl.wk[1], *w = pl.wk[2], *z = pl.wk[3], *p = pl.wk[4],
-         *q = pl.wk[5], *tmp = pl.wk[6], *dw = pl.wk[7];
   int total_iters = 0, total_outer = 0;
   double worst_rel = 0.0;
   phs_status st = PHS_OK;
   for (int c = 0; c < nrhs; ++c) {
-    gather_cols(f + (int64_t)c * n, pl.order, n, ft, s);
-    // b = sign * Pi f
-    scale_copy(r, ft, (double)pl.sign, n, s);
-    project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
-    const double bn = std::sqrt(dot_host(pl, r, r, s));
-    const double fn = std::sqrt(dot_host(pl, ft, ft, s));
-    const double tol_abs = rtol * bn;
-    double rel = 0.0;
-    // data in span(B) to rounding level: the polynomial alone interpolates
-    if (bn <= 1e-13 * fn) {
-      fill(w, 0.0, n, s);
-    } else if (prec == PHS_FP64) {
-      PcgResult pr = pcg(pl, w, r, tol_abs, maxit, check_every, PHS_FP64, z, p, q, tmp, s);
-      total_iters += pr.iters;
-      if (pr.breakdown) st = PHS_ERR_BREAKDOWN;
-      else if (!pr.converged && st == PHS_OK) st = PHS_ERR_NOT_CONVERGED;
-    } else {
-      // Mixed precision: inner PCG on FP32 matvecs, outer FP64 residual
-      // (iterative refinement).  The FP32 operator carries the cancellation of
-      // the Hadamard far field, so on the smoothest modes it may lose
-      // definiteness: an inner solve stops at breakdown or stagnation, and if
-      // an outer step stops reducing the FP64 residual the remainder is solved
-      // with the FP64 operator.  The exit test is always on the FP64 residual.
-      fill(w, 0.0, n, s);
-      double rn = bn;
-      int outer = 0, budget = maxit;
-      bool fp64_finish = false;
-      while (rn > tol_abs && budget > 0) {
-        // FP32 far field: small steps (its error is relative to ||M||); FP32
-        // near field only: the operator is accurate enough to go to rtol at once
-        const double inner_tol =
-            prec == PHS_NEAR32 ? 0.5 * tol_abs : std::max(tol_abs, 1e-4 * rn);
-        const int inner_prec = fp64_finish ? PHS_FP64 : prec;
-        PcgResult pr = pcg(pl, dw, r, fp64_finish ? tol_abs : inner_tol,
-                           (fp64_finish || prec == PHS_NEAR32) ? budget : std::min(budget, 60),
-                           check_every,
-                           inner_prec, z, p, q, tmp, s);
-        total_iters += pr.iters;
-        budget -= pr.iters;
-        if (pr.breakdown && pr.iters <= 1) {
-          if (fp64_finish) {
-            st = PHS_ERR_BREAKDOWN;
-            break;
-          }
-          fp64_finish = true;  // no usable FP32 step: restart this residual in FP64
-          matvec_tree(pl, w, q, PHS_FP64, s);
-          axpby(q, ft, 1.0, -1.0, n, s);
-          scale_copy(r, q, (double)pl.sign, n, s);
-          project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
-          continue;
-        }
-        axpby(w, dw, 1.0, 1.0, n, s);
-        // r = sign * Pi (f - M64 w)
-        matvec_tree(pl, w, q, PHS_FP64, s);
-        axpby(q, ft, 1.0, -1.0, n, s);  // q = f - M w
-        scale_copy(r, q, (double)pl.sign, n, s);
-        project(r, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
-        const double rn_new = std::sqrt(dot_host(pl, r, r, s));
-        ++outer;
-        if (!(rn_new < 0.5 * rn)) fp64_finish = true;
-        rn = rn_new;
-        if (!std::isfinite(rn)) {
-          st = PHS_ERR_BREAKDOWN;
-          break;
-        }
-      }
-      total_outer += outer;
-      if (rn > tol_abs && st == PHS_OK) st = PHS_ERR_NOT_CONVERGED;
-    }
-    // beta from R beta = Q^T (f - M w), FP64 matvec
-    matvec_tree(pl, w, q, PHS_FP64, s);
-    axpby(q, ft, 1.0, -1.0, n, s);  // q = f - M w
-    {
-      const double *pa[32], *pb[32];
-      for (int j = 0; j < pl.S; ++j) {
-        pa[j] = pl.Q + (int64_t)j * n;
-        pb[j] = q;
-      }
-      multi_dot(pa, pb, pl.S, n, pl.red, pl.scal + 40, s);
-      PHS_HIP(hipMemcpyAsync(pl.hscal + 40, pl.scal + 40, pl.S * 8, hipMemcpyDeviceToHost, s));
-      PHS_HIP(hipStreamSynchronize(s));
-      std::vector<double> bet(pl.S);
-      for (int i = pl.S - 1; i >= 0; --i) {
-        double acc = pl.hscal[40 + i];
-        for (int k2 = i + 1; k2 < pl.S; ++k2) acc -= pl.Rm[(size_t)i * pl.S + k2] * bet[k2];
-        bet[i] = acc / pl.Rm[(size_t)i * pl.S + i];
-      }
-      PHS_HIP(hipMemcpyAsync(beta_out + (int64_t)c * pl.S, bet.data(), pl.S * 8,
-                             hipMemcpyHostToDevice, s));
-      PHS_HIP(hipStreamSynchronize(s));
-    }
-    // relative residual of the projected system with the FP64 matvec
-    project(q, pl.Q, n, pl.S, pl.red, pl.scal + 8, s);
-    if (bn > 0) rel = std::sqrt(dot_host(pl, q, q, s)) / bn;
-    worst_rel = std::max(worst_rel, rel);
-    scatter_cols(w, pl.order, n, w_out + (int64_t)c * n, s);
+    std::vector<SolveJob> jobs(1);
+    jobs[0].sys = 0;
+    jobs[0].f = f + (int64_t)c * n;
+    jobs[0].w_out = w_out + (int64_t)c * n;
+    jobs[0].beta_out = beta_out + (int64_t)c * pl.S;
+    solve_forest(*pl.self, jobs, rtol, maxit, check_every, prec, s);
+    total_iters += jobs[0].iters;
+    total_outer += jobs[0].outer;
+    worst_rel = std::max(worst_rel, jobs[0].rel);
+    if (jobs[0].status != PHS_OK && st == PHS_OK) st = jobs[0].status;
+    if (jobs[0].status == PHS_ERR_BREAKDOWN) st = PHS_ERR_BREAKDOWN;
   }
   PHS_HIP(hipStreamSynchronize(s));
   if (info) {
@@ -673,10 +490,11 @@ phs_status phs_matvec(phs_plan_t plan, const double *v, double *y, int32_t nrhs,
                 PHS_ERR_INVALID_ARGUMENT, "bad precision");
     Plan &pl = plan->pl;
     hipStream_t s = S(stream);
+    Forest &F = *pl.self;
     for (int c = 0; c < nrhs; ++c) {
-      gather_cols(v + (int64_t)c * pl.n, pl.order, pl.n, pl.v_t, s);
-      if (pl.core_log) log_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, precision, s);
-      else dist_matvec(pl, pl.v_t, nullptr, y + (int64_t)c * pl.n, precision, s);
+      f_gather_user(F, 0, v + (int64_t)c * pl.n, V_IN, s);
+      f_matvec(F, F.mask[0], V_IN, V_OUT, precision, s);
+      f_scatter_user(F, 0, V_OUT, y + (int64_t)c * pl.n, s);
     }
     return PHS_OK;
   });
@@ -686,6 +504,7 @@ phs_status phs_precond_build(phs_plan_t plan, const phs_precond_opts *opts, void
   return guarded([&] {
     PHS_REQUIRE(plan && opts, PHS_ERR_INVALID_ARGUMENT, "bad precond arguments");
     vecchia_build(plan->pl, *opts, S(stream));
+    refresh_forest(*plan->pl.self, S(stream));
     return PHS_OK;
   });
 }
@@ -709,15 +528,15 @@ phs_status phs_eval(phs_plan_t plan, const double *w, const double *beta, int32_
     Plan &pl = plan->pl;
     hipStream_t s = S(stream);
     for (int c = 0; c < nrhs; ++c) {
-      gather_cols(w + (int64_t)c * pl.n, pl.order, pl.n, pl.v_t, s);
+      f_gather_user(*pl.self, 0, w + (int64_t)c * pl.n, V_IN, s);
+      const double *wt = pl.sw.v[V_IN];
       if (pl.core_log) {
-        log_expansions(pl, pl.v_t, s);
-        log_eval_targets(pl, pl.v_t, beta + (int64_t)c * pl.S, targets, m,
-                         out + (int64_t)c * m, s);
+        log_expansions(pl, V_IN, s);
+        log_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m, s);
       } else {
-        dist_expansions(pl, pl.v_t, s);
-        dist_eval_targets(pl, pl.v_t, beta + (int64_t)c * pl.S, targets, m,
-                          out + (int64_t)c * m, s);
+        dist_expansions(pl, V_IN, s);
+        dist_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m,
+                          s);
       }
     }
     return PHS_OK;
@@ -770,12 +589,60 @@ phs_status phs_precond_apply(phs_plan_t plan, const double *r, double *z, void *
     Plan &pl = plan->pl;
     PHS_REQUIRE(pl.has_pc, PHS_ERR_NOT_READY, "no preconditioner built");
     hipStream_t s = S(stream);
-    gather_cols(r, pl.order, pl.n, pl.v_t, s);
-    vecchia_apply(pl, pl.v_t, pl.v_y, pl.wk[7], s);
-    scatter_cols(pl.v_y, pl.order, pl.n, z, s);
+    Forest &F = *pl.self;
+    f_gather_user(F, 0, r, V_IN, s);
+    f_precond_apply(F, F.mask[0], V_IN, V_OUT, V_TMP, s);
+    f_scatter_user(F, 0, V_OUT, z, s);
     return PHS_OK;
   });
 }
+
+struct phs_batch_s {
+  Batch b;
+};
+
+phs_status phs_batch_create(const phs_plan_t *plans, int32_t nplans, const int32_t *nrhs,
+                            void *stream, phs_batch_t *out) {
+  if (!out) {
+    set_error(PHS_ERR_INVALID_ARGUMENT, "null output handle");
+    return PHS_ERR_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  phs_batch_s *h = new (std::nothrow) phs_batch_s();
+  if (!h) {
+    set_error(PHS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return PHS_ERR_OUT_OF_MEMORY;
+  }
+  phs_status st = guarded([&] {
+    PHS_REQUIRE(plans && nrhs && nplans >= 1, PHS_ERR_INVALID_ARGUMENT, "bad batch arguments");
+    std::vector<Plan *> pv;
+    std::vector<int> rv;
+    for (int i = 0; i < nplans; ++i) {
+      PHS_REQUIRE(plans[i], PHS_ERR_INVALID_ARGUMENT, "null plan in batch");
+      pv.push_back(&plans[i]->pl);
+      rv.push_back(nrhs[i]);
+    }
+    batch_create(h->b, pv, rv, S(stream));
+    return PHS_OK;
+  });
+  if (st != PHS_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return PHS_OK;
+}
+
+phs_status phs_batch_solve(phs_batch_t batch, const double *const *f, double *const *w,
+                           double *const *beta, const phs_solve_opts *opts,
+                           phs_solve_info *info, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(batch && f && w && beta, PHS_ERR_INVALID_ARGUMENT, "bad batch solve arguments");
+    return batch_solve(batch->b, f, w, beta, opts, info, S(stream));
+  });
+}
+
+void phs_batch_destroy(phs_batch_t batch) { delete batch; }
 
 void phs_plan_destroy(phs_plan_t plan) {
   if (!plan) return;

@@ -48,6 +48,24 @@ __device__ __forceinline__ void st2(typename Vec2<T>::type *p, C2<T> c) {
   v.y = c.im;
   *p = v;
 }
+// the same through the constant / global address spaces (component loads and
+// stores of one aligned pair, merged into one 8- or 16-byte access)
+template <class T>
+__device__ __forceinline__ C2<T> ld2(cptr<typename Vec2<T>::type> p) {
+  const cptr<T> q = (cptr<T>)p;
+  return {q[0], q[1]};
+}
+template <class T>
+__device__ __forceinline__ C2<T> ld2(gptr<typename Vec2<T>::type> p) {
+  const gptr<T> q = (gptr<T>)p;
+  return {q[0], q[1]};
+}
+template <class T>
+__device__ __forceinline__ void st2(gptr<typename Vec2<T>::type> p, C2<T> c) {
+  const gptr<T> q = (gptr<T>)p;
+  q[0] = c.re;
+  q[1] = c.im;
+}
 
 // z^e for 0 <= e < 64 by binary powering.
 template <class T>
@@ -158,7 +176,8 @@ __device__ __forceinline__ float phi_scale_f() {
 constexpr double kLn2Hi = 6.93147180369123816490e-01;  // 0x1.62e42fefa3800p-1
 constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln2 - kLn2Hi
 
-__device__ __forceinline__ double tang_log(double x, const double *__restrict__ tab) {
+template <class PT>
+__device__ __forceinline__ double tang_log(double x, PT tab) {
   const uint64_t b = (uint64_t)__double_as_longlong(x);
   const uint32_t hi = (uint32_t)(b >> 32), lo = (uint32_t)b;
   const int e = (int)(hi >> 20) - 1023;
@@ -180,20 +199,19 @@ __device__ __forceinline__ double tang_log(double x, const double *__restrict__ 
 // Host: fill the 256-entry table used by tang_log.
 void fill_log_table(double *tab);
 
-// sum_j phi(|x_i - y_j|) t_j over a contiguous source range, FP64.  For even
+// sum_j phi(|x_i - y_j|) t_j over a contiguous source range, FP64.  xy2
+// points to the interleaved source coordinates (x0, y0, x1, y1, ...).  For even
 // k the r = 0 term is removed by clamping r^2 to 1e-300 (phi is then ~1e-298,
 // below the rounding of any sum of O(1) terms).  Returns the sum without the
 // factor 1/2 of phi = r^k log r = (1/2) r^k log r^2 for even k.
-template <int K>
-__device__ __forceinline__ double near_range(double xi, double yi,
-                                             const double2 *__restrict__ xy2,
-                                             const double *__restrict__ t, int js, int je,
-                                             const double *__restrict__ tab) {
+template <int K, class PXY, class PT, class PTAB>
+__device__ __forceinline__ double near_range(double xi, double yi, PXY xy2, PT t, int js,
+                                             int je, PTAB tab) {
   double acc = 0.0;
 #pragma unroll 4
   for (int j = js; j < je; ++j) {
-    const double2 s = xy2[j];
-    const double dx = xi - s.x, dy = yi - s.y;
+    const double sx = xy2[2 * j], sy = xy2[2 * j + 1];
+    const double dx = xi - sx, dy = yi - sy;
     double r2 = fma(dy, dy, dx * dx);
     if constexpr (K == 1) {
       acc = fma(sqrt(r2), t[j], acc);

@@ -54,23 +54,32 @@ __device__ __forceinline__ void cheb_basis(T x, const T *__restrict__ Tk, T *S) 
 }
 
 // ---------------------------------------------------------------- P2M
+// Work item: one leaf of one system.
 template <class T, int K, int Q>
-__global__ __launch_bounds__(64) void k_cheb_p2m(const double *__restrict__ x,
-                                                 const double *__restrict__ y,
-                                                 const float *__restrict__ ux,
-                                                 const float *__restrict__ uy,
-                                                 const double *__restrict__ t,
-                                                 const int32_t *__restrict__ start, int L,
-                                                 double h, const T *__restrict__ Tk,
-                                                 T *__restrict__ W) {
+__global__ __launch_bounds__(64) void kf_cheb_p2m(const SysDev *__restrict__ sys,
+                                                  const BlkRef *__restrict__ tab,
+                                                  const int32_t *__restrict__ mask, int in,
+                                                  const T *__restrict__ Tk) {
   constexpr int R = Rank<K>::R;
   constexpr int QQ = Q * Q;
   constexpr int EPL = (QQ + 63) / 64;  // entries per lane
   __shared__ T s1[64][Q], s2[64][Q], qd[64][R];
   __shared__ T tk[Q * Q];
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int L = d.L;
+  const double h = d.h;
+  const cptr<double> x = ro(d.x);
+  const cptr<double> y = ro(d.y);
+  const cptr<float> ux = ro(d.ux);
+  const cptr<float> uy = ro(d.uy);
+  const cptr<double> t = ro(d.v[in]);
+  const cptr<int32_t> start = ro(d.leaf_start);
+  const gptr<T> W = rw((T *)d.mp + cheb_level_base(L, QQ, R));
   const int lane = threadIdx.x;
   const int G = 1 << L;
-  const int leaf = blockIdx.x;
+  const int leaf = br.blk;
   for (int i = lane; i < Q * Q; i += 64) tk[i] = Tk[i];
   const int b = start[leaf], e = start[leaf + 1];
   const double w = 2.0 * h / G;
@@ -134,13 +143,20 @@ __global__ __launch_bounds__(64) void k_cheb_p2m(const double *__restrict__ x,
 // Block per (box, density), QQ threads.  Tpm: [2][Q][Q] with Tpm[s][a][a'] =
 // S_a((xbar_a' + (2s-1))/2).
 template <class T, int Q>
-__global__ void k_cheb_m2m(const T *__restrict__ Wc, T *__restrict__ Wp, int lp, int nd,
-                           const T *__restrict__ Tpm) {
+__global__ void kf_cheb_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                            const int32_t *__restrict__ mask, int lp,
+                            const T *__restrict__ Tpm) {
   constexpr int QQ = Q * Q;
   __shared__ T tm[2 * QQ], wc[QQ], yy[QQ];
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R;
+  const cptr<T> Wc = ro((const T *)d.mp + cheb_level_base(lp + 1, QQ, nd));
+  const gptr<T> Wp = rw((T *)d.mp + cheb_level_base(lp, QQ, nd));
   const int tid = threadIdx.x;
   const int Gp = 1 << lp, Gc = 2 * Gp;
-  const int box = blockIdx.x, r = blockIdx.y;
+  const int box = br.blk / nd, r = br.blk % nd;
   const int bx = box % Gp, by = box / Gp;
   for (int i = tid; i < 2 * QQ; i += blockDim.x) tm[i] = Tpm[i];
   const int a = tid / Q, bb = tid % Q;
@@ -170,13 +186,20 @@ __global__ void k_cheb_m2m(const T *__restrict__ Wc, T *__restrict__ Wp, int lp,
 }
 
 template <class T, int Q>
-__global__ void k_cheb_l2l(const T *__restrict__ Gp, T *__restrict__ Gc, int lc, int nd,
-                           const T *__restrict__ Tpm) {
+__global__ void kf_cheb_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                            const int32_t *__restrict__ mask, int lc,
+                            const T *__restrict__ Tpm) {
   constexpr int QQ = Q * Q;
   __shared__ T tm[2 * QQ], gp[QQ], yy[QQ];
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R;
+  const gptr<T> Gp = rw((T *)d.loc + cheb_level_base(lc - 1, QQ, nd));
+  const gptr<T> Gc = rw((T *)d.loc + cheb_level_base(lc, QQ, nd));
   const int tid = threadIdx.x;
   const int G = 1 << lc;
-  const int box = blockIdx.x, r = blockIdx.y;
+  const int box = br.blk / nd, r = br.blk % nd;
   const int bx = box % G, by = box / G;
   const int cxx = bx & 1, cyy = by & 1;
   const int parent = (by >> 1) * (G / 2) + (bx >> 1);
@@ -196,7 +219,7 @@ __global__ void k_cheb_l2l(const T *__restrict__ Gp, T *__restrict__ Gc, int lc,
     T s = T(0);
 #pragma unroll
     for (int q1 = 0; q1 < Q; ++q1) s += tm[cxx * QQ + q1 * Q + a] * yy[q1 * Q + bb];
-    T *dst = &Gc[((int64_t)box * nd + r) * QQ + tid];
+    const gptr<T> dst = &Gc[((int64_t)box * nd + r) * QQ + tid];
     *dst += s;
   }
 }
@@ -209,18 +232,26 @@ __global__ void k_cheb_l2l(const T *__restrict__ Gp, T *__restrict__ Gc, int lc,
 constexpr int kCols = 64, kKc = 16;
 
 template <class T, int QQ>
-__global__ __launch_bounds__(256) void k_cheb_m2l(const T *__restrict__ Wall,
-                                                  T *__restrict__ Gall, int L, int nd,
-                                                  const T *__restrict__ Kd, double h) {
+__global__ __launch_bounds__(256) void kf_cheb_m2l(const SysDev *__restrict__ sys,
+                                                   const BlkRef *__restrict__ tab,
+                                                   const int32_t *__restrict__ mask,
+                                                   const T *__restrict__ Kd) {
   constexpr int RPT = (QQ + 15) / 16;  // rows per thread
   constexpr int AST = kKc + 1;         // padded row stride of the A tile
   __shared__ T As[QQ * AST];
   __shared__ T Bs[kKc * kCols];
   __shared__ int src_box[kCols];
   __shared__ int any_valid;
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const cptr<T> Wall = ro((const T *)d.mp);
+  const gptr<T> Gall = rw((T *)d.loc);
+  const int L = d.L, nd = d.R;
+  const double h = d.h;
   const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
   // locate level and tile
-  int64_t tcol = (int64_t)blockIdx.x * kCols;
+  int64_t tcol = (int64_t)br.blk * kCols;
   int l = 2;
   int64_t off = 0, base = 0;
   while (l <= L) {
@@ -235,8 +266,8 @@ __global__ __launch_bounds__(256) void k_cheb_m2l(const T *__restrict__ Wall,
   const int G = 1 << l;
   const int64_t nb = (int64_t)G * G;
   const int64_t col0 = tcol - off;
-  const T *Wl = Wall + base;
-  T *Gl = Gall + base;
+  const cptr<T> Wl = Wall + base;
+  const gptr<T> Gl = Gall + base;
   const T half_w = (T)(h / G);  // (w/2)
   // my columns: c = tx + 16 j
   T acc[RPT][4];
@@ -327,18 +358,31 @@ __global__ __launch_bounds__(256) void k_cheb_m2l(const T *__restrict__ Wall,
 
 // ---------------------------------------------------------------- leaf
 template <class T, class TN, int K, int Q>
-__global__ __launch_bounds__(64) void k_cheb_leaf_eval(
-    const double *__restrict__ x, const double *__restrict__ y,
-    const float *__restrict__ ux, const float *__restrict__ uy,
-    const double *__restrict__ t, const int32_t *__restrict__ start, int L, double h,
-    const T *__restrict__ Tk, const T *__restrict__ Gleaf, double *__restrict__ ytree,
-    double *__restrict__ yuser, const int32_t *__restrict__ order,
-    const double2 *__restrict__ xy2, const double *__restrict__ logtab) {
+__global__ __launch_bounds__(64) void kf_cheb_leaf_eval(const SysDev *__restrict__ sys,
+                                                        const BlkRef *__restrict__ tab,
+                                                        const int32_t *__restrict__ mask,
+                                                        int in, int out,
+                                                        const T *__restrict__ Tk,
+                                                        const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
   constexpr int QQ = Q * Q;
   __shared__ T tk[QQ];
+  const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int L = d.L;
+  const double h = d.h;
+  const cptr<double> x = ro(d.x);
+  const cptr<double> y = ro(d.y);
+  const cptr<float> ux = ro(d.ux);
+  const cptr<float> uy = ro(d.uy);
+  const cptr<double> t = ro(d.v[in]);
+  const cptr<int32_t> start = ro(d.leaf_start);
+  const cptr<double> xy2 = ro((const double *)d.xy2);
+  const cptr<T> Gleaf = ro((const T *)d.loc + cheb_level_base(L, QQ, R));
+  const gptr<double> ytree = rw(d.v[out]);
   const int G = 1 << L;
-  const int leaf = (int)xcd_remap(blockIdx.x, (int64_t)G * G);
+  const int leaf = br.blk;
   const int lane = threadIdx.x;
   for (int i = lane; i < QQ; i += 64) tk[i] = Tk[i];
   __syncthreads();
@@ -349,7 +393,7 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
   const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
   const int r0 = iy > 0 ? iy - 1 : 0, r1 = iy + 1 < G ? iy + 1 : G - 1;
   const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
-  const T *Gl = Gleaf + (int64_t)leaf * R * QQ;
+  const cptr<T> Gl = Gleaf + (int64_t)leaf * R * QQ;
   for (int i0 = b; i0 < e; i0 += 64) {
     const int i = i0 + lane;
     const bool act = i < e;
@@ -372,7 +416,7 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
       ufac<K, T>(xi, yi, u);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const T *g = Gl + r * QQ;
+        const cptr<T> g = Gl + r * QQ;
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
@@ -407,11 +451,7 @@ __global__ __launch_bounds__(64) void k_cheb_leaf_eval(
       }
       nearv *= phi_scale_f<K>();
     }
-    if (act) {
-      const double out = (double)far + (double)nearv;
-      if (ytree) ytree[i] = out;
-      if (yuser) yuser[order[i]] = out;
-    }
+    if (act) ytree[i] = (double)far + (double)nearv;
   }
 }
 
@@ -477,7 +517,7 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
     const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
     for (int row = r0; row <= r1; ++row) {
       const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-      nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
+      nearv += near_scale<K>() * near_range<K>(xi, yi, (const double *)xy2, wt, js, je, logtab);
     }
   } else {
     int stk_l[64];
@@ -509,7 +549,7 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
           }
       } else if (l == L) {
         const int js = start[box], je = start[box + 1];
-        nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
+        nearv += near_scale<K>() * near_range<K>(xi, yi, (const double *)xy2, wt, js, je, logtab);
       } else {
         for (int c = 0; c < 4; ++c) {
           stk_l[sp] = l + 1;
@@ -524,90 +564,94 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
 
 // ---------------------------------------------------------------- host
 template <class T, int Q>
-void far_field_q(Plan &pl, const double *t, const ChebTables &ct, hipStream_t s) {
+void far_field_q(Forest &F, const int32_t *mask, int in, const ChebTables &ct, hipStream_t s) {
   constexpr int QQ = Q * Q;
   const bool fp64 = std::is_same<T, double>::value;
   const T *Tk = fp64 ? (const T *)ct.nodes64 + Q : (const T *)ct.nodes32 + Q;
   const T *Tpm = fp64 ? (const T *)ct.S2c64 : (const T *)ct.S2c32;
   const T *Kd = fp64 ? (const T *)ct.K64 : (const T *)ct.K32;
-  const int nd = pl.R, L = pl.tree.L;
-  const double h = pl.tree.h;
-  T *W = (T *)pl.mp;
-  T *Gx = (T *)pl.loc;
-  const int64_t nleaf = boxes_at(L);
-  T *WL = W + cheb_level_base(L, QQ, nd);
-  if (pl.k == 1)
-    PHS_LAUNCH("cheb_p2m", s, k_cheb_p2m<T, 1, Q><<<nleaf, 64, 0, s>>>(
-        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, h, Tk, WL));
-  else
-    PHS_LAUNCH("cheb_p2m", s, k_cheb_p2m<T, 3, Q><<<nleaf, 64, 0, s>>>(
-        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, h, Tk, WL));
+  const int maxL = F.maxL_dist;
+  {
+    const Tab t1 = forest_tab(F, tab_key(1, 1, 0, 0), s);
+    if (t1.count)
+      PHS_LAUNCH("cheb_p2m", s, kf_cheb_p2m<T, 1, Q><<<(unsigned)t1.count, 64, 0, s>>>(
+                                    F.dsys, t1.d, mask, in, Tk));
+    const Tab t3 = forest_tab(F, tab_key(1, 3, 0, 0), s);
+    if (t3.count)
+      PHS_LAUNCH("cheb_p2m", s, kf_cheb_p2m<T, 3, Q><<<(unsigned)t3.count, 64, 0, s>>>(
+                                    F.dsys, t3.d, mask, in, Tk));
+  }
   const int thr = QQ <= 64 ? 64 : (QQ <= 128 ? 128 : 256);
-  for (int lp = L - 1; lp >= 2; --lp) {
-    dim3 grid((unsigned)boxes_at(lp), (unsigned)nd);
-    PHS_LAUNCH("cheb_m2m", s, k_cheb_m2m<T, Q><<<grid, thr, 0, s>>>(
-        W + cheb_level_base(lp + 1, QQ, nd), W + cheb_level_base(lp, QQ, nd), lp, nd, Tpm));
+  for (int lp = maxL - 1; lp >= 2; --lp) {
+    const Tab tb = forest_tab(F, tab_key(7, 0, 0, lp), s);
+    if (tb.count)
+      PHS_LAUNCH("cheb_m2m", s, kf_cheb_m2m<T, Q><<<(unsigned)tb.count, thr, 0, s>>>(
+                                    F.dsys, tb.d, mask, lp, Tpm));
   }
   {
-    int64_t tiles = 0;
-    for (int l = 2; l <= L; ++l) tiles += (boxes_at(l) * nd + kCols - 1) / kCols;
-    PHS_LAUNCH("cheb_m2l", s, k_cheb_m2l<T, QQ><<<tiles, 256, 0, s>>>(W, Gx, L, nd, Kd, h));
+    const Tab tb = forest_tab(F, tab_key(9, 0, 0, 0), s);
+    if (tb.count)
+      PHS_LAUNCH("cheb_m2l", s, kf_cheb_m2l<T, QQ><<<(unsigned)tb.count, 256, 0, s>>>(
+                                    F.dsys, tb.d, mask, Kd));
   }
-  for (int lc = 3; lc <= L; ++lc) {
-    dim3 grid((unsigned)boxes_at(lc), (unsigned)nd);
-    PHS_LAUNCH("cheb_l2l", s, k_cheb_l2l<T, Q><<<grid, thr, 0, s>>>(
-        Gx + cheb_level_base(lc - 1, QQ, nd), Gx + cheb_level_base(lc, QQ, nd), lc, nd, Tpm));
+  for (int lc = 3; lc <= maxL; ++lc) {
+    const Tab tb = forest_tab(F, tab_key(8, 0, 0, lc), s);
+    if (tb.count)
+      PHS_LAUNCH("cheb_l2l", s, kf_cheb_l2l<T, Q><<<(unsigned)tb.count, thr, 0, s>>>(
+                                    F.dsys, tb.d, mask, lc, Tpm));
   }
 }
 
 template <class T, class TN, int Q>
-void leaf_q(Plan &pl, const double *t, double *yt, double *yu, hipStream_t s) {
-  constexpr int QQ = Q * Q;
+void leaf_q(Forest &F, const int32_t *mask, int in, int out, const ChebTables &ct,
+            const double *logtab, hipStream_t s) {
   const bool fp64 = std::is_same<T, double>::value;
-  const ChebTables &ct = fp64 ? pl.ct64 : pl.ct32;
   const T *Tk = fp64 ? (const T *)ct.nodes64 + Q : (const T *)ct.nodes32 + Q;
-  const int L = pl.tree.L;
-  const T *GL = (const T *)pl.loc + cheb_level_base(L, QQ, pl.R);
-  const int64_t nleaf = boxes_at(L);
-  if (pl.k == 1)
-    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, TN, 1, Q><<<nleaf, 64, 0, s>>>(
-        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
-        pl.order, pl.xy2, pl.logtab));
-  else
-    PHS_LAUNCH("cheb_leaf_eval", s, k_cheb_leaf_eval<T, TN, 3, Q><<<nleaf, 64, 0, s>>>(
-        pl.x, pl.y, pl.ux, pl.uy, t, pl.tree.leaf_start, L, pl.tree.h, Tk, GL, yt, yu,
-        pl.order, pl.xy2, pl.logtab));
+  const Tab t1 = forest_tab(F, tab_key(1, 1, 0, 0), s);
+  if (t1.count)
+    PHS_LAUNCH("cheb_leaf_eval", s, kf_cheb_leaf_eval<T, TN, 1, Q><<<(unsigned)t1.count, 64, 0, s>>>(
+                                        F.dsys, t1.d, mask, in, out, Tk, logtab));
+  const Tab t3 = forest_tab(F, tab_key(1, 3, 0, 0), s);
+  if (t3.count)
+    PHS_LAUNCH("cheb_leaf_eval", s, kf_cheb_leaf_eval<T, TN, 3, Q><<<(unsigned)t3.count, 64, 0, s>>>(
+                                        F.dsys, t3.d, mask, in, out, Tk, logtab));
 }
 
 // One far-field pass (and, with `leaf`, the leaf pass) at Q nodes per axis;
 // `ct` holds the tables of that Q.
 template <class T, class TN>
-void run_q(Plan &pl, const double *t, double *yt, double *yu, bool leaf, int Q,
-           const ChebTables &ct, hipStream_t s) {
+void run_q(Forest &F, const int32_t *mask, int in, int out, bool leaf, int Q,
+           const ChebTables &ct, const double *logtab, hipStream_t s) {
   switch (Q) {
     case 8:
-      far_field_q<T, 8>(pl, t, ct, s);
-      if (leaf) leaf_q<T, TN, 8>(pl, t, yt, yu, s);
+      far_field_q<T, 8>(F, mask, in, ct, s);
+      if (leaf) leaf_q<T, TN, 8>(F, mask, in, out, ct, logtab, s);
       break;
     case 10:
-      far_field_q<T, 10>(pl, t, ct, s);
-      if (leaf) leaf_q<T, TN, 10>(pl, t, yt, yu, s);
+      far_field_q<T, 10>(F, mask, in, ct, s);
+      if (leaf) leaf_q<T, TN, 10>(F, mask, in, out, ct, logtab, s);
       break;
     case 12:
-      far_field_q<T, 12>(pl, t, ct, s);
-      if (leaf) leaf_q<T, TN, 12>(pl, t, yt, yu, s);
+      far_field_q<T, 12>(F, mask, in, ct, s);
+      if (leaf) leaf_q<T, TN, 12>(F, mask, in, out, ct, logtab, s);
       break;
     case 14:
-      far_field_q<T, 14>(pl, t, ct, s);
-      if (leaf) leaf_q<T, TN, 14>(pl, t, yt, yu, s);
+      far_field_q<T, 14>(F, mask, in, ct, s);
+      if (leaf) leaf_q<T, TN, 14>(F, mask, in, out, ct, logtab, s);
       break;
     case 16:
-      far_field_q<T, 16>(pl, t, ct, s);
-      if (leaf) leaf_q<T, TN, 16>(pl, t, yt, yu, s);
+      far_field_q<T, 16>(F, mask, in, ct, s);
+      if (leaf) leaf_q<T, TN, 16>(F, mask, in, out, ct, logtab, s);
       break;
     default:
       throw Error{PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16"};
   }
+}
+
+const Plan &dist_ref(const Forest &F) {
+  for (const Plan *p : F.plan)
+    if (!p->core_log) return *p;
+  throw Error{PHS_ERR_INVALID_ARGUMENT, "forest has no odd-order system"};
 }
 
 template <int Q>
@@ -617,8 +661,8 @@ void eval_q(Plan &pl, const double *w_tree, const double *beta, const double *ta
   const int L = pl.tree.L;
   const ChebTables &ct = pl.qe == pl.q64 ? pl.ct64 : pl.cte;
   const double *Tk = ct.nodes64 + Q;
-  const double *W = (const double *)pl.mp;
-  const double *GL = (const double *)pl.loc + cheb_level_base(L, QQ, pl.R);
+  const double *W = (const double *)pl.sw.mp;
+  const double *GL = (const double *)pl.sw.loc + cheb_level_base(L, QQ, pl.R);
   const int64_t nb = (m + 127) / 128;
   if (pl.k == 1)
     PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<1, Q><<<nb, 128, 0, s>>>(
@@ -711,19 +755,21 @@ size_t cheb_expansion_bytes(int L, int Q, int nd, bool fp64) {
   return (size_t)cheb_level_base(L + 1, Q * Q, nd) * (fp64 ? 8 : 4);
 }
 
-void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, int precision,
+void dist_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
                  hipStream_t s) {
+  const Plan &ref = dist_ref(F);
   if (precision == PHS_MIXED)
-    run_q<float, float>(pl, t_tree, y_tree, y_user, true, pl.q32, pl.ct32, s);
+    run_q<float, float>(F, mask, in, out, true, ref.q32, ref.ct32, ref.logtab, s);
   else if (precision == PHS_NEAR32)
-    run_q<double, float>(pl, t_tree, y_tree, y_user, true, pl.q64, pl.ct64, s);
+    run_q<double, float>(F, mask, in, out, true, ref.q64, ref.ct64, ref.logtab, s);
   else
-    run_q<double, double>(pl, t_tree, y_tree, y_user, true, pl.q64, pl.ct64, s);
+    run_q<double, double>(F, mask, in, out, true, ref.q64, ref.ct64, ref.logtab, s);
 }
 
-void dist_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
-  run_q<double, double>(pl, w_tree, nullptr, nullptr, false, pl.qe,
-                        pl.qe == pl.q64 ? pl.ct64 : pl.cte, s);
+void dist_expansions(Plan &pl, int in, hipStream_t s) {
+  Forest &F = *pl.self;
+  run_q<double, double>(F, F.mask[0], in, 0, false, pl.qe, pl.qe == pl.q64 ? pl.ct64 : pl.cte,
+                        pl.logtab, s);
 }
 
 void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,

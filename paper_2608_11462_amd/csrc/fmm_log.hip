@@ -33,25 +33,39 @@ __host__ __device__ inline int64_t level_base(int l, int P, int nd) {
 }
 
 // ------------------------------------------------------------------ P2M
+// Work item: 4 gpw leaves of one system, gpw = 64/(P+1) leaves per wavefront
+// (lane = coefficient), four wavefronts per block.
 template <class T, int K>
-__global__ void k_p2m(const double *__restrict__ x, const double *__restrict__ y,
-                      const float *__restrict__ ux, const float *__restrict__ uy,
-                      const double *__restrict__ t, const int32_t *__restrict__ start,
-                      int L, double h, int P, int gpw, V2<T> *__restrict__ A) {
+__global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
+                                              const BlkRef *__restrict__ tab,
+                                              const int32_t *__restrict__ mask, int P, int in) {
   constexpr int R = Rank<K>::R;
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int L = d.L;
   const int G = 1 << L;
   const int nleaf = G * G;
   const int P1 = P + 1;
+  const int gpw = p2m_leaves_per_wave(P);
   const int sub = lane / P1, kk = lane % P1;
-  const int leaf = (blockIdx.x * (blockDim.x >> 6) + wave) * gpw + sub;
-  const bool active = sub < gpw && leaf < nleaf;
+  const double h = d.h;
+  const cptr<double> x = ro(d.x);
+  const cptr<double> y = ro(d.y);
+  const cptr<float> ux = ro(d.ux);
+  const cptr<float> uy = ro(d.uy);
+  const cptr<double> t = ro(d.v[in]);
+  const cptr<int32_t> lstart = ro(d.leaf_start);
+  const gptr<V2<T>> A = rw((V2<T> *)d.mp + level_base(L, P, R));
+  const double w = 2.0 * h / G, invw = G / (2.0 * h);
+  const bool active = sub < gpw;
+  const int leaf = (br.blk * 4 + wave) * gpw + (active ? sub : 0);
   int b = 0, e = 0;
   if (active) {
-    b = start[leaf];
-    e = start[leaf + 1];
+    b = lstart[leaf];
+    e = lstart[leaf + 1];
   }
-  const double w = 2.0 * h / G, invw = G / (2.0 * h);
   const int ix = leaf % G, iy = leaf / G;
   const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
   T are[R], aim[R];
@@ -83,13 +97,21 @@ __global__ void k_p2m(const double *__restrict__ x, const double *__restrict__ y
 }
 
 // ------------------------------------------------------------------ M2M
+// Work item: 256 (parent box, density, coefficient) triples of one level.
 template <class T>
-__global__ void k_m2m(const V2<T> *__restrict__ Ac, V2<T> *__restrict__ Ap, int lp, int P,
-                      int nd, const V2<T> *__restrict__ tab) {
+__global__ void kf_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                       const int32_t *__restrict__ mask, int lp, int P,
+                       const V2<T> *__restrict__ m2m) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R;
   const int Gp = 1 << lp, Gc = 2 * Gp;
   const int64_t nbp = (int64_t)Gp * Gp, nbc = 4 * nbp;
-  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t tid = (int64_t)br.blk * 256 + threadIdx.x;
   if (tid >= nbp * nd * (P + 1)) return;
+  const cptr<V2<T>> Ac = ro((const V2<T> *)d.mp + level_base(lp + 1, P, nd));
+  const gptr<V2<T>> Ap = rw((V2<T> *)d.mp + level_base(lp, P, nd));
   const int box = (int)(tid % nbp);
   const int64_t rest = tid / nbp;
   const int r = (int)(rest % nd), lc = (int)(rest / nd);
@@ -97,7 +119,7 @@ __global__ void k_m2m(const V2<T> *__restrict__ Ac, V2<T> *__restrict__ Ap, int 
   C2<T> acc = {T(0), T(0)};
   for (int c = 0; c < 4; ++c) {
     const int child = (2 * iy + (c >> 1)) * Gc + 2 * ix + (c & 1);
-    const V2<T> *row = tab + ((int64_t)c * (P + 1) + lc) * (P + 1);
+    const V2<T> *row = m2m + ((int64_t)c * (P + 1) + lc) * (P + 1);
     for (int k = 0; k <= lc; ++k)
       acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Ac[((int64_t)k * nd + r) * nbc + child])));
   }
@@ -105,16 +127,23 @@ __global__ void k_m2m(const V2<T> *__restrict__ Ac, V2<T> *__restrict__ Ap, int 
 }
 
 // ------------------------------------------------------------------ M2L
-// One thread per (target box, density, chunk of LCH output coefficients),
-// all levels 2..L in one launch.  Boxes are enumerated by parity class so a
-// wavefront shares one interaction-list pattern.
+// Work item: (tile of 256 boxes over levels 2..L, density, chunk of LCH
+// output coefficients) of one system, chunk fastest.  Boxes are enumerated by
+// parity class so a wavefront shares one interaction-list pattern.  The table
+// index is remapped so that consecutive items run on one XCD.
 template <class T, int LCH>
-__global__ __launch_bounds__(256) void k_m2l(const V2<T> *__restrict__ A,
-                                             V2<T> *__restrict__ B, int L, int P,
-                                             int nd, const T *__restrict__ Ht,
-                                             double h, int nchunks, int64_t ntiles) {
-  // logical workgroup: chunk fastest, then density, then tile of 256 boxes
-  const int64_t lb = xcd_remap(blockIdx.x, (int64_t)nchunks * nd * ntiles);
+__global__ __launch_bounds__(256) void kf_m2l(const SysDev *__restrict__ sys,
+                                              const BlkRef *__restrict__ tab,
+                                              const int32_t *__restrict__ mask, int P,
+                                              const T *__restrict__ Ht, int nchunks) {
+  const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R, L = d.L;
+  const double h = d.h;
+  const cptr<V2<T>> A = ro((const V2<T> *)d.mp);
+  const gptr<V2<T>> B = rw((V2<T> *)d.loc);
+  const int64_t lb = br.blk;
   const int l0 = (int)(lb % nchunks) * LCH;
   const int r = (int)((lb / nchunks) % nd);
   const int64_t tile = lb / ((int64_t)nchunks * nd);
@@ -139,8 +168,8 @@ __global__ __launch_bounds__(256) void k_m2l(const V2<T> *__restrict__ A,
   const int brow = (int)(rest >> 2);
   const int ix = 2 * aa + (cls & 1);
   const int iy = 2 * brow + (cls >> 1);
-  const V2<T> *Al = A + base;
-  V2<T> *Bl = B + base;
+  const cptr<V2<T>> Al = A + base;
+  const gptr<V2<T>> Bl = B + base;
   const T logw = (T)log(2.0 * h / G);
   C2<T> acc[LCH];
 #pragma unroll
@@ -192,23 +221,30 @@ __global__ __launch_bounds__(256) void k_m2l(const V2<T> *__restrict__ A,
 
 // ------------------------------------------------------------------ L2L
 template <class T>
-__global__ void k_l2l(const V2<T> *__restrict__ Bp, V2<T> *__restrict__ Bc, int lc, int P,
-                      int nd, const V2<T> *__restrict__ tab) {
+__global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                       const int32_t *__restrict__ mask, int lc, int P,
+                       const V2<T> *__restrict__ l2l) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R;
   const int Gc = 1 << lc, Gp = Gc / 2;
   const int64_t nbc = (int64_t)Gc * Gc, nbp = nbc / 4;
-  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t tid = (int64_t)br.blk * 256 + threadIdx.x;
   if (tid >= nbc * nd * (P + 1)) return;
+  const gptr<V2<T>> Bp = rw((V2<T> *)d.loc + level_base(lc - 1, P, nd));
+  const gptr<V2<T>> Bc = rw((V2<T> *)d.loc + level_base(lc, P, nd));
   const int box = (int)(tid % nbc);
   const int64_t rest = tid / nbc;
   const int r = (int)(rest % nd), j = (int)(rest / nd);
   const int ix = box % Gc, iy = box / Gc;
   const int c = (iy & 1) * 2 + (ix & 1);
   const int parent = (iy >> 1) * Gp + (ix >> 1);
-  const V2<T> *row = tab + ((int64_t)c * (P + 1) + j) * (P + 1);
+  const V2<T> *row = l2l + ((int64_t)c * (P + 1) + j) * (P + 1);
   C2<T> acc = {T(0), T(0)};
   for (int k = j; k <= P; ++k)
     acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Bp[((int64_t)k * nd + r) * nbp + parent])));
-  V2<T> *dst = &Bc[((int64_t)j * nd + r) * nbc + box];
+  const gptr<V2<T>> dst = &Bc[((int64_t)j * nd + r) * nbc + box];
   st2<T>(dst, cadd(ld2<T>(dst), acc));
 }
 
@@ -217,21 +253,33 @@ __global__ void k_l2l(const V2<T> *__restrict__ Bp, V2<T> *__restrict__ Bc, int 
 // the leaf's incoming expansions (L2P) combined with U_r; near field by
 // direct phi over the 3x3 neighbouring leaves (step 2: direct evaluation).
 template <class T, class TN, int K>
-__global__ __launch_bounds__(64) void k_leaf_eval(
-    const double *__restrict__ x, const double *__restrict__ y,
-    const float *__restrict__ ux, const float *__restrict__ uy,
-    const double *__restrict__ t, const int32_t *__restrict__ start, int L, double h,
-    int P, const V2<T> *__restrict__ Bleaf, double *__restrict__ ytree,
-    double *__restrict__ yuser, const int32_t *__restrict__ order,
-    const double2 *__restrict__ xy2, const double *__restrict__ logtab) {
+__global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sys,
+                                                   const BlkRef *__restrict__ tab,
+                                                   const int32_t *__restrict__ mask, int P,
+                                                   int in, int out,
+                                                   const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
-  __shared__ double tab[256];
+  __shared__ double ltab[256];
+  const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int L = d.L;
+  const double h = d.h;
   const int G = 1 << L;
   const int nleaf = G * G;
-  const int leaf = (int)xcd_remap(blockIdx.x, nleaf);
+  const int leaf = br.blk;
   const int lane = threadIdx.x;
+  const cptr<double> x = ro(d.x);
+  const cptr<double> y = ro(d.y);
+  const cptr<float> ux = ro(d.ux);
+  const cptr<float> uy = ro(d.uy);
+  const cptr<double> t = ro(d.v[in]);
+  const cptr<double> xy2 = ro((const double *)d.xy2);
+  const cptr<int32_t> start = ro(d.leaf_start);
+  const cptr<V2<T>> Bleaf = ro((const V2<T> *)d.loc + level_base(L, P, R));
+  const gptr<double> ytree = rw(d.v[out]);
   if constexpr (std::is_same<TN, double>::value && K % 2 == 0) {
-    for (int i = lane; i < 256; i += 64) tab[i] = logtab[i];
+    for (int i = lane; i < 256; i += 64) ltab[i] = logtab[i];
     __syncthreads();
   }
   const int b = start[leaf], e = start[leaf + 1];
@@ -271,7 +319,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
     if constexpr (std::is_same<TN, double>::value) {
       for (int row = r0; row <= r1; ++row) {
         const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-        nearv += near_range<K>(xi, yi, xy2, t, js, je, tab);
+        nearv += near_range<K>(xi, yi, xy2, t, js, je, ltab);
       }
       nearv *= near_scale<K>();
     } else {
@@ -290,11 +338,7 @@ __global__ __launch_bounds__(64) void k_leaf_eval(
       }
       nearv *= phi_scale_f<K>();
     }
-    if (act) {
-      const double out = (double)far + (double)nearv;
-      if (ytree) ytree[i] = out;
-      if (yuser) yuser[order[i]] = out;
-    }
+    if (act) ytree[i] = (double)far + (double)nearv;
   }
 }
 
@@ -355,7 +399,7 @@ __global__ void k_eval_targets(const double *__restrict__ tg, int64_t m, double 
     const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
     for (int row = r0; row <= r1; ++row) {
       const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-      nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
+      nearv += near_scale<K>() * near_range<K>(xi, yi, (const double *)xy2, wt, js, je, logtab);
     }
   } else {
     // explicit-stack descent from level 2
@@ -393,7 +437,7 @@ __global__ void k_eval_targets(const double *__restrict__ tg, int64_t m, double 
         }
       } else if (l == L) {
         const int js = start[box], je = start[box + 1];
-        nearv += near_scale<K>() * near_range<K>(xi, yi, xy2, wt, js, je, logtab);
+        nearv += near_scale<K>() * near_range<K>(xi, yi, (const double *)xy2, wt, js, je, logtab);
       } else {
         for (int c = 0; c < 4; ++c) {
           stk_l[sp] = l + 1;
@@ -414,101 +458,86 @@ double binom(int n, int k) {
   return r;
 }
 
-// Upward pass, M2L and downward pass at order P with the tables of that order.
-// `m2l_name` labels the M2L launch in the per-kernel timing.
+// Upward pass, M2L and downward pass at order P with the tables of that order,
+// for the even-k systems of the forest.  `m2l_name` labels the M2L launch in
+// the per-kernel timing.
 template <class T>
-void far_field(Plan &pl, const double *t, int P, const LogTables &lt, const char *m2l_name,
-               hipStream_t s) {
+void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &lt,
+               const char *m2l_name, hipStream_t s) {
   const bool fp64 = std::is_same<T, double>::value;
-  const int nd = pl.R, L = pl.tree.L;
-  const double h = pl.tree.h;
-  V2<T> *A = (V2<T> *)pl.mp;
-  V2<T> *B = (V2<T> *)pl.loc;
   const V2<T> *M2M = fp64 ? (const V2<T> *)lt.M2M64 : (const V2<T> *)lt.M2M32;
   const V2<T> *L2L = fp64 ? (const V2<T> *)lt.L2L64 : (const V2<T> *)lt.L2L32;
   const T *Ht = fp64 ? (const T *)lt.Ht64 : (const T *)lt.Ht32;
-  // P2M at the leaves
+  const int maxL = F.maxL_log;
+  // P2M at the leaves, per order k (the Hadamard factors differ)
   {
-    const int gpw = std::max(1, 64 / (P + 1));
-    const int64_t nleaf = boxes_at(L);
-    const int64_t groups = (nleaf + gpw - 1) / gpw;
-    const int64_t nblk = (groups + 3) / 4;
-    V2<T> *AL = A + level_base(L, P, nd);
-    if (pl.k == 2)
-      PHS_LAUNCH("p2m", s, k_p2m<T, 2><<<nblk, 256, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
-                                                             pl.tree.leaf_start, L, h, P,
-                                                             gpw, AL));
-    else
-      PHS_LAUNCH("p2m", s, k_p2m<T, 4><<<nblk, 256, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
-                                                             pl.tree.leaf_start, L, h, P,
-                                                             gpw, AL));
+    const int gpw = p2m_leaves_per_wave(P);
+    const Tab t2 = forest_tab(F, tab_key(2, 2, gpw, 0), s);
+    if (t2.count)
+      PHS_LAUNCH("p2m", s, kf_p2m<T, 2><<<(unsigned)t2.count, 256, 0, s>>>(F.dsys, t2.d, mask, P, in));
+    const Tab t4 = forest_tab(F, tab_key(2, 4, gpw, 0), s);
+    if (t4.count)
+      PHS_LAUNCH("p2m", s, kf_p2m<T, 4><<<(unsigned)t4.count, 256, 0, s>>>(F.dsys, t4.d, mask, P, in));
   }
   // upward pass
-  for (int lp = L - 1; lp >= 2; --lp) {
-    const int64_t tot = boxes_at(lp) * nd * (P + 1);
-    PHS_LAUNCH("m2m", s,
-               k_m2m<T><<<(tot + 255) / 256, 256, 0, s>>>(A + level_base(lp + 1, P, nd),
-                                                         A + level_base(lp, P, nd), lp, P,
-                                                         nd, M2M));
+  for (int lp = maxL - 1; lp >= 2; --lp) {
+    const Tab tb = forest_tab(F, tab_key(3, 0, P, lp), s);
+    if (tb.count)
+      PHS_LAUNCH("m2m", s, kf_m2m<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lp, P, M2M));
   }
   // outgoing -> incoming on every level
   {
-    int64_t tot = 0;
-    for (int l = 2; l <= L; ++l) tot += boxes_at(l);
-    // chunk of LCH output coefficients: the widest of 16/14/12 that divides
-    // P+1, else 8 (the last chunk then stores only its first coefficients)
-    const int64_t ntiles = (tot + 255) / 256;
-    const int lch = ((P + 1) % 16 == 0) ? 16 : ((P + 1) % 14 == 0) ? 14
-                    : ((P + 1) % 12 == 0) ? 12 : 8;
+    const Tab tb = forest_tab(F, tab_key(5, 0, P, 0), s);
+    const int lch = m2l_chunk(P);
     const int nchunks = (P + 1 + lch - 1) / lch;
-    const unsigned nblk = (unsigned)(ntiles * nchunks * nd);
-    switch (lch) {
-    case 16:
-      PHS_LAUNCH(m2l_name, s, k_m2l<T, 16><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
-      break;
-    case 14:
-      PHS_LAUNCH(m2l_name, s, k_m2l<T, 14><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
-      break;
-    case 12:
-      PHS_LAUNCH(m2l_name, s, k_m2l<T, 12><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
-      break;
-    default:
-      PHS_LAUNCH(m2l_name, s, k_m2l<T, 8><<<nblk, 256, 0, s>>>(A, B, L, P, nd, Ht, h, nchunks, ntiles));
-      break;
+    if (tb.count) {
+      const unsigned nblk = (unsigned)tb.count;
+      switch (lch) {
+        case 16:
+          PHS_LAUNCH(m2l_name, s, kf_m2l<T, 16><<<nblk, 256, 0, s>>>(F.dsys, tb.d, mask, P, Ht, nchunks));
+          break;
+        case 14:
+          PHS_LAUNCH(m2l_name, s, kf_m2l<T, 14><<<nblk, 256, 0, s>>>(F.dsys, tb.d, mask, P, Ht, nchunks));
+          break;
+        case 12:
+          PHS_LAUNCH(m2l_name, s, kf_m2l<T, 12><<<nblk, 256, 0, s>>>(F.dsys, tb.d, mask, P, Ht, nchunks));
+          break;
+        default:
+          PHS_LAUNCH(m2l_name, s, kf_m2l<T, 8><<<nblk, 256, 0, s>>>(F.dsys, tb.d, mask, P, Ht, nchunks));
+          break;
+      }
     }
   }
   // downward pass
-  for (int lc = 3; lc <= L; ++lc) {
-    const int64_t tot = boxes_at(lc) * nd * (P + 1);
-    PHS_LAUNCH("l2l", s,
-               k_l2l<T><<<(tot + 255) / 256, 256, 0, s>>>(B + level_base(lc - 1, P, nd),
-                                                         B + level_base(lc, P, nd), lc, P,
-                                                         nd, L2L));
+  for (int lc = 3; lc <= maxL; ++lc) {
+    const Tab tb = forest_tab(F, tab_key(4, 0, P, lc), s);
+    if (tb.count)
+      PHS_LAUNCH("l2l", s, kf_l2l<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lc, P, L2L));
   }
 }
 
 template <class T, class TN>
-void leaf_pass(Plan &pl, const double *t, double *y_tree, double *y_user, hipStream_t s) {
-  const bool fp64 = std::is_same<T, double>::value;
-  const int P = fp64 ? pl.p64 : pl.p32;
-  const int L = pl.tree.L;
-  const V2<T> *BL = (const V2<T> *)pl.loc + level_base(L, P, pl.R);
-  const int64_t nleaf = boxes_at(L);
+void leaf_pass(Forest &F, const int32_t *mask, int in, int out, int P, const double *logtab,
+               hipStream_t s) {
   const char *name = std::is_same<T, float>::value    ? "leaf_eval_f32"
                      : std::is_same<TN, float>::value ? "leaf_eval_near32"
                                                       : "leaf_eval";
-  if (pl.k == 2)
+  const Tab t2 = forest_tab(F, tab_key(1, 2, 0, 0), s);
+  if (t2.count)
     PHS_LAUNCH(name, s,
-               k_leaf_eval<T, TN, 2><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
-                                                      pl.tree.leaf_start, L, pl.tree.h, P,
-                                                      BL, y_tree, y_user, pl.order, pl.xy2,
-                                                      pl.logtab));
-  else
+               kf_leaf_eval<T, TN, 2><<<(unsigned)t2.count, 64, 0, s>>>(F.dsys, t2.d, mask, P,
+                                                                      in, out, logtab));
+  const Tab t4 = forest_tab(F, tab_key(1, 4, 0, 0), s);
+  if (t4.count)
     PHS_LAUNCH(name, s,
-               k_leaf_eval<T, TN, 4><<<nleaf, 64, 0, s>>>(pl.x, pl.y, pl.ux, pl.uy, t,
-                                                      pl.tree.leaf_start, L, pl.tree.h, P,
-                                                      BL, y_tree, y_user, pl.order, pl.xy2,
-                                                      pl.logtab));
+               kf_leaf_eval<T, TN, 4><<<(unsigned)t4.count, 64, 0, s>>>(F.dsys, t4.d, mask, P,
+                                                                      in, out, logtab));
+}
+
+const Plan &log_ref(const Forest &F) {
+  for (const Plan *p : F.plan)
+    if (p->core_log) return *p;
+  throw Error{PHS_ERR_INVALID_ARGUMENT, "forest has no even-order system"};
 }
 
 }  // namespace
@@ -605,27 +634,37 @@ size_t log_expansion_bytes(int L, int P, int nd, bool fp64) {
   return (size_t)level_base(L + 1, P, nd) * (fp64 ? 16 : 8);
 }
 
-void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user, int precision,
+int m2l_chunk(int P) {
+  // widest of 16/14/12 dividing P+1, else 8 (the last chunk then stores only
+  // its first coefficients)
+  return ((P + 1) % 16 == 0) ? 16 : ((P + 1) % 14 == 0) ? 14 : ((P + 1) % 12 == 0) ? 12 : 8;
+}
+
+void log_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
                 hipStream_t s) {
+  const Plan &ref = log_ref(F);
   if (precision == PHS_MIXED) {
-    far_field<float>(pl, t_tree, pl.p32, pl.lt32, "m2l_f32", s);
-    leaf_pass<float, float>(pl, t_tree, y_tree, y_user, s);
+    far_field<float>(F, mask, in, ref.p32, ref.lt32, "m2l_f32", s);
+    leaf_pass<float, float>(F, mask, in, out, ref.p32, ref.logtab, s);
   } else {
-    far_field<double>(pl, t_tree, pl.p64, pl.lt64, "m2l", s);
-    if (precision == PHS_NEAR32) leaf_pass<double, float>(pl, t_tree, y_tree, y_user, s);
-    else leaf_pass<double, double>(pl, t_tree, y_tree, y_user, s);
+    far_field<double>(F, mask, in, ref.p64, ref.lt64, "m2l", s);
+    if (precision == PHS_NEAR32)
+      leaf_pass<double, float>(F, mask, in, out, ref.p64, ref.logtab, s);
+    else
+      leaf_pass<double, double>(F, mask, in, out, ref.p64, ref.logtab, s);
   }
 }
 
-void log_expansions(Plan &pl, const double *w_tree, hipStream_t s) {
-  far_field<double>(pl, w_tree, pl.pe, pl.pe == pl.p64 ? pl.lt64 : pl.lte, "m2l_eval", s);
+void log_expansions(Plan &pl, int in, hipStream_t s) {
+  Forest &F = *pl.self;
+  far_field<double>(F, F.mask[0], in, pl.pe, pl.pe == pl.p64 ? pl.lt64 : pl.lte, "m2l_eval", s);
 }
 
 void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                       const double *targets, int64_t m, double *out, hipStream_t s) {
   const int P = pl.pe, L = pl.tree.L;
-  const double2 *A = (const double2 *)pl.mp;
-  const double2 *BL = (const double2 *)pl.loc + level_base(L, P, pl.R);
+  const double2 *A = (const double2 *)pl.sw.mp;
+  const double2 *BL = (const double2 *)pl.sw.loc + level_base(L, P, pl.R);
   const int64_t nb = (m + 127) / 128;
   if (pl.k == 2)
     PHS_LAUNCH("eval_targets", s,

@@ -1,0 +1,585 @@
+// Systems and forests: the per-iteration vector kernels of projected PCG
+// (eq. phs_linsys_solve and the projector of Sec. 2) and the Vecchia
+// preconditioner apply (Sec. 2.2, Fig. vecchia_chol), written once over a set
+// of systems.  A launch walks a table of (system, block) items; every system
+// reads its own descriptor, so the arithmetic of one system does not depend on
+// which other systems share the launch.  Reductions are two-stage with a block
+// count that depends only on the system's n, so results are bitwise
+// reproducible and identical alone or in a batch.
+#include <algorithm>
+#include <cstring>
+
+#include "phs_internal.h"
+
+namespace phs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// ------------------------------------------------------------------ elementwise
+__global__ void kf_fill(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                        const int32_t *__restrict__ mask, int slot, double a) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  if (i < d.n) d.v[slot][i] = a;
+}
+
+__global__ void kf_copy(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                        const int32_t *__restrict__ mask, int dst, int src) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  if (i < d.n) d.v[dst][i] = d.v[src][i];
+}
+
+// y = a x + b y
+__global__ void kf_axpby(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                         const int32_t *__restrict__ mask, int y, int x, double a, double b) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  if (i < d.n) d.v[y][i] = a * d.v[x][i] + b * d.v[y][i];
+}
+
+// dst = sign_k * src
+__global__ void kf_scale_sign(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                              const int32_t *__restrict__ mask, int dst, int src) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  if (i < d.n) d.v[dst][i] = (double)d.sign * d.v[src][i];
+}
+
+// v -= Q c, c = sc[SC_PROJ ..]
+__global__ void kf_sub_Qc(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                          const int32_t *__restrict__ mask, int slot) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  if (i >= d.n) return;
+  const cptr<double> Q = ro(d.Q);
+  double s = 0.0;
+  for (int j = 0; j < d.S; ++j) s += Q[(int64_t)j * d.n + i] * d.sc[SC_PROJ + j];
+  rw(d.v[slot])[i] -= s;
+}
+
+// p = z + (rho_new / rho) p
+__global__ void kf_pcg_p(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                         const int32_t *__restrict__ mask) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  const double beta = d.sc[SC_RHO_NEW] / d.sc[SC_RHO];
+  if (i < d.n) d.v[V_P][i] = d.v[V_Z][i] + beta * d.v[V_P][i];
+}
+
+// ------------------------------------------------------------------ reductions
+// Partial sums over the system's nbdot blocks (grid stride nbdot * 256).
+// mode 0: one dot v[a].v[b]; mode 1: S dots Q_t.v[b].
+template <int ND>
+__global__ void kf_dot(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                       const int32_t *__restrict__ mask, int mode, int a, int b) {
+  __shared__ double sh[kBlock / 64];
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = mode == 0 ? 1 : d.S;
+  const int nb = d.nbdot;
+  const cptr<double> vb = ro(d.v[b]), va = ro(d.v[a]), Q = ro(d.Q);
+  double acc[ND];
+#pragma unroll
+  for (int t = 0; t < ND; ++t) acc[t] = 0.0;
+  for (int64_t i = (int64_t)br.blk * kBlock + threadIdx.x; i < d.n; i += (int64_t)nb * kBlock) {
+    const double bi = vb[i];
+    if (mode == 0) {
+      acc[0] += va[i] * bi;
+    } else {
+#pragma unroll
+      for (int t = 0; t < ND; ++t)
+        if (t < nd) acc[t] += Q[(int64_t)t * d.n + i] * bi;
+    }
+  }
+  for (int t = 0; t < ND; ++t) {
+    if (t >= nd) break;
+    const double s = block_sum(acc[t], sh);
+    if (threadIdx.x == 0) d.red[t * nb + br.blk] = s;
+  }
+}
+
+// One block per system: sc[out + t] = sum of the partials of dot t.
+__global__ void kf_dot_final(const SysDev *__restrict__ sys, const int32_t *__restrict__ mask,
+                             int mode, int out) {
+  __shared__ double sh[kBlock / 64];
+  const int sy = blockIdx.x;
+  if (!mask[sy]) return;
+  const SysDev &d = sys[sy];
+  const int nd = mode == 0 ? 1 : d.S;
+  const int nb = d.nbdot;
+  for (int t = 0; t < nd; ++t) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) v += d.red[t * nb + b];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) d.sc[out + t] = s;
+  }
+}
+
+// dw += alpha p, r -= alpha q, alpha = rho / (p.q); partial sums of r.r
+__global__ void kf_pcg_wr(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                          const int32_t *__restrict__ mask) {
+  __shared__ double sh[kBlock / 64];
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nb = d.nbdot;
+  const double alpha = d.sc[SC_RHO] / d.sc[SC_PQ];
+  const gptr<double> w = rw(d.v[V_DW]), r = rw(d.v[V_R]);
+  const cptr<double> p = ro(d.v[V_P]), q = ro(d.v[V_Q]);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)br.blk * kBlock + threadIdx.x; i < d.n; i += (int64_t)nb * kBlock) {
+    w[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) d.red[br.blk] = s;
+}
+
+__global__ void kf_sc_copy(const SysDev *__restrict__ sys, const int32_t *__restrict__ mask,
+                           int nsys, int dst, int src) {
+  const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sy >= nsys || !mask[sy]) return;
+  sys[sy].sc[dst] = sys[sy].sc[src];
+}
+
+__global__ void kf_read_sc(const SysDev *__restrict__ sys, int nsys, int off, int cnt,
+                           double *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsys * cnt) return;
+  const int sy = t / cnt, i = t % cnt;
+  out[sy * 8 + i] = sys[sy].sc[off + i];
+}
+
+// ------------------------------------------------------------------ preconditioner
+// yv = U~^T r: row j holds 1/c_j at j and -lambda/c_j at sigma(j); 32 lanes
+// per row read the node-major entries coalesced, a fixed butterfly sums them.
+// Systems without a factor copy r.
+__global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sys,
+                                                   const BlkRef *__restrict__ tab,
+                                                   const int32_t *__restrict__ mask, int rs,
+                                                   int ys) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t j = (int64_t)br.blk * 8 + (threadIdx.x >> 5);
+  const int g = threadIdx.x & 31;
+  if (j >= d.n) return;
+  const double *r = d.v[rs];
+  if (!d.has_pc) {
+    if (g == 0) d.v[ys][j] = r[j];
+    return;
+  }
+  const int m = d.m;
+  const cptr<int32_t> nbr = ro(d.nbr);
+  const cptr<double> coef = ro(d.coef);
+  const cptr<double> rr = ro(r);
+  double acc = 0.0;
+  for (int s2 = g; s2 < m; s2 += 32) {
+    const int q = nbr[j * m + s2];
+    if (q >= 0) acc += coef[j * m + s2] * rr[q];
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+  if (g == 0) rw(d.v[ys])[j] = ro(d.dinv)[j] * rr[j] + acc;
+}
+
+// z = U~ yv: row gather of the transposed factor (CSR by row).
+__global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys,
+                                                  const BlkRef *__restrict__ tab,
+                                                  const int32_t *__restrict__ mask, int ys,
+                                                  int zs) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int64_t i = (int64_t)br.blk * 8 + (threadIdx.x >> 5);
+  const int g = threadIdx.x & 31;
+  if (i >= d.n) return;
+  const double *yv = d.v[ys];
+  if (!d.has_pc) {
+    if (g == 0) d.v[zs][i] = yv[i];
+    return;
+  }
+  const cptr<int32_t> tstart = ro(d.tstart), tidx = ro(d.tidx);
+  const cptr<double> tcoef = ro(d.tcoef), yy = ro(yv);
+  const int b = tstart[i], e = tstart[i + 1];
+  double acc = 0.0;
+  for (int a = b + g; a < e; a += 32) acc += tcoef[a] * yy[tidx[a]];
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+  if (g == 0) rw(d.v[zs])[i] = ro(d.dinv)[i] * yy[i] + acc;
+}
+
+__global__ void k_gather_one(const double *__restrict__ src, const int32_t *__restrict__ order,
+                             int64_t n, double *__restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[order[i]];
+}
+
+__global__ void k_scatter_one(const double *__restrict__ src, const int32_t *__restrict__ order,
+                              int64_t n, double *__restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i < n) dst[order[i]] = src[i];
+}
+
+Tab upload_tab(const std::vector<BlkRef> &h, hipStream_t s) {
+  Tab t;
+  t.count = (int64_t)h.size();
+  t.d = dmalloc<BlkRef>(std::max<size_t>(h.size(), 1));
+  if (!h.empty())
+    PHS_HIP(hipMemcpyAsync(t.d, h.data(), h.size() * sizeof(BlkRef), hipMemcpyHostToDevice, s));
+  PHS_HIP(hipStreamSynchronize(s));
+  return t;
+}
+
+}  // namespace
+
+void SysWork::release() {
+  dfree(mp);
+  dfree(loc);
+  for (auto &p : v) dfree(p);
+  dfree(red);
+  dfree(sc);
+  mp = loc = nullptr;
+  for (auto &p : v) p = nullptr;
+  red = sc = nullptr;
+}
+
+void alloc_syswork(SysWork &w, const Plan &pl) {
+  try {
+    w.mp = dmalloc<char>(pl.exp_bytes);
+    w.loc = dmalloc<char>(pl.exp_bytes);
+    for (auto &p : w.v) p = dmalloc<double>(pl.n);
+    w.red = dmalloc<double>((size_t)dot_blocks(pl.n) * 32);
+    w.sc = dmalloc<double>(kSysScal);
+  } catch (...) {
+    w.release();
+    throw;
+  }
+}
+
+SysDev make_sysdev(const Plan &pl, const SysWork &w) {
+  SysDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.x = pl.x;
+  d.y = pl.y;
+  d.ux = pl.ux;
+  d.uy = pl.uy;
+  d.xy2 = pl.xy2;
+  d.leaf_start = pl.tree.leaf_start;
+  d.order = pl.order;
+  d.Q = pl.Q;
+  d.nbr = pl.pc_nbr;
+  d.coef = pl.pc_coef;
+  d.dinv = pl.pc_dinv;
+  d.tstart = pl.pc_tstart;
+  d.tidx = pl.pc_tidx;
+  d.tcoef = pl.pc_tcoef;
+  d.mp = w.mp;
+  d.loc = w.loc;
+  for (int i = 0; i < kSysVecs; ++i) d.v[i] = w.v[i];
+  d.red = w.red;
+  d.sc = w.sc;
+  d.n = pl.n;
+  d.h = pl.tree.h;
+  d.S = pl.S;
+  d.L = pl.tree.L;
+  d.k = pl.k;
+  d.R = pl.R;
+  d.sign = pl.sign;
+  d.nbdot = dot_blocks(pl.n);
+  d.m = pl.m;
+  d.has_pc = pl.has_pc ? 1 : 0;
+  return d;
+}
+
+Forest::~Forest() {
+  dfree(dsys);
+  for (int i = 0; i < kMasks; ++i) {
+    if (mask_ev[i]) {
+      (void)hipEventSynchronize(mask_ev[i]);
+      (void)hipEventDestroy(mask_ev[i]);
+    }
+    dfree(mask[i]);
+    if (hmask[i]) (void)hipHostFree(hmask[i]);
+  }
+  dfree(gsc);
+  if (hgsc) (void)hipHostFree(hgsc);
+  dfree(vec.d);
+  dfree(dot.d);
+  dfree(pc.d);
+  for (auto &kv : cache) dfree(kv.second.d);
+}
+
+void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector<SysWork *> &work,
+                  hipStream_t s) {
+  F.plan = plans;
+  F.work = work;
+  F.nsys = (int)plans.size();
+  F.hsys.resize(F.nsys);
+  F.maxS = 1;
+  F.maxL_log = F.maxL_dist = 0;
+  std::vector<BlkRef> hv, hd, hp;
+  for (int i = 0; i < F.nsys; ++i) {
+    const Plan &pl = *plans[i];
+    F.hsys[i] = make_sysdev(pl, *work[i]);
+    F.maxS = std::max(F.maxS, pl.S);
+    if (pl.core_log) F.maxL_log = std::max(F.maxL_log, pl.tree.L);
+    else F.maxL_dist = std::max(F.maxL_dist, pl.tree.L);
+    const int64_t nv = (pl.n + kBlock - 1) / kBlock;
+    for (int64_t b = 0; b < nv; ++b) hv.push_back({i, (int32_t)b});
+    for (int b = 0; b < dot_blocks(pl.n); ++b) hd.push_back({i, b});
+    const int64_t np = (pl.n + 7) / 8;
+    for (int64_t b = 0; b < np; ++b) hp.push_back({i, (int32_t)b});
+  }
+  F.dsys = dmalloc<SysDev>(F.nsys);
+  PHS_HIP(hipMemcpyAsync(F.dsys, F.hsys.data(), F.nsys * sizeof(SysDev), hipMemcpyHostToDevice,
+                         s));
+  for (int i = 0; i < Forest::kMasks; ++i) {
+    F.mask[i] = dmalloc<int32_t>(F.nsys);
+    PHS_HIP(hipHostMalloc((void **)&F.hmask[i], F.nsys * sizeof(int32_t), 0));
+    for (int j = 0; j < F.nsys; ++j) F.hmask[i][j] = 1;
+    PHS_HIP(hipMemcpyAsync(F.mask[i], F.hmask[i], F.nsys * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    PHS_HIP(hipEventCreateWithFlags(&F.mask_ev[i], hipEventDisableTiming));
+    PHS_HIP(hipEventRecord(F.mask_ev[i], s));
+    F.mask_pending[i] = true;
+  }
+  F.gsc = dmalloc<double>((size_t)F.nsys * 8);
+  PHS_HIP(hipHostMalloc((void **)&F.hgsc, (size_t)F.nsys * 8 * sizeof(double), 0));
+  F.vec = upload_tab(hv, s);
+  F.dot = upload_tab(hd, s);
+  F.pc = upload_tab(hp, s);
+}
+
+void refresh_forest(Forest &F, hipStream_t s) {
+  for (int i = 0; i < F.nsys; ++i) F.hsys[i] = make_sysdev(*F.plan[i], *F.work[i]);
+  PHS_HIP(hipMemcpyAsync(F.dsys, F.hsys.data(), F.nsys * sizeof(SysDev), hipMemcpyHostToDevice,
+                         s));
+  PHS_HIP(hipStreamSynchronize(s));
+}
+
+uint64_t tab_key(int kind, int K, int P, int level) {
+  return ((uint64_t)kind << 40) | ((uint64_t)K << 32) | ((uint64_t)P << 8) | (uint64_t)level;
+}
+
+void set_mask(Forest &F, int i, const std::vector<int32_t> &m, hipStream_t s) {
+  if (std::equal(m.begin(), m.end(), F.hmask[i])) return;
+  if (F.mask_pending[i]) PHS_HIP(hipEventSynchronize(F.mask_ev[i]));
+  std::copy(m.begin(), m.end(), F.hmask[i]);
+  PHS_HIP(hipMemcpyAsync(F.mask[i], F.hmask[i], F.nsys * sizeof(int32_t), hipMemcpyHostToDevice,
+                         s));
+  PHS_HIP(hipEventRecord(F.mask_ev[i], s));
+  F.mask_pending[i] = true;
+}
+
+// ------------------------------------------------------------------ launchers
+#define F_GRID(tab) (unsigned)(tab).count
+
+void f_fill(Forest &F, const int32_t *mask, int slot, double a, hipStream_t s) {
+  PHS_LAUNCH("fill", s, kf_fill<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, slot, a));
+}
+
+void f_copy(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s) {
+  PHS_LAUNCH("copy", s, kf_copy<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, dst, src));
+}
+
+void f_axpby(Forest &F, const int32_t *mask, int y, int x, double a, double b, hipStream_t s) {
+  PHS_LAUNCH("axpby", s,
+             kf_axpby<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, y, x, a, b));
+}
+
+void f_scale_sign(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s) {
+  PHS_LAUNCH("scale_sign", s,
+             kf_scale_sign<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, dst, src));
+}
+
+static void dot_launch(Forest &F, const int32_t *mask, int mode, int a, int b, int out,
+                       hipStream_t s) {
+  const int nd = mode == 0 ? 1 : F.maxS;
+  if (nd <= 1)
+    PHS_LAUNCH("dot", s, kf_dot<1><<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, mode, a, b));
+  else if (nd <= 8)
+    PHS_LAUNCH("dot", s, kf_dot<8><<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, mode, a, b));
+  else
+    PHS_LAUNCH("dot", s, kf_dot<32><<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, mode, a, b));
+  PHS_LAUNCH("dot_final", s,
+             kf_dot_final<<<(unsigned)F.nsys, kBlock, 0, s>>>(F.dsys, mask, mode, out));
+}
+
+void f_dot(Forest &F, const int32_t *mask, int a, int b, int out, hipStream_t s) {
+  dot_launch(F, mask, 0, a, b, out, s);
+}
+
+void f_qt(Forest &F, const int32_t *mask, int slot, int out, hipStream_t s) {
+  dot_launch(F, mask, 1, 0, slot, out, s);
+}
+
+void f_project(Forest &F, const int32_t *mask, int slot, hipStream_t s) {
+  dot_launch(F, mask, 1, 0, slot, SC_PROJ, s);
+  PHS_LAUNCH("project", s,
+             kf_sub_Qc<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, slot));
+}
+
+void f_pcg_wr(Forest &F, const int32_t *mask, hipStream_t s) {
+  PHS_LAUNCH("pcg_wr", s, kf_pcg_wr<<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask));
+  PHS_LAUNCH("dot_final", s,
+             kf_dot_final<<<(unsigned)F.nsys, kBlock, 0, s>>>(F.dsys, mask, 0, SC_RR));
+}
+
+void f_pcg_p(Forest &F, const int32_t *mask, hipStream_t s) {
+  PHS_LAUNCH("pcg_p", s, kf_pcg_p<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask));
+}
+
+void f_sc_copy(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s) {
+  PHS_LAUNCH("sc_copy", s,
+             kf_sc_copy<<<(F.nsys + 63) / 64, 64, 0, s>>>(F.dsys, mask, F.nsys, dst, src));
+}
+
+void f_read_scalars(Forest &F, int off, int cnt, hipStream_t s) {
+  const int tot = F.nsys * cnt;
+  PHS_LAUNCH("read_sc", s,
+             kf_read_sc<<<(tot + 255) / 256, 256, 0, s>>>(F.dsys, F.nsys, off, cnt, F.gsc));
+  PHS_HIP(hipMemcpyAsync(F.hgsc, F.gsc, (size_t)F.nsys * 8 * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  PHS_HIP(hipStreamSynchronize(s));
+}
+
+void f_precond_apply(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s) {
+  PHS_LAUNCH("precond_ut", s,
+             kf_apply_ut<<<F_GRID(F.pc), 256, 0, s>>>(F.dsys, F.pc.d, mask, r, tmp));
+  PHS_LAUNCH("precond_u", s,
+             kf_apply_u<<<F_GRID(F.pc), 256, 0, s>>>(F.dsys, F.pc.d, mask, tmp, z));
+}
+
+void f_precond(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s) {
+  f_precond_apply(F, mask, r, z, tmp, s);
+  f_project(F, mask, z, s);
+}
+
+void f_gather_user(Forest &F, int sys, const double *src_user, int slot, hipStream_t s) {
+  const SysDev &d = F.hsys[sys];
+  PHS_LAUNCH("gather", s,
+             k_gather_one<<<(unsigned)((d.n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+                 src_user, d.order, d.n, d.v[slot]));
+}
+
+void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t s) {
+  const SysDev &d = F.hsys[sys];
+  PHS_LAUNCH("scatter", s,
+             k_scatter_one<<<(unsigned)((d.n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+                 d.v[slot], d.order, d.n, dst_user));
+}
+
+void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hipStream_t s) {
+  if (F.maxL_log > 0) log_matvec(F, mask, in, out, precision, s);
+  if (F.maxL_dist > 0) dist_matvec(F, mask, in, out, precision, s);
+}
+
+// Work-item tables of the FMM kernels, built on first use per (kind, K, P,
+// level) and kept for the forest's lifetime.
+Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s);
+
+Tab forest_tab(Forest &F, uint64_t key, hipStream_t s) {
+  for (auto &kv : F.cache)
+    if (kv.first == key) return kv.second;
+  const int kind = (int)(key >> 40), K = (int)((key >> 32) & 0xff),
+            P = (int)((key >> 8) & 0xffffff), level = (int)(key & 0xff);
+  F.cache.push_back({key, build_fmm_tab(F, kind, K, P, level, s)});
+  return F.cache.back().second;
+}
+
+// kinds: 1 leaf (k == K), 2 P2M groups of 4 x P leaves (k == K), 3 log M2M level,
+// 4 log L2L level, 5 log M2L, 7 Chebyshev M2M level, 8 Chebyshev L2L level,
+// 9 Chebyshev M2L
+int m2l_chunk(int P);
+
+Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
+  std::vector<BlkRef> h;
+  for (int i = 0; i < F.nsys; ++i) {
+    const Plan &pl = *F.plan[i];
+    const int L = pl.tree.L, R = pl.R;
+    const bool log_k = pl.core_log;
+    switch (kind) {
+      case 1:
+        if (pl.k == K)
+          for (int64_t b = 0; b < boxes_at(L); ++b) h.push_back({i, (int32_t)b});
+        break;
+      case 2:  // P = leaves per wavefront; four wavefronts per item
+        if (pl.k == K)
+          for (int64_t b = 0; b < boxes_at(L) / (4 * P); ++b) h.push_back({i, (int32_t)b});
+        break;
+      case 3:  // M2M into level `level` from level+1
+        if (log_k && L > level) {
+          const int64_t tot = boxes_at(level) * R * (P + 1);
+          for (int64_t b = 0; b < (tot + 255) / 256; ++b) h.push_back({i, (int32_t)b});
+        }
+        break;
+      case 4:  // L2L into level `level` from level-1
+        if (log_k && L >= level) {
+          const int64_t tot = boxes_at(level) * R * (P + 1);
+          for (int64_t b = 0; b < (tot + 255) / 256; ++b) h.push_back({i, (int32_t)b});
+        }
+        break;
+      case 5:
+        if (log_k) {
+          int64_t tot = 0;
+          for (int l = 2; l <= L; ++l) tot += boxes_at(l);
+          const int64_t ntiles = (tot + 255) / 256;
+          const int lch = m2l_chunk(P);
+          const int64_t nch = (P + 1 + lch - 1) / lch;
+          for (int64_t b = 0; b < ntiles * nch * R; ++b) h.push_back({i, (int32_t)b});
+        }
+        break;
+      case 7:
+        if (!log_k && L > level)
+          for (int64_t b = 0; b < boxes_at(level) * R; ++b) h.push_back({i, (int32_t)b});
+        break;
+      case 8:
+        if (!log_k && L >= level)
+          for (int64_t b = 0; b < boxes_at(level) * R; ++b) h.push_back({i, (int32_t)b});
+        break;
+      case 9:
+        if (!log_k) {
+          int64_t tiles = 0;
+          for (int l = 2; l <= L; ++l) tiles += (boxes_at(l) * R + 63) / 64;
+          for (int64_t b = 0; b < tiles; ++b) h.push_back({i, (int32_t)b});
+        }
+        break;
+      default:
+        throw Error{PHS_ERR_INVALID_ARGUMENT, "unknown table kind"};
+    }
+  }
+  return upload_tab(h, s);
+}
+
+}  // namespace phs

@@ -59,6 +59,24 @@ struct ProfScope {
     PHS_HIP(hipGetLastError());                                               \
   } while (0)
 
+// ------------------------------------------------------------------ address spaces
+// Kernels reach most arrays through per-system descriptors, i.e. as generic
+// pointers read from memory.  Read-only inputs are viewed through the
+// constant address space (a wave-uniform address then becomes a scalar load)
+// and outputs through the global one (global rather than flat stores).
+template <class T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ cptr<T> ro(const T *p) {
+  return (cptr<T>)(p);
+}
+template <class T>
+__device__ __forceinline__ gptr<T> rw(T *p) {
+  return (gptr<T>)(p);
+}
+
 // ------------------------------------------------------------------ memory
 template <class T>
 T *dmalloc(size_t count) {
@@ -128,6 +146,53 @@ struct ChebTables {  // Chebyshev interpolation tables for Q nodes per axis
   float *K32 = nullptr;
 };
 
+// ------------------------------------------------------------------ systems
+// A "system" is one right-hand side being solved on one plan: it owns the
+// PCG vectors, the FMM expansion slabs and the reduction scratch, and shares
+// the plan's tree, polynomial block and preconditioner.  Every per-iteration
+// kernel runs over a set of systems (a forest: one plan alone, or many plans
+// in a batch) through a table of (system, block) work items, so a system's
+// arithmetic is the same whatever else runs in the launch.
+constexpr int kSysVecs = 10;
+constexpr int kSysScal = 128;
+enum VecSlot { V_F = 0, V_R, V_W, V_Z, V_P, V_Q, V_TMP, V_DW, V_IN, V_OUT };
+// device scalar slots: [0] rho_new [1] rho [2] p.q [3] r.r [4] generic dot
+// [8..8+S) projection coefficients, [40..40+S) Q^T (f - M w)
+enum ScalSlot { SC_RHO_NEW = 0, SC_RHO = 1, SC_PQ = 2, SC_RR = 3, SC_DOT = 4, SC_PROJ = 8,
+                SC_QTF = 40 };
+
+struct SysDev {
+  const double *x, *y;
+  const float *ux, *uy;
+  const double2 *xy2;
+  const int32_t *leaf_start;
+  const int32_t *order;
+  const double *Q;
+  const int32_t *nbr;
+  const double *coef, *dinv;
+  const int32_t *tstart, *tidx;
+  const double *tcoef;
+  void *mp, *loc;
+  double *v[kSysVecs];
+  double *red;
+  double *sc;
+  int64_t n;
+  double h;
+  int32_t S, L, k, R, sign, nbdot, m, has_pc;
+};
+
+struct BlkRef {
+  int32_t sys, blk;
+};
+
+struct SysWork {  // device workspace of one system
+  void *mp = nullptr, *loc = nullptr;
+  double *v[kSysVecs] = {};
+  double *red = nullptr;
+  double *sc = nullptr;
+  void release();
+};
+
 // ------------------------------------------------------------------ plan
 struct Plan {
   int64_t n = 0;
@@ -157,20 +222,17 @@ struct Plan {
   double *Q = nullptr;  // n x S column-major, tree order, orthonormal columns
   std::vector<double> Rm;  // S x S upper triangular (row-major), B = Q R
 
-  // FMM workspace (sized for FP64 at the largest order in use)
-  void *mp = nullptr;   // multipole expansions levels 2..L
-  void *loc = nullptr;  // local expansions levels 2..L
+  // FMM workspace of one system, in bytes (FP64 at the largest order in use)
   size_t exp_bytes = 0;
   LogTables lt64, lt32;  // tables for p64 (FP64) and p32 (FP32)
   ChebTables ct64, ct32;
   LogTables lte;         // tables for pe when pe != p64
   ChebTables cte;        // tables for qe when qe != q64
 
-  // vectors (tree order), n each
-  double *v_t = nullptr;    // density in tree order
-  double *v_y = nullptr;    // matvec output in tree order
-  double *wk[8] = {};       // PCG work vectors
-  double *red = nullptr;    // reduction partials
+  // the plan's own system (matvec, solve one column at a time, evaluation)
+  SysWork sw;
+  struct Forest *self = nullptr;
+  double *red = nullptr;    // reduction partials (plan-time reductions)
   int red_cap = 0;
   double *scal = nullptr;   // device scalars
   double *hscal = nullptr;  // pinned host mirror
@@ -191,6 +253,102 @@ struct Plan {
 
   ~Plan();
 };
+
+// ------------------------------------------------------------------ forest
+struct Tab {
+  BlkRef *d = nullptr;
+  int64_t count = 0;
+};
+
+struct Forest {
+  std::vector<Plan *> plan;   // plan of each system
+  std::vector<SysWork *> work;
+  std::vector<SysDev> hsys;
+  SysDev *dsys = nullptr;
+  int nsys = 0;
+  int maxS = 1;
+  int maxL_log = 0, maxL_dist = 0;
+  // masks: device int32[nsys] each, host pinned mirrors
+  static constexpr int kMasks = 10;
+  int32_t *mask[kMasks] = {};
+  int32_t *hmask[kMasks] = {};   // pinned staging of the last upload
+  hipEvent_t mask_ev[kMasks] = {};
+  bool mask_pending[kMasks] = {};
+  double *gsc = nullptr, *hgsc = nullptr;  // packed scalar readback (nsys x 8)
+  Tab vec, dot, pc;                     // element blocks, dot blocks, 8-row blocks
+  std::vector<std::pair<uint64_t, Tab>> cache;  // FMM tables keyed by (kind, K, P, level)
+  ~Forest();
+};
+
+// build a forest over systems (plan[i], work[i]); uploads descriptors and the
+// element/dot/preconditioner tables.  refresh_forest re-reads the plans'
+// preconditioner pointers after phs_precond_build.
+void build_forest(Forest &F, const std::vector<Plan *> &plans,
+                  const std::vector<SysWork *> &work, hipStream_t s);
+void refresh_forest(Forest &F, hipStream_t s);
+void alloc_syswork(SysWork &w, const Plan &pl);
+Tab forest_tab(Forest &F, uint64_t key, hipStream_t s);
+// log-kernel P2M packs this many leaves per wavefront (lane = coefficient)
+__host__ __device__ inline int p2m_leaves_per_wave(int P) {
+  const int g = 64 / (P + 1);
+  return g >= 4 ? 4 : (g >= 2 ? 2 : 1);
+}
+int m2l_chunk(int P);
+uint64_t tab_key(int kind, int K, int P, int level);
+SysDev make_sysdev(const Plan &pl, const SysWork &w);
+
+// set device mask i to m (nsys flags); uploads only when it changes, and
+// never rewrites the pinned staging buffer while its last copy is in flight
+void set_mask(Forest &F, int i, const std::vector<int32_t> &m, hipStream_t s);
+
+// forest vector operations (systems with mask[sys] != 0)
+void f_fill(Forest &F, const int32_t *mask, int slot, double a, hipStream_t s);
+void f_copy(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s);
+void f_axpby(Forest &F, const int32_t *mask, int y, int x, double a, double b, hipStream_t s);
+void f_scale_sign(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s);
+void f_dot(Forest &F, const int32_t *mask, int a, int b, int out, hipStream_t s);
+void f_project(Forest &F, const int32_t *mask, int slot, hipStream_t s);
+void f_qt(Forest &F, const int32_t *mask, int slot, int out, hipStream_t s);
+void f_pcg_wr(Forest &F, const int32_t *mask, hipStream_t s);
+void f_pcg_p(Forest &F, const int32_t *mask, hipStream_t s);
+void f_sc_copy(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s);
+void f_read_scalars(Forest &F, int off, int cnt, hipStream_t s);  // -> F.hgsc[sys*8+i]
+// z = Pi U~ U~^T r (f_precond) or U~ U~^T r (f_precond_apply)
+void f_precond(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s);
+void f_precond_apply(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s);
+void f_gather_user(Forest &F, int sys, const double *src_user, int slot, hipStream_t s);
+void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t s);
+// y[out] = M v[in] for every masked system, in tree order
+void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hipStream_t s);
+
+// one right-hand side of one system: inputs in caller order, results
+struct SolveJob {
+  int sys = 0;
+  const double *f = nullptr;
+  double *w_out = nullptr;
+  double *beta_out = nullptr;
+  int iters = 0, outer = 0;
+  double rel = 0.0, bn = 0.0;
+  phs_status status = PHS_OK;
+  std::vector<double> beta_host;
+};
+void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit,
+                  int check_every, int prec, hipStream_t s);
+
+// ------------------------------------------------------------------ batch
+struct Batch {
+  std::vector<Plan *> plans;
+  std::vector<int> nrhs;
+  std::vector<SysWork> works;  // one per system
+  std::vector<int> sys_plan, sys_col;
+  Forest F;
+  ~Batch();
+};
+void batch_create(Batch &b, const std::vector<Plan *> &plans, const std::vector<int> &nrhs,
+                  hipStream_t s);
+phs_status batch_solve(Batch &b, const double *const *f, double *const *w,
+                       double *const *beta, const phs_solve_opts *o, phs_solve_info *info,
+                       hipStream_t s);
 
 // ------------------------------------------------------------------ launchers
 // tree.hip
@@ -252,19 +410,19 @@ void copy(double *dst, const double *src, int64_t n, hipStream_t s);
 void build_log_tables(LogTables &t, int P);
 void free_log_tables(LogTables &t);
 size_t log_expansion_bytes(int L, int P, int ndens, bool fp64);
-void log_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user,
-                int precision, hipStream_t s);
-// Upward pass only (for evaluation at targets): fills pl.mp/pl.loc with
-// expansions of the densities V_r * w.
-void log_expansions(Plan &pl, const double *w_tree, hipStream_t s);
+// even-k systems of the forest: y[out] = M v[in]
+void log_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
+                hipStream_t s);
+// expansions at the evaluation order of system `sys` of the plan's own forest
+void log_expansions(Plan &pl, int in, hipStream_t s);
 
 // fmm_dist.hip
 void build_cheb_tables(ChebTables &t, int Q);
 void free_cheb_tables(ChebTables &t);
 size_t cheb_expansion_bytes(int L, int Q, int ndens, bool fp64);
-void dist_matvec(Plan &pl, const double *t_tree, double *y_tree, double *y_user,
-                 int precision, hipStream_t s);
-void dist_expansions(Plan &pl, const double *w_tree, hipStream_t s);
+void dist_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
+                 hipStream_t s);
+void dist_expansions(Plan &pl, int in, hipStream_t s);
 
 void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                       const double *targets, int64_t m, double *out, hipStream_t s);
@@ -273,14 +431,9 @@ void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,
 
 // vecchia.hip
 void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s);
-void vecchia_apply(Plan &pl, const double *r, double *z, double *tmp,
-                   hipStream_t s);
 void vecchia_free(Plan &pl);
 void vecchia_export(Plan &pl, int32_t *rank, int32_t *nbr, double *coef, double *diag,
                     hipStream_t s);
 
-// api.hip
-void matvec_tree(Plan &pl, const double *t_tree, double *y_tree, int precision,
-                 hipStream_t s);
 
 }  // namespace phs

@@ -1,0 +1,321 @@
+// Projected PCG over a forest of systems (paper eq. phs_linsys_solve with the
+// preconditioner of Sec. 2.2), in lockstep: every GPU step of the method is
+// one masked launch over all systems that take that step in the current
+// round, so one plan alone and many plans in a batch run the same arithmetic
+// per system.
+//
+// Per system (x0 = 0, b = sign_k Pi f):
+//   FP64:  PCG on sign_k Pi M Pi with z = Pi U~ U~^T r, stop when
+//          ||r|| <= rtol ||b||, r the recursively updated residual.
+//   MIXED / NEAR32: iterative refinement.  Inner PCG on the FP32 operator
+//          for the correction dw, then w += dw and the FP64 residual
+//          r = sign_k Pi (f - M64 w).  An inner solve that breaks down at
+//          once, or an outer step that does not halve the FP64 residual,
+//          switches the rest of the solve to the FP64 operator.  The exit test
+//          is always on the FP64 residual.
+//   Then beta from R beta = Q^T (f - M64 w), and the FP64 relative residual.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "phs_internal.h"
+
+namespace phs {
+
+namespace {
+
+enum JobState { J_INIT, J_START, J_PCG, J_PCG_END, J_RESID, J_FINISH, J_DONE };
+
+// masks of the solve (slot 0 is all ones and never changed)
+enum MaskSlot {
+  MK_ALL = 0,
+  MK_PCG = 1,
+  MK_P64 = 2,
+  MK_P32 = 3,
+  MK_PN32 = 4,
+  MK_CONT = 5,
+  MK_START = 6,
+  MK_RESID = 7,
+  MK_FINISH = 8,
+  MK_UPD = 9
+};
+
+struct JobRun {
+  SolveJob *job;
+  JobState state = J_INIT;
+  double bn = 0, fn = 0, tol_abs = 0, rn = 0;
+  // PCG
+  int it = 0, maxit_inner = 0, inner_prec = PHS_FP64;
+  double inner_tol = 0;
+  bool pcg_conv = false, pcg_break = false;
+  // refinement
+  int budget = 0;
+  bool fp64_finish = false;
+  bool count_outer = false;
+  bool apply_dw = false;  // fold the inner iterate into w this round
+};
+
+void set_mask(Forest &F, int slot, const std::vector<JobRun> &jr, bool (*pred)(const JobRun &),
+              bool &any, hipStream_t s) {
+  std::vector<int32_t> m(F.nsys, 0);
+  any = false;
+  for (const auto &r : jr)
+    if (pred(r)) {
+      m[r.job->sys] = 1;
+      any = true;
+    }
+  set_mask(F, slot, m, s);
+}
+
+}  // namespace
+
+void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit,
+                  int check_every, int prec, hipStream_t s) {
+  PHS_REQUIRE(F.nsys >= 1 && Forest::kMasks >= 10, PHS_ERR_INVALID_ARGUMENT, "empty forest");
+  const bool mixed = prec != PHS_FP64;
+  std::vector<JobRun> jr(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) jr[i].job = &jobs[i];
+  bool any = false;
+
+  // ---- INIT: f in tree order, b = sign Pi f, ||b||, ||f||
+  for (auto &r : jr) f_gather_user(F, r.job->sys, r.job->f, V_F, s);
+  set_mask(F, MK_START, jr, [](const JobRun &r) { return r.state == J_INIT; }, any, s);
+  f_scale_sign(F, F.mask[MK_START], V_R, V_F, s);
+  f_project(F, F.mask[MK_START], V_R, s);
+  f_dot(F, F.mask[MK_START], V_R, V_R, SC_DOT, s);
+  f_dot(F, F.mask[MK_START], V_F, V_F, SC_DOT + 1, s);
+  f_fill(F, F.mask[MK_START], V_W, 0.0, s);
+  f_read_scalars(F, SC_DOT, 2, s);
+  for (auto &r : jr) {
+    const int sy = r.job->sys;
+    r.bn = std::sqrt(F.hgsc[sy * 8 + 0]);
+    r.fn = std::sqrt(F.hgsc[sy * 8 + 1]);
+    r.job->bn = r.bn;
+    r.tol_abs = rtol * r.bn;
+    r.rn = r.bn;
+    r.budget = maxit;
+    if (r.bn <= 1e-13 * r.fn) {
+      // data in span(B) to rounding level: the polynomial alone interpolates
+      r.state = J_FINISH;
+    } else {
+      r.state = J_START;
+    }
+  }
+
+  auto start_pcg = [&](JobRun &r) {
+    if (!mixed) {
+      r.inner_prec = PHS_FP64;
+      r.inner_tol = r.tol_abs;
+      r.maxit_inner = maxit;
+    } else {
+      // FP32 far field: small steps (its error is relative to ||M||); FP32
+      // near field only: the operator is accurate enough to go to rtol at once
+      r.inner_prec = r.fp64_finish ? PHS_FP64 : prec;
+      r.inner_tol = r.fp64_finish ? r.tol_abs
+                                  : (prec == PHS_NEAR32 ? 0.5 * r.tol_abs
+                                                        : std::max(r.tol_abs, 1e-4 * r.rn));
+      r.maxit_inner = (r.fp64_finish || prec == PHS_NEAR32) ? r.budget : std::min(r.budget, 60);
+    }
+    r.it = 0;
+    r.pcg_conv = r.pcg_break = false;
+    r.state = J_START;
+  };
+  for (auto &r : jr)
+    if (r.state == J_START) start_pcg(r);
+
+  for (;;) {
+    bool live = false;
+    for (auto &r : jr) live = live || r.state != J_DONE;
+    if (!live) break;
+
+    // ---- START: dw = 0, z = precond(r), rho = r.z, p = z
+    set_mask(F, MK_START, jr, [](const JobRun &r) { return r.state == J_START; }, any, s);
+    if (any) {
+      f_fill(F, F.mask[MK_START], V_DW, 0.0, s);
+      f_precond(F, F.mask[MK_START], V_R, V_Z, V_TMP, s);
+      f_dot(F, F.mask[MK_START], V_R, V_Z, SC_RHO, s);
+      f_copy(F, F.mask[MK_START], V_P, V_Z, s);
+      for (auto &r : jr)
+        if (r.state == J_START) r.state = J_PCG;
+    }
+
+    // ---- PCG iteration
+    set_mask(F, MK_PCG, jr, [](const JobRun &r) { return r.state == J_PCG; }, any, s);
+    if (any) {
+      bool a64 = false, a32 = false, an32 = false;
+      set_mask(F, MK_P64, jr,
+               [](const JobRun &r) { return r.state == J_PCG && r.inner_prec == PHS_FP64; }, a64,
+               s);
+      set_mask(F, MK_P32, jr,
+               [](const JobRun &r) { return r.state == J_PCG && r.inner_prec == PHS_MIXED; },
+               a32, s);
+      set_mask(F, MK_PN32, jr,
+               [](const JobRun &r) { return r.state == J_PCG && r.inner_prec == PHS_NEAR32; },
+               an32, s);
+      // q = sign Pi M p
+      if (a64) f_matvec(F, F.mask[MK_P64], V_P, V_Q, PHS_FP64, s);
+      if (a32) f_matvec(F, F.mask[MK_P32], V_P, V_Q, PHS_MIXED, s);
+      if (an32) f_matvec(F, F.mask[MK_PN32], V_P, V_Q, PHS_NEAR32, s);
+      f_project(F, F.mask[MK_PCG], V_Q, s);
+      f_scale_sign(F, F.mask[MK_PCG], V_Q, V_Q, s);
+      f_dot(F, F.mask[MK_PCG], V_P, V_Q, SC_PQ, s);
+      const int32_t *upd_mask = F.mask[MK_PCG];
+      if (check_every == 1 && (a32 || an32)) {
+        // curvature check before the update so a breakdown step of an inexact
+        // (FP32) operator is never applied
+        f_read_scalars(F, SC_PQ, 1, s);
+        bool drop = false;
+        for (auto &r : jr)
+          if (r.state == J_PCG && r.inner_prec != PHS_FP64 &&
+              !(F.hgsc[r.job->sys * 8] > 0.0)) {
+            r.pcg_break = true;
+            r.state = J_PCG_END;
+            drop = true;
+          }
+        if (drop) {
+          set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.state == J_PCG; }, any, s);
+          upd_mask = F.mask[MK_UPD];
+        }
+      }
+      f_pcg_wr(F, upd_mask, s);
+      bool need_check = false;
+      for (auto &r : jr)
+        if (r.state == J_PCG) {
+          ++r.it;
+          if (r.it % check_every == 0 || r.it == r.maxit_inner) need_check = true;
+        }
+      if (need_check) f_read_scalars(F, 0, 4, s);
+      for (auto &r : jr) {
+        if (r.state != J_PCG) continue;
+        if (!(r.it % check_every == 0 || r.it == r.maxit_inner)) continue;
+        const double *g = F.hgsc + r.job->sys * 8;
+        if (!(g[SC_PQ] > 0.0)) {
+          r.pcg_break = true;
+          r.state = J_PCG_END;
+        } else if (std::sqrt(g[SC_RR]) <= r.inner_tol) {
+          r.pcg_conv = true;
+          r.state = J_PCG_END;
+        } else if (r.it >= r.maxit_inner) {
+          r.state = J_PCG_END;
+        }
+      }
+      // z = precond(r), rho_new = r.z, p = z + (rho_new / rho) p, rho = rho_new
+      set_mask(F, MK_CONT, jr, [](const JobRun &r) { return r.state == J_PCG; }, any, s);
+      if (any) {
+        f_precond(F, F.mask[MK_CONT], V_R, V_Z, V_TMP, s);
+        f_dot(F, F.mask[MK_CONT], V_R, V_Z, SC_RHO_NEW, s);
+        f_pcg_p(F, F.mask[MK_CONT], s);
+        f_sc_copy(F, F.mask[MK_CONT], SC_RHO, SC_RHO_NEW, s);
+      }
+    }
+
+    // ---- end of an inner solve
+    for (auto &r : jr) {
+      if (r.state != J_PCG_END) continue;
+      r.job->iters += r.it;
+      if (!mixed) {
+        if (r.pcg_break) r.job->status = PHS_ERR_BREAKDOWN;
+        else if (!r.pcg_conv) r.job->status = PHS_ERR_NOT_CONVERGED;
+        r.state = J_FINISH;
+        r.apply_dw = true;
+        continue;
+      }
+      r.budget -= r.it;
+      if (r.pcg_break && r.it <= 1) {
+        if (r.fp64_finish) {
+          r.job->status = PHS_ERR_BREAKDOWN;
+          r.state = J_FINISH;
+          continue;
+        }
+        r.fp64_finish = true;  // no usable FP32 step: restart this residual in FP64
+        r.count_outer = false;
+        r.state = J_RESID;
+        continue;
+      }
+      r.count_outer = true;
+      r.apply_dw = true;
+      r.state = J_RESID;
+    }
+    // w = dw (FP64: the PCG iterate) or w += dw (refinement)
+    set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.apply_dw; }, any, s);
+    if (any) {
+      if (mixed) f_axpby(F, F.mask[MK_UPD], V_W, V_DW, 1.0, 1.0, s);
+      else f_copy(F, F.mask[MK_UPD], V_W, V_DW, s);
+    }
+    for (auto &r : jr) r.apply_dw = false;
+
+    // ---- FP64 residual of the refinement: r = sign Pi (f - M64 w)
+    set_mask(F, MK_RESID, jr, [](const JobRun &r) { return r.state == J_RESID; }, any, s);
+    if (any) {
+      f_matvec(F, F.mask[MK_RESID], V_W, V_Q, PHS_FP64, s);
+      f_axpby(F, F.mask[MK_RESID], V_Q, V_F, 1.0, -1.0, s);  // q = f - M w
+      f_scale_sign(F, F.mask[MK_RESID], V_R, V_Q, s);
+      f_project(F, F.mask[MK_RESID], V_R, s);
+      f_dot(F, F.mask[MK_RESID], V_R, V_R, SC_DOT, s);
+      f_read_scalars(F, SC_DOT, 1, s);
+      for (auto &r : jr) {
+        if (r.state != J_RESID) continue;
+        if (r.count_outer) {
+          const double rn_new = std::sqrt(F.hgsc[r.job->sys * 8]);
+          ++r.job->outer;
+          if (!(rn_new < 0.5 * r.rn)) r.fp64_finish = true;
+          r.rn = rn_new;
+          if (!std::isfinite(r.rn)) {
+            r.job->status = PHS_ERR_BREAKDOWN;
+            r.state = J_FINISH;
+            continue;
+          }
+        }
+        if (r.rn > r.tol_abs && r.budget > 0) {
+          start_pcg(r);
+        } else {
+          if (r.rn > r.tol_abs && r.job->status == PHS_OK) r.job->status = PHS_ERR_NOT_CONVERGED;
+          r.state = J_FINISH;
+        }
+      }
+    }
+
+    // ---- beta from R beta = Q^T (f - M w), the FP64 residual, w to the caller
+    set_mask(F, MK_FINISH, jr, [](const JobRun &r) { return r.state == J_FINISH; }, any, s);
+    if (any) {
+      f_matvec(F, F.mask[MK_FINISH], V_W, V_Q, PHS_FP64, s);
+      f_axpby(F, F.mask[MK_FINISH], V_Q, V_F, 1.0, -1.0, s);  // q = f - M w
+      f_qt(F, F.mask[MK_FINISH], V_Q, SC_QTF, s);
+      f_project(F, F.mask[MK_FINISH], V_Q, s);
+      f_dot(F, F.mask[MK_FINISH], V_Q, V_Q, SC_DOT, s);
+      // Q^T q (S <= 28 values) and ||Pi q||^2 per system
+      std::vector<std::vector<double>> qtf(jr.size());
+      for (int off = 0; off < F.maxS; off += 8) {
+        const int cnt = std::min(8, F.maxS - off);
+        f_read_scalars(F, SC_QTF + off, cnt, s);
+        for (size_t i = 0; i < jr.size(); ++i) {
+          if (jr[i].state != J_FINISH) continue;
+          for (int c = 0; c < cnt; ++c)
+            qtf[i].push_back(F.hgsc[jr[i].job->sys * 8 + c]);
+        }
+      }
+      f_read_scalars(F, SC_DOT, 1, s);
+      for (size_t i = 0; i < jr.size(); ++i) {
+        JobRun &r = jr[i];
+        if (r.state != J_FINISH) continue;
+        const Plan &pl = *F.plan[r.job->sys];
+        const int S = pl.S;
+        std::vector<double> bet(S);
+        for (int a = S - 1; a >= 0; --a) {
+          double acc = qtf[i][a];
+          for (int k2 = a + 1; k2 < S; ++k2) acc -= pl.Rm[(size_t)a * S + k2] * bet[k2];
+          bet[a] = acc / pl.Rm[(size_t)a * S + a];
+        }
+        r.job->beta_host = bet;
+        r.job->rel = r.bn > 0 ? std::sqrt(F.hgsc[r.job->sys * 8]) / r.bn : 0.0;
+        PHS_HIP(hipMemcpyAsync(r.job->beta_out, r.job->beta_host.data(), S * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        f_scatter_user(F, r.job->sys, V_W, r.job->w_out, s);
+        r.state = J_DONE;
+      }
+      PHS_HIP(hipStreamSynchronize(s));
+    }
+  }
+}
+
+}  // namespace phs

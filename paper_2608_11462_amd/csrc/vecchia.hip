@@ -429,42 +429,6 @@ __global__ void k_tfill(const int32_t *vals, int64_t nnz, int64_t n, int m, cons
   tcoef[p] = coef[e];
 }
 
-// ---------------------------------------------------------------- apply
-// y = U~^T r: row j of U~^T holds 1/c_j at j and -lambda/c_j at sigma(j);
-// 32 lanes per row read the node-major entries coalesced.
-__global__ __launch_bounds__(256) void k_apply_ut(const double *r, int64_t n, int m,
-                                                  const int32_t *nbr, const double *coef,
-                                                  const double *dinv, double *yv) {
-  const int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 5;
-  const int g = threadIdx.x & 31;
-  if (j >= n) return;
-  double acc = 0.0;
-  for (int s2 = g; s2 < m; s2 += 32) {
-    const int q = nbr[j * m + s2];
-    if (q >= 0) acc += coef[j * m + s2] * r[q];
-  }
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-  if (g == 0) yv[j] = dinv[j] * r[j] + acc;
-}
-
-// Row gather of the transposed factor, 32 lanes per row: lanes stride over the
-// row's entries (coalesced) and a fixed butterfly sums the partial sums.
-__global__ __launch_bounds__(256) void k_apply_u(const double *yv, int64_t n,
-                                                 const int32_t *tstart, const int32_t *tidx,
-                                                 const double *tcoef, const double *dinv,
-                                                 double *z) {
-  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 5;
-  const int g = threadIdx.x & 31;
-  if (i >= n) return;
-  const int b = tstart[i], e = tstart[i + 1];
-  double acc = 0.0;
-  for (int a = b + g; a < e; a += 32) acc += tcoef[a] * yv[tidx[a]];
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-  if (g == 0) z[i] = dinv[i] * yv[i] + acc;
-}
-
 // export in caller order
 __global__ void k_export(int64_t n, int m, const int32_t *order, const int32_t *rank_tree,
                          const int32_t *nbr, const double *coef, const double *dinv,
@@ -661,17 +625,6 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
                   (void *)d_coff, (void *)d_gb, (void *)xr, (void *)yr, (void *)pos_of_rank,
                   (void *)cnt, (void *)nfail})
     dfree(q);
-}
-
-void vecchia_apply(Plan &pl, const double *r, double *z, double *tmp, hipStream_t s) {
-  const int64_t n = pl.n;
-  const int B = 256;
-  PHS_LAUNCH("precond_ut", s,
-             k_apply_ut<<<(n * 32 + B - 1) / B, B, 0, s>>>(r, n, pl.m, pl.pc_nbr, pl.pc_coef,
-                                                          pl.pc_dinv, tmp));
-  PHS_LAUNCH("precond_u", s,
-             k_apply_u<<<(n * 32 + B - 1) / B, B, 0, s>>>(tmp, n, pl.pc_tstart, pl.pc_tidx,
-                                                         pl.pc_tcoef, pl.pc_dinv, z));
 }
 
 void vecchia_export(Plan &pl, int32_t *rank, int32_t *nbr, double *coef, double *diag,

@@ -26,7 +26,8 @@ STATUS = {
 
 EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval",
            "phs_plan_info", "phs_plan_tree", "phs_precond_export", "phs_precond_apply",
-           "phs_plan_destroy", "phs_last_error", "phs_profile_enable", "phs_profile_read")
+           "phs_plan_destroy", "phs_batch_create", "phs_batch_solve", "phs_batch_destroy",
+           "phs_last_error", "phs_profile_enable", "phs_profile_read")
 
 
 class PlanOpts(C.Structure):
@@ -82,6 +83,11 @@ def lib() -> C.CDLL:
         L.phs_precond_apply.argtypes = [vp, dp, dp, vp]
         L.phs_plan_destroy.argtypes = [vp]
         L.phs_plan_destroy.restype = None
+        L.phs_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(i32), vp, C.POINTER(vp)]
+        L.phs_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                      C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.phs_batch_destroy.argtypes = [vp]
+        L.phs_batch_destroy.restype = None
         L.phs_last_error.restype = C.c_char_p
         L.phs_profile_enable.argtypes = [i32]
         L.phs_profile_enable.restype = None
@@ -89,7 +95,7 @@ def lib() -> C.CDLL:
         L.phs_profile_read.restype = i32
         for name in ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval",
                      "phs_plan_info", "phs_plan_tree", "phs_precond_export",
-                     "phs_precond_apply"):
+                     "phs_precond_apply", "phs_batch_create", "phs_batch_solve"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -224,6 +230,62 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().phs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several plans (and several right-hand sides per plan) solved together:
+    every PCG step is one launch over all systems still iterating."""
+
+    def __init__(self, plans: list, nrhs: list | None = None):
+        self.plans = list(plans)
+        self.nrhs = list(nrhs) if nrhs is not None else [1] * len(self.plans)
+        hs = (C.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        rs = (C.c_int32 * len(self.plans))(*self.nrhs)
+        h = C.c_void_p()
+        _check(lib().phs_batch_create(hs, len(self.plans), rs, _stream(), C.byref(h)))
+        self._h = h
+
+    def solve(self, fs: list, rtol: float = 1e-8, maxit: int = 0, check_every: int = 0,
+              precision: int = -1, raise_on_error: bool = True):
+        """fs[i]: n_i (one RHS) or n_i x nrhs_i tensor for plan i.  Returns a
+        list of (w, beta) in the same shapes and a list of Info per plan."""
+        np_ = len(self.plans)
+        fc = [_cols(f) for f in fs]
+        ws = [torch.empty_like(f) for f in fc]
+        bs = [torch.empty(r * p.S, dtype=torch.float64, device=f.device)
+              for f, r, p in zip(fc, self.nrhs, self.plans)]
+        for f, p, r in zip(fc, self.plans, self.nrhs):
+            _dev(f, "f")
+            if f.numel() != p.n * r:
+                raise ValueError("right-hand side shape does not match the plan")
+        fp = (C.c_void_p * np_)(*[f.data_ptr() for f in fc])
+        wp = (C.c_void_p * np_)(*[w.data_ptr() for w in ws])
+        bp = (C.c_void_p * np_)(*[b.data_ptr() for b in bs])
+        o = SolveOpts(rtol, maxit, check_every, precision)
+        infs = (SolveInfo * np_)()
+        st = lib().phs_batch_solve(self._h, fp, wp, bp, C.byref(o), infs, _stream())
+        if raise_on_error:
+            _check(st)
+        out = []
+        for f, w, b, p, r in zip(fs, ws, bs, self.plans, self.nrhs):
+            if f.dim() == 1:
+                out.append((w, b))
+            else:
+                out.append((w.view(r, p.n).t(), b.view(r, p.S).t()))
+        infos = [Info(i.iters, i.outer_refinements, i.rel_residual, i.t_solve,
+                      STATUS.get(st, str(st))) for i in infs]
+        return out, infos
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().phs_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

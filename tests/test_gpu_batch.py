@@ -1,0 +1,134 @@
+"""Batching: problems of uneven n, order k and polynomial degree, with several
+right-hand sides per point set, solved together (every PCG step one launch
+over all systems still iterating).
+
+Gates:
+* each system's (w, beta) is bitwise equal to solving that plan alone with
+  phs_solve (same arithmetic per system), in FP64 and in mixed precision, and
+  so are its iteration counts;
+* against the dense FP64 oracle: node residual RMS(f - M w - B beta)/RMS(f)
+  <= 1e-8 (all k) and the interpolant at targets <= 1e-8 relative (even k),
+  after a 1e-10 solve.
+"""
+import numpy as np
+import pytest
+
+from oracle import phs_dense as D
+from paper_2608_11462_amd import native as N
+from paper_2608_11462_amd import workloads as W
+from tests.gpu_util import dev, host, rel
+
+pytestmark = pytest.mark.gpu
+
+# (n, k, degree, nrhs, clustered, preconditioner m or 0 for none)
+SMALL = [(1500, 2, 1, 2, False, 30), (900, 3, 1, 1, True, 40), (2200, 1, 0, 1, False, 20),
+         (700, 4, 2, 1, False, 40), (1200, 2, 2, 3, True, 25), (400, 1, 0, 1, False, 0)]
+
+
+def _problem(i, spec):
+    n, k, d, r, clustered, m = spec
+    rng = W.rng_for(900 + i)
+    xy = W.clustered_points(rng, n) if clustered else W.uniform_points(rng, n)
+    f = np.stack([W.fourier_field(rng, kmax=4)(xy) for _ in range(r)], axis=1)
+    tg = W.uniform_points(rng, 200)
+    return xy, f, tg
+
+
+def _plans(specs):
+    out = []
+    for i, spec in enumerate(specs):
+        n, k, d, r, clustered, m = spec
+        xy, f, tg = _problem(i, spec)
+        pl = N.Plan(dev(xy), k, d)
+        if m:
+            pl.precond_build(m=m, nu=k / 2.0, seed=i)
+        out.append((pl, xy, f, tg))
+    return out
+
+
+def _rhs(f):
+    return dev(f[:, 0]) if f.shape[1] == 1 else dev(f)
+
+
+@pytest.mark.parametrize("precision", [N.PHS_FP64, N.PHS_MIXED])
+def test_batch_bitwise_equals_alone(precision):
+    print(f"[case] batch of {len(SMALL)} plans precision={precision}", flush=True)
+    items = _plans(SMALL)
+    batch = N.Batch([it[0] for it in items], [s[3] for s in SMALL])
+    res, infos = batch.solve([_rhs(it[2]) for it in items], rtol=1e-10, maxit=3000,
+                             precision=precision)
+    for i, (it, (wb, bb), inf) in enumerate(zip(items, res, infos)):
+        pl, xy, f, tg = it
+        wa, ba, ia = pl.solve(_rhs(f), rtol=1e-10, maxit=3000, precision=precision)
+        wb, bb, wa, ba = host(wb), host(bb), host(wa), host(ba)
+        print(f"plan {i} k={pl.k} n={pl.n} iters batch={inf.iters} alone={ia.iters} "
+              f"outer {inf.outer_refinements}/{ia.outer_refinements} "
+              f"resid {inf.rel_residual:.2e}/{ia.rel_residual:.2e} "
+              f"max|dw|={np.abs(wb - wa).max():.1e}")
+        assert inf.iters == ia.iters
+        assert inf.outer_refinements == ia.outer_refinements
+        np.testing.assert_array_equal(wb, wa)
+        np.testing.assert_array_equal(bb, ba)
+    batch.close()
+
+
+def test_batch_against_oracle():
+    print("[case] batch vs dense oracle", flush=True)
+    items = _plans(SMALL)
+    batch = N.Batch([it[0] for it in items], [s[3] for s in SMALL])
+    res, infos = batch.solve([_rhs(it[2]) for it in items], rtol=1e-10, maxit=3000)
+    for i, (it, (w, beta), inf, spec) in enumerate(zip(items, res, infos, SMALL)):
+        pl, xy, f, tg = it
+        k, d = spec[1], spec[2]
+        w = host(w).reshape(pl.n, -1)
+        beta = host(beta).reshape(pl.S, -1)
+        c, rho, xi = D.normalize(xy, k)
+        M = D.kernel_matrix(k, xi, xi)
+        B = D.poly_block(xi, d)
+        for col in range(f.shape[1]):
+            res_ = f[:, col] - M @ w[:, col] - B @ beta[:, col]
+            er = np.sqrt(np.mean(res_ ** 2)) / np.sqrt(np.mean(f[:, col] ** 2))
+            msg = f"plan {i} k={k} col {col} iters={inf.iters} node residual {er:.2e}"
+            if k % 2 == 0:
+                ref = D.solve_complement(xy, f[:, col], k, d)
+                s = host(pl.eval(dev(w[:, col]), dev(beta[:, col]), dev(tg)))
+                s_ref = D.interpolant(ref, k, tg)
+                es = np.abs(s - s_ref).max() / np.abs(s_ref).max()
+                msg += f" interp {es:.2e}"
+                assert es <= 1e-8
+            print(msg)
+            assert er <= 1e-8
+    batch.close()
+
+
+def test_batch_uneven_many():
+    """A batch of 24 problems, n log-uniform in [1e3, 3e4], k in {1,2,3,4},
+    uniform or clustered, 2 right-hand sides, FP64: every system converges
+    and three sampled plans match their solo solves bitwise."""
+    rng = W.rng_for(4242)
+    specs = []
+    for i in range(24):
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(3e4)))))
+        k = int(rng.integers(1, 5))
+        specs.append((n, k, -1, 2, bool(rng.random() < 0.5), int(rng.integers(20, 41))))
+    print(f"[case] uneven batch sizes={[s[0] for s in specs]}", flush=True)
+    items = []
+    for i, (n, k, d, r, cl, m) in enumerate(specs):
+        g = W.rng_for(5000 + i)
+        xy = W.clustered_points(g, n) if cl else W.uniform_points(g, n)
+        f = np.stack([W.fourier_field(g, kmax=4)(xy) for _ in range(r)], axis=1)
+        pl = N.Plan(dev(xy), k, d)
+        pl.precond_build(m=m, nu=k / 2.0, seed=i)
+        items.append((pl, f))
+    batch = N.Batch([p for p, _ in items], [s[3] for s in specs])
+    res, infos = batch.solve([dev(f) for _, f in items], rtol=1e-8, maxit=2000)
+    for i, inf in enumerate(infos):
+        assert inf.rel_residual <= 1e-8, (i, inf)
+    for i in (0, 11, 23):
+        pl, f = items[i]
+        wa, ba, ia = pl.solve(dev(f), rtol=1e-8, maxit=2000)
+        np.testing.assert_array_equal(host(res[i][0]), host(wa))
+        np.testing.assert_array_equal(host(res[i][1]), host(ba))
+        assert infos[i].iters == ia.iters
+    print("iters per plan:", [inf.iters for inf in infos])
+    batch.close()
