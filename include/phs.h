@@ -212,6 +212,75 @@ phs_status phs_batch_solve(phs_batch_t batch, const double *const *f, double *co
 
 void phs_batch_destroy(phs_batch_t batch);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop over solve + evaluate requests of differing size.  Requests
+ * wait in a FIFO queue until a slot (max_active) and device memory (an
+ * estimate of the request's tree, preconditioner, Krylov vectors and FMM
+ * workspace against hbm_budget) are free; admitted requests build their plan
+ * and preconditioner and then keep all of it resident in HBM while their PCG
+ * iterations run in lockstep with every other active request (continuous
+ * batching: one launch per PCG step covers all of them, and requests join or
+ * leave between steps).  A finished request is evaluated at its targets, its
+ * device memory is released, and a waiting request can take its place.  Each
+ * request's results are bitwise those of phs_plan + phs_precond_build +
+ * phs_solve + phs_eval with the same options. */
+typedef struct phs_server_s *phs_server_t;
+
+typedef struct {
+  int64_t hbm_budget;  /* bytes of device memory requests may hold; 0 => 3/4
+                          of the free device memory at creation */
+  int32_t max_active;  /* requests in flight; 0 => 64 */
+  int32_t precision;   /* PHS_FP64, PHS_MIXED or PHS_NEAR32 */
+  double rtol;         /* 0 => 1e-8 */
+  int32_t maxit;       /* 0 => 500 */
+} phs_server_opts;
+
+typedef struct {
+  const double *xy;      /* device n x 2 nodes (caller order) */
+  const double *f;       /* device n values */
+  const double *targets; /* device m x 2 evaluation points (may be NULL if m = 0) */
+  int64_t n, m;
+  int32_t k, poly_degree;       /* as phs_plan_opts (-1 => minimal degree) */
+  phs_precond_opts precond;     /* as phs_precond_build */
+  double *w;       /* device n: weights (out) */
+  double *beta;    /* device S: polynomial coefficients (out) */
+  double *values;  /* device m: interpolant at the targets (out) */
+} phs_request;
+/* All request arrays are owned by the caller and must stay valid until the
+ * request is done or failed (phs_server_poll). */
+
+enum { PHS_REQ_QUEUED = 0, PHS_REQ_ACTIVE = 1, PHS_REQ_DONE = 2, PHS_REQ_FAILED = 3 };
+
+typedef struct {
+  int32_t state;          /* PHS_REQ_* */
+  int32_t status;         /* phs_status of a done or failed request */
+  int32_t iters;          /* PCG iterations */
+  double rel_residual;    /* as phs_solve_info */
+  double t_submit, t_admit, t_done;  /* seconds since phs_server_create */
+  int64_t bytes;          /* device bytes charged to the request */
+} phs_request_info;
+
+phs_status phs_server_create(const phs_server_opts *opts, void *stream, phs_server_t *out);
+
+/* Queue a request (host-side only; nothing runs until phs_server_step).  id:
+ * host, receives the request id.  Errors: INVALID_ARGUMENT. */
+phs_status phs_server_submit(phs_server_t srv, const phs_request *req, int64_t *id);
+
+/* One scheduling step: admit waiting requests that fit, run one PCG round of
+ * every active request, evaluate and release those that finished.  active,
+ * queued: host, may be NULL, receive the counts after the step.  A failure of
+ * one request (bad input, out of memory, breakdown) is recorded in that
+ * request and does not fail the step.  Synchronises `stream`. */
+phs_status phs_server_step(phs_server_t srv, int32_t *active, int32_t *queued);
+
+/* State and timing of a request.  info: host. */
+phs_status phs_server_poll(phs_server_t srv, int64_t id, phs_request_info *info);
+
+/* Device bytes held by requests now and at most so far (host, may be NULL). */
+phs_status phs_server_memory(phs_server_t srv, int64_t *in_use, int64_t *peak);
+
+void phs_server_destroy(phs_server_t srv);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *phs_last_error(void);
 

@@ -388,6 +388,25 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
 
 }  // namespace
 
+void create_plan(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_t s, Plan &pl) {
+  plan_create(xy, n, o, s, pl);
+}
+
+void eval_plan(Plan &pl, const double *w, const double *beta, int nrhs, const double *targets,
+               int64_t m, double *out, hipStream_t s) {
+  for (int c = 0; c < nrhs; ++c) {
+    f_gather_user(*pl.self, 0, w + (int64_t)c * pl.n, V_IN, s);
+    const double *wt = pl.sw.v[V_IN];
+    if (pl.core_log) {
+      log_expansions(pl, V_IN, s);
+      log_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m, s);
+    } else {
+      dist_expansions(pl, V_IN, s);
+      dist_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m, s);
+    }
+  }
+}
+
 namespace {
 
 // One column at a time through the plan's own forest (one system), so a
@@ -525,20 +544,7 @@ phs_status phs_eval(phs_plan_t plan, const double *w, const double *beta, int32_
                 "bad eval arguments");
     if (m == 0) return PHS_OK;
     PHS_REQUIRE(targets && out, PHS_ERR_INVALID_ARGUMENT, "null targets/out");
-    Plan &pl = plan->pl;
-    hipStream_t s = S(stream);
-    for (int c = 0; c < nrhs; ++c) {
-      f_gather_user(*pl.self, 0, w + (int64_t)c * pl.n, V_IN, s);
-      const double *wt = pl.sw.v[V_IN];
-      if (pl.core_log) {
-        log_expansions(pl, V_IN, s);
-        log_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m, s);
-      } else {
-        dist_expansions(pl, V_IN, s);
-        dist_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m,
-                          s);
-      }
-    }
+    eval_plan(plan->pl, w, beta, nrhs, targets, m, out, S(stream));
     return PHS_OK;
   });
 }
@@ -643,6 +649,71 @@ phs_status phs_batch_solve(phs_batch_t batch, const double *const *f, double *co
 }
 
 void phs_batch_destroy(phs_batch_t batch) { delete batch; }
+
+struct phs_server_s {
+  Server sv;
+};
+
+phs_status phs_server_create(const phs_server_opts *opts, void *stream, phs_server_t *out) {
+  if (!out) {
+    set_error(PHS_ERR_INVALID_ARGUMENT, "null output handle");
+    return PHS_ERR_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  phs_server_s *h = new (std::nothrow) phs_server_s();
+  if (!h) {
+    set_error(PHS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return PHS_ERR_OUT_OF_MEMORY;
+  }
+  phs_status st = guarded([&] {
+    PHS_REQUIRE(opts, PHS_ERR_INVALID_ARGUMENT, "null server options");
+    server_create(h->sv, *opts, S(stream));
+    return PHS_OK;
+  });
+  if (st != PHS_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return PHS_OK;
+}
+
+phs_status phs_server_submit(phs_server_t srv, const phs_request *req, int64_t *id) {
+  return guarded([&] {
+    PHS_REQUIRE(srv && req && id, PHS_ERR_INVALID_ARGUMENT, "bad submit arguments");
+    *id = server_submit(srv->sv, *req);
+    return PHS_OK;
+  });
+}
+
+phs_status phs_server_step(phs_server_t srv, int32_t *active, int32_t *queued) {
+  return guarded([&] {
+    PHS_REQUIRE(srv, PHS_ERR_INVALID_ARGUMENT, "null server");
+    server_step(srv->sv);
+    if (active) *active = (int32_t)srv->sv.active.size();
+    if (queued) *queued = (int32_t)srv->sv.queue.size();
+    return PHS_OK;
+  });
+}
+
+phs_status phs_server_poll(phs_server_t srv, int64_t id, phs_request_info *info) {
+  return guarded([&] {
+    PHS_REQUIRE(srv && info, PHS_ERR_INVALID_ARGUMENT, "bad poll arguments");
+    server_poll(srv->sv, id, *info);
+    return PHS_OK;
+  });
+}
+
+phs_status phs_server_memory(phs_server_t srv, int64_t *in_use, int64_t *peak) {
+  return guarded([&] {
+    PHS_REQUIRE(srv, PHS_ERR_INVALID_ARGUMENT, "null server");
+    if (in_use) *in_use = srv->sv.in_use;
+    if (peak) *peak = srv->sv.peak;
+    return PHS_OK;
+  });
+}
+
+void phs_server_destroy(phs_server_t srv) { delete srv; }
 
 void phs_plan_destroy(phs_plan_t plan) {
   if (!plan) return;

@@ -321,19 +321,43 @@ void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t 
 // y[out] = M v[in] for every masked system, in tree order
 void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hipStream_t s);
 
-// one right-hand side of one system: inputs in caller order, results
+// one right-hand side of one system: inputs in caller order, results, and
+// the state of its solve between rounds
+enum JobState { J_INIT, J_START, J_PCG, J_PCG_END, J_RESID, J_FINISH, J_DONE };
 struct SolveJob {
   int sys = 0;
   const double *f = nullptr;
   double *w_out = nullptr;
   double *beta_out = nullptr;
   int iters = 0, outer = 0;
-  double rel = 0.0, bn = 0.0;
+  double rel = 0.0;
   phs_status status = PHS_OK;
   std::vector<double> beta_host;
+  // solve state
+  JobState state = J_INIT;
+  double bn = 0, fn = 0, tol_abs = 0, rn = 0;
+  int it = 0, maxit_inner = 0, inner_prec = PHS_FP64;
+  double inner_tol = 0;
+  bool pcg_conv = false, pcg_break = false;
+  int budget = 0;
+  bool fp64_finish = false, count_outer = false, apply_dw = false;
 };
+struct SolveParams {
+  double rtol;
+  int maxit, check_every, prec;
+};
+// solve_begin: first step for jobs in state J_INIT (all must be systems of F);
+// solve_round: one lockstep round of every job not yet J_DONE; false when
+// none is left.  Jobs may join between rounds through solve_begin.
+void solve_begin(Forest &F, std::vector<SolveJob *> &jobs, const SolveParams &P, hipStream_t s);
+bool solve_round(Forest &F, std::vector<SolveJob *> &jobs, const SolveParams &P, hipStream_t s);
 void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit,
                   int check_every, int prec, hipStream_t s);
+
+// ------------------------------------------------------------------ plans
+void create_plan(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_t s, Plan &pl);
+void eval_plan(Plan &pl, const double *w, const double *beta, int nrhs, const double *targets,
+               int64_t m, double *out, hipStream_t s);
 
 // ------------------------------------------------------------------ batch
 struct Batch {
@@ -349,6 +373,39 @@ void batch_create(Batch &b, const std::vector<Plan *> &plans, const std::vector<
 phs_status batch_solve(Batch &b, const double *const *f, double *const *w,
                        double *const *beta, const phs_solve_opts *o, phs_solve_info *info,
                        hipStream_t s);
+
+// ------------------------------------------------------------------ serving
+struct Request {
+  int64_t id = 0;
+  phs_request in;
+  int state = PHS_REQ_QUEUED;
+  phs_status status = PHS_OK;
+  Plan *plan = nullptr;
+  SolveJob job;
+  int64_t bytes = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+struct Server {
+  phs_server_opts opts{};
+  SolveParams P{1e-8, 500, 1, PHS_FP64};
+  hipStream_t s = nullptr;
+  int64_t budget = 0, in_use = 0, peak = 0;
+  int64_t next_id = 1;
+  std::vector<Request *> queue;    // FIFO
+  std::vector<Request *> active;
+  std::vector<Request *> all;      // every request ever submitted (owned)
+  Forest *F = nullptr;
+  bool changed = false;
+  double t0 = 0;
+  ~Server();
+};
+void server_create(Server &sv, const phs_server_opts &o, hipStream_t s);
+int64_t server_submit(Server &sv, const phs_request &r);
+void server_step(Server &sv);
+void server_poll(Server &sv, int64_t id, phs_request_info &info);
+// device bytes a request of n nodes, order k and conditioning-set size m holds
+int64_t request_bytes(int64_t n, int k, int m);
 
 // ------------------------------------------------------------------ launchers
 // tree.hip

@@ -1,0 +1,229 @@
+// Serving: a request loop with continuous batching over the lockstep PCG
+// engine.  Requests wait in FIFO order until a slot and device memory are
+// free; an admitted request builds its plan (tree, polynomial block, FMM
+// tables, workspace) and Vecchia preconditioner, which stay resident in HBM
+// with its Krylov vectors until it finishes.  Each step runs one PCG round of
+// every active request in shared launches; requests that finish are evaluated
+// at their targets and release their memory, and the forest of active systems
+// is rebuilt before the next round.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "phs_internal.h"
+
+namespace phs {
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+// Upper estimate of the device memory of one request with the default plan
+// options (leaf size 40/64, FP64 log orders 27 and 31, Chebyshev 12 and 16):
+// node arrays, polynomial block, FMM workspace of one system and its tables,
+// ten Krylov vectors, the Vecchia factor and its transpose, and the peak of
+// the temporaries of the preconditioner build.
+int64_t request_bytes(int64_t n, int k, int m) {
+  const bool log_k = (k % 2 == 0);
+  const int leaf = log_k ? 40 : 64;
+  int L = (int)std::lround(std::log((double)std::max<int64_t>(n, 1) / leaf) / std::log(4.0));
+  L = std::max(2, std::min(10, L));
+  const int64_t boxes = ((int64_t)1 << (2 * (L + 1))) - 16;  // levels 2..L, x3
+  const int R = hadamard_rank(k);
+  const int S = n_monomials(std::max(min_degree(k), 2));
+  const int mm = m > 0 ? m : (k == 2 ? 30 : 50);
+  int64_t exp;
+  int64_t tables;
+  if (log_k) {
+    exp = 32LL * R * boxes / 3 * 16;
+    tables = 3 * (32LL * 32 * 8 * 9 + 512);
+  } else {
+    exp = 256LL * R * boxes / 3 * 8;
+    tables = 40LL * (144 * 144 * 12 + 256 * 256 * 8 + 64 * 64 * 4);
+  }
+  const int64_t nodes = n * (52 + 8LL * S + 10 * 8 + 4);
+  const int64_t vecchia = n * (16 + 24LL * mm);
+  const int64_t transient = n * (100 + 16LL * mm);
+  return 2 * exp + tables + nodes + vecchia + transient + (int64_t)(1 << 22);
+}
+
+Server::~Server() {
+  (void)hipDeviceSynchronize();
+  delete F;
+  for (Request *r : all) {
+    delete r->plan;
+    delete r;
+  }
+}
+
+void server_create(Server &sv, const phs_server_opts &o, hipStream_t s) {
+  PHS_REQUIRE(o.precision == PHS_FP64 || o.precision == PHS_MIXED || o.precision == PHS_NEAR32,
+              PHS_ERR_INVALID_ARGUMENT, "bad precision");
+  PHS_REQUIRE(o.hbm_budget >= 0 && o.max_active >= 0 && o.maxit >= 0 && o.rtol >= 0,
+              PHS_ERR_INVALID_ARGUMENT, "bad server options");
+  sv.opts = o;
+  sv.s = s;
+  sv.P = SolveParams{o.rtol > 0 ? o.rtol : 1e-8, o.maxit > 0 ? o.maxit : 500, 1, o.precision};
+  if (o.max_active <= 0) sv.opts.max_active = 64;
+  if (o.hbm_budget > 0) {
+    sv.budget = o.hbm_budget;
+  } else {
+    size_t fr = 0, tot = 0;
+    PHS_HIP(hipMemGetInfo(&fr, &tot));
+    sv.budget = (int64_t)(fr / 4 * 3);
+  }
+  sv.t0 = now_s();
+}
+
+int64_t server_submit(Server &sv, const phs_request &r) {
+  PHS_REQUIRE(r.xy && r.f && r.w && r.beta && r.n >= 1 && r.m >= 0, PHS_ERR_INVALID_ARGUMENT,
+              "bad request arrays");
+  PHS_REQUIRE(r.m == 0 || (r.targets && r.values), PHS_ERR_INVALID_ARGUMENT,
+              "request with targets needs targets and values arrays");
+  PHS_REQUIRE(r.k >= 1 && r.k <= 4, PHS_ERR_INVALID_ARGUMENT, "k must be 1..4");
+  Request *q = new Request();
+  q->id = sv.next_id++;
+  q->in = r;
+  q->t_submit = now_s() - sv.t0;
+  q->bytes = request_bytes(r.n, r.k, r.precond.m);
+  sv.all.push_back(q);
+  sv.queue.push_back(q);
+  return q->id;
+}
+
+namespace {
+
+void fail(Server &sv, Request *r, phs_status st) {
+  r->state = PHS_REQ_FAILED;
+  r->status = st;
+  r->t_done = now_s() - sv.t0;
+  delete r->plan;
+  r->plan = nullptr;
+}
+
+// plan + preconditioner of a request; returns false (request failed) on error
+bool admit(Server &sv, Request *r) {
+  const phs_request &in = r->in;
+  phs_plan_opts po{};
+  po.k = in.k;
+  po.poly_degree = in.poly_degree;
+  po.precision = sv.opts.precision;
+  try {
+    r->plan = new Plan();
+    create_plan(in.xy, in.n, &po, sv.s, *r->plan);
+    vecchia_build(*r->plan, in.precond, sv.s);
+  } catch (const Error &e) {
+    set_error(e.code, e.msg);
+    (void)hipStreamSynchronize(sv.s);
+    fail(sv, r, e.code);
+    return false;
+  } catch (const std::bad_alloc &) {
+    fail(sv, r, PHS_ERR_OUT_OF_MEMORY);
+    return false;
+  }
+  r->state = PHS_REQ_ACTIVE;
+  r->t_admit = now_s() - sv.t0;
+  r->job = SolveJob();
+  r->job.f = in.f;
+  r->job.w_out = in.w;
+  r->job.beta_out = in.beta;
+  return true;
+}
+
+}  // namespace
+
+void server_step(Server &sv) {
+  hipStream_t s = sv.s;
+  // 1. admission, FIFO, by slot and memory budget
+  std::vector<Request *> fresh;
+  while (!sv.queue.empty() && (int)sv.active.size() < sv.opts.max_active) {
+    Request *r = sv.queue.front();
+    if (r->bytes > sv.budget) {
+      sv.queue.erase(sv.queue.begin());
+      set_error(PHS_ERR_OUT_OF_MEMORY, "request larger than the server's memory budget");
+      fail(sv, r, PHS_ERR_OUT_OF_MEMORY);
+      continue;
+    }
+    if (sv.in_use + r->bytes > sv.budget) break;
+    sv.queue.erase(sv.queue.begin());
+    if (!admit(sv, r)) continue;
+    sv.in_use += r->bytes;
+    sv.peak = std::max(sv.peak, sv.in_use);
+    sv.active.push_back(r);
+    fresh.push_back(r);
+    sv.changed = true;
+  }
+  // 2. the forest of active systems
+  if (sv.changed) {
+    delete sv.F;
+    sv.F = nullptr;
+    if (!sv.active.empty()) {
+      std::vector<Plan *> pl;
+      std::vector<SysWork *> wk;
+      for (size_t i = 0; i < sv.active.size(); ++i) {
+        pl.push_back(sv.active[i]->plan);
+        wk.push_back(&sv.active[i]->plan->sw);
+        sv.active[i]->job.sys = (int)i;
+      }
+      sv.F = new Forest();
+      build_forest(*sv.F, pl, wk, s);
+    }
+    sv.changed = false;
+  }
+  if (sv.active.empty()) return;
+  Forest &F = *sv.F;
+  if (!fresh.empty()) {
+    std::vector<SolveJob *> js;
+    for (Request *r : fresh) js.push_back(&r->job);
+    solve_begin(F, js, sv.P, s);
+  }
+  // 3. one lockstep round of every active request
+  std::vector<SolveJob *> js;
+  for (Request *r : sv.active) js.push_back(&r->job);
+  solve_round(F, js, sv.P, s);
+  // 4. finished requests: evaluate, release
+  std::vector<Request *> keep;
+  for (Request *r : sv.active) {
+    if (r->job.state != J_DONE) {
+      keep.push_back(r);
+      continue;
+    }
+    try {
+      if (r->in.m > 0)
+        eval_plan(*r->plan, r->in.w, r->in.beta, 1, r->in.targets, r->in.m, r->in.values, s);
+      PHS_HIP(hipStreamSynchronize(s));
+      r->status = r->job.status;
+      r->state = PHS_REQ_DONE;
+    } catch (const Error &e) {
+      set_error(e.code, e.msg);
+      r->status = e.code;
+      r->state = PHS_REQ_FAILED;
+    }
+    r->t_done = now_s() - sv.t0;
+    delete r->plan;
+    r->plan = nullptr;
+    sv.in_use -= r->bytes;
+    sv.changed = true;
+  }
+  sv.active = keep;
+}
+
+void server_poll(Server &sv, int64_t id, phs_request_info &info) {
+  PHS_REQUIRE(id >= 1 && id < sv.next_id, PHS_ERR_INVALID_ARGUMENT, "unknown request id");
+  const Request &r = *sv.all[id - 1];
+  info.state = r.state;
+  info.status = r.status;
+  info.iters = r.job.iters;
+  info.rel_residual = r.job.rel;
+  info.t_submit = r.t_submit;
+  info.t_admit = r.t_admit;
+  info.t_done = r.t_done;
+  info.bytes = r.bytes;
+}
+
+}  // namespace phs

@@ -24,8 +24,6 @@ namespace phs {
 
 namespace {
 
-enum JobState { J_INIT, J_START, J_PCG, J_PCG_END, J_RESID, J_FINISH, J_DONE };
-
 // masks of the solve (slot 0 is all ones and never changed)
 enum MaskSlot {
   MK_ALL = 0,
@@ -40,45 +38,47 @@ enum MaskSlot {
   MK_UPD = 9
 };
 
-struct JobRun {
-  SolveJob *job;
-  JobState state = J_INIT;
-  double bn = 0, fn = 0, tol_abs = 0, rn = 0;
-  // PCG
-  int it = 0, maxit_inner = 0, inner_prec = PHS_FP64;
-  double inner_tol = 0;
-  bool pcg_conv = false, pcg_break = false;
-  // refinement
-  int budget = 0;
-  bool fp64_finish = false;
-  bool count_outer = false;
-  bool apply_dw = false;  // fold the inner iterate into w this round
-};
+using JobRun = SolveJob;
 
-void set_mask(Forest &F, int slot, const std::vector<JobRun> &jr, bool (*pred)(const JobRun &),
+void set_mask(Forest &F, int slot, const std::vector<SolveJob *> &jr, bool (*pred)(const JobRun &),
               bool &any, hipStream_t s) {
   std::vector<int32_t> m(F.nsys, 0);
   any = false;
-  for (const auto &r : jr)
-    if (pred(r)) {
-      m[r.job->sys] = 1;
+  for (const auto *r : jr)
+    if (pred(*r)) {
+      m[r->sys] = 1;
       any = true;
     }
   set_mask(F, slot, m, s);
 }
 
+void start_pcg(JobRun &r, const SolveParams &P) {
+  const bool mixed = P.prec != PHS_FP64;
+  if (!mixed) {
+    r.inner_prec = PHS_FP64;
+    r.inner_tol = r.tol_abs;
+    r.maxit_inner = P.maxit;
+  } else {
+    // FP32 far field: small steps (its error is relative to ||M||); FP32
+    // near field only: the operator is accurate enough to go to rtol at once
+    r.inner_prec = r.fp64_finish ? PHS_FP64 : P.prec;
+    r.inner_tol = r.fp64_finish ? r.tol_abs
+                                : (P.prec == PHS_NEAR32 ? 0.5 * r.tol_abs
+                                                        : std::max(r.tol_abs, 1e-4 * r.rn));
+    r.maxit_inner = (r.fp64_finish || P.prec == PHS_NEAR32) ? r.budget : std::min(r.budget, 60);
+  }
+  r.it = 0;
+  r.pcg_conv = r.pcg_break = false;
+  r.state = J_START;
+}
+
 }  // namespace
 
-void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit,
-                  int check_every, int prec, hipStream_t s) {
+void solve_begin(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, hipStream_t s) {
   PHS_REQUIRE(F.nsys >= 1 && Forest::kMasks >= 10, PHS_ERR_INVALID_ARGUMENT, "empty forest");
-  const bool mixed = prec != PHS_FP64;
-  std::vector<JobRun> jr(jobs.size());
-  for (size_t i = 0; i < jobs.size(); ++i) jr[i].job = &jobs[i];
   bool any = false;
-
   // ---- INIT: f in tree order, b = sign Pi f, ||b||, ||f||
-  for (auto &r : jr) f_gather_user(F, r.job->sys, r.job->f, V_F, s);
+  for (auto *r : jr) f_gather_user(F, r->sys, r->f, V_F, s);
   set_mask(F, MK_START, jr, [](const JobRun &r) { return r.state == J_INIT; }, any, s);
   f_scale_sign(F, F.mask[MK_START], V_R, V_F, s);
   f_project(F, F.mask[MK_START], V_R, s);
@@ -86,47 +86,31 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
   f_dot(F, F.mask[MK_START], V_F, V_F, SC_DOT + 1, s);
   f_fill(F, F.mask[MK_START], V_W, 0.0, s);
   f_read_scalars(F, SC_DOT, 2, s);
-  for (auto &r : jr) {
-    const int sy = r.job->sys;
+  for (auto *rp : jr) {
+    JobRun &r = *rp;
+    const int sy = r.sys;
     r.bn = std::sqrt(F.hgsc[sy * 8 + 0]);
     r.fn = std::sqrt(F.hgsc[sy * 8 + 1]);
-    r.job->bn = r.bn;
-    r.tol_abs = rtol * r.bn;
+    r.tol_abs = P.rtol * r.bn;
     r.rn = r.bn;
-    r.budget = maxit;
+    r.budget = P.maxit;
     if (r.bn <= 1e-13 * r.fn) {
       // data in span(B) to rounding level: the polynomial alone interpolates
       r.state = J_FINISH;
     } else {
-      r.state = J_START;
+      start_pcg(r, P);
     }
   }
+}
 
-  auto start_pcg = [&](JobRun &r) {
-    if (!mixed) {
-      r.inner_prec = PHS_FP64;
-      r.inner_tol = r.tol_abs;
-      r.maxit_inner = maxit;
-    } else {
-      // FP32 far field: small steps (its error is relative to ||M||); FP32
-      // near field only: the operator is accurate enough to go to rtol at once
-      r.inner_prec = r.fp64_finish ? PHS_FP64 : prec;
-      r.inner_tol = r.fp64_finish ? r.tol_abs
-                                  : (prec == PHS_NEAR32 ? 0.5 * r.tol_abs
-                                                        : std::max(r.tol_abs, 1e-4 * r.rn));
-      r.maxit_inner = (r.fp64_finish || prec == PHS_NEAR32) ? r.budget : std::min(r.budget, 60);
-    }
-    r.it = 0;
-    r.pcg_conv = r.pcg_break = false;
-    r.state = J_START;
-  };
-  for (auto &r : jr)
-    if (r.state == J_START) start_pcg(r);
-
-  for (;;) {
+bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, hipStream_t s) {
+  const bool mixed = P.prec != PHS_FP64;
+  const int check_every = P.check_every;
+  bool any = false;
+  {
     bool live = false;
-    for (auto &r : jr) live = live || r.state != J_DONE;
-    if (!live) break;
+    for (auto *r : jr) live = live || r->state != J_DONE;
+    if (!live) return false;
 
     // ---- START: dw = 0, z = precond(r), rho = r.z, p = z
     set_mask(F, MK_START, jr, [](const JobRun &r) { return r.state == J_START; }, any, s);
@@ -135,7 +119,7 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
       f_precond(F, F.mask[MK_START], V_R, V_Z, V_TMP, s);
       f_dot(F, F.mask[MK_START], V_R, V_Z, SC_RHO, s);
       f_copy(F, F.mask[MK_START], V_P, V_Z, s);
-      for (auto &r : jr)
+      for (auto *rp_ : jr) if (auto &r = *rp_; true)
         if (r.state == J_START) r.state = J_PCG;
     }
 
@@ -165,9 +149,9 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
         // (FP32) operator is never applied
         f_read_scalars(F, SC_PQ, 1, s);
         bool drop = false;
-        for (auto &r : jr)
+        for (auto *rp_ : jr) if (auto &r = *rp_; true)
           if (r.state == J_PCG && r.inner_prec != PHS_FP64 &&
-              !(F.hgsc[r.job->sys * 8] > 0.0)) {
+              !(F.hgsc[r.sys * 8] > 0.0)) {
             r.pcg_break = true;
             r.state = J_PCG_END;
             drop = true;
@@ -179,16 +163,16 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
       }
       f_pcg_wr(F, upd_mask, s);
       bool need_check = false;
-      for (auto &r : jr)
+      for (auto *rp_ : jr) if (auto &r = *rp_; true)
         if (r.state == J_PCG) {
           ++r.it;
           if (r.it % check_every == 0 || r.it == r.maxit_inner) need_check = true;
         }
       if (need_check) f_read_scalars(F, 0, 4, s);
-      for (auto &r : jr) {
+      for (auto *rp_ : jr) if (auto &r = *rp_; true) {
         if (r.state != J_PCG) continue;
         if (!(r.it % check_every == 0 || r.it == r.maxit_inner)) continue;
-        const double *g = F.hgsc + r.job->sys * 8;
+        const double *g = F.hgsc + r.sys * 8;
         if (!(g[SC_PQ] > 0.0)) {
           r.pcg_break = true;
           r.state = J_PCG_END;
@@ -210,12 +194,12 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
     }
 
     // ---- end of an inner solve
-    for (auto &r : jr) {
+    for (auto *rp_ : jr) if (auto &r = *rp_; true) {
       if (r.state != J_PCG_END) continue;
-      r.job->iters += r.it;
+      r.iters += r.it;
       if (!mixed) {
-        if (r.pcg_break) r.job->status = PHS_ERR_BREAKDOWN;
-        else if (!r.pcg_conv) r.job->status = PHS_ERR_NOT_CONVERGED;
+        if (r.pcg_break) r.status = PHS_ERR_BREAKDOWN;
+        else if (!r.pcg_conv) r.status = PHS_ERR_NOT_CONVERGED;
         r.state = J_FINISH;
         r.apply_dw = true;
         continue;
@@ -223,7 +207,7 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
       r.budget -= r.it;
       if (r.pcg_break && r.it <= 1) {
         if (r.fp64_finish) {
-          r.job->status = PHS_ERR_BREAKDOWN;
+          r.status = PHS_ERR_BREAKDOWN;
           r.state = J_FINISH;
           continue;
         }
@@ -242,7 +226,7 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
       if (mixed) f_axpby(F, F.mask[MK_UPD], V_W, V_DW, 1.0, 1.0, s);
       else f_copy(F, F.mask[MK_UPD], V_W, V_DW, s);
     }
-    for (auto &r : jr) r.apply_dw = false;
+    for (auto *rp_ : jr) if (auto &r = *rp_; true) r.apply_dw = false;
 
     // ---- FP64 residual of the refinement: r = sign Pi (f - M64 w)
     set_mask(F, MK_RESID, jr, [](const JobRun &r) { return r.state == J_RESID; }, any, s);
@@ -253,23 +237,23 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
       f_project(F, F.mask[MK_RESID], V_R, s);
       f_dot(F, F.mask[MK_RESID], V_R, V_R, SC_DOT, s);
       f_read_scalars(F, SC_DOT, 1, s);
-      for (auto &r : jr) {
+      for (auto *rp_ : jr) if (auto &r = *rp_; true) {
         if (r.state != J_RESID) continue;
         if (r.count_outer) {
-          const double rn_new = std::sqrt(F.hgsc[r.job->sys * 8]);
-          ++r.job->outer;
+          const double rn_new = std::sqrt(F.hgsc[r.sys * 8]);
+          ++r.outer;
           if (!(rn_new < 0.5 * r.rn)) r.fp64_finish = true;
           r.rn = rn_new;
           if (!std::isfinite(r.rn)) {
-            r.job->status = PHS_ERR_BREAKDOWN;
+            r.status = PHS_ERR_BREAKDOWN;
             r.state = J_FINISH;
             continue;
           }
         }
         if (r.rn > r.tol_abs && r.budget > 0) {
-          start_pcg(r);
+          start_pcg(r, P);
         } else {
-          if (r.rn > r.tol_abs && r.job->status == PHS_OK) r.job->status = PHS_ERR_NOT_CONVERGED;
+          if (r.rn > r.tol_abs && r.status == PHS_OK) r.status = PHS_ERR_NOT_CONVERGED;
           r.state = J_FINISH;
         }
       }
@@ -289,16 +273,16 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
         const int cnt = std::min(8, F.maxS - off);
         f_read_scalars(F, SC_QTF + off, cnt, s);
         for (size_t i = 0; i < jr.size(); ++i) {
-          if (jr[i].state != J_FINISH) continue;
+          if (jr[i]->state != J_FINISH) continue;
           for (int c = 0; c < cnt; ++c)
-            qtf[i].push_back(F.hgsc[jr[i].job->sys * 8 + c]);
+            qtf[i].push_back(F.hgsc[jr[i]->sys * 8 + c]);
         }
       }
       f_read_scalars(F, SC_DOT, 1, s);
       for (size_t i = 0; i < jr.size(); ++i) {
-        JobRun &r = jr[i];
+        JobRun &r = *jr[i];
         if (r.state != J_FINISH) continue;
-        const Plan &pl = *F.plan[r.job->sys];
+        const Plan &pl = *F.plan[r.sys];
         const int S = pl.S;
         std::vector<double> bet(S);
         for (int a = S - 1; a >= 0; --a) {
@@ -306,15 +290,26 @@ void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit
           for (int k2 = a + 1; k2 < S; ++k2) acc -= pl.Rm[(size_t)a * S + k2] * bet[k2];
           bet[a] = acc / pl.Rm[(size_t)a * S + a];
         }
-        r.job->beta_host = bet;
-        r.job->rel = r.bn > 0 ? std::sqrt(F.hgsc[r.job->sys * 8]) / r.bn : 0.0;
-        PHS_HIP(hipMemcpyAsync(r.job->beta_out, r.job->beta_host.data(), S * sizeof(double),
+        r.beta_host = bet;
+        r.rel = r.bn > 0 ? std::sqrt(F.hgsc[r.sys * 8]) / r.bn : 0.0;
+        PHS_HIP(hipMemcpyAsync(r.beta_out, r.beta_host.data(), S * sizeof(double),
                                hipMemcpyHostToDevice, s));
-        f_scatter_user(F, r.job->sys, V_W, r.job->w_out, s);
+        f_scatter_user(F, r.sys, V_W, r.w_out, s);
         r.state = J_DONE;
       }
       PHS_HIP(hipStreamSynchronize(s));
     }
+  }
+  return true;
+}
+
+void solve_forest(Forest &F, std::vector<SolveJob> &jobs, double rtol, int maxit,
+                  int check_every, int prec, hipStream_t s) {
+  const SolveParams P{rtol, maxit, check_every, prec};
+  std::vector<SolveJob *> jr;
+  for (auto &j : jobs) jr.push_back(&j);
+  solve_begin(F, jr, P, s);
+  while (solve_round(F, jr, P, s)) {
   }
 }
 

@@ -27,7 +27,10 @@ STATUS = {
 EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval",
            "phs_plan_info", "phs_plan_tree", "phs_precond_export", "phs_precond_apply",
            "phs_plan_destroy", "phs_batch_create", "phs_batch_solve", "phs_batch_destroy",
+           "phs_server_create", "phs_server_submit", "phs_server_step", "phs_server_poll",
+           "phs_server_memory", "phs_server_destroy",
            "phs_last_error", "phs_profile_enable", "phs_profile_read")
+PHS_REQ_QUEUED, PHS_REQ_ACTIVE, PHS_REQ_DONE, PHS_REQ_FAILED = 0, 1, 2, 3
 
 
 class PlanOpts(C.Structure):
@@ -44,6 +47,24 @@ class PrecondOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
                 ("precision", C.c_int32)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("precision", C.c_int32),
+                ("rtol", C.c_double), ("maxit", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("f", C.c_void_p), ("targets", C.c_void_p),
+                ("n", C.c_int64), ("m", C.c_int64), ("k", C.c_int32),
+                ("poly_degree", C.c_int32), ("precond", PrecondOpts), ("w", C.c_void_p),
+                ("beta", C.c_void_p), ("values", C.c_void_p)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("iters", C.c_int32),
+                ("rel_residual", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("bytes", C.c_int64)]
 
 
 class SolveInfo(C.Structure):
@@ -88,6 +109,13 @@ def lib() -> C.CDLL:
                                       C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.phs_batch_destroy.argtypes = [vp]
         L.phs_batch_destroy.restype = None
+        L.phs_server_create.argtypes = [C.POINTER(ServerOpts), vp, C.POINTER(vp)]
+        L.phs_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(i64)]
+        L.phs_server_step.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+        L.phs_server_poll.argtypes = [vp, i64, C.POINTER(RequestInfo)]
+        L.phs_server_memory.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.phs_server_destroy.argtypes = [vp]
+        L.phs_server_destroy.restype = None
         L.phs_last_error.restype = C.c_char_p
         L.phs_profile_enable.argtypes = [i32]
         L.phs_profile_enable.restype = None
@@ -95,7 +123,9 @@ def lib() -> C.CDLL:
         L.phs_profile_read.restype = i32
         for name in ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval",
                      "phs_plan_info", "phs_plan_tree", "phs_precond_export",
-                     "phs_precond_apply", "phs_batch_create", "phs_batch_solve"):
+                     "phs_precond_apply", "phs_batch_create", "phs_batch_solve",
+                     "phs_server_create", "phs_server_submit", "phs_server_step",
+                     "phs_server_poll", "phs_server_memory"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -286,6 +316,76 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().phs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def n_monomials(k: int, degree: int) -> int:
+    d = degree if degree >= 0 else ((k + 1) // 2 - 1 if k % 2 else k // 2)
+    return (d + 1) * (d + 2) // 2
+
+
+class Server:
+    """Request loop with continuous batching (see phs_server_* in phs.h).  The
+    binding keeps each request's tensors alive until it is done or failed."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 0, precision: int = PHS_FP64,
+                 rtol: float = 1e-8, maxit: int = 0):
+        o = ServerOpts(hbm_budget, max_active, precision, rtol, maxit)
+        h = C.c_void_p()
+        _check(lib().phs_server_create(C.byref(o), _stream(), C.byref(h)))
+        self._h = h
+        self._t = {}
+
+    def submit(self, xy: torch.Tensor, f: torch.Tensor, k: int, degree: int = -1,
+               targets: torch.Tensor | None = None, m: int = 0, nu: float = 0.0,
+               range_: float = 0.0, range_units: int = PHS_RANGE_NORMALIZED,
+               seed: int = 0) -> int:
+        xy, f = xy.contiguous(), f.contiguous()
+        _dev(xy, "xy")
+        _dev(f, "f")
+        n = xy.shape[0]
+        nt = 0 if targets is None else targets.shape[0]
+        tg = targets.contiguous() if nt else None
+        w = torch.empty(n, dtype=torch.float64, device=xy.device)
+        beta = torch.empty(n_monomials(k, degree), dtype=torch.float64, device=xy.device)
+        vals = torch.empty(max(nt, 1), dtype=torch.float64, device=xy.device)
+        req = Request(xy.data_ptr(), f.data_ptr(), tg.data_ptr() if nt else None, n, nt, k,
+                      degree, PrecondOpts(m, nu, range_, range_units, seed), w.data_ptr(),
+                      beta.data_ptr(), vals.data_ptr())
+        rid = C.c_int64()
+        _check(lib().phs_server_submit(self._h, C.byref(req), C.byref(rid)))
+        self._t[rid.value] = (xy, f, tg, w, beta, vals[:nt])
+        return rid.value
+
+    def step(self):
+        a, q = C.c_int32(), C.c_int32()
+        _check(lib().phs_server_step(self._h, C.byref(a), C.byref(q)))
+        return a.value, q.value
+
+    def poll(self, rid: int) -> RequestInfo:
+        inf = RequestInfo()
+        _check(lib().phs_server_poll(self._h, rid, C.byref(inf)))
+        return inf
+
+    def result(self, rid: int):
+        """(w, beta, values) of a request (valid once it is done)."""
+        t = self._t[rid]
+        return t[3], t[4], t[5]
+
+    def memory(self):
+        u, p = C.c_int64(), C.c_int64()
+        _check(lib().phs_server_memory(self._h, C.byref(u), C.byref(p)))
+        return u.value, p.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().phs_server_destroy(self._h)
             self._h = None
 
     def __del__(self):
