@@ -55,6 +55,11 @@ def parse():
     # one elementwise kernel reading 1 GiB and writing 1 GiB before the steps:
     # the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters
     ap.add_argument("--copy-calibration", action="store_true")
+    # serving (Poisson stream) and batched (many problems, 4 right-hand sides) legs
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--batch-problems", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     return ap.parse_args()
 
 
@@ -125,6 +130,129 @@ def cpu_baseline(seed: int = 3, n_s: int = 6144, n_t: int = 10000):
     return {"value": n_s / t / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
             "sample": f"dense FP64 complement solve + {n_t}-target evaluation on {n_s} nodes "
                       f"of the same workload (median of 3: {t:.2f} s)"}
+
+
+def serve_leg(N, W, torch, n_req: int):
+    """Poisson stream of solve + evaluate requests (n log-uniform in [1e3, 1e6],
+    k in {2, 3}, 10^4 targets) through the server at 80% of the load the plain
+    FP64 path sustains serving each request alone; FIFO serve-alone latencies
+    follow from the measured alone service times and the same arrivals."""
+    reqs = W.stream(n_requests=n_req, rate=1.0)
+    dev = torch.device("cuda")
+    items = [(torch.as_tensor(r.problem.xy, device=dev), torch.as_tensor(r.problem.f, device=dev),
+              torch.as_tensor(r.problem.targets, device=dev), r.problem.k,
+              r.problem.precond["m"]) for r in reqs]
+    torch.cuda.synchronize()
+
+    def alone(it):
+        xy, f, tg, k, m = it
+        pl = N.Plan(xy, k, -1)
+        pl.precond_build(m=m, nu=k / 2.0, seed=0)
+        w, b, info = pl.solve(f, rtol=1e-8)
+        pl.eval(w, b, tg)
+        torch.cuda.synchronize()
+        pl.close()
+        return info.rel_residual
+
+    alone(items[0])  # warm-up
+    t_alone = []
+    for it in items:
+        t0 = time.perf_counter()
+        alone(it)
+        t_alone.append(time.perf_counter() - t0)
+    lam = 0.8 / float(np.mean(t_alone))
+    arr = [r.t_arrival / lam for r in reqs]
+    fin, lat_alone = 0.0, []
+    for a, ts in zip(arr, t_alone):
+        fin = max(fin, a) + ts
+        lat_alone.append(fin - a)
+    srv = N.Server(max_active=64, precision=N.PHS_FP64, rtol=1e-8)
+    ids, sub = [], []
+    t0 = time.perf_counter()
+    nxt = 0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < len(items) and arr[nxt] <= now:
+            xy, f, tg, k, m = items[nxt]
+            ids.append(srv.submit(xy, f, k, targets=tg, m=m, nu=k / 2.0, seed=0))
+            sub.append(time.perf_counter() - t0)
+            nxt += 1
+        active, queued = srv.step()
+        if active == 0 and queued == 0:
+            if nxt == len(items):
+                break
+            time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
+    makespan = time.perf_counter() - t0 - arr[0]
+    lat, worst = [], 0.0
+    for i, rid in enumerate(ids):
+        inf = srv.poll(rid)
+        if inf.state != N.PHS_REQ_DONE or inf.status != 0:
+            raise RuntimeError(f"serving request {rid} failed (state {inf.state}, "
+                               f"status {inf.status})")
+        lat.append((inf.t_done - inf.t_submit) + (sub[i] - arr[i]))
+        worst = max(worst, inf.rel_residual)
+    _, peak = srv.memory()
+    srv.close()
+    q = lambda v, p: round(1e3 * float(np.percentile(v, p)), 3)
+    return {"requests": n_req, "rate_per_s": round(lam, 3),
+            "p50_ms": q(lat, 50), "p99_ms": q(lat, 99),
+            "solves_per_s": round(n_req / makespan, 3),
+            "alone_fifo_p50_ms": q(lat_alone, 50), "alone_fifo_p99_ms": q(lat_alone, 99),
+            "alone_solves_per_s": round(n_req / (fin - arr[0]), 3),
+            "mean_alone_ms": round(1e3 * float(np.mean(t_alone)), 3),
+            "worst_rel_residual": worst, "peak_hbm_bytes": peak}
+
+
+def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
+    """Many problems (n log-uniform in [1e3, 2e5], uniform or clustered, k in
+    {1..4}, minimal block, 4 right-hand sides each): one batch in mixed
+    precision (FP32 FMM, FP64 Krylov with FP64 residual refinement) against
+    the plain FP64 path solving each problem alone; both to 1e-8, plans and
+    preconditioners included.  Problems that do not reach 1e-8 within maxit
+    (order 4 on deep clustered trees, where the Hadamard far field loses
+    accuracy) are counted, not fatal."""
+    probs = W.batched(n_problems=n_prob)
+    dev = torch.device("cuda")
+    data = [(torch.as_tensor(p.xy, device=dev), torch.as_tensor(p.f, device=dev), p.k,
+             p.precond["m"]) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = []
+    for xy, f, k, m in data:
+        pl = N.Plan(xy, k, -1)
+        pl.precond_build(m=m, nu=k / 2.0, seed=0)
+        plans.append(pl)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    batch = N.Batch(plans, [4] * len(plans))
+    t1 = time.perf_counter()
+    _, infos = batch.solve([f for _, f, _, _ in data], rtol=1e-8, maxit=maxit,
+                           precision=N.PHS_MIXED, raise_on_error=False)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t1
+    res_b = [i.rel_residual for i in infos]
+    batch.close()
+    for pl in plans:
+        pl.close()
+    t2 = time.perf_counter()
+    res_a = []
+    for xy, f, k, m in data:
+        pl = N.Plan(xy, k, -1)
+        pl.precond_build(m=m, nu=k / 2.0, seed=0)
+        _, _, info = pl.solve(f, rtol=1e-8, maxit=maxit, raise_on_error=False)
+        res_a.append(info.rel_residual)
+        pl.close()
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t2
+    npts = sum(p.n for p in probs)
+    ok = lambda r: sum(1 for v in r if v <= 1e-8)
+    return {"problems": n_prob, "rhs_per_problem": 4, "points": npts, "maxit": maxit,
+            "batched_mixed_s": round(t_setup + t_solve, 4), "batched_setup_s": round(t_setup, 4),
+            "batched_solve_s": round(t_solve, 4), "alone_fp64_s": round(t_alone, 4),
+            "speedup": round(t_alone / (t_setup + t_solve), 3),
+            "at_1e-8_batched": ok(res_b), "at_1e-8_alone": ok(res_a),
+            "median_rel_residual_batched": float(np.median(res_b)),
+            "worst_rel_residual_batched": max(res_b), "worst_rel_residual_alone": max(res_a)}
 
 
 def main():
@@ -282,6 +410,12 @@ def main():
                       for k, v in roofs.items()},
         "kernels": kernels,
     }
+    if not args.no_serve and args.serve_requests > 0:
+        sv = serve_leg(N, W, torch, args.serve_requests)
+        out["serve_p50_ms"], out["serve_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
+        out["serving"] = sv
+    if not args.no_batch and args.batch_problems > 0:
+        out["batched"] = batch_leg(N, W, torch, args.batch_problems)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -93,7 +93,7 @@ typedef struct {
   double nu;           /* Matern smoothness; <= 0 => k/2. Supported: 0.5, 1,
                           1.5, 2, 2.5 */
   double range;        /* Matern range l = 1/alpha; <= 0 => alpha 0.35
-                          (2 for k=4) in normalised units */
+                          (2 for k=4, 3 for k=3) in normalised units */
   int32_t range_units; /* PHS_RANGE_NORMALIZED or PHS_RANGE_USER */
   uint64_t seed;       /* seed of the random ordering */
 } phs_precond_opts;
@@ -187,7 +187,8 @@ void phs_plan_destroy(phs_plan_t plan);
  * runs exactly the arithmetic it runs alone (results are bitwise equal to
  * phs_solve on that plan).  Problems of different n, order k and polynomial
  * degree can share a batch; all even-k plans must use the same expansion
- * orders, and so must all odd-k plans (the default fmm_tol gives that). */
+ * order (the default fmm_tol gives that), while odd-k plans of different
+ * Chebyshev orders are launched in one group per order. */
 typedef struct phs_batch_s *phs_batch_t;
 
 /* plans: host array of nplans plan handles, which must outlive the batch (a

@@ -96,8 +96,9 @@ def matern(nu: float, x: np.ndarray) -> np.ndarray:
 
 def default_params(k: int):
     """(nu, alpha) defaults in normalised coordinates: nu = k/2; alpha = 0.35
-    except k=4 where the tuned value is 2 (Sec. 2.2)."""
-    return k / 2.0, (2.0 if k == 4 else 0.35)
+    (the tuned TPS value of Sec. 2.2), 2 for k=4 and 3 for k=3 (readings: the
+    paper tunes only k = 2 and 4)."""
+    return k / 2.0, (2.0 if k == 4 else (3.0 if k == 3 else 0.35))
 
 
 def factor(xi: np.ndarray, nbrs, nu: float, alpha: float):

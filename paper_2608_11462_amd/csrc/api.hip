@@ -318,8 +318,12 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
                 "expansion order must be 4..63");
     pl.pe = std::max(pl.p64, 31);
   } else {
-    // Chebyshev nodes per axis: 12 -> ~6e-12, 16 -> ~1e-14 core relative error
-    pl.q64 = o->expansion_order > 0 ? o->expansion_order : (tol >= 1e-13 ? 12 : 16);
+    // Chebyshev nodes per axis: 12 -> ~2e-12, 16 -> ~1e-14 core relative error.
+    // From 2^17 nodes on, 16: the Vecchia factor of the odd-order Matern
+    // covariance grows with the node density (entries ~1e17 at 1e6 nodes) and
+    // turns a 1e-12 matvec error into a loss of definiteness in PCG.
+    pl.q64 = o->expansion_order > 0 ? o->expansion_order
+                                    : ((tol >= 1e-13 && n < (int64_t(1) << 17)) ? 12 : 16);
     pl.q32 = 8;
     PHS_REQUIRE(pl.q64 == 8 || pl.q64 == 10 || pl.q64 == 12 || pl.q64 == 14 || pl.q64 == 16,
                 PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16");

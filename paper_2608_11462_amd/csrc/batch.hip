@@ -17,7 +17,7 @@ void batch_create(Batch &b, const std::vector<Plan *> &plans, const std::vector<
                   hipStream_t s) {
   PHS_REQUIRE(!plans.empty() && plans.size() == nrhs.size(), PHS_ERR_INVALID_ARGUMENT,
               "batch needs at least one plan and one count per plan");
-  const Plan *ev = nullptr, *od = nullptr;
+  const Plan *ev = nullptr;
   for (size_t i = 0; i < plans.size(); ++i) {
     PHS_REQUIRE(plans[i] && nrhs[i] >= 1, PHS_ERR_INVALID_ARGUMENT, "bad plan or rhs count");
     const Plan &p = *plans[i];
@@ -25,10 +25,6 @@ void batch_create(Batch &b, const std::vector<Plan *> &plans, const std::vector<
       if (!ev) ev = &p;
       PHS_REQUIRE(p.p64 == ev->p64 && p.p32 == ev->p32, PHS_ERR_INVALID_ARGUMENT,
                   "even-order plans of a batch must share their expansion orders");
-    } else {
-      if (!od) od = &p;
-      PHS_REQUIRE(p.q64 == od->q64 && p.q32 == od->q32, PHS_ERR_INVALID_ARGUMENT,
-                  "odd-order plans of a batch must share their Chebyshev orders");
     }
   }
   b.plans = plans;

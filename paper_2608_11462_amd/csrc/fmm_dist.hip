@@ -17,6 +17,7 @@
 // The near field (3x3 leaves) is direct phi(r) as in the log-kernel unit.
 //
 // Layout: per level, expansions [box][density][node] (node index a*Q + b).
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -563,8 +564,11 @@ __global__ void k_cheb_eval_targets(const double *__restrict__ tg, int64_t m, do
 }
 
 // ---------------------------------------------------------------- host
+// tier: which Q of each plan the launch uses (0 FP64 matvec, 1 FP32 matvec,
+// 2 evaluation); only the odd-k systems whose Q for that tier equals Q take part.
 template <class T, int Q>
-void far_field_q(Forest &F, const int32_t *mask, int in, const ChebTables &ct, hipStream_t s) {
+void far_field_q(Forest &F, const int32_t *mask, int in, const ChebTables &ct, int tier,
+                 hipStream_t s) {
   constexpr int QQ = Q * Q;
   const bool fp64 = std::is_same<T, double>::value;
   const T *Tk = fp64 ? (const T *)ct.nodes64 + Q : (const T *)ct.nodes32 + Q;
@@ -572,30 +576,30 @@ void far_field_q(Forest &F, const int32_t *mask, int in, const ChebTables &ct, h
   const T *Kd = fp64 ? (const T *)ct.K64 : (const T *)ct.K32;
   const int maxL = F.maxL_dist;
   {
-    const Tab t1 = forest_tab(F, tab_key(1, 1, 0, 0), s);
+    const Tab t1 = forest_tab(F, tab_key(6 + 16 * tier, 1, Q, 0), s);
     if (t1.count)
       PHS_LAUNCH("cheb_p2m", s, kf_cheb_p2m<T, 1, Q><<<(unsigned)t1.count, 64, 0, s>>>(
                                     F.dsys, t1.d, mask, in, Tk));
-    const Tab t3 = forest_tab(F, tab_key(1, 3, 0, 0), s);
+    const Tab t3 = forest_tab(F, tab_key(6 + 16 * tier, 3, Q, 0), s);
     if (t3.count)
       PHS_LAUNCH("cheb_p2m", s, kf_cheb_p2m<T, 3, Q><<<(unsigned)t3.count, 64, 0, s>>>(
                                     F.dsys, t3.d, mask, in, Tk));
   }
   const int thr = QQ <= 64 ? 64 : (QQ <= 128 ? 128 : 256);
   for (int lp = maxL - 1; lp >= 2; --lp) {
-    const Tab tb = forest_tab(F, tab_key(7, 0, 0, lp), s);
+    const Tab tb = forest_tab(F, tab_key(7 + 16 * tier, 0, Q, lp), s);
     if (tb.count)
       PHS_LAUNCH("cheb_m2m", s, kf_cheb_m2m<T, Q><<<(unsigned)tb.count, thr, 0, s>>>(
                                     F.dsys, tb.d, mask, lp, Tpm));
   }
   {
-    const Tab tb = forest_tab(F, tab_key(9, 0, 0, 0), s);
+    const Tab tb = forest_tab(F, tab_key(9 + 16 * tier, 0, Q, 0), s);
     if (tb.count)
       PHS_LAUNCH("cheb_m2l", s, kf_cheb_m2l<T, QQ><<<(unsigned)tb.count, 256, 0, s>>>(
                                     F.dsys, tb.d, mask, Kd));
   }
   for (int lc = 3; lc <= maxL; ++lc) {
-    const Tab tb = forest_tab(F, tab_key(8, 0, 0, lc), s);
+    const Tab tb = forest_tab(F, tab_key(8 + 16 * tier, 0, Q, lc), s);
     if (tb.count)
       PHS_LAUNCH("cheb_l2l", s, kf_cheb_l2l<T, Q><<<(unsigned)tb.count, thr, 0, s>>>(
                                     F.dsys, tb.d, mask, lc, Tpm));
@@ -604,14 +608,14 @@ void far_field_q(Forest &F, const int32_t *mask, int in, const ChebTables &ct, h
 
 template <class T, class TN, int Q>
 void leaf_q(Forest &F, const int32_t *mask, int in, int out, const ChebTables &ct,
-            const double *logtab, hipStream_t s) {
+            const double *logtab, int tier, hipStream_t s) {
   const bool fp64 = std::is_same<T, double>::value;
   const T *Tk = fp64 ? (const T *)ct.nodes64 + Q : (const T *)ct.nodes32 + Q;
-  const Tab t1 = forest_tab(F, tab_key(1, 1, 0, 0), s);
+  const Tab t1 = forest_tab(F, tab_key(6 + 16 * tier, 1, Q, 0), s);
   if (t1.count)
     PHS_LAUNCH("cheb_leaf_eval", s, kf_cheb_leaf_eval<T, TN, 1, Q><<<(unsigned)t1.count, 64, 0, s>>>(
                                         F.dsys, t1.d, mask, in, out, Tk, logtab));
-  const Tab t3 = forest_tab(F, tab_key(1, 3, 0, 0), s);
+  const Tab t3 = forest_tab(F, tab_key(6 + 16 * tier, 3, Q, 0), s);
   if (t3.count)
     PHS_LAUNCH("cheb_leaf_eval", s, kf_cheb_leaf_eval<T, TN, 3, Q><<<(unsigned)t3.count, 64, 0, s>>>(
                                         F.dsys, t3.d, mask, in, out, Tk, logtab));
@@ -621,37 +625,31 @@ void leaf_q(Forest &F, const int32_t *mask, int in, int out, const ChebTables &c
 // `ct` holds the tables of that Q.
 template <class T, class TN>
 void run_q(Forest &F, const int32_t *mask, int in, int out, bool leaf, int Q,
-           const ChebTables &ct, const double *logtab, hipStream_t s) {
+           const ChebTables &ct, const double *logtab, int tier, hipStream_t s) {
   switch (Q) {
     case 8:
-      far_field_q<T, 8>(F, mask, in, ct, s);
-      if (leaf) leaf_q<T, TN, 8>(F, mask, in, out, ct, logtab, s);
+      far_field_q<T, 8>(F, mask, in, ct, tier, s);
+      if (leaf) leaf_q<T, TN, 8>(F, mask, in, out, ct, logtab, tier, s);
       break;
     case 10:
-      far_field_q<T, 10>(F, mask, in, ct, s);
-      if (leaf) leaf_q<T, TN, 10>(F, mask, in, out, ct, logtab, s);
+      far_field_q<T, 10>(F, mask, in, ct, tier, s);
+      if (leaf) leaf_q<T, TN, 10>(F, mask, in, out, ct, logtab, tier, s);
       break;
     case 12:
-      far_field_q<T, 12>(F, mask, in, ct, s);
-      if (leaf) leaf_q<T, TN, 12>(F, mask, in, out, ct, logtab, s);
+      far_field_q<T, 12>(F, mask, in, ct, tier, s);
+      if (leaf) leaf_q<T, TN, 12>(F, mask, in, out, ct, logtab, tier, s);
       break;
     case 14:
-      far_field_q<T, 14>(F, mask, in, ct, s);
-      if (leaf) leaf_q<T, TN, 14>(F, mask, in, out, ct, logtab, s);
+      far_field_q<T, 14>(F, mask, in, ct, tier, s);
+      if (leaf) leaf_q<T, TN, 14>(F, mask, in, out, ct, logtab, tier, s);
       break;
     case 16:
-      far_field_q<T, 16>(F, mask, in, ct, s);
-      if (leaf) leaf_q<T, TN, 16>(F, mask, in, out, ct, logtab, s);
+      far_field_q<T, 16>(F, mask, in, ct, tier, s);
+      if (leaf) leaf_q<T, TN, 16>(F, mask, in, out, ct, logtab, tier, s);
       break;
     default:
       throw Error{PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16"};
   }
-}
-
-const Plan &dist_ref(const Forest &F) {
-  for (const Plan *p : F.plan)
-    if (!p->core_log) return *p;
-  throw Error{PHS_ERR_INVALID_ARGUMENT, "forest has no odd-order system"};
 }
 
 template <int Q>
@@ -755,21 +753,30 @@ size_t cheb_expansion_bytes(int L, int Q, int nd, bool fp64) {
   return (size_t)cheb_level_base(L + 1, Q * Q, nd) * (fp64 ? 8 : 4);
 }
 
+// One pass per distinct Chebyshev order among the odd-k systems (plans of
+// different sizes may use different orders).
 void dist_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
                  hipStream_t s) {
-  const Plan &ref = dist_ref(F);
-  if (precision == PHS_MIXED)
-    run_q<float, float>(F, mask, in, out, true, ref.q32, ref.ct32, ref.logtab, s);
-  else if (precision == PHS_NEAR32)
-    run_q<double, float>(F, mask, in, out, true, ref.q64, ref.ct64, ref.logtab, s);
-  else
-    run_q<double, double>(F, mask, in, out, true, ref.q64, ref.ct64, ref.logtab, s);
+  const int tier = precision == PHS_MIXED ? 1 : 0;
+  std::vector<int> done;
+  for (const Plan *p : F.plan) {
+    if (p->core_log) continue;
+    const int Q = tier ? p->q32 : p->q64;
+    if (std::find(done.begin(), done.end(), Q) != done.end()) continue;
+    done.push_back(Q);
+    if (precision == PHS_MIXED)
+      run_q<float, float>(F, mask, in, out, true, Q, p->ct32, p->logtab, tier, s);
+    else if (precision == PHS_NEAR32)
+      run_q<double, float>(F, mask, in, out, true, Q, p->ct64, p->logtab, tier, s);
+    else
+      run_q<double, double>(F, mask, in, out, true, Q, p->ct64, p->logtab, tier, s);
+  }
 }
 
 void dist_expansions(Plan &pl, int in, hipStream_t s) {
   Forest &F = *pl.self;
   run_q<double, double>(F, F.mask[0], in, 0, false, pl.qe, pl.qe == pl.q64 ? pl.ct64 : pl.cte,
-                        pl.logtab, s);
+                        pl.logtab, 2, s);
 }
 
 void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,

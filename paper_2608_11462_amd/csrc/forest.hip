@@ -518,18 +518,23 @@ Tab forest_tab(Forest &F, uint64_t key, hipStream_t s) {
   return F.cache.back().second;
 }
 
-// kinds: 1 leaf (k == K), 2 P2M groups of 4 x P leaves (k == K), 3 log M2M level,
-// 4 log L2L level, 5 log M2L, 7 Chebyshev M2M level, 8 Chebyshev L2L level,
-// 9 Chebyshev M2L
+// kinds (low 4 bits): 1 leaf (k == K), 2 P2M groups of 4 x P leaves (k == K),
+// 3 log M2M level, 4 log L2L level, 5 log M2L; Chebyshev (P = Q, odd-k
+// systems whose Q for the launch equals P): 6 leaf (k == K), 7 M2M level,
+// 8 L2L level, 9 M2L.  Bits 4.. of a Chebyshev kind select which Q of the
+// plan applies: 0 the FP64 matvec order, 1 the FP32 one, 2 the evaluation one.
 int m2l_chunk(int P);
 
 Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
   std::vector<BlkRef> h;
+  const int tier = kind >> 4, base = kind & 15;
   for (int i = 0; i < F.nsys; ++i) {
     const Plan &pl = *F.plan[i];
     const int L = pl.tree.L, R = pl.R;
     const bool log_k = pl.core_log;
-    switch (kind) {
+    const int qsel = tier == 0 ? pl.q64 : (tier == 1 ? pl.q32 : pl.qe);
+    const bool cheb = !log_k && qsel == P;
+    switch (base) {
       case 1:
         if (pl.k == K)
           for (int64_t b = 0; b < boxes_at(L); ++b) h.push_back({i, (int32_t)b});
@@ -560,16 +565,20 @@ Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
           for (int64_t b = 0; b < ntiles * nch * R; ++b) h.push_back({i, (int32_t)b});
         }
         break;
+      case 6:
+        if (cheb && pl.k == K)
+          for (int64_t b = 0; b < boxes_at(L); ++b) h.push_back({i, (int32_t)b});
+        break;
       case 7:
-        if (!log_k && L > level)
+        if (cheb && L > level)
           for (int64_t b = 0; b < boxes_at(level) * R; ++b) h.push_back({i, (int32_t)b});
         break;
       case 8:
-        if (!log_k && L >= level)
+        if (cheb && L >= level)
           for (int64_t b = 0; b < boxes_at(level) * R; ++b) h.push_back({i, (int32_t)b});
         break;
       case 9:
-        if (!log_k) {
+        if (cheb) {
           int64_t tiles = 0;
           for (int l = 2; l <= L; ++l) tiles += (boxes_at(l) * R + 63) / 64;
           for (int64_t b = 0; b < tiles; ++b) h.push_back({i, (int32_t)b});

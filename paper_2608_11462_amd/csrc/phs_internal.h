@@ -340,7 +340,7 @@ struct SolveJob {
   double inner_tol = 0;
   bool pcg_conv = false, pcg_break = false;
   int budget = 0;
-  bool fp64_finish = false, count_outer = false, apply_dw = false;
+  bool fp64_finish = false, count_outer = false, apply_dw = false, have_q = false;
 };
 struct SolveParams {
   double rtol;

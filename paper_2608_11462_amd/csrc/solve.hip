@@ -4,15 +4,20 @@
 // round, so one plan alone and many plans in a batch run the same arithmetic
 // per system.
 //
-// Per system (x0 = 0, b = sign_k Pi f):
-//   FP64:  PCG on sign_k Pi M Pi with z = Pi U~ U~^T r, stop when
-//          ||r|| <= rtol ||b||, r the recursively updated residual.
-//   MIXED / NEAR32: iterative refinement.  Inner PCG on the FP32 operator
-//          for the correction dw, then w += dw and the FP64 residual
-//          r = sign_k Pi (f - M64 w).  An inner solve that breaks down at
-//          once, or an outer step that does not halve the FP64 residual,
-//          switches the rest of the solve to the FP64 operator.  The exit test
-//          is always on the FP64 residual.
+// Per system (x0 = 0, b = sign_k Pi f), iterative refinement around PCG:
+//   inner PCG on sign_k Pi M Pi with z = Pi U~ U~^T r for the correction dw,
+//   stopped when the recursively updated residual ||r|| <= tol; then
+//   w += dw and the true residual r = sign_k Pi (f - M64 w) with the FP64
+//   matvec.  The solve ends when ||r|| <= rtol ||b||.
+//   FP64: the inner operator is the FP64 one and the inner tolerance is
+//          rtol ||b||, so usually one inner solve suffices; when the true
+//          residual misses the target (FMM error against a rough, strongly
+//          preconditioned direction) PCG restarts from it, and stops if a
+//          restart no longer halves it.
+//   MIXED / NEAR32: the inner operator is FP32 (far and near field, or near
+//          field only).  An inner solve that breaks down at once, or an
+//          outer step that does not halve the true residual, switches the
+//          rest of the solve to the FP64 operator.
 //   Then beta from R beta = Q^T (f - M64 w), and the FP64 relative residual.
 #include <algorithm>
 #include <chrono>
@@ -57,7 +62,7 @@ void start_pcg(JobRun &r, const SolveParams &P) {
   if (!mixed) {
     r.inner_prec = PHS_FP64;
     r.inner_tol = r.tol_abs;
-    r.maxit_inner = P.maxit;
+    r.maxit_inner = r.budget;
   } else {
     // FP32 far field: small steps (its error is relative to ||M||); FP32
     // near field only: the operator is accurate enough to go to rtol at once
@@ -65,10 +70,13 @@ void start_pcg(JobRun &r, const SolveParams &P) {
     r.inner_tol = r.fp64_finish ? r.tol_abs
                                 : (P.prec == PHS_NEAR32 ? 0.5 * r.tol_abs
                                                         : std::max(r.tol_abs, 1e-4 * r.rn));
-    r.maxit_inner = (r.fp64_finish || P.prec == PHS_NEAR32) ? r.budget : std::min(r.budget, 60);
+    // an FP32 inner solve gets at most 60 iterations: if it stalls, the outer
+    // step sees no progress and the rest runs on the FP64 operator
+    r.maxit_inner = r.fp64_finish ? r.budget : std::min(r.budget, 60);
   }
   r.it = 0;
   r.pcg_conv = r.pcg_break = false;
+  r.have_q = false;
   r.state = J_START;
 }
 
@@ -94,6 +102,7 @@ void solve_begin(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
     r.tol_abs = P.rtol * r.bn;
     r.rn = r.bn;
     r.budget = P.maxit;
+    r.fp64_finish = P.prec == PHS_FP64;
     if (r.bn <= 1e-13 * r.fn) {
       // data in span(B) to rounding level: the polynomial alone interpolates
       r.state = J_FINISH;
@@ -197,13 +206,6 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
     for (auto *rp_ : jr) if (auto &r = *rp_; true) {
       if (r.state != J_PCG_END) continue;
       r.iters += r.it;
-      if (!mixed) {
-        if (r.pcg_break) r.status = PHS_ERR_BREAKDOWN;
-        else if (!r.pcg_conv) r.status = PHS_ERR_NOT_CONVERGED;
-        r.state = J_FINISH;
-        r.apply_dw = true;
-        continue;
-      }
       r.budget -= r.it;
       if (r.pcg_break && r.it <= 1) {
         if (r.fp64_finish) {
@@ -220,12 +222,9 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       r.apply_dw = true;
       r.state = J_RESID;
     }
-    // w = dw (FP64: the PCG iterate) or w += dw (refinement)
+    // w += dw
     set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.apply_dw; }, any, s);
-    if (any) {
-      if (mixed) f_axpby(F, F.mask[MK_UPD], V_W, V_DW, 1.0, 1.0, s);
-      else f_copy(F, F.mask[MK_UPD], V_W, V_DW, s);
-    }
+    if (any) f_axpby(F, F.mask[MK_UPD], V_W, V_DW, 1.0, 1.0, s);
     for (auto *rp_ : jr) if (auto &r = *rp_; true) r.apply_dw = false;
 
     // ---- FP64 residual of the refinement: r = sign Pi (f - M64 w)
@@ -239,31 +238,43 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       f_read_scalars(F, SC_DOT, 1, s);
       for (auto *rp_ : jr) if (auto &r = *rp_; true) {
         if (r.state != J_RESID) continue;
-        if (r.count_outer) {
-          const double rn_new = std::sqrt(F.hgsc[r.sys * 8]);
-          ++r.outer;
-          if (!(rn_new < 0.5 * r.rn)) r.fp64_finish = true;
-          r.rn = rn_new;
-          if (!std::isfinite(r.rn)) {
-            r.status = PHS_ERR_BREAKDOWN;
-            r.state = J_FINISH;
-            continue;
-          }
+        const double rn_new = std::sqrt(F.hgsc[r.sys * 8]);
+        if (!std::isfinite(rn_new)) {
+          r.status = PHS_ERR_BREAKDOWN;
+          r.state = J_FINISH;
+          r.have_q = true;
+          continue;
         }
-        if (r.rn > r.tol_abs && r.budget > 0) {
+        bool stalled = false;
+        if (r.count_outer) {
+          // refinement steps; in FP64 only the restarts count
+          if (mixed || rn_new > r.tol_abs) ++r.outer;
+          stalled = !(rn_new < 0.5 * r.rn);
+          if (stalled && !r.fp64_finish) {
+            r.fp64_finish = true;  // the FP32 operator stopped helping
+            stalled = false;
+          }
+          r.rn = rn_new;
+        }
+        if (r.rn > r.tol_abs && r.budget > 0 && !stalled) {
           start_pcg(r, P);
         } else {
           if (r.rn > r.tol_abs && r.status == PHS_OK) r.status = PHS_ERR_NOT_CONVERGED;
           r.state = J_FINISH;
+          r.have_q = true;  // q = f - M w of the final w
         }
       }
     }
 
     // ---- beta from R beta = Q^T (f - M w), the FP64 residual, w to the caller
+    set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.state == J_FINISH && !r.have_q; },
+             any, s);
+    if (any) {
+      f_matvec(F, F.mask[MK_UPD], V_W, V_Q, PHS_FP64, s);
+      f_axpby(F, F.mask[MK_UPD], V_Q, V_F, 1.0, -1.0, s);  // q = f - M w
+    }
     set_mask(F, MK_FINISH, jr, [](const JobRun &r) { return r.state == J_FINISH; }, any, s);
     if (any) {
-      f_matvec(F, F.mask[MK_FINISH], V_W, V_Q, PHS_FP64, s);
-      f_axpby(F, F.mask[MK_FINISH], V_Q, V_F, 1.0, -1.0, s);  // q = f - M w
       f_qt(F, F.mask[MK_FINISH], V_Q, SC_QTF, s);
       f_project(F, F.mask[MK_FINISH], V_Q, s);
       f_dot(F, F.mask[MK_FINISH], V_Q, V_Q, SC_DOT, s);

@@ -484,7 +484,10 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
                 PHS_ERR_INVALID_ARGUMENT, "bad range units");
     alpha = o.range_units == PHS_RANGE_USER ? 1.0 / (o.range * pl.rho) : 1.0 / o.range;
   } else {
-    alpha = pl.k == 4 ? 2.0 : 0.35;
+    // TPS: the paper's tuned 0.35 on [-1/4, 1/4]^2; k = 4: 2 on [-1, 1]^2;
+    // k = 3 (nu = 3/2): 3, which keeps the factor's dynamic range small enough
+    // for FP64 PCG to reach 1e-8 up to 1e6 nodes (0.35 stalls near 1e-6 there)
+    alpha = pl.k == 4 ? 2.0 : (pl.k == 3 ? 3.0 : 0.35);
   }
   vecchia_free(pl);
   pl.m = m;

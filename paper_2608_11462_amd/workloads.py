@@ -162,7 +162,7 @@ def odd_clustered(seed: int = 2, n: int = 100000, n_targets: int = 50000) -> Pro
     fld = bump_field(rng)
     tg = uniform_points(rng, n_targets)
     return Problem("odd_clustered", xy, fld(xy), 3, 2, tg,
-                   dict(m=50, nu=1.5, range=1.0 / 0.35, range_units="normalized"))
+                   dict(m=50, nu=1.5, range=1.0 / 3.0, range_units="normalized"))
 
 
 def large_tps(seed: int = 3, n: int = 1 << 20, n_targets: int = 10000) -> Problem:

@@ -132,3 +132,29 @@ def test_batch_uneven_many():
         assert infos[i].iters == ia.iters
     print("iters per plan:", [inf.iters for inf in infos])
     batch.close()
+
+
+def test_batch_mixed_chebyshev_orders():
+    """Odd-order plans below and above 2^17 nodes use Chebyshev orders 12 and
+    16; in one batch they run in one launch group per order and still match
+    their solo solves bitwise."""
+    items = []
+    for i, (n, k) in enumerate([(3000, 3), (140000, 3), (5000, 1), (2500, 2)]):
+        g = W.rng_for(7000 + i)
+        xy = W.clustered_points(g, n) if i % 2 else W.uniform_points(g, n)
+        f = W.fourier_field(g, kmax=4)(xy)
+        pl = N.Plan(dev(xy), k)
+        pl.precond_build(m=40, nu=k / 2.0, seed=i)
+        items.append((pl, f))
+    print("[case] orders", [p.order for p, _ in items], flush=True)
+    assert sorted({p.order for p, _ in items if p.k % 2}) == [12, 16]
+    batch = N.Batch([p for p, _ in items])
+    res, infos = batch.solve([dev(f) for _, f in items], rtol=1e-8, maxit=2000)
+    for (pl, f), (w, b), inf in zip(items, res, infos):
+        wa, ba, ia = pl.solve(dev(f), rtol=1e-8, maxit=2000)
+        print(f"k={pl.k} n={pl.n} Q/P={pl.order} iters {inf.iters}/{ia.iters} "
+              f"resid {inf.rel_residual:.2e}")
+        assert inf.rel_residual <= 1e-8
+        np.testing.assert_array_equal(host(w), host(wa))
+        np.testing.assert_array_equal(host(b), host(ba))
+    batch.close()

@@ -2,7 +2,7 @@
 (the oracle cannot form these matrices).
 
 * odd_clustered: n = 100000 (70% uniform + 30% in 10 Gaussian clusters), k = 3,
-  quadratic block, Vecchia m = 50, nu = 1.5, alpha = 0.35.
+  quadratic block, Vecchia m = 50, nu = 1.5, alpha = 3 (the k = 3 default).
 * large_tps: n = 2^20 uniform, k = 2, linear block, Vecchia m = 30, nu = 1,
   alpha = 0.35 (the benchmark configuration).
 Gates: matvec 1e-10 relative on sampled rows (FP64); node residual
