@@ -5,7 +5,9 @@
 // with its Krylov vectors until it finishes.  Each step runs one PCG round of
 // every active request in shared launches; requests that finish are evaluated
 // at their targets and release their memory, and the forest of active systems
-// is rebuilt before the next round.
+// is rebuilt before the next round.  Requests much smaller than the largest
+// active one get extra rounds of their own between full rounds (time sharing),
+// so they are not held to the pace of the largest request.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -184,9 +186,30 @@ void server_step(Server &sv) {
   }
   // 3. one lockstep round of every active request
   std::vector<SolveJob *> js;
-  for (Request *r : sv.active) js.push_back(&r->job);
+  int64_t n_big = 0;
+  for (Request *r : sv.active) {
+    js.push_back(&r->job);
+    n_big = std::max(n_big, r->in.n);
+  }
+  const double ta = now_s();
   solve_round(F, js, sv.P, s);
-  // 4. finished requests: evaluate, release
+  const double t_full = now_s() - ta;
+  // 4. time sharing: a round lasts as long as the largest request's
+  // iteration, so requests at most a quarter of its size get extra rounds of
+  // their own, for up to half the time of the full round
+  std::vector<SolveJob *> small;
+  for (Request *r : sv.active)
+    if (r->in.n * 4 <= n_big && r->job.state != J_DONE) small.push_back(&r->job);
+  double t_extra = 0.0;
+  for (int rounds = 0; !small.empty() && t_extra < 0.5 * t_full && rounds < 32; ++rounds) {
+    const double tb = now_s();
+    if (!solve_round(F, small, sv.P, s)) break;
+    t_extra += now_s() - tb;
+    small.erase(std::remove_if(small.begin(), small.end(),
+                               [](const SolveJob *j) { return j->state == J_DONE; }),
+                small.end());
+  }
+  // 5. finished requests: evaluate, release
   std::vector<Request *> keep;
   for (Request *r : sv.active) {
     if (r->job.state != J_DONE) {
