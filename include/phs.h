@@ -285,10 +285,12 @@ void phs_server_destroy(phs_server_t srv);
 /* Message for the last non-OK status returned on this thread. */
 const char *phs_last_error(void);
 
-/* Per-kernel timing.  When enabled, each library kernel launch is bracketed by
- * HIP events on its own stream; phs_profile_read copies up to `cap` records
- * (name, launches, total milliseconds) to host arrays and resets the counters.
- * names: host array of `cap` char[48].  Returns the number of records. */
+/* Per-kernel timing.  on = 1: each library kernel launch is bracketed by HIP
+ * events on its own stream; on = 2: only the leaf, M2L, Vecchia factor and
+ * KNN, and preconditioner-apply kernels; 0: off.  phs_profile_read copies up
+ * to `cap` records (name, launches, total milliseconds) to host arrays and
+ * resets the counters.  names: host array of `cap` char[48].  Returns the
+ * number of records. */
 void phs_profile_enable(int32_t on);
 int32_t phs_profile_read(char (*names)[48], int64_t *launches, double *total_ms,
                          int32_t cap);

@@ -40,6 +40,7 @@ struct Pending {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+int g_prof_level = 0;
 std::map<std::string, ProfRec> g_prof;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;  // recycled events
@@ -75,6 +76,17 @@ void prof_flush_locked() {
 }  // namespace
 
 bool profiling_on() { return g_prof_on; }
+
+// level 2 times only the kernels the roofline figures use
+bool prof_wants(const char *name) {
+  if (g_prof_level != 2) return true;
+  static const char *keep[] = {"leaf_eval", "leaf_eval_near32", "leaf_eval_f32", "m2l",
+                               "m2l_f32", "vecchia_factor", "vecchia_knn", "precond_u",
+                               "precond_ut"};
+  for (const char *k : keep)
+    if (std::strcmp(k, name) == 0) return true;
+  return false;
+}
 
 void prof_begin(const char *name, hipStream_t s) {
   hipEvent_t a = pool_get();
@@ -388,6 +400,7 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
   pl.self = new Forest();
   build_forest(*pl.self, {&pl}, {&pl.sw}, s);
   PHS_HIP(hipStreamSynchronize(s));
+  pool_mark_idle();
 }
 
 }  // namespace
@@ -652,7 +665,10 @@ phs_status phs_batch_solve(phs_batch_t batch, const double *const *f, double *co
   });
 }
 
-void phs_batch_destroy(phs_batch_t batch) { delete batch; }
+void phs_batch_destroy(phs_batch_t batch) {
+  delete batch;
+  pool_mark_idle();
+}
 
 struct phs_server_s {
   Server sv;
@@ -717,12 +733,16 @@ phs_status phs_server_memory(phs_server_t srv, int64_t *in_use, int64_t *peak) {
   });
 }
 
-void phs_server_destroy(phs_server_t srv) { delete srv; }
+void phs_server_destroy(phs_server_t srv) {
+  delete srv;
+  pool_mark_idle();
+}
 
 void phs_plan_destroy(phs_plan_t plan) {
   if (!plan) return;
   (void)hipDeviceSynchronize();
   delete plan;
+  pool_mark_idle();
 }
 
 const char *phs_last_error(void) { return g_last_error.c_str(); }
@@ -730,6 +750,7 @@ const char *phs_last_error(void) { return g_last_error.c_str(); }
 void phs_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
+  g_prof_level = on;
 }
 
 int32_t phs_profile_read(char (*names)[48], int64_t *launches, double *total_ms,

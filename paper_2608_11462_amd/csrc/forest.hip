@@ -251,13 +251,15 @@ __global__ void k_scatter_one(const double *__restrict__ src, const int32_t *__r
   if (i < n) dst[order[i]] = src[i];
 }
 
-Tab upload_tab(const std::vector<BlkRef> &h, hipStream_t s) {
+// The host copy stays alive with the forest, so the copy needs no wait.
+Tab upload_tab(Forest &F, std::vector<BlkRef> &&h, hipStream_t s) {
   Tab t;
   t.count = (int64_t)h.size();
   t.d = dmalloc<BlkRef>(std::max<size_t>(h.size(), 1));
-  if (!h.empty())
-    PHS_HIP(hipMemcpyAsync(t.d, h.data(), h.size() * sizeof(BlkRef), hipMemcpyHostToDevice, s));
-  PHS_HIP(hipStreamSynchronize(s));
+  F.hcopies.push_back(std::move(h));
+  const auto &hc = F.hcopies.back();
+  if (!hc.empty())
+    PHS_HIP(hipMemcpyAsync(t.d, hc.data(), hc.size() * sizeof(BlkRef), hipMemcpyHostToDevice, s));
   return t;
 }
 
@@ -330,10 +332,9 @@ Forest::~Forest() {
       (void)hipEventDestroy(mask_ev[i]);
     }
     dfree(mask[i]);
-    if (hmask[i]) (void)hipHostFree(hmask[i]);
   }
   dfree(gsc);
-  if (hgsc) (void)hipHostFree(hgsc);
+  if (hpin) (void)hipHostFree(hpin);
   dfree(vec.d);
   dfree(dot.d);
   dfree(pc.d);
@@ -364,9 +365,15 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
   F.dsys = dmalloc<SysDev>(F.nsys);
   PHS_HIP(hipMemcpyAsync(F.dsys, F.hsys.data(), F.nsys * sizeof(SysDev), hipMemcpyHostToDevice,
                          s));
+  {
+    const size_t mb = ((size_t)F.nsys * sizeof(int32_t) + 63) / 64 * 64;
+    PHS_HIP(hipHostMalloc(&F.hpin, mb * Forest::kMasks + (size_t)F.nsys * 8 * sizeof(double), 0));
+    for (int i = 0; i < Forest::kMasks; ++i)
+      F.hmask[i] = (int32_t *)((char *)F.hpin + mb * i);
+    F.hgsc = (double *)((char *)F.hpin + mb * Forest::kMasks);
+  }
   for (int i = 0; i < Forest::kMasks; ++i) {
     F.mask[i] = dmalloc<int32_t>(F.nsys);
-    PHS_HIP(hipHostMalloc((void **)&F.hmask[i], F.nsys * sizeof(int32_t), 0));
     for (int j = 0; j < F.nsys; ++j) F.hmask[i][j] = 1;
     PHS_HIP(hipMemcpyAsync(F.mask[i], F.hmask[i], F.nsys * sizeof(int32_t),
                            hipMemcpyHostToDevice, s));
@@ -375,10 +382,9 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
     F.mask_pending[i] = true;
   }
   F.gsc = dmalloc<double>((size_t)F.nsys * 8);
-  PHS_HIP(hipHostMalloc((void **)&F.hgsc, (size_t)F.nsys * 8 * sizeof(double), 0));
-  F.vec = upload_tab(hv, s);
-  F.dot = upload_tab(hd, s);
-  F.pc = upload_tab(hp, s);
+  F.vec = upload_tab(F, std::move(hv), s);
+  F.dot = upload_tab(F, std::move(hd), s);
+  F.pc = upload_tab(F, std::move(hp), s);
 }
 
 void refresh_forest(Forest &F, hipStream_t s) {
@@ -588,7 +594,7 @@ Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
         throw Error{PHS_ERR_INVALID_ARGUMENT, "unknown table kind"};
     }
   }
-  return upload_tab(h, s);
+  return upload_tab(F, std::move(h), s);
 }
 
 }  // namespace phs

@@ -38,13 +38,14 @@ void set_error(phs_status code, const std::string &msg);
 // Kernel launches go through launch(); when profiling is on each launch is
 // bracketed by events on its stream and the elapsed time is charged to name.
 bool profiling_on();
+bool prof_wants(const char *name);
 void prof_begin(const char *name, hipStream_t s);
 void prof_end(hipStream_t s);
 
 struct ProfScope {
   hipStream_t s;
   bool on;
-  ProfScope(const char *name, hipStream_t st) : s(st), on(profiling_on()) {
+  ProfScope(const char *name, hipStream_t st) : s(st), on(profiling_on() && prof_wants(name)) {
     if (on) prof_begin(name, s);
   }
   ~ProfScope() {
@@ -78,20 +79,23 @@ __device__ __forceinline__ gptr<T> rw(T *p) {
 }
 
 // ------------------------------------------------------------------ memory
+// Device memory comes from a caching pool: a freed block is parked on the
+// freeing thread's pending list and becomes reusable only at pool_mark_idle,
+// which synchronises the device first, so a block is never handed out while
+// work that used it may still run.  Plans built and destroyed over and over
+// (one per solve) then cost no hipMalloc/hipFree in steady state.
+void *pool_alloc(size_t bytes);
+void pool_free(void *p);
+void pool_mark_idle();  // synchronises the device, then recycles pending blocks
+void pool_trim();       // returns every idle cached block to HIP
+
 template <class T>
 T *dmalloc(size_t count) {
-  void *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc(&p, count * sizeof(T));
-  if (e != hipSuccess)
-    throw Error{PHS_ERR_OUT_OF_MEMORY,
-                "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
-  return static_cast<T *>(p);
+  return static_cast<T *>(pool_alloc(count * sizeof(T)));
 }
 
-inline void dfree(void *p) {
-  if (p) (void)hipFree(p);
-}
+inline void dfree(void *p) { pool_free(p); }
 
 // ------------------------------------------------------------------ sizes
 inline int64_t boxes_at(int l) { return int64_t(1) << (2 * l); }
@@ -275,6 +279,8 @@ struct Forest {
   hipEvent_t mask_ev[kMasks] = {};
   bool mask_pending[kMasks] = {};
   double *gsc = nullptr, *hgsc = nullptr;  // packed scalar readback (nsys x 8)
+  void *hpin = nullptr;                    // one pinned block: host masks + hgsc
+  std::vector<std::vector<BlkRef>> hcopies;  // host sources of the table uploads
   Tab vec, dot, pc;                     // element blocks, dot blocks, 8-row blocks
   std::vector<std::pair<uint64_t, Tab>> cache;  // FMM tables keyed by (kind, K, P, level)
   ~Forest();

@@ -233,6 +233,7 @@ void server_step(Server &sv) {
     sv.in_use -= r->bytes;
     sv.changed = true;
   }
+  if (keep.size() != sv.active.size()) pool_mark_idle();
   sv.active = keep;
 }
 

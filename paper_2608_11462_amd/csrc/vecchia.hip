@@ -628,6 +628,7 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
                   (void *)d_coff, (void *)d_gb, (void *)xr, (void *)yr, (void *)pos_of_rank,
                   (void *)cnt, (void *)nfail})
     dfree(q);
+  pool_mark_idle();
 }
 
 void vecchia_export(Plan &pl, int32_t *rank, int32_t *nbr, double *coef, double *diag,

@@ -395,8 +395,10 @@ class Server:
             pass
 
 
-def profile_enable(on: bool = True) -> None:
-    lib().phs_profile_enable(1 if on else 0)
+def profile_enable(on=True) -> None:
+    """on: False/0 off, True/1 every kernel, 2 only the kernels the roofline
+    figures use (leaf, M2L, Vecchia factor and KNN, preconditioner apply)."""
+    lib().phs_profile_enable(int(on))
 
 
 def profile_read(cap: int = 256) -> dict:
