@@ -14,6 +14,7 @@
 namespace phs {
 
 void fill_log_table(double *tab);
+void fill_near_log_table(double *tab);
 
 void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                       const double *targets, int64_t m, double *out, hipStream_t s);
@@ -121,6 +122,7 @@ Plan::~Plan() {
   dfree(uy);
   dfree(xy2);
   dfree(logtab);
+  dfree(neartab);
   dfree(Q);
   dfree(tree.leaf_start);
   free_log_tables(lt64);
@@ -395,6 +397,10 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     fill_log_table(tab.data());
     pl.logtab = dmalloc<double>(256);
     PHS_HIP(hipMemcpy(pl.logtab, tab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> nt(512);
+    fill_near_log_table(nt.data());
+    pl.neartab = dmalloc<double>(512);
+    PHS_HIP(hipMemcpy(pl.neartab, nt.data(), 512 * sizeof(double), hipMemcpyHostToDevice));
   }
   alloc_syswork(pl.sw, pl);
   pl.self = new Forest();

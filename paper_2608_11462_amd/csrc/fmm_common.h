@@ -199,8 +199,39 @@ __device__ __forceinline__ double tang_log(double x, PT tab) {
 // Host: fill the 256-entry table used by tang_log.
 void fill_log_table(double *tab);
 
+// log x for the near field, where phi = r^k log r enters sums of O(1) terms and
+// an absolute error of a few 1e-16 suffices: x = 2^e m, m in [1, 2),
+// c = 1 + j/256 from the top eight mantissa bits, r = m (1/c) - 1 in one
+// fused multiply-add (|r| < 2^-8), log1p(r) by its degree-6 Taylor polynomial
+// (remainder < r^7/7 < 3e-18), log x = e ln2 + log c + log1p(r).  Absolute
+// error about 2e-16.  tab: 1/c for j < 256, then log c.  x must be a positive
+// normal number.
+__device__ __forceinline__ double near_log_core(double x, double invc, double logc) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t hi = (uint32_t)(b >> 32);
+  const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FF00000u), (int)(uint32_t)b);
+  const double r = fma(m, invc, -1.0);
+  double p = -1.0 / 6.0;
+  p = fma(p, r, 1.0 / 5.0);
+  p = fma(p, r, -0.25);
+  p = fma(p, r, 1.0 / 3.0);
+  p = fma(p, r, -0.5);
+  p = fma(p, r, 1.0);
+  const double ed = (double)((int)(hi >> 20) - 1023);
+  return fma(ed, 0.69314718055994530942, fma(p, r, logc));
+}
+template <class PT>
+__device__ __forceinline__ double near_log(double x, PT tab) {
+  const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(x) >> 32);
+  const int j = (int)((hi >> 12) & 255u);
+  return near_log_core(x, tab[j], tab[256 + j]);
+}
+// Host: fill the 512-entry table of near_log.
+void fill_near_log_table(double *tab);
+
 // sum_j phi(|x_i - y_j|) t_j over a contiguous source range, FP64.  xy2
-// points to the interleaved source coordinates (x0, y0, x1, y1, ...).  For even
+// points to the interleaved source coordinates (x0, y0, x1, y1, ...); tab is
+// the near_log table.  For even
 // k the r = 0 term is removed by clamping r^2 to 1e-300 (phi is then ~1e-298,
 // below the rounding of any sum of O(1) terms).  Returns the sum without the
 // factor 1/2 of phi = r^k log r = (1/2) r^k log r^2 for even k.
@@ -219,7 +250,7 @@ __device__ __forceinline__ double near_range(double xi, double yi, PXY xy2, PT t
       acc = fma(r2 * sqrt(r2), t[j], acc);
     } else {
       r2 = fmax(r2, 1e-300);
-      double ph = r2 * tang_log(r2, tab);
+      double ph = r2 * near_log(r2, tab);
       if constexpr (K == 4) ph *= r2;
       acc = fma(ph, t[j], acc);
     }

@@ -665,11 +665,11 @@ void eval_q(Plan &pl, const double *w_tree, const double *beta, const double *ta
   if (pl.k == 1)
     PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<1, Q><<<nb, 128, 0, s>>>(
         targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
-        pl.tree.h, Tk, ct.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
+        pl.tree.h, Tk, ct.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.neartab));
   else
     PHS_LAUNCH("eval_targets", s, k_cheb_eval_targets<3, Q><<<nb, 128, 0, s>>>(
         targets, m, pl.c[0], pl.c[1], pl.rho, pl.x, pl.y, w_tree, pl.tree.leaf_start, L,
-        pl.tree.h, Tk, ct.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.logtab));
+        pl.tree.h, Tk, ct.nodes64, W, GL, beta, pl.d, out, pl.xy2, pl.neartab));
 }
 
 std::vector<double> cheb_nodes(int Q) {
@@ -765,18 +765,18 @@ void dist_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
     if (std::find(done.begin(), done.end(), Q) != done.end()) continue;
     done.push_back(Q);
     if (precision == PHS_MIXED)
-      run_q<float, float>(F, mask, in, out, true, Q, p->ct32, p->logtab, tier, s);
+      run_q<float, float>(F, mask, in, out, true, Q, p->ct32, p->neartab, tier, s);
     else if (precision == PHS_NEAR32)
-      run_q<double, float>(F, mask, in, out, true, Q, p->ct64, p->logtab, tier, s);
+      run_q<double, float>(F, mask, in, out, true, Q, p->ct64, p->neartab, tier, s);
     else
-      run_q<double, double>(F, mask, in, out, true, Q, p->ct64, p->logtab, tier, s);
+      run_q<double, double>(F, mask, in, out, true, Q, p->ct64, p->neartab, tier, s);
   }
 }
 
 void dist_expansions(Plan &pl, int in, hipStream_t s) {
   Forest &F = *pl.self;
   run_q<double, double>(F, F.mask[0], in, 0, false, pl.qe, pl.qe == pl.q64 ? pl.ct64 : pl.cte,
-                        pl.logtab, 2, s);
+                        pl.neartab, 2, s);
 }
 
 void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,

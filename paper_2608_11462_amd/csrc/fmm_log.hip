@@ -259,7 +259,7 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
                                                    int in, int out,
                                                    const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
-  __shared__ double ltab[256];
+  __shared__ double ltab[512];
   const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
   const cptr<V2<T>> Bleaf = ro((const V2<T> *)d.loc + level_base(L, P, R));
   const gptr<double> ytree = rw(d.v[out]);
   if constexpr (std::is_same<TN, double>::value && K % 2 == 0) {
-    for (int i = lane; i < 256; i += 64) ltab[i] = logtab[i];
+    for (int i = lane; i < 512; i += 64) ltab[i] = logtab[i];
     __syncthreads();
   }
   const int b = start[leaf], e = start[leaf + 1];
@@ -630,6 +630,13 @@ void fill_log_table(double *tab) {
   }
 }
 
+void fill_near_log_table(double *tab) {
+  for (int j = 0; j < 256; ++j) {
+    tab[j] = 1.0 / (1.0 + j / 256.0);
+    tab[256 + j] = std::log1p(j / 256.0);
+  }
+}
+
 size_t log_expansion_bytes(int L, int P, int nd, bool fp64) {
   return (size_t)level_base(L + 1, P, nd) * (fp64 ? 16 : 8);
 }
@@ -645,13 +652,13 @@ void log_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
   const Plan &ref = log_ref(F);
   if (precision == PHS_MIXED) {
     far_field<float>(F, mask, in, ref.p32, ref.lt32, "m2l_f32", s);
-    leaf_pass<float, float>(F, mask, in, out, ref.p32, ref.logtab, s);
+    leaf_pass<float, float>(F, mask, in, out, ref.p32, ref.neartab, s);
   } else {
     far_field<double>(F, mask, in, ref.p64, ref.lt64, "m2l", s);
     if (precision == PHS_NEAR32)
-      leaf_pass<double, float>(F, mask, in, out, ref.p64, ref.logtab, s);
+      leaf_pass<double, float>(F, mask, in, out, ref.p64, ref.neartab, s);
     else
-      leaf_pass<double, double>(F, mask, in, out, ref.p64, ref.logtab, s);
+      leaf_pass<double, double>(F, mask, in, out, ref.p64, ref.neartab, s);
   }
 }
 
@@ -671,13 +678,13 @@ void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                k_eval_targets<2><<<nb, 128, 0, s>>>(targets, m, pl.c[0], pl.c[1], pl.rho,
                                                     pl.x, pl.y, w_tree, pl.tree.leaf_start,
                                                     L, pl.tree.h, P, A, BL, beta, pl.d,
-                                                    out, pl.xy2, pl.logtab));
+                                                    out, pl.xy2, pl.neartab));
   else
     PHS_LAUNCH("eval_targets", s,
                k_eval_targets<4><<<nb, 128, 0, s>>>(targets, m, pl.c[0], pl.c[1], pl.rho,
                                                     pl.x, pl.y, w_tree, pl.tree.leaf_start,
                                                     L, pl.tree.h, P, A, BL, beta, pl.d,
-                                                    out, pl.xy2, pl.logtab));
+                                                    out, pl.xy2, pl.neartab));
 }
 
 }  // namespace phs

@@ -220,7 +220,8 @@ struct Plan {
   double *x = nullptr, *y = nullptr;   // normalised coordinates
   float *ux = nullptr, *uy = nullptr;  // FP32 offsets from the leaf centre
   double2 *xy2 = nullptr;              // packed (x, y), source records of the near field
-  double *logtab = nullptr;            // 256-entry table of the near-field logarithm
+  double *logtab = nullptr;            // 256-entry table of the 1-ulp logarithm (Matern)
+  double *neartab = nullptr;           // 512-entry table of the near-field logarithm
 
   // polynomial block
   double *Q = nullptr;  // n x S column-major, tree order, orthonormal columns
