@@ -284,6 +284,29 @@ __device__ double matern_fast(int nu2, double x, const double *__restrict__ ser,
   return 2.0 * q * k0 + xk1;
 }
 
+// The same from x2 = x^2, the form the factor kernel needs: for the K_1 and
+// K_2 forms on x <= 2 no square root is taken (q = x^2/4 and
+// log(x/2) = log(q)/2), and the series stops once q^k/(k!)^2 < 1e-17.
+__device__ __forceinline__ double horner_n(const double *c, double q, int nt) {
+  double v = c[nt - 1];
+  for (int k = nt - 2; k >= 0; --k) v = fma(v, q, c[k]);
+  return v;
+}
+
+__device__ double matern_fast2(int nu2, double x2, const double *__restrict__ ser,
+                               const double *__restrict__ logtab) {
+  if (x2 == 0.0) return 1.0;
+  if ((nu2 & 1) || x2 > 4.0) return matern_fast(nu2, sqrt(x2), ser, logtab);
+  const double q = 0.25 * x2;
+  const int nt = q < 1e-4 ? 4 : (q < 1e-2 ? 6 : (q < 0.1 ? 9 : kSerTerms));
+  const double lg = 0.5 * tang_log(q, logtab);
+  const double xk1 = 1.0 + 2.0 * q * lg * horner_n(ser + 2 * kSerTerms, q, nt) -
+                     q * horner_n(ser + 3 * kSerTerms, q, nt);
+  if (nu2 == 2) return xk1;
+  const double k0 = -(lg + kEuler) * horner_n(ser, q, nt) + horner_n(ser + kSerTerms, q, nt);
+  return 2.0 * q * k0 + xk1;
+}
+
 // normalised Matern correlation, value 1 at x = 0; nu2 = 2*nu in {1,2,3,4,5}
 __device__ double matern(int nu2, double x) {
   if (x == 0.0) return 1.0;
@@ -318,94 +341,143 @@ __device__ __forceinline__ void tri_index(int e, int &a, int &b) {
   b = e - a * (a + 1) / 2;
 }
 
-// One wavefront per node: Cholesky of the Matern block of sigma(j) u {j}
-// (node last), right-looking in LDS with every step's trailing update spread
-// over all 64 lanes.  Row |sigma| of the factor is (L_s^{-1} k, c), and
-// lambda = L_s^{-T} (L_s^{-1} k) by a column-oriented back substitution.
+// Factor of the Vecchia conditionals (eq. conditionals, Fig. vecchia_chol):
+// for node j with conditioning set sigma(j) (K <= m points), the Cholesky
+// factor L of the Matern block of sigma(j) u {j} (node last) has last row
+// (L_s^{-1} k, c), and lambda = L_s^{-T} (L_s^{-1} k).
+//
+// A wavefront factors G = 64/MM nodes, MM the padded block size.  Each block
+// is padded to MM rows with identity rows in front (their entries of k and
+// lambda are zero), so every node has the same shape.  All 64 lanes first
+// build the lower triangles in LDS; then lane (g, r) keeps row r of block g in
+// registers and runs a fully unrolled left-looking Cholesky: at step c it
+// forms A[r][c] - sum_k L[r][k] L[c][k] with row c read from LDS (the same
+// address across the block's lanes), the pivot comes from lane c by readlane,
+// and rows below scale by its reciprocal square root.  A block that is not numerically positive
+// definite is refactored with a diagonal nugget (1e-12, then x100), and the
+// nodes that needed one, or still fail, are counted.
 template <int MM>
 __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y, int64_t n,
                                                int m, const int32_t *nbr, const int32_t *cnt,
                                                int nu2, double alpha, double *coef,
                                                double *dinv, int32_t *nfail,
                                                const double *ser, const double *logtab) {
+  constexpr int G = 64 / MM;
   constexpr int LD = MM + 1;
-  __shared__ double C[MM * LD];
-  __shared__ double px[MM], py[MM], vv[MM];
-  const int p = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int K = cnt[p];
-  const int N1 = K + 1;
-  for (int a = lane; a < K; a += 64) {
-    const int q = nbr[(int64_t)p * m + a];
-    px[a] = x[q];
-    py[a] = y[q];
+  constexpr int T = MM * (MM + 1) / 2;
+  __shared__ double Lm[G][MM * LD];
+  __shared__ double px[G][MM], py[G][MM], dgi[G][MM];
+  __shared__ double nugs[G];
+  const int lane = threadIdx.x, g = lane / MM, r = lane % MM;
+  const int64_t p = (int64_t)blockIdx.x * G + g;
+  const bool valid = p < n;
+  const int K = valid ? cnt[p] : 0;
+  const int pad = MM - 1 - K;
+  // coordinates: padding rows, then sigma(j), then the node
+  {
+    double cx = 0.0, cy = 0.0;
+    if (valid && r >= pad && r < MM - 1) {
+      const int q = nbr[p * m + (r - pad)];
+      cx = x[q];
+      cy = y[q];
+    } else if (valid && r == MM - 1) {
+      cx = x[p];
+      cy = y[p];
+    }
+    px[g][r] = cx;
+    py[g][r] = cy;
   }
-  if (lane == 0) {
-    px[K] = x[p];
-    py[K] = y[p];
-  }
-  __syncthreads();
-  const int ntri = N1 * (N1 + 1) / 2;
+  double nug = 0.0;  // this lane's copy of its block's nugget
   bool ok = false;
-  double nug = 0.0;
-  for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
-    for (int e = lane; e < ntri; e += 64) {
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    if (r == 0) nugs[g] = nug;
+    __syncthreads();
+    // lower triangles of all G blocks, spread over the whole wavefront
+    for (int e = lane; e < G * T; e += 64) {
+      const int gg = e / T;
       int a, b;
-      tri_index(e, a, b);
-      double v = 1.0 + nug;
-      if (b != a) {
-        const double dx = px[a] - px[b], dy = py[a] - py[b];
-        v = matern_fast(nu2, alpha * sqrt(dx * dx + dy * dy), ser, logtab);
+      tri_index(e - gg * T, a, b);
+      const int pg = MM - 1 - (((int64_t)blockIdx.x * G + gg) < n
+                                   ? cnt[(int64_t)blockIdx.x * G + gg] : 0);
+      double v;
+      if (a == b) {
+        v = a < pg ? 1.0 : 1.0 + nugs[gg];
+      } else if (b < pg) {
+        v = 0.0;
+      } else {
+        const double dx = px[gg][a] - px[gg][b], dy = py[gg][a] - py[gg][b];
+        v = matern_fast2(nu2, alpha * alpha * (dx * dx + dy * dy), ser, logtab);
       }
-      C[a * LD + b] = v;
+      Lm[gg][a * LD + b] = v;
     }
     __syncthreads();
-    ok = true;
-    for (int c = 0; c < N1; ++c) {
-      const double dg = C[c * LD + c];
-      if (!(dg > 0.0)) {
-        ok = false;
-        break;
+    // Left-looking Cholesky, one column per step.  The block's lanes sit in one
+    // wavefront, whose LDS accesses execute in program order, so row c written
+    // at earlier steps is visible without a barrier; the pivot of each block is
+    // taken from lane c by readlane.
+    double Lr[MM];
+#pragma unroll
+    for (int c = 0; c < MM; ++c) Lr[c] = c <= r ? Lm[g][r * LD + c] : 0.0;
+    bool badl = false;
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+      // four independent partial sums keep the FMA pipeline busy
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < c; ++k) s4[k & 3] = fma(Lr[k], Lm[g][c * LD + k], s4[k & 3]);
+      const double sacc = Lr[c] - ((s4[0] + s4[1]) + (s4[2] + s4[3]));
+      double pc = sacc;
+#pragma unroll
+      for (int gg = 0; gg < G; ++gg) {
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(sacc), gg * MM + c);
+        const int lo = __builtin_amdgcn_readlane(__double2loint(sacc), gg * MM + c);
+        if (gg == g) pc = __hiloint2double(hi, lo);
       }
-      const double d = sqrt(dg);
-      const double inv = 1.0 / d;
-      for (int r = c + 1 + lane; r < N1; r += 64) C[r * LD + c] *= inv;
-      __syncthreads();
-      if (lane == 0) C[c * LD + c] = d;
-      const int Mp = N1 - c - 1;
-      const int np = Mp * (Mp + 1) / 2;
-      for (int e = lane; e < np; e += 64) {
-        int a, b;
-        tri_index(e, a, b);
-        const int r = c + 1 + a, s2 = c + 1 + b;
-        C[r * LD + s2] = fma(-C[r * LD + c], C[s2 * LD + c], C[r * LD + s2]);
+      if (!(pc > 0.0)) {
+        badl = true;
+        pc = 1.0;
       }
-      __syncthreads();
+      const double inv = rsqrt(pc);
+      if (r == c) {
+        Lr[c] = pc * inv;
+        Lm[g][c * LD + c] = Lr[c];
+        dgi[g][c] = inv;
+      } else if (r > c) {
+        Lr[c] = sacc * inv;
+        Lm[g][r * LD + c] = Lr[c];
+      }
     }
-    __syncthreads();
+    ok = !badl;
+    if (__all(ok)) break;
     if (!ok) {
-      nug = (attempt == 0) ? 1e-12 : nug * 100.0;
-      if (lane == 0 && attempt == 0) atomicAdd(&nfail[0], 1);
+      if (attempt == 0 && r == 0) atomicAdd(&nfail[0], 1);
+      nug = attempt == 0 ? 1e-12 : nug * 100.0;
     }
+    __syncthreads();  // the next attempt rebuilds the blocks in LDS
   }
-  if (!ok) {
-    if (lane == 0) atomicAdd(&nfail[1], 1);
-    return;
+  if (!ok && r == 0 && valid) atomicAdd(&nfail[1], 1);
+  // lambda = L_s^{-T} l, l = the node's row without its diagonal; lane r
+  // holds l_r and ends with lambda_r
+  double v = r < MM - 1 ? Lm[g][(MM - 1) * LD + r] : 0.0;
+#pragma unroll
+  for (int i = MM - 2; i >= 0; --i) {
+    double li = v;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int hi = __builtin_amdgcn_readlane(__double2hiint(v), gg * MM + i);
+      const int lo = __builtin_amdgcn_readlane(__double2loint(v), gg * MM + i);
+      if (gg == g) li = __hiloint2double(hi, lo);
+    }
+    li *= dgi[g][i];
+    if (r < i) v = fma(-Lm[g][i * LD + r], li, v);
+    else if (r == i) v = li;
   }
-  for (int a = lane; a < K; a += 64) vv[a] = C[K * LD + a];
-  const double cc = C[K * LD + K];
-  __syncthreads();
-  // column-oriented back substitution with L_s^T (one wavefront: the reads of
-  // vv[i] precede lane 0's write in program order)
-  for (int i = K - 1; i >= 0; --i) {
-    const double li = vv[i] / C[i * LD + i];
-    for (int l = lane; l < i; l += 64) vv[l] = fma(-C[i * LD + l], li, vv[l]);
-    if (lane == 0) vv[i] = li;
-    __syncthreads();
-  }
-  const double inv_c = 1.0 / cc;
-  for (int a = lane; a < m; a += 64) coef[(int64_t)p * m + a] = a < K ? -vv[a] * inv_c : 0.0;
-  if (lane == 0) dinv[p] = inv_c;
+  if (!valid || !ok) return;
+  const double inv_c = dgi[g][MM - 1];
+  // lane r < MM-1 holds lambda of row r = pad + a; padding coefficients are 0
+  if (r >= pad && r < MM - 1) coef[p * m + (r - pad)] = -v * inv_c;
+  for (int a = K + r; a < m; a += MM) coef[p * m + a] = 0.0;
+  if (r == 0) dinv[p] = inv_c;
 }
 
 // ---------------------------------------------------------------- transpose
@@ -573,15 +645,20 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     pl.pc_coef = dmalloc<double>((size_t)n * m);
     pl.pc_dinv = dmalloc<double>(n);
     PHS_HIP(hipMemsetAsync(nfail, 0, 8, s));
-    if (m <= 31)
+    if (m <= 15)
       PHS_LAUNCH("vecchia_factor", s,
-                 k_factor<32><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
-                                              pl.pc_coef, pl.pc_dinv, nfail, ser, pl.logtab));
+                 k_factor<16><<<(n + 3) / 4, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
+                                                         alpha, pl.pc_coef, pl.pc_dinv, nfail,
+                                                         ser, pl.logtab));
+    else if (m <= 31)
+      PHS_LAUNCH("vecchia_factor", s,
+                 k_factor<32><<<(n + 1) / 2, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
+                                                         alpha, pl.pc_coef, pl.pc_dinv, nfail,
+                                                         ser, pl.logtab));
     else
       PHS_LAUNCH("vecchia_factor", s,
-                 k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
-                                                 alpha, pl.pc_coef, pl.pc_dinv, nfail, ser,
-                                                 pl.logtab));
+                 k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
+                                              pl.pc_coef, pl.pc_dinv, nfail, ser, pl.logtab));
     dfree(ser);
     // 5. transpose: stable radix sort of the entries by row
     {
