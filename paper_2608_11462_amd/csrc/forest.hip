@@ -181,9 +181,12 @@ __global__ void kf_read_sc(const SysDev *__restrict__ sys, int nsys, int off, in
 }
 
 // ------------------------------------------------------------------ preconditioner
-// yv = U~^T r: row j holds 1/c_j at j and -lambda/c_j at sigma(j); 32 lanes
-// per row read the node-major entries coalesced, a fixed butterfly sums them.
-// Systems without a factor copy r.
+// yv = U~^T r: row j holds 1/c_j at j and -lambda/c_j at sigma(j).  A group of
+// 32 lanes takes eight consecutive rows (a work item is 64 rows: eight groups
+// per block), reading each row's node-major entries coalesced and summing
+// them with a fixed butterfly.  Systems without a factor copy r.
+constexpr int kPcRows = 8;  // rows per 32-lane group
+
 __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sys,
                                                    const BlkRef *__restrict__ tab,
                                                    const int32_t *__restrict__ mask, int rs,
@@ -191,29 +194,34 @@ __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sy
   const BlkRef br = tab[blockIdx.x];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
-  const int64_t j = (int64_t)br.blk * 8 + (threadIdx.x >> 5);
+  const int64_t j0 = ((int64_t)br.blk * 8 + (threadIdx.x >> 5)) * kPcRows;
   const int g = threadIdx.x & 31;
-  if (j >= d.n) return;
-  const double *r = d.v[rs];
+  const cptr<double> rr = ro(d.v[rs]);
+  const gptr<double> yv = rw(d.v[ys]);
   if (!d.has_pc) {
-    if (g == 0) d.v[ys][j] = r[j];
+    for (int i = 0; i < kPcRows; ++i)
+      if (g == 0 && j0 + i < d.n) yv[j0 + i] = rr[j0 + i];
     return;
   }
   const int m = d.m;
   const cptr<int32_t> nbr = ro(d.nbr);
-  const cptr<double> coef = ro(d.coef);
-  const cptr<double> rr = ro(r);
-  double acc = 0.0;
-  for (int s2 = g; s2 < m; s2 += 32) {
-    const int q = nbr[j * m + s2];
-    if (q >= 0) acc += coef[j * m + s2] * rr[q];
-  }
+  const cptr<double> coef = ro(d.coef), dinv = ro(d.dinv);
+#pragma unroll 4
+  for (int i = 0; i < kPcRows; ++i) {
+    const int64_t j = j0 + i;
+    if (j >= d.n) break;
+    double acc = 0.0;
+    for (int s2 = g; s2 < m; s2 += 32) {
+      const int q = nbr[j * m + s2];
+      if (q >= 0) acc += coef[j * m + s2] * rr[q];
+    }
 #pragma unroll
-  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-  if (g == 0) rw(d.v[ys])[j] = ro(d.dinv)[j] * rr[j] + acc;
+    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+    if (g == 0) yv[j] = dinv[j] * rr[j] + acc;
+  }
 }
 
-// z = U~ yv: row gather of the transposed factor (CSR by row).
+// z = U~ yv: row gather of the transposed factor (CSR by row), same layout.
 __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys,
                                                   const BlkRef *__restrict__ tab,
                                                   const int32_t *__restrict__ mask, int ys,
@@ -221,22 +229,28 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
   const BlkRef br = tab[blockIdx.x];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
-  const int64_t i = (int64_t)br.blk * 8 + (threadIdx.x >> 5);
+  const int64_t i0 = ((int64_t)br.blk * 8 + (threadIdx.x >> 5)) * kPcRows;
   const int g = threadIdx.x & 31;
-  if (i >= d.n) return;
-  const double *yv = d.v[ys];
+  const cptr<double> yy = ro(d.v[ys]);
+  const gptr<double> z = rw(d.v[zs]);
   if (!d.has_pc) {
-    if (g == 0) d.v[zs][i] = yv[i];
+    for (int i = 0; i < kPcRows; ++i)
+      if (g == 0 && i0 + i < d.n) z[i0 + i] = yy[i0 + i];
     return;
   }
   const cptr<int32_t> tstart = ro(d.tstart), tidx = ro(d.tidx);
-  const cptr<double> tcoef = ro(d.tcoef), yy = ro(yv);
-  const int b = tstart[i], e = tstart[i + 1];
-  double acc = 0.0;
-  for (int a = b + g; a < e; a += 32) acc += tcoef[a] * yy[tidx[a]];
+  const cptr<double> tcoef = ro(d.tcoef), dinv = ro(d.dinv);
+#pragma unroll 4
+  for (int k = 0; k < kPcRows; ++k) {
+    const int64_t i = i0 + k;
+    if (i >= d.n) break;
+    const int b = tstart[i], e = tstart[i + 1];
+    double acc = 0.0;
+    for (int a = b + g; a < e; a += 32) acc += tcoef[a] * yy[tidx[a]];
 #pragma unroll
-  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-  if (g == 0) rw(d.v[zs])[i] = ro(d.dinv)[i] * yy[i] + acc;
+    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+    if (g == 0) z[i] = dinv[i] * yy[i] + acc;
+  }
 }
 
 __global__ void k_gather_one(const double *__restrict__ src, const int32_t *__restrict__ order,
@@ -359,7 +373,7 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
     const int64_t nv = (pl.n + kBlock - 1) / kBlock;
     for (int64_t b = 0; b < nv; ++b) hv.push_back({i, (int32_t)b});
     for (int b = 0; b < dot_blocks(pl.n); ++b) hd.push_back({i, b});
-    const int64_t np = (pl.n + 7) / 8;
+    const int64_t np = (pl.n + 8 * kPcRows - 1) / (8 * kPcRows);
     for (int64_t b = 0; b < np; ++b) hp.push_back({i, (int32_t)b});
   }
   F.dsys = dmalloc<SysDev>(F.nsys);
