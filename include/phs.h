@@ -151,11 +151,13 @@ phs_status phs_eval(phs_plan_t plan, const double *w, const double *beta,
                     int32_t nrhs, const double *targets, int64_t m, double *out,
                     void *stream);
 
-/* Plan facts.  center[2], scale, S, R, leaf_level, order: host pointers, any
- * may be NULL.  R is the Hadamard rank (number of core-kernel densities). */
+/* Plan facts.  center[2], scale, S, R, leaf_level, order, tree_half_width:
+ * host pointers, any may be NULL.  R is the Hadamard rank (number of
+ * core-kernel densities).  The quadtree covers [-t, t]^2 in normalised
+ * coordinates, t = tree_half_width (the normalisation half-width h_k). */
 phs_status phs_plan_info(phs_plan_t plan, double *center, double *scale,
                          int32_t *S, int32_t *R, int32_t *leaf_level,
-                         int32_t *order);
+                         int32_t *order, double *tree_half_width);
 
 /* Copy the plan's internal node order and leaf keys to caller device buffers
  * (int32, n each): order[i] = caller index of the i-th node in tree order,

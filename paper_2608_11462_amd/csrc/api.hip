@@ -245,6 +245,7 @@ void build_tree(Plan &pl, const double *xy, int leaf_size, hipStream_t s) {
   try {
     int L = (int)std::lround(std::log((double)n / leaf_size) / std::log(4.0));
     L = std::max(2, std::min(10, L));
+    pl.tree.h = pl.hnorm;
     std::vector<int32_t> hstart;
     for (;;) {
       const int G = 1 << L;
@@ -323,7 +324,8 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
   pl.core_log = (pl.k % 2 == 0);
   pl.sign = definiteness_sign(pl.k);
   pl.precision = o->precision;
-  pl.tree.h = domain_half_width(pl.k);
+  pl.hnorm = domain_half_width(pl.k);
+  pl.tree.h = pl.hnorm;
   const double tol = o->fmm_tol > 0 ? o->fmm_tol : 1e-12;
   if (pl.core_log) {
     pl.p64 = o->expansion_order > 0 ? o->expansion_order : order_for_tol(tol, true);
@@ -364,7 +366,7 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     const double ex = mxx - mnx, ey = mxy - mny;
     const double half = std::max(ex, ey) * 0.5;
     PHS_REQUIRE(half > 0.0, PHS_ERR_INVALID_ARGUMENT, "nodes have zero extent");
-    pl.rho = pl.tree.h / half;
+    pl.rho = pl.tree.h / half;  // the normalised nodes fill [-h_k, h_k]^2
   }
   int leaf_size = o->leaf_size > 0 ? o->leaf_size : (pl.core_log ? 40 : 64);
   build_tree(pl, xy, leaf_size, s);
@@ -573,7 +575,8 @@ phs_status phs_eval(phs_plan_t plan, const double *w, const double *beta, int32_
 }
 
 phs_status phs_plan_info(phs_plan_t plan, double *center, double *scale, int32_t *Sout,
-                         int32_t *Rout, int32_t *leaf_level, int32_t *order) {
+                         int32_t *Rout, int32_t *leaf_level, int32_t *order,
+                         double *tree_half_width) {
   return guarded([&] {
     PHS_REQUIRE(plan, PHS_ERR_INVALID_ARGUMENT, "null plan");
     const Plan &pl = plan->pl;
@@ -586,6 +589,7 @@ phs_status phs_plan_info(phs_plan_t plan, double *center, double *scale, int32_t
     if (Rout) *Rout = pl.R;
     if (leaf_level) *leaf_level = pl.tree.L;
     if (order) *order = pl.core_log ? pl.p64 : pl.q64;
+    if (tree_half_width) *tree_half_width = pl.tree.h;
     return PHS_OK;
   });
 }

@@ -206,6 +206,7 @@ struct Plan {
   bool core_log = true;
   double c[2] = {0, 0};
   double rho = 1;
+  double hnorm = 0.25;  // half-width of the normalised domain (tree.h >= hnorm)
   Tree tree;
   int p64 = 31, p32 = 15;  // log expansion order (terms beyond the constant)
   int q64 = 16, q32 = 10;  // Chebyshev nodes per axis (distance kernel)

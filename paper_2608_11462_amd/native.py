@@ -98,7 +98,7 @@ def lib() -> C.CDLL:
         L.phs_eval.argtypes = [vp, dp, dp, i32, dp, i64, dp, vp]
         L.phs_plan_info.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
-                                    C.POINTER(i32)]
+                                    C.POINTER(i32), C.POINTER(C.c_double)]
         L.phs_plan_tree.argtypes = [vp, dp, dp, vp]
         L.phs_precond_export.argtypes = [vp, dp, dp, dp, dp, vp]
         L.phs_precond_apply.argtypes = [vp, dp, dp, vp]
@@ -182,10 +182,12 @@ class Plan:
         c = (C.c_double * 2)()
         sc = C.c_double()
         S, R, L, P = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        th = C.c_double()
         _check(lib().phs_plan_info(h, c, C.byref(sc), C.byref(S), C.byref(R), C.byref(L),
-                                   C.byref(P)))
+                                   C.byref(P), C.byref(th)))
         self.center = (c[0], c[1])
         self.scale = sc.value
+        self.tree_half_width = th.value
         self.S, self.R, self.leaf_level, self.order = S.value, R.value, L.value, P.value
 
     # -- kernel matvec ---------------------------------------------------

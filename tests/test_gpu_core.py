@@ -37,7 +37,8 @@ def test_normalisation_and_tree_bit_exact(small, k):
     assert pl.center == (c[0], c[1])
     assert pl.scale == rho
     order, leaf = pl.tree()
-    order_ref, keys_ref = D.leaf_order(xi, D.h_domain(k), pl.leaf_level)
+    assert pl.tree_half_width >= D.h_domain(k)
+    order_ref, keys_ref = D.leaf_order(xi, pl.tree_half_width, pl.leaf_level)
     np.testing.assert_array_equal(host(order), order_ref)
     np.testing.assert_array_equal(host(leaf), keys_ref)
 
