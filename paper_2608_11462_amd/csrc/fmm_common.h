@@ -200,25 +200,25 @@ __device__ __forceinline__ double tang_log(double x, PT tab) {
 void fill_log_table(double *tab);
 
 // log x for the near field, where phi = r^k log r enters sums of O(1) terms and
-// an absolute error of a few 1e-16 suffices: x = 2^e m, m in [1, 2),
-// c = 1 + j/256 from the top eight mantissa bits, r = m (1/c) - 1 in one
-// fused multiply-add (|r| < 2^-8), log1p(r) by its degree-6 Taylor polynomial
-// (remainder < r^7/7 < 3e-18), log x = e ln2 + log c + log1p(r).  Absolute
-// error about 2e-16.  tab: 1/c for j < 256, then log c.  x must be a positive
-// normal number.
+// an absolute error of a few 1e-16 suffices: x = 2^e m with m in [1/2, 1)
+// (frexp), c = (1 + (j + 1/2)/256)/2 the centre of the subinterval of m given
+// by the top eight fraction bits j, r = m (1/c) - 1 in one fused multiply-add
+// (|r| <= 2^-9), log1p(r) by its degree-5 Taylor polynomial (remainder
+// < |r|^6/6 < 1e-17), log x = e ln2 - log(1/c) + log1p(r), where the table
+// holds the rounded 1/c and minus the logarithm of that rounded value, so the
+// rounding of 1/c cancels.  Absolute error about 1e-16.  tab: 1/c for j < 256,
+// then -log(1/c).  x = 0 gives a finite value (m = 0, e = 0), so x log x and
+// x^2 log x are exactly 0 there.
 __device__ __forceinline__ double near_log_core(double x, double invc, double logc) {
-  const uint64_t b = (uint64_t)__double_as_longlong(x);
-  const uint32_t hi = (uint32_t)(b >> 32);
-  const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FF00000u), (int)(uint32_t)b);
+  const double m = __builtin_amdgcn_frexp_mant(x);
+  const int e = __builtin_amdgcn_frexp_exp(x);
   const double r = fma(m, invc, -1.0);
-  double p = -1.0 / 6.0;
-  p = fma(p, r, 1.0 / 5.0);
+  double p = 0.2;
   p = fma(p, r, -0.25);
   p = fma(p, r, 1.0 / 3.0);
   p = fma(p, r, -0.5);
   p = fma(p, r, 1.0);
-  const double ed = (double)((int)(hi >> 20) - 1023);
-  return fma(ed, 0.69314718055994530942, fma(p, r, logc));
+  return fma((double)e, 0.69314718055994530942, fma(p, r, logc));
 }
 template <class PT>
 __device__ __forceinline__ double near_log(double x, PT tab) {
@@ -231,10 +231,9 @@ void fill_near_log_table(double *tab);
 
 // sum_j phi(|x_i - y_j|) t_j over a contiguous source range, FP64.  xy2
 // points to the interleaved source coordinates (x0, y0, x1, y1, ...); tab is
-// the near_log table.  For even
-// k the r = 0 term is removed by clamping r^2 to 1e-300 (phi is then ~1e-298,
-// below the rounding of any sum of O(1) terms).  Returns the sum without the
-// factor 1/2 of phi = r^k log r = (1/2) r^k log r^2 for even k.
+// the near_log table.  For even k the r = 0 term is exactly 0, as near_log(0)
+// is finite.  Returns the sum without the factor 1/2 of
+// phi = r^k log r = (1/2) r^k log r^2 for even k.
 template <int K, class PXY, class PT, class PTAB>
 __device__ __forceinline__ double near_range(double xi, double yi, PXY xy2, PT t, int js,
                                              int je, PTAB tab) {
@@ -249,11 +248,57 @@ __device__ __forceinline__ double near_range(double xi, double yi, PXY xy2, PT t
     } else if constexpr (K == 3) {
       acc = fma(r2 * sqrt(r2), t[j], acc);
     } else {
-      r2 = fmax(r2, 1e-300);
       double ph = r2 * near_log(r2, tab);
       if constexpr (K == 4) ph *= r2;
       acc = fma(ph, t[j], acc);
     }
+  }
+  return acc;
+}
+
+// near_range in batches of eight sources: the eight source loads, then the
+// eight table reads, then the arithmetic, so a wavefront waits for scalar
+// and LDS loads twice per eight pairs instead of once per pair (both kinds
+// of load share one completion counter).  Even k only; same sums as
+// near_range up to the order of the additions within a batch (none: the
+// accumulation order is unchanged).
+template <int K, class PXY, class PT, class PTAB>
+__device__ __forceinline__ double near_range8(double xi, double yi, PXY xy2, PT t, int js, int je,
+                                              PTAB tab) {
+  static_assert(K % 2 == 0, "even k");
+  double acc = 0.0;
+  int j = js;
+  for (; j + 8 <= je; j += 8) {
+    double r2[8], tj[8], ic[8], lc[8];
+    // one base address per batch, constant offsets: wide merged loads
+    const auto pxy = xy2 + 2 * j;
+    const auto pt = t + j;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double dx = xi - pxy[2 * i], dy = yi - pxy[2 * i + 1];
+      r2[i] = fma(dy, dy, dx * dx);
+      tj[i] = pt[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
+      const int q = (int)((hi >> 12) & 255u);
+      ic[i] = tab[q];
+      lc[i] = tab[256 + q];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      double ph = r2[i] * near_log_core(r2[i], ic[i], lc[i]);
+      if constexpr (K == 4) ph *= r2[i];
+      acc = fma(ph, tj[i], acc);
+    }
+  }
+  for (; j < je; ++j) {
+    const double dx = xi - xy2[2 * j], dy = yi - xy2[2 * j + 1];
+    const double r2 = fma(dy, dy, dx * dx);
+    double ph = r2 * near_log(r2, tab);
+    if constexpr (K == 4) ph *= r2;
+    acc = fma(ph, t[j], acc);
   }
   return acc;
 }

@@ -190,16 +190,36 @@ __global__ __launch_bounds__(256) void kf_m2l(const SysDev *__restrict__ sys,
 #pragma unroll
       for (int c = 0; c < LCH; ++c) Y[c] = {T(0), T(0)};
       C2<T> dk = {T(1), T(0)};
-      for (int k = 0; k <= P; ++k) {
-        const C2<T> a = ld2<T>(&Al[((int64_t)k * nd + r) * nb + src]);
-        const C2<T> xk = cmul(a, dk);
-        const T *hrow = Ht + k * (P + 1) + l0;
+      // coefficients k = k0..k0+3 are loaded one group ahead of their use, so
+      // four loads are in flight while the previous group is multiplied
+      const cptr<V2<T>> ap = Al + (int64_t)r * nb + src;
+      const int64_t ks = (int64_t)nd * nb;
+      C2<T> nx[4];
 #pragma unroll
-        for (int c = 0; c < LCH; ++c) {
-          Y[c].re += hrow[c] * xk.re;
-          Y[c].im += hrow[c] * xk.im;
+      for (int i = 0; i < 4; ++i) nx[i] = i <= P ? ld2<T>(&ap[i * ks]) : C2<T>{T(0), T(0)};
+      const T a0 = nx[0].re;
+      for (int k0 = 0; k0 <= P; k0 += 4) {
+        C2<T> cu[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cu[i] = nx[i];
+        if (k0 + 4 <= P) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            nx[i] = k0 + 4 + i <= P ? ld2<T>(&ap[(k0 + 4 + i) * ks]) : C2<T>{T(0), T(0)};
         }
-        dk = cmul(dk, Dinv);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = k0 + i;
+          if (k > P) break;
+          const C2<T> xk = cmul(cu[i], dk);
+          const T *hrow = Ht + k * (P + 1) + l0;
+#pragma unroll
+          for (int c = 0; c < LCH; ++c) {
+            Y[c].re += hrow[c] * xk.re;
+            Y[c].im += hrow[c] * xk.im;
+          }
+          dk = cmul(dk, Dinv);
+        }
       }
       C2<T> e = cpow_small(Dinv, l0);
 #pragma unroll
@@ -207,10 +227,7 @@ __global__ __launch_bounds__(256) void kf_m2l(const SysDev *__restrict__ sys,
         acc[c] = cadd(acc[c], cmul(e, Y[c]));
         e = cmul(e, Dinv);
       }
-      if (l0 == 0) {
-        const T a0 = ld2<T>(&Al[(int64_t)r * nb + src]).re;
-        acc[0].re += a0 * (logw + T(0.5) * (T)log((double)dd));
-      }
+      if (l0 == 0) acc[0].re += a0 * (logw + T(0.5) * (T)log((double)dd));
     }
   }
   const int64_t tgt = (int64_t)iy * G + ix;
@@ -632,8 +649,9 @@ void fill_log_table(double *tab) {
 
 void fill_near_log_table(double *tab) {
   for (int j = 0; j < 256; ++j) {
-    tab[j] = 1.0 / (1.0 + j / 256.0);
-    tab[256 + j] = std::log1p(j / 256.0);
+    const double invc = 1.0 / (0.5 * (1.0 + (j + 0.5) / 256.0));
+    tab[j] = invc;
+    tab[256 + j] = (double)(-std::log((long double)invc));
   }
 }
 
