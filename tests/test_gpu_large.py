@@ -5,8 +5,12 @@
   quadratic block, Vecchia m = 50, nu = 1.5, alpha = 3 (the k = 3 default).
 * large_tps: n = 2^20 uniform, k = 2, linear block, Vecchia m = 30, nu = 1,
   alpha = 0.35 (the benchmark configuration).
-Gates: matvec 1e-10 relative on sampled rows (FP64); node residual
-RMS(f - M w - B beta)/RMS(f) <= 1e-8 on sampled nodes after a 1e-8 solve;
+Gates: matvec 1e-10 relative on sampled rows (FP64); the solver's own FP64
+residual over all nodes <= 1e-8; the node residual RMS(f - M w - B beta)/RMS(f)
+recomputed by direct summation on the sampled nodes <= 1.25e-8 (an RMS over
+128 sampled rows estimates the full one with a relative standard error of
+about sqrt(2/128)/2 = 6%, so a solve that stops just under 1e-8 can read
+above it on the sample; 1.25 is four standard errors);
 evaluation at sampled targets (4096 in the FP64 benchmark case) <= 1e-10
 relative to direct summation with the same (w, beta).  The interpolant is a
 sum of large alternating w_j phi terms (an FMM error of ~2e-14 relative to
@@ -52,7 +56,7 @@ def _run(pr, m, nu, rows, ntg, precision=N.PHS_FP64):
           f"resid={info.rel_residual:.2e} node-resid {e_res:.2e} eval {e_ev:.2e}")
     assert e_mv <= 1e-10
     assert info.rel_residual <= 1e-8
-    assert e_res <= 1e-8
+    assert e_res <= 1.25e-8  # sampled estimate of a residual the solver holds to 1e-8
     assert e_ev <= 1e-10
     return info
 
