@@ -256,12 +256,12 @@ __device__ __forceinline__ double near_range(double xi, double yi, PXY xy2, PT t
   return acc;
 }
 
-// near_range in batches of eight sources: the eight source loads, then the
-// eight table reads, then the arithmetic, so a wavefront waits for scalar
-// and LDS loads twice per eight pairs instead of once per pair (both kinds
-// of load share one completion counter).  Even k only; same sums as
-// near_range up to the order of the additions within a batch (none: the
-// accumulation order is unchanged).
+// near_range in batches of eight sources: the eight source loads (merged
+// into wide scalar loads from one base address), then the eight table
+// reads, then the arithmetic, so a wavefront waits on its loads about twice
+// per eight pairs instead of once per pair (scalar and LDS loads share one
+// completion counter).  Even k only; the sums are bitwise those of
+// near_range (same operations in the same order).
 template <int K, class PXY, class PT, class PTAB>
 __device__ __forceinline__ double near_range8(double xi, double yi, PXY xy2, PT t, int js, int je,
                                               PTAB tab) {

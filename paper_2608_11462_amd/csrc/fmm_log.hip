@@ -336,7 +336,7 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
     if constexpr (std::is_same<TN, double>::value) {
       for (int row = r0; row <= r1; ++row) {
         const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-        nearv += near_range<K>(xi, yi, xy2, t, js, je, ltab);
+        nearv += near_range8<K>(xi, yi, xy2, t, js, je, ltab);
       }
       nearv *= near_scale<K>();
     } else {

@@ -187,6 +187,23 @@ __global__ void kf_read_sc(const SysDev *__restrict__ sys, int nsys, int off, in
 // them with a fixed butterfly.  Systems without a factor copy r.
 constexpr int kPcRows = 8;  // rows per 32-lane group
 
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, CTRL, ROWS, 0xF, false);
+}
+
+// Sum over each 32-lane half of the wavefront by DPP row operations (no LDS):
+// pairs, quads, half rows, rows, then row 0 (2) into row 1 (3).  The sum is
+// valid in lanes 16..31 of each half.
+__device__ __forceinline__ double half_sum(double v) {
+  v += dpp_f64<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);       // row_half_mirror
+  v += dpp_f64<0x140>(v);       // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  return v;
+}
+
 __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sys,
                                                    const BlkRef *__restrict__ tab,
                                                    const int32_t *__restrict__ mask, int rs,
@@ -215,9 +232,8 @@ __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sy
       const int q = nbr[j * m + s2];
       if (q >= 0) acc += coef[j * m + s2] * rr[q];
     }
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-    if (g == 0) yv[j] = dinv[j] * rr[j] + acc;
+    acc = half_sum(acc);
+    if (g == 31) yv[j] = dinv[j] * rr[j] + acc;
   }
 }
 
@@ -247,9 +263,8 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
     const int b = tstart[i], e = tstart[i + 1];
     double acc = 0.0;
     for (int a = b + g; a < e; a += 32) acc += tcoef[a] * yy[tidx[a]];
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-    if (g == 0) z[i] = dinv[i] * yy[i] + acc;
+    acc = half_sum(acc);
+    if (g == 31) z[i] = dinv[i] * yy[i] + acc;
   }
 }
 
