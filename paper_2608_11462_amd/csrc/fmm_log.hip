@@ -236,6 +236,135 @@ __global__ __launch_bounds__(256) void kf_m2l(const SysDev *__restrict__ sys,
     if (l0 + c <= P) st2<T>(&Bl[((int64_t)(l0 + c) * nd + r) * nb + tgt], acc[c]);
 }
 
+// ------------------------------------------------------------------ M2L, matrix cores
+// The FP64 outgoing->incoming translation as a product with the one real
+// matrix H, on the matrix cores.  Work item: one wavefront = (strip of 16
+// boxes of one parity class that are neighbours in x on one level, density
+// r).  The interaction offset D is the same for the whole strip, so per
+// offset, with lane = column c (box) + 16 q:
+//   X[k][c] = D^{-k} A_k(source of c)     prescale, k = 4 s + q
+//   Y = H X                               v_mfma_f64_16x16x4f64, two 16-row
+//                                         tiles of l, NKS steps of 4 in k
+//   B[l][c] += D^{-l} Y[l][c]             postscale, l = 16 t + q + 4 j
+// plus A_0 (log w + log|D|) into B_0.  H (zero padded to 32 x 4 NKS) stays in
+// the A-operand registers for the whole item.  Lane layout of the 16x16x4
+// FP64 product (row m, column n, inner index k): A[m][k] at lane m + 16 k,
+// B[k][n] at lane n + 16 k, result D[m][n] at lane n + 16 (m mod 4) in
+// register m / 4.  Columns whose source box lies outside the grid, and
+// columns past the end of a short strip, get X = 0.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int NKS>
+__global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys,
+                                                  const BlkRef *__restrict__ tab,
+                                                  const int32_t *__restrict__ mask, int P,
+                                                  const double *__restrict__ Ht) {
+  const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R, L = d.L;
+  const double h = d.h;
+  const int lane = threadIdx.x;
+  const int c = lane & 15, q = lane >> 4;
+  const int r = (int)(br.blk % nd);
+  int64_t strip = br.blk / nd;
+  int l = 2;
+  int64_t base = 0;
+  int G = 4, half = 2, nsr = 1;
+  for (;;) {
+    G = 1 << l;
+    half = G >> 1;
+    nsr = (half + 15) >> 4;
+    const int64_t S = 4LL * half * nsr;
+    if (strip < S) break;
+    strip -= S;
+    base += (int64_t)(P + 1) * nd * G * G;
+    if (++l > L) return;
+  }
+  const int sr = (int)(strip % nsr);
+  const int64_t rest = strip / nsr;
+  const int cls = (int)(rest & 3), brow = (int)(rest >> 2);
+  const int aa = sr * 16 + c;
+  const bool colok = aa < half;
+  const int px = cls & 1, py = cls >> 1;
+  const int ix = 2 * aa + px, iy = 2 * brow + py;
+  const int64_t nb = (int64_t)G * G;
+  const cptr<double2> Al = ro((const double2 *)d.mp + base);
+  const gptr<double2> Bl = rw((double2 *)d.loc + base);
+  const double logw = log(2.0 * h / G);
+  double hA[2][NKS];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int st = 0; st < NKS; ++st) {
+      const int lr = 16 * t + c, kk = 4 * st + q;
+      hA[t][st] = (lr <= P && kk <= P) ? Ht[kk * (P + 1) + lr] : 0.0;
+    }
+  C2<double> acc[2][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[t][j] = {0.0, 0.0};
+  for (int oy = -3; oy <= 3; ++oy) {
+    const int jy = iy + oy;
+    if (jy < 0 || jy >= G || abs((jy >> 1) - brow) > 1) continue;
+    for (int ox = -3; ox <= 3; ++ox) {
+      if (abs(ox) <= 1 && abs(oy) <= 1) continue;
+      if (abs((px + ox) >> 1) > 1) continue;  // source parent not adjacent
+      const int jx = ix + ox;
+      const bool ok = colok && jx >= 0 && jx < G;
+      const int64_t src = (int64_t)jy * G + (ok ? jx : 0);
+      const double Dx = -ox, Dy = -oy, dd = Dx * Dx + Dy * Dy;
+      const C2<double> Di = {Dx / dd, -Dy / dd};
+      const C2<double> D2 = cmul(Di, Di), D3 = cmul(D2, Di), D4 = cmul(D2, D2);
+      const C2<double> pq = q == 0 ? C2<double>{1.0, 0.0} : q == 1 ? Di : q == 2 ? D2 : D3;
+      double xr[NKS], xim[NKS];
+      double a0 = 0.0;
+      C2<double> pw = pq;
+#pragma unroll
+      for (int st = 0; st < NKS; ++st) {
+        const int kk = 4 * st + q;
+        const C2<double> a = (ok && kk <= P) ? ld2<double>(&Al[((int64_t)kk * nd + r) * nb + src])
+                                             : C2<double>{0.0, 0.0};
+        if (st == 0) a0 = a.re;
+        const C2<double> x = cmul(a, pw);
+        xr[st] = x.re;
+        xim[st] = x.im;
+        pw = cmul(pw, D4);
+      }
+      dbl4 yr0 = {0.0, 0.0, 0.0, 0.0}, yr1 = yr0, yi0 = yr0, yi1 = yr0;
+#pragma unroll
+      for (int st = 0; st < NKS; ++st) {
+        yr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(hA[0][st], xr[st], yr0, 0, 0, 0);
+        yi0 = __builtin_amdgcn_mfma_f64_16x16x4f64(hA[0][st], xim[st], yi0, 0, 0, 0);
+        yr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(hA[1][st], xr[st], yr1, 0, 0, 0);
+        yi1 = __builtin_amdgcn_mfma_f64_16x16x4f64(hA[1][st], xim[st], yi1, 0, 0, 0);
+      }
+      C2<double> e = pq;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[0][j] = cadd(acc[0][j], cmul(e, C2<double>{yr0[j], yi0[j]}));
+        e = cmul(e, D4);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[1][j] = cadd(acc[1][j], cmul(e, C2<double>{yr1[j], yi1[j]}));
+        e = cmul(e, D4);
+      }
+      if (q == 0) acc[0][0].re += a0 * (logw + 0.5 * log(dd));
+    }
+  }
+  if (!colok) return;
+  const int64_t tgt = (int64_t)iy * G + ix;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int lr = 16 * t + q + 4 * j;
+      if (lr <= P) st2<double>(&Bl[((int64_t)lr * nd + r) * nb + tgt], acc[t][j]);
+    }
+}
+
 // ------------------------------------------------------------------ L2L
 template <class T>
 __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
@@ -502,8 +631,32 @@ void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &l
     if (tb.count)
       PHS_LAUNCH("m2m", s, kf_m2m<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lp, P, M2M));
   }
-  // outgoing -> incoming on every level
-  {
+  // outgoing -> incoming on every level: FP64 on the matrix cores (P < 32),
+  // otherwise on the vector units
+  if (fp64 && P >= 12 && P <= 31) {
+    const Tab tb = forest_tab(F, tab_key(10, 0, P, 0), s);
+    if (tb.count) {
+      const unsigned nblk = (unsigned)tb.count;
+      const double *H = lt.Ht64;
+      switch ((P + 4) / 4) {
+        case 4:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<4><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+          break;
+        case 5:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<5><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+          break;
+        case 6:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<6><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+          break;
+        case 7:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<7><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+          break;
+        default:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<8><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+          break;
+      }
+    }
+  } else {
     const Tab tb = forest_tab(F, tab_key(5, 0, P, 0), s);
     const int lch = m2l_chunk(P);
     const int nchunks = (P + 1 + lch - 1) / lch;

@@ -554,7 +554,8 @@ Tab forest_tab(Forest &F, uint64_t key, hipStream_t s) {
 }
 
 // kinds (low 4 bits): 1 leaf (k == K), 2 P2M groups of 4 x P leaves (k == K),
-// 3 log M2M level, 4 log L2L level, 5 log M2L; Chebyshev (P = Q, odd-k
+// 3 log M2M level, 4 log L2L level, 5 log M2L, 10 log M2L on the matrix
+// cores (strips of 16 boxes x densities); Chebyshev (P = Q, odd-k
 // systems whose Q for the launch equals P): 6 leaf (k == K), 7 M2M level,
 // 8 L2L level, 9 M2L.  Bits 4.. of a Chebyshev kind select which Q of the
 // plan applies: 0 the FP64 matvec order, 1 the FP32 one, 2 the evaluation one.
@@ -598,6 +599,16 @@ Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
           const int lch = m2l_chunk(P);
           const int64_t nch = (P + 1 + lch - 1) / lch;
           for (int64_t b = 0; b < ntiles * nch * R; ++b) h.push_back({i, (int32_t)b});
+        }
+        break;
+      case 10:  // log M2L on the matrix cores: (strip of 16 boxes, density)
+        if (log_k) {
+          int64_t strips = 0;
+          for (int l = 2; l <= L; ++l) {
+            const int64_t half = (int64_t)1 << (l - 1);
+            strips += 4 * half * ((half + 15) / 16);
+          }
+          for (int64_t b = 0; b < strips * R; ++b) h.push_back({i, (int32_t)b});
         }
         break;
       case 6:
