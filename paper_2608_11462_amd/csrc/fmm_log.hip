@@ -254,11 +254,13 @@ __global__ __launch_bounds__(256) void kf_m2l(const SysDev *__restrict__ sys,
 // columns past the end of a short strip, get X = 0.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-template <int NKS>
+template <int P>
 __global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys,
                                                   const BlkRef *__restrict__ tab,
-                                                  const int32_t *__restrict__ mask, int P,
-                                                  const double *__restrict__ Ht) {
+                                                  const int32_t *__restrict__ mask,
+                                                  const double *__restrict__ Ht,
+                                                  const double *__restrict__ Off) {
+  constexpr int NKS = (P + 4) / 4;
   const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
@@ -289,7 +291,8 @@ __global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys
   const int px = cls & 1, py = cls >> 1;
   const int ix = 2 * aa + px, iy = 2 * brow + py;
   const int64_t nb = (int64_t)G * G;
-  const cptr<double2> Al = ro((const double2 *)d.mp + base);
+  const int64_t kstride = (int64_t)nd * nb;
+  const cptr<double2> Al = ro((const double2 *)d.mp + base + (int64_t)r * nb);
   const gptr<double2> Bl = rw((double2 *)d.loc + base);
   const double logw = log(2.0 * h / G);
   double hA[2][NKS];
@@ -305,6 +308,7 @@ __global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[t][j] = {0.0, 0.0};
+  const cptr<double> offt = ro(Off);
   for (int oy = -3; oy <= 3; ++oy) {
     const int jy = iy + oy;
     if (jy < 0 || jy >= G || abs((jy >> 1) - brow) > 1) continue;
@@ -314,23 +318,25 @@ __global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys
       const int jx = ix + ox;
       const bool ok = colok && jx >= 0 && jx < G;
       const int64_t src = (int64_t)jy * G + (ok ? jx : 0);
-      const double Dx = -ox, Dy = -oy, dd = Dx * Dx + Dy * Dy;
-      const C2<double> Di = {Dx / dd, -Dy / dd};
-      const C2<double> D2 = cmul(Di, Di), D3 = cmul(D2, Di), D4 = cmul(D2, D2);
-      const C2<double> pq = q == 0 ? C2<double>{1.0, 0.0} : q == 1 ? Di : q == 2 ? D2 : D3;
+      // D^-1, D^-4, D^-q and log|D| of this offset (uniform: scalar loads)
+      const cptr<double> ot = offt + 16 * (7 * (oy + 3) + (ox + 3));
+      const C2<double> D4 = {ot[2], ot[3]};
+      C2<double> pw[8];  // pw[m] = D^-(4 m + q)
+      pw[0] = {q == 0 ? ot[4] : q == 1 ? ot[6] : q == 2 ? ot[8] : ot[10],
+               q == 0 ? ot[5] : q == 1 ? ot[7] : q == 2 ? ot[9] : ot[11]};
+#pragma unroll
+      for (int mm = 1; mm < 8; ++mm) pw[mm] = cmul(pw[mm - 1], D4);
       double xr[NKS], xim[NKS];
       double a0 = 0.0;
-      C2<double> pw = pq;
 #pragma unroll
       for (int st = 0; st < NKS; ++st) {
         const int kk = 4 * st + q;
-        const C2<double> a = (ok && kk <= P) ? ld2<double>(&Al[((int64_t)kk * nd + r) * nb + src])
-                                             : C2<double>{0.0, 0.0};
+        C2<double> a = {0.0, 0.0};
+        if (ok && (4 * st + 3 <= P || kk <= P)) a = ld2<double>(&Al[kk * kstride + src]);
         if (st == 0) a0 = a.re;
-        const C2<double> x = cmul(a, pw);
+        const C2<double> x = cmul(a, pw[st]);
         xr[st] = x.re;
         xim[st] = x.im;
-        pw = cmul(pw, D4);
       }
       dbl4 yr0 = {0.0, 0.0, 0.0, 0.0}, yr1 = yr0, yi0 = yr0, yi1 = yr0;
 #pragma unroll
@@ -340,18 +346,12 @@ __global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys
         yr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(hA[1][st], xr[st], yr1, 0, 0, 0);
         yi1 = __builtin_amdgcn_mfma_f64_16x16x4f64(hA[1][st], xim[st], yi1, 0, 0, 0);
       }
-      C2<double> e = pq;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        acc[0][j] = cadd(acc[0][j], cmul(e, C2<double>{yr0[j], yi0[j]}));
-        e = cmul(e, D4);
+        acc[0][j] = cadd(acc[0][j], cmul(pw[j], C2<double>{yr0[j], yi0[j]}));
+        acc[1][j] = cadd(acc[1][j], cmul(pw[4 + j], C2<double>{yr1[j], yi1[j]}));
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        acc[1][j] = cadd(acc[1][j], cmul(e, C2<double>{yr1[j], yi1[j]}));
-        e = cmul(e, D4);
-      }
-      if (q == 0) acc[0][0].re += a0 * (logw + 0.5 * log(dd));
+      if (q == 0) acc[0][0].re += a0 * (logw + ot[12]);
     }
   }
   if (!colok) return;
@@ -631,28 +631,25 @@ void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &l
     if (tb.count)
       PHS_LAUNCH("m2m", s, kf_m2m<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lp, P, M2M));
   }
-  // outgoing -> incoming on every level: FP64 on the matrix cores (P < 32),
-  // otherwise on the vector units
-  if (fp64 && P >= 12 && P <= 31) {
+  // outgoing -> incoming on every level: FP64 with the standard orders on
+  // the matrix cores, otherwise on the vector units
+  if (fp64 && (P == 15 || P == 23 || P == 27 || P == 31)) {
     const Tab tb = forest_tab(F, tab_key(10, 0, P, 0), s);
     if (tb.count) {
       const unsigned nblk = (unsigned)tb.count;
-      const double *H = lt.Ht64;
-      switch ((P + 4) / 4) {
-        case 4:
-          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<4><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+      const double *H = lt.Ht64, *O = lt.Off64;
+      switch (P) {
+        case 15:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<15><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, H, O));
           break;
-        case 5:
-          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<5><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+        case 23:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<23><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, H, O));
           break;
-        case 6:
-          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<6><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
-          break;
-        case 7:
-          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<7><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+        case 27:
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<27><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, H, O));
           break;
         default:
-          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<8><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, P, H));
+          PHS_LAUNCH(m2l_name, s, kf_m2l_mfma<31><<<nblk, 64, 0, s>>>(F.dsys, tb.d, mask, H, O));
           break;
       }
     }
@@ -763,6 +760,30 @@ void build_log_tables(LogTables &t, int P) {
         L2L[((size_t)c * P1 + j) * P1 + k] = make_double2(re, im);
       }
   }
+  // per M2L offset o = 7 (oy + 3) + (ox + 3), D = -(ox, oy) in box widths:
+  // D^-1, D^-4, D^-q for q = 0..3, log|D| (entries 0..12 of 16)
+  std::vector<double> Off(49 * 16, 0.0);
+  for (int o = 0; o < 49; ++o) {
+    const int oy = o / 7 - 3, ox = o % 7 - 3;
+    if (ox == 0 && oy == 0) continue;
+    const double Dx = -ox, Dy = -oy, dd = Dx * Dx + Dy * Dy;
+    const double ir = Dx / dd, ii = -Dy / dd;
+    double pr = 1.0, pi = 0.0;
+    for (int e = 0; e < 4; ++e) {
+      Off[o * 16 + 4 + 2 * e] = pr;
+      Off[o * 16 + 5 + 2 * e] = pi;
+      const double nr = pr * ir - pi * ii, ni = pr * ii + pi * ir;
+      pr = nr;
+      pi = ni;
+    }
+    Off[o * 16 + 0] = ir;
+    Off[o * 16 + 1] = ii;
+    Off[o * 16 + 2] = pr;  // D^-4
+    Off[o * 16 + 3] = pi;
+    Off[o * 16 + 12] = 0.5 * std::log(dd);
+  }
+  t.Off64 = dmalloc<double>(Off.size());
+  PHS_HIP(hipMemcpy(t.Off64, Off.data(), Off.size() * 8, hipMemcpyHostToDevice));
   std::vector<float> Hf(H.begin(), H.end());
   std::vector<float2> M2Mf(M2M.size()), L2Lf(L2L.size());
   for (size_t i = 0; i < M2M.size(); ++i) {
@@ -784,6 +805,7 @@ void build_log_tables(LogTables &t, int P) {
 }
 
 void free_log_tables(LogTables &t) {
+  dfree(t.Off64);
   dfree(t.Ht64);
   dfree(t.Ht32);
   dfree(t.M2M64);

@@ -138,6 +138,7 @@ struct LogTables {  // translation tables for one expansion order P
   double2 *L2L64 = nullptr; // 4 x (P+1)^2, [c][j][k]
   float2 *M2M32 = nullptr;
   float2 *L2L32 = nullptr;
+  double *Off64 = nullptr;  // 49 x 16 per M2L offset: D^-1, D^-4, D^-q (q=0..3), log|D|
 };
 
 struct ChebTables {  // Chebyshev interpolation tables for Q nodes per axis
