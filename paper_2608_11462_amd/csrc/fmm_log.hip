@@ -436,8 +436,17 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
   const int r0 = iy > 0 ? iy - 1 : 0, r1 = iy + 1 < G ? iy + 1 : G - 1;
   const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
   for (int i0 = b; i0 < e; i0 += 64) {
-    const int i = i0 + lane;
-    const bool act = i < e;
+    // A pass with at most 32 targets left (the tail of a leaf of more than 64
+    // nodes, or a small leaf) runs G = 64/W groups of W lanes on the same W
+    // targets, each group over 1/G of every source range, and sums the groups'
+    // partial sums: the lanes a plain pass would leave idle share the work.
+    const int rem = e - i0;
+    int W = 64;
+    if constexpr (std::is_same<TN, double>::value)
+      W = rem <= 8 ? 8 : rem <= 16 ? 16 : rem <= 32 ? 32 : 64;
+    const int gi = lane / W, li = lane % W;
+    const int i = i0 + li;
+    const bool act = li < rem;
     const int ii = act ? i : b;
     const double xi = x[ii], yi = y[ii];
     // far field
@@ -463,9 +472,20 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
     // near field
     TN nearv = TN(0);
     if constexpr (std::is_same<TN, double>::value) {
-      for (int row = r0; row <= r1; ++row) {
-        const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-        nearv += near_range8<K>(xi, yi, xy2, t, js, je, ltab);
+      if (W == 64) {
+        for (int row = r0; row <= r1; ++row) {
+          const int js = start[row * G + c0], je = start[row * G + c1 + 1];
+          nearv += near_range8<K>(xi, yi, xy2, t, js, je, ltab);
+        }
+      } else {
+        const int ng = 64 / W;
+        for (int row = r0; row <= r1; ++row) {
+          const int js = start[row * G + c0], je = start[row * G + c1 + 1];
+          const int len = je - js;
+          nearv += near_range<K>(xi, yi, xy2, t, js + len * gi / ng, js + len * (gi + 1) / ng,
+                                 ltab);
+        }
+        for (int o = W; o < 64; o <<= 1) nearv += __shfl_xor(nearv, o);
       }
       nearv *= near_scale<K>();
     } else {
@@ -484,7 +504,7 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
       }
       nearv *= phi_scale_f<K>();
     }
-    if (act) ytree[i] = (double)far + (double)nearv;
+    if (act && gi == 0) ytree[i] = (double)far + (double)nearv;
   }
 }
 
