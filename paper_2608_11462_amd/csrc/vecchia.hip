@@ -417,7 +417,7 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
     // taken from lane c by readlane.
     double Lr[MM];
 #pragma unroll
-    for (int c = 0; c < MM; ++c) Lr[c] = c <= r ? Lm[g][r * LD + c] : 0.0;
+    for (int c = 0; c < MM; ++c) Lr[c] = Lm[g][r * LD + c];  // c > r: never read validly
     bool badl = false;
 #pragma unroll
     for (int c = 0; c < MM; ++c) {
@@ -431,21 +431,20 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
       for (int gg = 0; gg < G; ++gg) {
         const int hi = __builtin_amdgcn_readlane(__double2hiint(sacc), gg * MM + c);
         const int lo = __builtin_amdgcn_readlane(__double2loint(sacc), gg * MM + c);
-        if (gg == g) pc = __hiloint2double(hi, lo);
+        pc = gg == g ? __hiloint2double(hi, lo) : pc;
       }
-      if (!(pc > 0.0)) {
-        badl = true;
-        pc = 1.0;
-      }
-      const double inv = rsqrt(pc);
-      if (r == c) {
-        Lr[c] = pc * inv;
-        Lm[g][c * LD + c] = Lr[c];
-        dgi[g][c] = inv;
-      } else if (r > c) {
-        Lr[c] = sacc * inv;
-        Lm[g][r * LD + c] = Lr[c];
-      }
+      badl = badl || !(pc > 0.0);
+      pc = pc > 0.0 ? pc : 1.0;
+      // 1/sqrt(pc): hardware estimate and one Newton step
+      double inv = __builtin_amdgcn_rsq(pc);
+      inv = fma(inv, fma(-0.5 * pc * inv, inv, 0.5), inv);
+      // L[r][c] for the lanes r >= c (lane c: sacc is the pivot, so this is
+      // its square root).  Lanes r < c compute values of the upper triangle
+      // that no valid result reads: lane r's own entries depend only on its
+      // columns k <= r, and its results at columns c > r are discarded.
+      Lr[c] = sacc * inv;
+      Lm[g][r * LD + c] = Lr[c];
+      dgi[g][c] = inv;
     }
     ok = !badl;
     if (__all(ok)) break;
@@ -456,22 +455,25 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
     __syncthreads();  // the next attempt rebuilds the blocks in LDS
   }
   if (!ok && r == 0 && valid) atomicAdd(&nfail[1], 1);
-  // lambda = L_s^{-T} l, l = the node's row without its diagonal; lane r
-  // holds l_r and ends with lambda_r
-  double v = r < MM - 1 ? Lm[g][(MM - 1) * LD + r] : 0.0;
+  // lambda = L_s^{-T} l, l = the node's row without its diagonal, column by
+  // column from the last: lambda_i = u_i / L_ii, then u_r -= L[i][r] lambda_i.
+  // With the diagonal and upper triangle of every row zeroed (the diagonal is
+  // kept in dgi) the update applies to all lanes unchanged: lanes r >= i see
+  // L[i][r] = 0.  Lane r holds u_r and ends with lambda_r = u_r / L_rr.
+  double u = r < MM - 1 ? Lm[g][(MM - 1) * LD + r] : 0.0;
+  for (int c = r; c < MM; ++c) Lm[g][r * LD + c] = 0.0;
 #pragma unroll
   for (int i = MM - 2; i >= 0; --i) {
-    double li = v;
+    double ui = u;
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) {
-      const int hi = __builtin_amdgcn_readlane(__double2hiint(v), gg * MM + i);
-      const int lo = __builtin_amdgcn_readlane(__double2loint(v), gg * MM + i);
-      if (gg == g) li = __hiloint2double(hi, lo);
+      const int hi = __builtin_amdgcn_readlane(__double2hiint(u), gg * MM + i);
+      const int lo = __builtin_amdgcn_readlane(__double2loint(u), gg * MM + i);
+      ui = gg == g ? __hiloint2double(hi, lo) : ui;
     }
-    li *= dgi[g][i];
-    if (r < i) v = fma(-Lm[g][i * LD + r], li, v);
-    else if (r == i) v = li;
+    u = fma(-Lm[g][i * LD + r], ui * dgi[g][i], u);
   }
+  const double v = u * dgi[g][r];
   if (!valid || !ok) return;
   const double inv_c = dgi[g][MM - 1];
   // lane r < MM-1 holds lambda of row r = pad + a; padding coefficients are 0
