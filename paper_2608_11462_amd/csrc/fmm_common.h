@@ -80,6 +80,15 @@ __device__ __forceinline__ C2<T> cpow_small(C2<T> z, int e) {
   return r;
 }
 
+// Sum over each group of four consecutive lanes (DPP quad permutations), the
+// result in all four lanes.  The whole quad must be active.
+template <class T>
+__device__ __forceinline__ T quad_sum(T v) {
+  v += __builtin_amdgcn_update_dpp(T(0), v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(T(0), v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  return v;
+}
+
 // Number of core densities for order K.
 template <int K> struct Rank;
 template <> struct Rank<1> { static constexpr int R = 1; };

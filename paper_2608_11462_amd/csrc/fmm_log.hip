@@ -97,7 +97,9 @@ __global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
 }
 
 // ------------------------------------------------------------------ M2M
-// Work item: 256 (parent box, density, coefficient) triples of one level.
+// Work item: 256 lanes over (parent box, density, coefficient) triples of one
+// level; on coarse levels four lanes per triple, lane c summing child c's
+// contribution, added over the quad.
 template <class T>
 __global__ void kf_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
                        const int32_t *__restrict__ mask, int lp, int P,
@@ -108,20 +110,28 @@ __global__ void kf_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   const int nd = d.R;
   const int Gp = 1 << lp, Gc = 2 * Gp;
   const int64_t nbp = (int64_t)Gp * Gp, nbc = 4 * nbp;
+  const int split = shift_split(lp);
   const int64_t tid = (int64_t)br.blk * 256 + threadIdx.x;
-  if (tid >= nbp * nd * (P + 1)) return;
+  if (tid >= nbp * nd * (P + 1) * split) return;  // whole quads
   const cptr<V2<T>> Ac = ro((const V2<T> *)d.mp + level_base(lp + 1, P, nd));
   const gptr<V2<T>> Ap = rw((V2<T> *)d.mp + level_base(lp, P, nd));
-  const int box = (int)(tid % nbp);
-  const int64_t rest = tid / nbp;
+  const int64_t o = split == 4 ? tid >> 2 : tid;
+  const int c0 = split == 4 ? (int)(tid & 3) : 0, c1 = split == 4 ? c0 + 1 : 4;
+  const int box = (int)(o % nbp);
+  const int64_t rest = o / nbp;
   const int r = (int)(rest % nd), lc = (int)(rest / nd);
   const int ix = box % Gp, iy = box / Gp;
   C2<T> acc = {T(0), T(0)};
-  for (int c = 0; c < 4; ++c) {
+  for (int c = c0; c < c1; ++c) {
     const int child = (2 * iy + (c >> 1)) * Gc + 2 * ix + (c & 1);
     const V2<T> *row = m2m + ((int64_t)c * (P + 1) + lc) * (P + 1);
     for (int k = 0; k <= lc; ++k)
       acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Ac[((int64_t)k * nd + r) * nbc + child])));
+  }
+  if (split == 4) {
+    acc.re = quad_sum(acc.re);
+    acc.im = quad_sum(acc.im);
+    if (c0 != 0) return;
   }
   st2<T>(&Ap[((int64_t)lc * nd + r) * nbp + box], acc);
 }
@@ -366,6 +376,9 @@ __global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys
 }
 
 // ------------------------------------------------------------------ L2L
+// Work item: 256 lanes over (child box, density, coefficient) triples of one
+// level; on coarse levels four lanes per triple over every fourth parent
+// coefficient, added over the quad.
 template <class T>
 __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
                        const int32_t *__restrict__ mask, int lc, int P,
@@ -376,20 +389,28 @@ __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   const int nd = d.R;
   const int Gc = 1 << lc, Gp = Gc / 2;
   const int64_t nbc = (int64_t)Gc * Gc, nbp = nbc / 4;
+  const int split = shift_split(lc);
   const int64_t tid = (int64_t)br.blk * 256 + threadIdx.x;
-  if (tid >= nbc * nd * (P + 1)) return;
+  if (tid >= nbc * nd * (P + 1) * split) return;  // whole quads
   const gptr<V2<T>> Bp = rw((V2<T> *)d.loc + level_base(lc - 1, P, nd));
   const gptr<V2<T>> Bc = rw((V2<T> *)d.loc + level_base(lc, P, nd));
-  const int box = (int)(tid % nbc);
-  const int64_t rest = tid / nbc;
+  const int64_t o = split == 4 ? tid >> 2 : tid;
+  const int sq = split == 4 ? (int)(tid & 3) : 0;
+  const int box = (int)(o % nbc);
+  const int64_t rest = o / nbc;
   const int r = (int)(rest % nd), j = (int)(rest / nd);
   const int ix = box % Gc, iy = box / Gc;
   const int c = (iy & 1) * 2 + (ix & 1);
   const int parent = (iy >> 1) * Gp + (ix >> 1);
   const V2<T> *row = l2l + ((int64_t)c * (P + 1) + j) * (P + 1);
   C2<T> acc = {T(0), T(0)};
-  for (int k = j; k <= P; ++k)
+  for (int k = j + sq; k <= P; k += split)
     acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Bp[((int64_t)k * nd + r) * nbp + parent])));
+  if (split == 4) {
+    acc.re = quad_sum(acc.re);
+    acc.im = quad_sum(acc.im);
+    if (sq != 0) return;
+  }
   const gptr<V2<T>> dst = &Bc[((int64_t)j * nd + r) * nbc + box];
   st2<T>(dst, cadd(ld2<T>(dst), acc));
 }
@@ -624,6 +645,16 @@ double binom(int n, int k) {
   return r;
 }
 
+// Timing label of a per-level launch: "m2m_5", "l2l_7", ...
+const char *level_name(const char *base, int l) {
+  static const char *m2m[] = {"m2m_0", "m2m_1", "m2m_2", "m2m_3", "m2m_4", "m2m_5", "m2m_6",
+                              "m2m_7", "m2m_8", "m2m_9", "m2m_10", "m2m_11"};
+  static const char *l2l[] = {"l2l_0", "l2l_1", "l2l_2", "l2l_3", "l2l_4", "l2l_5", "l2l_6",
+                              "l2l_7", "l2l_8", "l2l_9", "l2l_10", "l2l_11"};
+  const int i = l < 0 ? 0 : (l > 11 ? 11 : l);
+  return base[0] == 'm' ? m2m[i] : l2l[i];
+}
+
 // Upward pass, M2L and downward pass at order P with the tables of that order,
 // for the even-k systems of the forest.  `m2l_name` labels the M2L launch in
 // the per-kernel timing.
@@ -649,7 +680,7 @@ void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &l
   for (int lp = maxL - 1; lp >= 2; --lp) {
     const Tab tb = forest_tab(F, tab_key(3, 0, P, lp), s);
     if (tb.count)
-      PHS_LAUNCH("m2m", s, kf_m2m<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lp, P, M2M));
+      PHS_LAUNCH(level_name("m2m", lp), s, kf_m2m<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lp, P, M2M));
   }
   // outgoing -> incoming on every level: FP64 with the standard orders on
   // the matrix cores, otherwise on the vector units
@@ -699,7 +730,7 @@ void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &l
   for (int lc = 3; lc <= maxL; ++lc) {
     const Tab tb = forest_tab(F, tab_key(4, 0, P, lc), s);
     if (tb.count)
-      PHS_LAUNCH("l2l", s, kf_l2l<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lc, P, L2L));
+      PHS_LAUNCH(level_name("l2l", lc), s, kf_l2l<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lc, P, L2L));
   }
 }
 

@@ -581,13 +581,13 @@ Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
         break;
       case 3:  // M2M into level `level` from level+1
         if (log_k && L > level) {
-          const int64_t tot = boxes_at(level) * R * (P + 1);
+          const int64_t tot = boxes_at(level) * R * (P + 1) * shift_split(level);
           for (int64_t b = 0; b < (tot + 255) / 256; ++b) h.push_back({i, (int32_t)b});
         }
         break;
       case 4:  // L2L into level `level` from level-1
         if (log_k && L >= level) {
-          const int64_t tot = boxes_at(level) * R * (P + 1);
+          const int64_t tot = boxes_at(level) * R * (P + 1) * shift_split(level);
           for (int64_t b = 0; b < (tot + 255) / 256; ++b) h.push_back({i, (int32_t)b});
         }
         break;

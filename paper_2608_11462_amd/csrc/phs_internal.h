@@ -100,6 +100,11 @@ inline void dfree(void *p) { pool_free(p); }
 // ------------------------------------------------------------------ sizes
 inline int64_t boxes_at(int l) { return int64_t(1) << (2 * l); }
 
+// Lanes per output of the log M2M / L2L kernels on level l: the coarse levels,
+// whose few threads each run a long chain of dependent loads, split every
+// sum over a quad of lanes.
+__host__ __device__ inline int shift_split(int l) { return l <= 5 ? 4 : 1; }
+
 // Number of core-kernel densities (Hadamard rank) for order k.
 inline int hadamard_rank(int k) {
   switch (k) {
