@@ -204,37 +204,35 @@ __device__ __forceinline__ double half_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sys,
-                                                   const BlkRef *__restrict__ tab,
-                                                   const int32_t *__restrict__ mask, int rs,
-                                                   int ys) {
+// yv = U^T r over the forward factor in column-major (ELL) layout: one lane
+// per row, the m entries of row j at s*n + j, so a wavefront's loads of one
+// slot are contiguous; 64 rows per block (8 * kPcRows).
+__global__ __launch_bounds__(64) void kf_apply_ut(const SysDev *__restrict__ sys,
+                                                  const BlkRef *__restrict__ tab,
+                                                  const int32_t *__restrict__ mask, int rs,
+                                                  int ys) {
   const BlkRef br = tab[blockIdx.x];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
-  const int64_t j0 = ((int64_t)br.blk * 8 + (threadIdx.x >> 5)) * kPcRows;
-  const int g = threadIdx.x & 31;
+  const int64_t j = (int64_t)br.blk * 64 + threadIdx.x;
+  if (j >= d.n) return;
   const cptr<double> rr = ro(d.v[rs]);
   const gptr<double> yv = rw(d.v[ys]);
   if (!d.has_pc) {
-    for (int i = 0; i < kPcRows; ++i)
-      if (g == 0 && j0 + i < d.n) yv[j0 + i] = rr[j0 + i];
+    yv[j] = rr[j];
     return;
   }
   const int m = d.m;
+  const int64_t n = d.n;
   const cptr<int32_t> nbr = ro(d.nbr);
   const cptr<double> coef = ro(d.coef), dinv = ro(d.dinv);
-#pragma unroll 4
-  for (int i = 0; i < kPcRows; ++i) {
-    const int64_t j = j0 + i;
-    if (j >= d.n) break;
-    double acc = 0.0;
-    for (int s2 = g; s2 < m; s2 += 32) {
-      const int q = nbr[j * m + s2];
-      if (q >= 0) acc += coef[j * m + s2] * rr[q];
-    }
-    acc = half_sum(acc);
-    if (g == 31) yv[j] = dinv[j] * rr[j] + acc;
+  double acc = dinv[j] * rr[j];
+#pragma unroll 6
+  for (int sl = 0; sl < m; ++sl) {
+    const int q = nbr[sl * n + j];
+    if (q >= 0) acc = fma(coef[sl * n + j], rr[q], acc);
   }
+  yv[j] = acc;
 }
 
 // z = U~ yv: row gather of the transposed factor (CSR by row), same layout.
@@ -511,7 +509,7 @@ void f_read_scalars(Forest &F, int off, int cnt, hipStream_t s) {
 
 void f_precond_apply(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s) {
   PHS_LAUNCH("precond_ut", s,
-             kf_apply_ut<<<F_GRID(F.pc), 256, 0, s>>>(F.dsys, F.pc.d, mask, r, tmp));
+             kf_apply_ut<<<F_GRID(F.pc), 64, 0, s>>>(F.dsys, F.pc.d, mask, r, tmp));
   PHS_LAUNCH("precond_u", s,
              kf_apply_u<<<F_GRID(F.pc), 256, 0, s>>>(F.dsys, F.pc.d, mask, tmp, z));
 }

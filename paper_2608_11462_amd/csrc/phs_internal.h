@@ -256,8 +256,9 @@ struct Plan {
   double nu = 1, alpha = 0.35;
   int pc_nugget_nodes = 0;      // nodes whose block needed a diagonal nugget
   int32_t *pc_rank = nullptr;   // tree position -> rank
-  int32_t *pc_nbr = nullptr;    // n x m (tree positions, -1 padded), row per tree pos
-  double *pc_coef = nullptr;    // n x m  (-lambda / c)
+  // after the build: column-major m x n, entry s of node p at s*n + p
+  int32_t *pc_nbr = nullptr;    // tree positions, -1 padded
+  double *pc_coef = nullptr;    // -lambda / c
   double *pc_dinv = nullptr;    // n      (1 / c)
   int32_t *pc_tstart = nullptr; // n + 1  transpose CSR
   int32_t *pc_tidx = nullptr;   // n*m

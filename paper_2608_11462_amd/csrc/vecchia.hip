@@ -503,7 +503,30 @@ __global__ void k_tfill(const int32_t *vals, int64_t nnz, int64_t n, int m, cons
   tcoef[p] = coef[e];
 }
 
-// export in caller order
+// Node-major (n x m) neighbour lists and coefficients to the column-major
+// (m x n) layout the preconditioner apply reads one row per lane.  A block
+// moves 64 nodes through LDS, so reads and writes are both contiguous.
+__global__ __launch_bounds__(256) void k_ell(const int32_t *__restrict__ nbr,
+                                             const double *__restrict__ coef, int64_t n, int m,
+                                             int32_t *__restrict__ nbrT,
+                                             double *__restrict__ coefT) {
+  __shared__ int32_t sn[64 * kMaxM];
+  __shared__ double sc[64 * kMaxM];
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int cnt = (int)(n - p0 < 64 ? n - p0 : 64);
+  for (int e = threadIdx.x; e < cnt * m; e += 256) {
+    sn[e] = nbr[p0 * m + e];
+    sc[e] = coef[p0 * m + e];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < cnt * m; e += 256) {
+    const int sl = e / cnt, pp = e % cnt;
+    nbrT[(int64_t)sl * n + p0 + pp] = sn[pp * m + sl];
+    coefT[(int64_t)sl * n + p0 + pp] = sc[pp * m + sl];
+  }
+}
+
+// export in caller order (factor stored column-major, entry s of node p at s*n + p)
 __global__ void k_export(int64_t n, int m, const int32_t *order, const int32_t *rank_tree,
                          const int32_t *nbr, const double *coef, const double *dinv,
                          int32_t *rank_u, int32_t *nbr_u, double *coef_u, double *diag_u) {
@@ -513,9 +536,9 @@ __global__ void k_export(int64_t n, int m, const int32_t *order, const int32_t *
   rank_u[u] = rank_tree[p];
   diag_u[u] = dinv[p];
   for (int s = 0; s < m; ++s) {
-    const int q = nbr[(int64_t)p * m + s];
+    const int q = nbr[(int64_t)s * n + p];
     nbr_u[(int64_t)u * m + s] = q >= 0 ? order[q] : -1;
-    coef_u[(int64_t)u * m + s] = coef[(int64_t)p * m + s];
+    coef_u[(int64_t)u * m + s] = coef[(int64_t)s * n + p];
   }
 }
 
@@ -685,6 +708,24 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
                    k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(tv, nnz, n, m, pl.pc_coef,
                                                           pl.pc_tidx, pl.pc_tcoef));
       for (void *q : {(void *)tk, (void *)tkt, (void *)tv, (void *)tvt, (void *)tscr}) dfree(q);
+    }
+    // 6. forward factor to the column-major layout of the apply
+    {
+      int32_t *nbrT = dmalloc<int32_t>((size_t)n * m);
+      double *coefT = nullptr;
+      try {
+        coefT = dmalloc<double>((size_t)n * m);
+      } catch (...) {
+        dfree(nbrT);
+        throw;
+      }
+      PHS_LAUNCH("vecchia_ell", s,
+                 k_ell<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(pl.pc_nbr, pl.pc_coef, n, m,
+                                                                 nbrT, coefT));
+      dfree(pl.pc_nbr);
+      dfree(pl.pc_coef);
+      pl.pc_nbr = nbrT;
+      pl.pc_coef = coefT;
     }
     int32_t hfail[2] = {0, 0};
     PHS_HIP(hipMemcpyAsync(hfail, nfail, 8, hipMemcpyDeviceToHost, s));
