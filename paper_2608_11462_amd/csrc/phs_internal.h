@@ -356,6 +356,7 @@ struct SolveJob {
   bool pcg_conv = false, pcg_break = false;
   int budget = 0;
   bool fp64_finish = false, count_outer = false, apply_dw = false, have_q = false;
+  bool undo_dw = false;  // the last correction raised the residual: take it back
 };
 struct SolveParams {
   double rtol;

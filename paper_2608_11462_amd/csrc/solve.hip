@@ -245,7 +245,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
           r.have_q = true;
           continue;
         }
-        bool stalled = false;
+        bool stalled = false, worse = false;
         if (r.count_outer) {
           // refinement steps; in FP64 only the restarts count
           if (mixed || rn_new > r.tol_abs) ++r.outer;
@@ -254,17 +254,25 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
             r.fp64_finish = true;  // the FP32 operator stopped helping
             stalled = false;
           }
-          r.rn = rn_new;
+          // a final correction that raised the residual is taken back, so
+          // the solve returns the best iterate of its restarts
+          worse = stalled && rn_new > r.rn;
+          if (!worse) r.rn = rn_new;
         }
         if (r.rn > r.tol_abs && r.budget > 0 && !stalled) {
           start_pcg(r, P);
         } else {
           if (r.rn > r.tol_abs && r.status == PHS_OK) r.status = PHS_ERR_NOT_CONVERGED;
           r.state = J_FINISH;
-          r.have_q = true;  // q = f - M w of the final w
+          r.have_q = !worse;  // q = f - M w of the final w
+          r.undo_dw = worse;
         }
       }
     }
+    // w -= dw where the last correction was taken back
+    set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.undo_dw; }, any, s);
+    if (any) f_axpby(F, F.mask[MK_UPD], V_W, V_DW, -1.0, 1.0, s);  // w = w - dw
+    for (auto *rp_ : jr) if (auto &r = *rp_; true) r.undo_dw = false;
 
     // ---- beta from R beta = Q^T (f - M w), the FP64 residual, w to the caller
     set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.state == J_FINISH && !r.have_q; },
