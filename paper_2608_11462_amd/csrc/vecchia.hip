@@ -103,20 +103,39 @@ __device__ __forceinline__ bool lessp(double da, int ra, double db, int rb) {
   return da < db || (da == db && ra < rb);
 }
 
-// Ordered nearest predecessors; one thread per rank, lists in LDS.
+// Query order of the KNN: the ranks grouped by the grid level their search
+// uses (lv = bit length of the rank, at most T), in tree order within a level,
+// so a wavefront's queries share one grid and search neighbouring cells (rank
+// order is random in space).  Keys per tree position p: lv(rank(p)), value
+// rank(p); a stable sort by key gives the order.
+__global__ void k_qkeys(const int32_t *__restrict__ rank, int64_t n, int T, uint32_t *keys,
+                        int32_t *vals) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int t = rank[p];
+  int lv = 64 - __clzll((unsigned long long)t);
+  if (lv > T) lv = T;
+  keys[p] = (uint32_t)lv;
+  vals[p] = t;
+}
+
+// Ordered nearest predecessors; one thread per query (in the order above),
+// lists in LDS.
 __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, int64_t n,
                                             int m, int T, double h, const int32_t *gbits,
                                             const int64_t *cell_off, const int32_t *cell_start,
                                             const int32_t *sorted_rank,
                                             const double2 *__restrict__ gxy,
-                                            const int32_t *pos_of_rank, int32_t *nbr,
+                                            const int32_t *pos_of_rank,
+                                            const int32_t *__restrict__ qord, int32_t *nbr,
                                             int32_t *cnt_out) {
   // per-lane candidate lists, m entries each (dynamic LDS: 64 m (8 + 4) bytes)
   extern __shared__ double d2s[];
   int *rks = (int *)(d2s + 64 * m);
   const int lane = threadIdx.x;
-  const int64_t t = blockIdx.x * (int64_t)64 + lane;
-  if (t >= n) return;
+  const int64_t qi = blockIdx.x * (int64_t)64 + lane;
+  if (qi >= n) return;
+  const int64_t t = qord[qi];  // query rank
   const int K = (int)(t < m ? t : m);
   const int p = pos_of_rank[t];
   if (K == 0) {
@@ -618,6 +637,7 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
   double *xr = dmalloc<double>(n), *yr = dmalloc<double>(n);
   int32_t *pos_of_rank = dmalloc<int32_t>(n), *cnt = dmalloc<int32_t>(n);
   int32_t *nfail = dmalloc<int32_t>(2);
+  int32_t *qord = nullptr;
   try {
     PHS_LAUNCH("vecchia_rank_keys", s,
                k_rank_keys<<<(n + B - 1) / B, B, 0, s>>>(n, o.seed, k64, perm));
@@ -640,12 +660,21 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     PHS_LAUNCH("vecchia_cell_start", s,
                k_cell_start<<<(ncells + B - 1) / B, B, 0, s>>>(gk, total, T, d_gb, d_coff,
                                                               ncells, cstart));
-    // 3. ordered nearest predecessors
+    // 3. ordered nearest predecessors, queries by grid level then tree position
+    qord = dmalloc<int32_t>(n);
+    {
+      uint32_t *qk = reinterpret_cast<uint32_t *>(k64), *qkt = reinterpret_cast<uint32_t *>(k64t);
+      PHS_LAUNCH("vecchia_qkeys", s,
+                 k_qkeys<<<(n + B - 1) / B, B, 0, s>>>(pl.pc_rank, n, T, qk, qord));
+      int qbits = 1;
+      while ((1 << qbits) <= T) ++qbits;
+      radix_sort_u32(qk, qord, n, qbits, qkt, vt, scr, s);  // sorted ranks in qord
+    }
     pl.pc_nbr = dmalloc<int32_t>((size_t)n * m);
     PHS_LAUNCH("vecchia_knn", s,
                k_knn<<<(n + 63) / 64, 64, (size_t)64 * m * 12, s>>>(xr, yr, n, m, T, h, d_gb,
                                                                    d_coff, cstart, gv,
-                                                  gxy, pos_of_rank, pl.pc_nbr, cnt));
+                                                  gxy, pos_of_rank, qord, pl.pc_nbr, cnt));
     dfree(gxy);
     // series coefficients of the Bessel functions (host, exact rationals in FP64)
     double *ser = dmalloc<double>(4 * kSerTerms);
@@ -739,14 +768,14 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     for (void *q : {(void *)k64, (void *)k64t, (void *)perm, (void *)vt, (void *)scr, (void *)gk,
                     (void *)gkt, (void *)gv, (void *)gvt, (void *)cstart, (void *)d_lvl,
                     (void *)d_coff, (void *)d_gb, (void *)xr, (void *)yr, (void *)pos_of_rank,
-                    (void *)cnt, (void *)nfail})
+                    (void *)cnt, (void *)nfail, (void *)qord})
       dfree(q);
     throw;
   }
   for (void *q : {(void *)k64, (void *)k64t, (void *)perm, (void *)vt, (void *)scr, (void *)gk,
                   (void *)gkt, (void *)gv, (void *)gvt, (void *)cstart, (void *)d_lvl,
                   (void *)d_coff, (void *)d_gb, (void *)xr, (void *)yr, (void *)pos_of_rank,
-                  (void *)cnt, (void *)nfail})
+                  (void *)cnt, (void *)nfail, (void *)qord})
     dfree(q);
   pool_mark_idle();
 }
