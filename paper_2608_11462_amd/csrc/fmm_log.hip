@@ -60,34 +60,70 @@ __global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
   const gptr<V2<T>> A = rw((V2<T> *)d.mp + level_base(L, P, R));
   const double w = 2.0 * h / G, invw = G / (2.0 * h);
   const bool active = sub < gpw;
-  const int leaf = (br.blk * 4 + wave) * gpw + (active ? sub : 0);
-  int b = 0, e = 0;
-  if (active) {
-    b = lstart[leaf];
-    e = lstart[leaf + 1];
-  }
+  const int leaf0 = (br.blk * 4 + wave) * gpw;
+  const int leaf = leaf0 + (active ? sub : 0);
+  // the wave's leaves (uniform ranges) and the longest of them
+  int bg[4] = {0, 0, 0, 0}, eg[4] = {0, 0, 0, 0};
+  int maxcnt = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+    if (g < gpw) {
+      bg[g] = lstart[leaf0 + g];
+      eg[g] = lstart[leaf0 + g + 1];
+      maxcnt = max(maxcnt, eg[g] - bg[g]);
+    }
+  const int b = active ? bg[sub] : 0, e = active ? eg[sub] : 0;
   const int ix = leaf % G, iy = leaf / G;
   const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
   T are[R], aim[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) are[r] = aim[r] = T(0);
-  for (int j = b; j < e; ++j) {
-    C2<T> z;
-    if constexpr (std::is_same<T, float>::value) {
-      z = {ux[j] * (float)invw, uy[j] * (float)invw};
-    } else {
-      z = {(x[j] - cx) * invw, (y[j] - cy) * invw};
+  // The points pass through LDS in chunks of CH per leaf, one coalesced load
+  // per chunk instead of a memory round trip per point.  Each wave has its own
+  // LDS slots, and a wavefront's LDS accesses complete in program order, so no
+  // barrier is needed between a chunk's stores and the loads of it.
+  constexpr int SLOTS = 256;
+  __shared__ double sx[4][SLOTS], sy[4][SLOTS], st[4][SLOTS];
+  __shared__ float sux[4][std::is_same<T, float>::value ? SLOTS : 1];
+  __shared__ float suy[4][std::is_same<T, float>::value ? SLOTS : 1];
+  const int CH = SLOTS / gpw;
+  for (int off = 0; off < maxcnt; off += CH) {
+    for (int i = lane; i < gpw * CH; i += 64) {
+      const int g = i / CH;
+      const int j = bg[g] + off + (i - g * CH);
+      if (j < eg[g]) {
+        sx[wave][i] = x[j];
+        sy[wave][i] = y[j];
+        st[wave][i] = t[j];
+        if constexpr (std::is_same<T, float>::value) {
+          sux[wave][i] = ux[j];
+          suy[wave][i] = uy[j];
+        }
+      }
     }
-    C2<T> zk = cpow_small(z, kk);
-    T v[R];
-    vfac<K, T>(x[j], y[j], v);
-    const T tj = (T)t[j];
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = active ? min(CH, e - b - off) : 0;
+    for (int jj = 0; jj < cnt; ++jj) {
+      const int i = sub * CH + jj;
+      const double xj = sx[wave][i], yj = sy[wave][i];
+      C2<T> z;
+      if constexpr (std::is_same<T, float>::value) {
+        z = {sux[wave][i] * (float)invw, suy[wave][i] * (float)invw};
+      } else {
+        z = {(xj - cx) * invw, (yj - cy) * invw};
+      }
+      C2<T> zk = cpow_small(z, kk);
+      T v[R];
+      vfac<K, T>(xj, yj, v);
+      const T tj = (T)st[wave][i];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      T q = v[r] * tj;
-      are[r] += q * zk.re;
-      aim[r] += q * zk.im;
+      for (int r = 0; r < R; ++r) {
+        T q = v[r] * tj;
+        are[r] += q * zk.re;
+        aim[r] += q * zk.im;
+      }
     }
+    __builtin_amdgcn_wave_barrier();
   }
   if (!active) return;
   const T sc = kk == 0 ? T(1) : T(-1) / T(kk);
