@@ -282,6 +282,141 @@ __global__ __launch_bounds__(256) void kf_m2l(const SysDev *__restrict__ sys,
     if (l0 + c <= P) st2<T>(&Bl[((int64_t)(l0 + c) * nd + r) * nb + tgt], acc[c]);
 }
 
+// ------------------------------------------------------------------ M2M / L2L, deep levels
+// With the child centre offset delta_c = rho u_c (|u_c| = 1, rho = sqrt(2)/4
+// in parent widths, the same for all four children), the shifts factor as
+// M2M[c][l][k] = u_c^l Rm[l][k] u_c^-k and L2L[c][j][k] = u_c^-j Rl[j][k] u_c^k
+// with real triangular Rm, Rl shared by the four children.  On the deep
+// levels a block stages one row segment of coefficients in LDS once, where
+// the per-coefficient kernels re-read each one from the cache dozens of times.
+
+// Upward, parent level lp with at least 16 boxes per row: a block takes 16
+// consecutive parents of one row and one density; their 64 children's
+// coefficients are staged prescaled by u_c^-k, and thread (parent, lg) forms
+// B_l = sum_c u_c^l sum_{k<=l} Rm[l][k] x_{c,k} for l = lg and lg + 16.
+template <int P>
+__global__ __launch_bounds__(256) void kf_m2m_seg(const SysDev *__restrict__ sys,
+                                                 const BlkRef *__restrict__ tab,
+                                                 const int32_t *__restrict__ mask, int lp,
+                                                 const double *__restrict__ Rm,
+                                                 const double2 *__restrict__ Ph) {
+  constexpr int P1 = P + 1;
+  __shared__ double2 sx[64 * P1];  // [k][child of the segment]
+  __shared__ double srm[P1 * P1];
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R;
+  const int Gp = 1 << lp, Gc = 2 * Gp;
+  const int nseg = Gp / 16;
+  const int r = (int)(br.blk % nd);
+  const int64_t sg = br.blk / nd;
+  const int py = (int)(sg / nseg), px0 = (int)(sg % nseg) * 16;
+  const int64_t nbp = (int64_t)Gp * Gp, nbc = 4 * nbp;
+  const cptr<double2> Ac = ro((const double2 *)d.mp + level_base(lp + 1, P, nd));
+  const gptr<double2> Ap = rw((double2 *)d.mp + level_base(lp, P, nd));
+  for (int e = threadIdx.x; e < 64 * P1; e += 256) {
+    const int k = e >> 6, ch = e & 63;
+    const int ccx = 2 * px0 + (ch & 31), ccy = 2 * py + (ch >> 5);
+    const int c = (ccy & 1) * 2 + (ccx & 1);
+    const C2<double> a = ld2<double>(&Ac[((int64_t)k * nd + r) * nbc + (int64_t)ccy * Gc + ccx]);
+    const C2<double> uk = ld2<double>(&Ph[c * 32 + k]);
+    sx[e] = make_double2(a.re * uk.re + a.im * uk.im, a.im * uk.re - a.re * uk.im);
+  }
+  for (int e = threadIdx.x; e < P1 * P1; e += 256) srm[e] = Rm[e];
+  __syncthreads();
+  const int pl = threadIdx.x & 15, lg = threadIdx.x >> 4;
+  const int64_t parent = (int64_t)py * Gp + px0 + pl;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int l = lg + 16 * h;
+    if (l > P) break;
+    C2<double> acc = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int ch = (c >> 1) * 32 + 2 * pl + (c & 1);
+      C2<double> y = {0.0, 0.0};
+      for (int k = 0; k <= l; ++k) {
+        const double m = srm[l * P1 + k];
+        const double2 xv = sx[k * 64 + ch];
+        y.re = fma(m, xv.x, y.re);
+        y.im = fma(m, xv.y, y.im);
+      }
+      acc = cadd(acc, cmul(ld2<double>(&Ph[c * 32 + l]), y));
+    }
+    st2<double>(&Ap[((int64_t)l * nd + r) * nbp + parent], acc);
+  }
+}
+
+// Downward, child level lc >= 7 (at least 64 parents per row: enough blocks
+// for these long per-thread sums; used from level 7): a block takes 32
+// consecutive parents of one row and one density, stages their incoming
+// coefficients, and two threads per child (output orders j of either parity)
+// form u_c^-j sum_{k>=j} Rl[j][k] u_c^k B_k, added to the child's expansion.
+template <int P>
+__global__ __launch_bounds__(256) void kf_l2l_seg(const SysDev *__restrict__ sys,
+                                                 const BlkRef *__restrict__ tab,
+                                                 const int32_t *__restrict__ mask, int lc,
+                                                 const double *__restrict__ Rl,
+                                                 const double2 *__restrict__ Ph) {
+  constexpr int P1 = P + 1, NJ = P1 / 2;
+  __shared__ double2 sb[32 * P1];  // [k][parent of the segment]
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nd = d.R;
+  const int Gc = 1 << lc, Gp = Gc / 2;
+  const int nseg = Gp / 32;
+  const int r = (int)(br.blk % nd);
+  const int64_t sg = br.blk / nd;
+  const int py = (int)(sg / nseg), px0 = (int)(sg % nseg) * 32;
+  const int64_t nbc = (int64_t)Gc * Gc, nbp = nbc / 4;
+  const cptr<double2> Bp = ro((const double2 *)d.loc + level_base(lc - 1, P, nd));
+  const gptr<double2> Bc = rw((double2 *)d.loc + level_base(lc, P, nd));
+  for (int e = threadIdx.x; e < 32 * P1; e += 256) {
+    const int k = e >> 5, q = e & 31;
+    const C2<double> bv = ld2<double>(&Bp[((int64_t)k * nd + r) * nbp + (int64_t)py * Gp + px0 + q]);
+    sb[e] = make_double2(bv.re, bv.im);
+  }
+  __syncthreads();
+  const int ci = threadIdx.x & 127, par = threadIdx.x >> 7;
+  const int cx = 2 * px0 + (ci & 63), cy = 2 * py + (ci >> 6);
+  const int c = (cy & 1) * 2 + (cx & 1);
+  const int q = (ci & 63) >> 1;
+  const cptr<double> rl = ro(Rl);
+  const C2<double> u = ld2<double>(&Ph[c * 32 + 1]);
+  C2<double> uk = {1.0, 0.0};
+  C2<double> y[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) y[i] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k <= P; ++k) {
+    const double2 bv = sb[k * 32 + q];
+    const C2<double> b = cmul(C2<double>{bv.x, bv.y}, uk);
+    uk = cmul(uk, u);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      const int j = 2 * i + par;
+      if (j <= k) {
+        const double m = rl[j * P1 + k];
+        y[i].re = fma(m, b.re, y[i].re);
+        y[i].im = fma(m, b.im, y[i].im);
+      }
+    }
+  }
+  const int64_t child = (int64_t)cy * Gc + cx;
+  const C2<double> u2 = cmul(u, u);
+  C2<double> uj = par ? u : C2<double>{1.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const int j = 2 * i + par;
+    const C2<double> o = {y[i].re * uj.re + y[i].im * uj.im, y[i].im * uj.re - y[i].re * uj.im};
+    const gptr<double2> dst = &Bc[((int64_t)j * nd + r) * nbc + child];
+    st2<double>(dst, cadd(ld2<double>(dst), o));
+    uj = cmul(uj, u2);
+  }
+}
+
 // ------------------------------------------------------------------ M2L, matrix cores
 // The FP64 outgoing->incoming translation as a product with the one real
 // matrix H, on the matrix cores.  Work item: one wavefront = (strip of 16
@@ -713,7 +848,25 @@ void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &l
       PHS_LAUNCH("p2m", s, kf_p2m<T, 4><<<(unsigned)t4.count, 256, 0, s>>>(F.dsys, t4.d, mask, P, in));
   }
   // upward pass
+  // FP64 with the standard orders: row segments through LDS on the deep levels
+  const bool seg = fp64 && (P == 15 || P == 23 || P == 27 || P == 31);
   for (int lp = maxL - 1; lp >= 2; --lp) {
+    if (seg && lp >= 4) {
+      const Tab tb = forest_tab(F, tab_key(13, 0, P, lp), s);
+      if (tb.count) {
+        const unsigned nb = (unsigned)tb.count;
+        const double *Rm = lt.Rm64;
+        const double2 *Ph = lt.Ph64;
+        const char *nm = level_name("m2m", lp);
+        switch (P) {
+          case 15: PHS_LAUNCH(nm, s, kf_m2m_seg<15><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lp, Rm, Ph)); break;
+          case 23: PHS_LAUNCH(nm, s, kf_m2m_seg<23><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lp, Rm, Ph)); break;
+          case 27: PHS_LAUNCH(nm, s, kf_m2m_seg<27><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lp, Rm, Ph)); break;
+          default: PHS_LAUNCH(nm, s, kf_m2m_seg<31><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lp, Rm, Ph)); break;
+        }
+      }
+      continue;
+    }
     const Tab tb = forest_tab(F, tab_key(3, 0, P, lp), s);
     if (tb.count)
       PHS_LAUNCH(level_name("m2m", lp), s, kf_m2m<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lp, P, M2M));
@@ -764,6 +917,22 @@ void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &l
   }
   // downward pass
   for (int lc = 3; lc <= maxL; ++lc) {
+    if (seg && lc >= 7) {
+      const Tab tb = forest_tab(F, tab_key(14, 0, P, lc), s);
+      if (tb.count) {
+        const unsigned nb = (unsigned)tb.count;
+        const double *Rl = lt.Rl64;
+        const double2 *Ph = lt.Ph64;
+        const char *nm = level_name("l2l", lc);
+        switch (P) {
+          case 15: PHS_LAUNCH(nm, s, kf_l2l_seg<15><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lc, Rl, Ph)); break;
+          case 23: PHS_LAUNCH(nm, s, kf_l2l_seg<23><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lc, Rl, Ph)); break;
+          case 27: PHS_LAUNCH(nm, s, kf_l2l_seg<27><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lc, Rl, Ph)); break;
+          default: PHS_LAUNCH(nm, s, kf_l2l_seg<31><<<nb, 256, 0, s>>>(F.dsys, tb.d, mask, lc, Rl, Ph)); break;
+        }
+      }
+      continue;
+    }
     const Tab tb = forest_tab(F, tab_key(4, 0, P, lc), s);
     if (tb.count)
       PHS_LAUNCH(level_name("l2l", lc), s, kf_l2l<T><<<(unsigned)tb.count, 256, 0, s>>>(F.dsys, tb.d, mask, lc, P, L2L));
@@ -869,6 +1038,43 @@ void build_log_tables(LogTables &t, int P) {
     Off[o * 16 + 3] = pi;
     Off[o * 16 + 12] = 0.5 * std::log(dd);
   }
+  // factored shifts: rho = sqrt(2)/4 (child centre offset in parent widths),
+  // u_c = delta_c / rho
+  {
+    const double rho = std::sqrt(2.0) / 4.0;
+    std::vector<double> Rm((size_t)P1 * P1, 0.0), Rl((size_t)P1 * P1, 0.0);
+    std::vector<double> rp(2 * P1 + 1);
+    rp[0] = 1.0;
+    for (int e = 1; e <= 2 * P1; ++e) rp[e] = rp[e - 1] * rho;
+    for (int l = 0; l <= P; ++l)
+      for (int k = 0; k <= P; ++k) {
+        double v = 0.0;
+        if (l == 0) v = (k == 0) ? 1.0 : 0.0;
+        else if (k == 0) v = -rp[l] / l;
+        else if (k <= l) v = binom(l - 1, k - 1) * std::ldexp(1.0, -k) * rp[l - k];
+        Rm[(size_t)l * P1 + k] = v;
+      }
+    for (int j = 0; j <= P; ++j)
+      for (int k = 0; k <= P; ++k)
+        Rl[(size_t)j * P1 + k] = k >= j ? binom(k, j) * std::ldexp(1.0, -j) * rp[k - j] : 0.0;
+    std::vector<double2> Ph(4 * 32);
+    for (int c = 0; c < 4; ++c) {
+      const double ur = ((c & 1) ? 0.25 : -0.25) / rho, ui = ((c & 2) ? 0.25 : -0.25) / rho;
+      double pr = 1.0, pi = 0.0;
+      for (int k = 0; k < 32; ++k) {
+        Ph[c * 32 + k] = make_double2(pr, pi);
+        const double nr = pr * ur - pi * ui, ni = pr * ui + pi * ur;
+        pr = nr;
+        pi = ni;
+      }
+    }
+    t.Rm64 = dmalloc<double>(Rm.size());
+    t.Rl64 = dmalloc<double>(Rl.size());
+    t.Ph64 = dmalloc<double2>(Ph.size());
+    PHS_HIP(hipMemcpy(t.Rm64, Rm.data(), Rm.size() * 8, hipMemcpyHostToDevice));
+    PHS_HIP(hipMemcpy(t.Rl64, Rl.data(), Rl.size() * 8, hipMemcpyHostToDevice));
+    PHS_HIP(hipMemcpy(t.Ph64, Ph.data(), Ph.size() * 16, hipMemcpyHostToDevice));
+  }
   t.Off64 = dmalloc<double>(Off.size());
   PHS_HIP(hipMemcpy(t.Off64, Off.data(), Off.size() * 8, hipMemcpyHostToDevice));
   std::vector<float> Hf(H.begin(), H.end());
@@ -893,6 +1099,9 @@ void build_log_tables(LogTables &t, int P) {
 
 void free_log_tables(LogTables &t) {
   dfree(t.Off64);
+  dfree(t.Rm64);
+  dfree(t.Rl64);
+  dfree(t.Ph64);
   dfree(t.Ht64);
   dfree(t.Ht32);
   dfree(t.M2M64);

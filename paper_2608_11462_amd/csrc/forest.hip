@@ -553,7 +553,9 @@ Tab forest_tab(Forest &F, uint64_t key, hipStream_t s) {
 
 // kinds (low 4 bits): 1 leaf (k == K), 2 P2M groups of 4 x P leaves (k == K),
 // 3 log M2M level, 4 log L2L level, 5 log M2L, 10 log M2L on the matrix
-// cores (strips of 16 boxes x densities); Chebyshev (P = Q, odd-k
+// cores (strips of 16 boxes x densities), 13 log M2M by row segments of 16
+// parents x densities, 14 log L2L by row segments of 32 parents x densities;
+// Chebyshev (P = Q, odd-k
 // systems whose Q for the launch equals P): 6 leaf (k == K), 7 M2M level,
 // 8 L2L level, 9 M2L.  Bits 4.. of a Chebyshev kind select which Q of the
 // plan applies: 0 the FP64 matvec order, 1 the FP32 one, 2 the evaluation one.
@@ -608,6 +610,14 @@ Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
           }
           for (int64_t b = 0; b < strips * R; ++b) h.push_back({i, (int32_t)b});
         }
+        break;
+      case 13:  // log M2M into level `level` (>= 4) by row segments of 16 parents
+        if (log_k && L > level)
+          for (int64_t b = 0; b < boxes_at(level) / 16 * R; ++b) h.push_back({i, (int32_t)b});
+        break;
+      case 14:  // log L2L into level `level` (>= 7) by row segments of 32 parents
+        if (log_k && L >= level)
+          for (int64_t b = 0; b < boxes_at(level - 1) / 32 * R; ++b) h.push_back({i, (int32_t)b});
         break;
       case 6:
         if (cheb && pl.k == K)

@@ -144,6 +144,11 @@ struct LogTables {  // translation tables for one expansion order P
   float2 *M2M32 = nullptr;
   float2 *L2L32 = nullptr;
   double *Off64 = nullptr;  // 49 x 16 per M2L offset: D^-1, D^-4, D^-q (q=0..3), log|D|
+  // shifts in factored form M2M[c] = U_c Rm U_c^-1, L2L[c] = U_c^-1 Rl U_c with
+  // U_c = diag(u_c^l), u_c the unit phase of child c's centre offset
+  double *Rm64 = nullptr;   // (P+1)^2 real, [l][k]
+  double *Rl64 = nullptr;   // (P+1)^2 real, [j][k]
+  double2 *Ph64 = nullptr;  // 4 x 32: u_c^k
 };
 
 struct ChebTables {  // Chebyshev interpolation tables for Q nodes per axis
