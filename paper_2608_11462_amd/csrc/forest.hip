@@ -235,34 +235,49 @@ __global__ __launch_bounds__(64) void kf_apply_ut(const SysDev *__restrict__ sys
   yv[j] = acc;
 }
 
-// z = U~ yv: row gather of the transposed factor (CSR by row), same layout.
+// z = U~ yv: row gather of the transposed factor (CSR by row), kApplyLanes
+// lanes per row (rows average m entries), 64 rows per block.
+constexpr int kApplyLanes = 16;
+
+template <int LPR>
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
+  if constexpr (LPR >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+  if constexpr (LPR >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+  if constexpr (LPR >= 32) v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  return v;
+}
+
 __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys,
                                                   const BlkRef *__restrict__ tab,
                                                   const int32_t *__restrict__ mask, int ys,
                                                   int zs) {
+  constexpr int LPR = kApplyLanes, RPG = LPR / 4;  // rows per lane group
   const BlkRef br = tab[blockIdx.x];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
-  const int64_t i0 = ((int64_t)br.blk * 8 + (threadIdx.x >> 5)) * kPcRows;
-  const int g = threadIdx.x & 31;
+  const int64_t i0 = ((int64_t)br.blk * (256 / LPR) + threadIdx.x / LPR) * RPG;
+  const int g = threadIdx.x % LPR;
+  const int wl = LPR == 32 ? 31 : 0;  // lane holding the group's sum
   const cptr<double> yy = ro(d.v[ys]);
   const gptr<double> z = rw(d.v[zs]);
   if (!d.has_pc) {
-    for (int i = 0; i < kPcRows; ++i)
+    for (int i = 0; i < RPG; ++i)
       if (g == 0 && i0 + i < d.n) z[i0 + i] = yy[i0 + i];
     return;
   }
   const cptr<int32_t> tstart = ro(d.tstart), tidx = ro(d.tidx);
   const cptr<double> tcoef = ro(d.tcoef), dinv = ro(d.dinv);
-#pragma unroll 4
-  for (int k = 0; k < kPcRows; ++k) {
+#pragma unroll
+  for (int k = 0; k < RPG; ++k) {
     const int64_t i = i0 + k;
-    if (i >= d.n) break;
-    const int b = tstart[i], e = tstart[i + 1];
+    const bool in = i < d.n;
+    const int b = in ? tstart[i] : 0, e = in ? tstart[i + 1] : 0;
     double acc = 0.0;
-    for (int a = b + g; a < e; a += 32) acc += tcoef[a] * yy[tidx[a]];
-    acc = half_sum(acc);
-    if (g == 31) z[i] = dinv[i] * yy[i] + acc;
+    for (int a = b + g; a < e; a += LPR) acc += tcoef[a] * yy[tidx[a]];
+    acc = group_sum<LPR>(acc);
+    if (in && g == wl) z[i] = dinv[i] * yy[i] + acc;
   }
 }
 
