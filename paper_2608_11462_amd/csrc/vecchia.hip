@@ -283,6 +283,8 @@ __device__ __forceinline__ double horner(const double *c, double q) {
 
 // normalised Matern correlation for the factor kernel: division-free series
 // and the table-driven logarithm for x <= 2, the trapezoid rule beyond.
+// logtab is the near_log table (the log enters only through terms scaled by
+// q = x^2/4, so its absolute error of ~3e-16 leaves the value at rounding level).
 __device__ double matern_fast(int nu2, double x, const double *__restrict__ ser,
                               const double *__restrict__ logtab) {
   if (x == 0.0) return 1.0;
@@ -295,7 +297,7 @@ __device__ double matern_fast(int nu2, double x, const double *__restrict__ ser,
     return nu2 == 2 ? x * K1 : 0.5 * x * x * K0 + x * K1;
   }
   const double q = 0.25 * x * x;
-  const double lg = tang_log(0.5 * x, logtab);
+  const double lg = near_log(0.5 * x, logtab);
   const double xk1 = 1.0 + 2.0 * q * lg * horner(ser + 2 * kSerTerms, q) -
                      q * horner(ser + 3 * kSerTerms, q);
   if (nu2 == 2) return xk1;
@@ -318,7 +320,7 @@ __device__ double matern_fast2(int nu2, double x2, const double *__restrict__ se
   if ((nu2 & 1) || x2 > 4.0) return matern_fast(nu2, sqrt(x2), ser, logtab);
   const double q = 0.25 * x2;
   const int nt = q < 1e-4 ? 4 : (q < 1e-2 ? 6 : (q < 0.1 ? 9 : kSerTerms));
-  const double lg = 0.5 * tang_log(q, logtab);
+  const double lg = 0.5 * near_log(q, logtab);
   const double xk1 = 1.0 + 2.0 * q * lg * horner_n(ser + 2 * kSerTerms, q, nt) -
                      q * horner_n(ser + 3 * kSerTerms, q, nt);
   if (nu2 == 2) return xk1;
@@ -703,16 +705,16 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<16><<<(n + 3) / 4, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
                                                          alpha, pl.pc_coef, pl.pc_dinv, nfail,
-                                                         ser, pl.logtab));
+                                                         ser, pl.neartab));
     else if (m <= 31)
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<32><<<(n + 1) / 2, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
                                                          alpha, pl.pc_coef, pl.pc_dinv, nfail,
-                                                         ser, pl.logtab));
+                                                         ser, pl.neartab));
     else
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
-                                              pl.pc_coef, pl.pc_dinv, nfail, ser, pl.logtab));
+                                              pl.pc_coef, pl.pc_dinv, nfail, ser, pl.neartab));
     dfree(ser);
     // 5. transpose: stable radix sort of the entries by row
     {
