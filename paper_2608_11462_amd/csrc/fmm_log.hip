@@ -112,7 +112,11 @@ __global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
       } else {
         z = {(xj - cx) * invw, (yj - cy) * invw};
       }
-      C2<T> zk = cpow_small(z, kk);
+      C2<T> zk;
+      if (P <= 31)
+        zk = cpow32(z, kk);
+      else
+        zk = cpow_small(z, kk);
       T v[R];
       vfac<K, T>(xj, yj, v);
       const T tj = (T)st[wave][i];
