@@ -266,27 +266,71 @@ __device__ void bessel_k01(double x, double &K0, double &K1) {
 }
 
 // Power-series coefficients for q = x^2/4 <= 1 (x <= 2), kSerTerms each:
-// ser[0][k] = 1/(k!)^2,                     I0(x) = sum ser0 q^k
-// ser[1][k] = H_k/(k!)^2,                   K0 = -(log(x/2)+gamma) I0 + sum ser1 q^k
-// ser[2][k] = 1/(k!(k+1)!),                 I1(x) = (x/2) sum ser2 q^k
-// ser[3][k] = (2H_k + 1/(k+1) - 2 gamma)/(k!(k+1)!),
-//                                           x K1 = 1 + 2q log(x/2) I1s - q sum ser3 q^k
-// (H_k the harmonic numbers; the logarithmic series of K0 and K1).
+// c[0][k] = 1/(k!)^2,                     I0(x) = sum c0 q^k
+// c[1][k] = H_k/(k!)^2,                   K0 = -(log(x/2)+gamma) I0 + sum c1 q^k
+// c[2][k] = 1/(k!(k+1)!),                 I1(x) = (x/2) sum c2 q^k
+// c[3][k] = (2H_k + 1/(k+1) - 2 gamma)/(k!(k+1)!),
+//                                         x K1 = 1 + 2q log(x/2) I1s - q sum c3 q^k
+// (H_k the harmonic numbers; the logarithmic series of K0 and K1).  They are
+// compile-time constants kept in constant memory: the factor kernel reads them
+// with scalar loads where it uses them (held in registers for the whole
+// kernel, the 70 coefficients of the four truncations would take 140 VGPRs).
 constexpr int kSerTerms = 16;
+struct SerCoef {
+  double c[4][kSerTerms];
+};
+constexpr SerCoef make_ser_coef() {
+  SerCoef t{};
+  double fk = 1.0, H = 0.0;  // k!, H_k
+  for (int k = 0; k < kSerTerms; ++k) {
+    if (k > 0) {
+      fk *= k;
+      H += 1.0 / k;
+    }
+    const double fk1 = fk * (k + 1);
+    t.c[0][k] = 1.0 / (fk * fk);
+    t.c[1][k] = H / (fk * fk);
+    t.c[2][k] = 1.0 / (fk * fk1);
+    t.c[3][k] = (2.0 * H + 1.0 / (k + 1) - 2.0 * kEuler) / (fk * fk1);
+  }
+  return t;
+}
+__constant__ SerCoef kSerTab = make_ser_coef();
+typedef const __attribute__((address_space(4))) double *SerPtr;
 
-__device__ __forceinline__ double horner(const double *c, double q) {
-  double v = c[kSerTerms - 1];
+// a pointer to the coefficients that the compiler cannot treat as loop
+// invariant, so their loads stay where they are used
+__device__ __forceinline__ SerPtr ser_coef() {
+  SerPtr p = (SerPtr)&kSerTab.c[0][0];
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// sum_{k < NT} c[S][k] q^k
+template <int S, int NT>
+__device__ __forceinline__ double horner_c(SerPtr c, double q) {
+  double v = c[S * kSerTerms + NT - 1];
 #pragma unroll
-  for (int k = kSerTerms - 2; k >= 0; --k) v = fma(v, q, c[k]);
+  for (int k = NT - 2; k >= 0; --k) v = fma(v, q, c[S * kSerTerms + k]);
   return v;
+}
+
+// Even orders nu2 in {2, 4} on q = x^2/4 <= 1 from NT series terms, with
+// lg = log(x/2).
+template <int NT>
+__device__ __forceinline__ double matern_series(int nu2, double q, double lg) {
+  const SerPtr c = ser_coef();
+  const double xk1 = 1.0 + 2.0 * q * lg * horner_c<2, NT>(c, q) - q * horner_c<3, NT>(c, q);
+  if (nu2 == 2) return xk1;
+  const double k0 = -(lg + kEuler) * horner_c<0, NT>(c, q) + horner_c<1, NT>(c, q);
+  return 2.0 * q * k0 + xk1;
 }
 
 // normalised Matern correlation for the factor kernel: division-free series
 // and the table-driven logarithm for x <= 2, the trapezoid rule beyond.
 // logtab is the near_log table (the log enters only through terms scaled by
 // q = x^2/4, so its absolute error of ~3e-16 leaves the value at rounding level).
-__device__ double matern_fast(int nu2, double x, const double *__restrict__ ser,
-                              const double *__restrict__ logtab) {
+__device__ double matern_fast(int nu2, double x, const double *__restrict__ logtab) {
   if (x == 0.0) return 1.0;
   if (nu2 == 1) return exp(-x);
   if (nu2 == 3) return (1.0 + x) * exp(-x);
@@ -296,62 +340,41 @@ __device__ double matern_fast(int nu2, double x, const double *__restrict__ ser,
     bessel_k01(x, K0, K1);
     return nu2 == 2 ? x * K1 : 0.5 * x * x * K0 + x * K1;
   }
-  const double q = 0.25 * x * x;
-  const double lg = near_log(0.5 * x, logtab);
-  const double xk1 = 1.0 + 2.0 * q * lg * horner(ser + 2 * kSerTerms, q) -
-                     q * horner(ser + 3 * kSerTerms, q);
-  if (nu2 == 2) return xk1;
-  const double k0 = -(lg + kEuler) * horner(ser, q) + horner(ser + kSerTerms, q);
-  return 2.0 * q * k0 + xk1;
+  return matern_series<kSerTerms>(nu2, 0.25 * x * x, near_log(0.5 * x, logtab));
 }
 
 // The same from x2 = x^2, the form the factor kernel needs: for the K_1 and
 // K_2 forms on x <= 2 no square root is taken (q = x^2/4 and
 // log(x/2) = log(q)/2), and the series stops once q^k/(k!)^2 < 1e-17.
-__device__ __forceinline__ double horner_n(const double *c, double q, int nt) {
-  double v = c[nt - 1];
-  for (int k = nt - 2; k >= 0; --k) v = fma(v, q, c[k]);
-  return v;
+// out of line: the factor kernel reaches it only for odd orders and for
+// x > 2, and inlined it would raise the register count of the whole kernel
+__device__ __forceinline__ double matern_far(int nu2, double x2, const double *__restrict__ logtab) {
+  return matern_fast(nu2, sqrt(x2), logtab);
 }
 
-__device__ double matern_fast2(int nu2, double x2, const double *__restrict__ ser,
-                               const double *__restrict__ logtab) {
+__device__ double matern_fast2(int nu2, double x2, const double *__restrict__ logtab) {
   if (x2 == 0.0) return 1.0;
-  if ((nu2 & 1) || x2 > 4.0) return matern_fast(nu2, sqrt(x2), ser, logtab);
+  if ((nu2 & 1) || x2 > 4.0) return matern_far(nu2, x2, logtab);
   const double q = 0.25 * x2;
-  const int nt = q < 1e-4 ? 4 : (q < 1e-2 ? 6 : (q < 0.1 ? 9 : kSerTerms));
   const double lg = 0.5 * near_log(q, logtab);
-  const double xk1 = 1.0 + 2.0 * q * lg * horner_n(ser + 2 * kSerTerms, q, nt) -
-                     q * horner_n(ser + 3 * kSerTerms, q, nt);
-  if (nu2 == 2) return xk1;
-  const double k0 = -(lg + kEuler) * horner_n(ser, q, nt) + horner_n(ser + kSerTerms, q, nt);
-  return 2.0 * q * k0 + xk1;
+  if (q < 1e-4) return matern_series<4>(nu2, q, lg);
+  if (q < 1e-2) return matern_series<6>(nu2, q, lg);
+  if (q < 0.1) return matern_series<9>(nu2, q, lg);
+  return matern_series<kSerTerms>(nu2, q, lg);
 }
 
-// normalised Matern correlation, value 1 at x = 0; nu2 = 2*nu in {1,2,3,4,5}
-__device__ double matern(int nu2, double x) {
-  if (x == 0.0) return 1.0;
-  switch (nu2) {
-    case 1: return exp(-x);
-    case 3: return (1.0 + x) * exp(-x);
-    case 5: return (1.0 + x + x * x / 3.0) * exp(-x);
-    case 2: {
-      double K0, K1;
-      bessel_k01(x, K0, K1);
-      return x * K1;
-    }
-    default: {  // nu = 2: x^2 K_2(x) / 2, K_2 = K_0 + 2 K_1 / x
-      double K0, K1;
-      bessel_k01(x, K0, K1);
-      return 0.5 * x * x * K0 + x * K1;
-    }
+// value v of lane gg*MM + i, for the block gg = g this lane belongs to (i
+// uniform across the wavefront)
+template <int G, int MM>
+__device__ __forceinline__ double block_bcast(double v, int i, int g) {
+  double out = v;
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) {
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), gg * MM + i);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), gg * MM + i);
+    out = gg == g ? __hiloint2double(hi, lo) : out;
   }
-}
-
-__device__ __forceinline__ double bcast(double v, int lane) {
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  return __hiloint2double(hi, lo);
+  return out;
 }
 
 // (a, b), b <= a, of the e-th entry of a lower triangle enumerated row by row
@@ -370,25 +393,25 @@ __device__ __forceinline__ void tri_index(int e, int &a, int &b) {
 // A wavefront factors G = 64/MM nodes, MM the padded block size.  Each block
 // is padded to MM rows with identity rows in front (their entries of k and
 // lambda are zero), so every node has the same shape.  All 64 lanes first
-// build the lower triangles in LDS; then lane (g, r) keeps row r of block g in
-// registers and runs a fully unrolled left-looking Cholesky: at step c it
-// forms A[r][c] - sum_k L[r][k] L[c][k] with row c read from LDS (the same
-// address across the block's lanes), the pivot comes from lane c by readlane,
-// and rows below scale by its reciprocal square root.  A block that is not numerically positive
-// definite is refactored with a diagonal nugget (1e-12, then x100), and the
-// nodes that needed one, or still fail, are counted.
+// build the lower triangles in LDS, packed by rows (row a starts at
+// a(a+1)/2); then lane (g, r) keeps row r of block g in registers and runs a
+// fully unrolled left-looking Cholesky: at step c it forms
+// A[r][c] - sum_k L[r][k] L[c][k] with row c read from LDS (the same address
+// across the block's lanes), the pivot comes from lane c by readlane, and rows
+// below scale by its reciprocal square root.  Lane r keeps 1/L[r][r].  A block
+// that is not numerically positive definite is refactored with a diagonal
+// nugget (1e-12, then x100), and the nodes that needed one, or still fail,
+// are counted.  The packed triangles (about 9.5 KB per wavefront at MM = 32)
+// and a cap of 128 VGPRs let four wavefronts share a SIMD.
 template <int MM>
-__global__ __launch_bounds__(64) void k_factor(const double *x, const double *y, int64_t n,
-                                               int m, const int32_t *nbr, const int32_t *cnt,
-                                               int nu2, double alpha, double *coef,
-                                               double *dinv, int32_t *nfail,
-                                               const double *ser, const double *logtab) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t *nbr,
+              const int32_t *cnt, int nu2, double alpha, double *coef, double *dinv,
+              int32_t *nfail, const double *logtab) {
   constexpr int G = 64 / MM;
-  constexpr int LD = MM + 1;
   constexpr int T = MM * (MM + 1) / 2;
-  __shared__ double Lm[G][MM * LD];
-  __shared__ double px[G][MM], py[G][MM], dgi[G][MM];
-  __shared__ double nugs[G];
+  __shared__ double Lm[G][T];
+  __shared__ double px[G][MM], py[G][MM];
   const int lane = threadIdx.x, g = lane / MM, r = lane % MM;
   const int64_t p = (int64_t)blockIdx.x * G + g;
   const bool valid = p < n;
@@ -408,52 +431,69 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
     px[g][r] = cx;
     py[g][r] = cy;
   }
-  double nug = 0.0;  // this lane's copy of its block's nugget
+  int padv[G];  // padding rows of every block of the wavefront (uniform)
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) padv[gg] = __builtin_amdgcn_readlane(pad, gg * MM);
+  const double a2 = alpha * alpha;
+  const int rb = r * (r + 1) / 2;  // row r in the packed triangle
+  double nug = 0.0;                // this lane's copy of its block's nugget
+  double myinv = 0.0;              // 1 / L[r][r]
   bool ok = false;
   for (int attempt = 0; attempt < 4; ++attempt) {
-    if (r == 0) nugs[g] = nug;
+    double nugv[G];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int hi = __builtin_amdgcn_readlane(__double2hiint(nug), gg * MM);
+      const int lo = __builtin_amdgcn_readlane(__double2loint(nug), gg * MM);
+      nugv[gg] = __hiloint2double(hi, lo);
+    }
     __syncthreads();
     // lower triangles of all G blocks, spread over the whole wavefront
     for (int e = lane; e < G * T; e += 64) {
       const int gg = e / T;
       int a, b;
       tri_index(e - gg * T, a, b);
-      const int pg = MM - 1 - (((int64_t)blockIdx.x * G + gg) < n
-                                   ? cnt[(int64_t)blockIdx.x * G + gg] : 0);
+      int pg = padv[0];
+      double ng = nugv[0];
+#pragma unroll
+      for (int h = 1; h < G; ++h) {
+        pg = gg == h ? padv[h] : pg;
+        ng = gg == h ? nugv[h] : ng;
+      }
       double v;
       if (a == b) {
-        v = a < pg ? 1.0 : 1.0 + nugs[gg];
+        v = a < pg ? 1.0 : 1.0 + ng;
       } else if (b < pg) {
         v = 0.0;
       } else {
         const double dx = px[gg][a] - px[gg][b], dy = py[gg][a] - py[gg][b];
-        v = matern_fast2(nu2, alpha * alpha * (dx * dx + dy * dy), ser, logtab);
+        v = matern_fast2(nu2, a2 * (dx * dx + dy * dy), logtab);
       }
-      Lm[gg][a * LD + b] = v;
+      Lm[gg][e - gg * T] = v;
     }
     __syncthreads();
     // Left-looking Cholesky, one column per step.  The block's lanes sit in one
     // wavefront, whose LDS accesses execute in program order, so row c written
-    // at earlier steps is visible without a barrier; the pivot of each block is
-    // taken from lane c by readlane.
+    // at earlier steps is visible without a barrier.
     double Lr[MM];
 #pragma unroll
-    for (int c = 0; c < MM; ++c) Lr[c] = Lm[g][r * LD + c];  // c > r: never read validly
+    for (int c = 0; c < MM; ++c) Lr[c] = Lm[g][rb + c];  // c > r: never read validly
     bool badl = false;
 #pragma unroll
     for (int c = 0; c < MM; ++c) {
       // four independent partial sums keep the FMA pipeline busy
+      // (row c is read in chunks of eight, so no more than eight of its
+      // entries are held in registers at once)
       double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < c; ++k) s4[k & 3] = fma(Lr[k], Lm[g][c * LD + k], s4[k & 3]);
-      const double sacc = Lr[c] - ((s4[0] + s4[1]) + (s4[2] + s4[3]));
-      double pc = sacc;
+      for (int k0 = 0; k0 < c; k0 += 8) {
 #pragma unroll
-      for (int gg = 0; gg < G; ++gg) {
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(sacc), gg * MM + c);
-        const int lo = __builtin_amdgcn_readlane(__double2loint(sacc), gg * MM + c);
-        pc = gg == g ? __hiloint2double(hi, lo) : pc;
+        for (int k = k0; k < k0 + 8 && k < c; ++k)
+          s4[k & 3] = fma(Lr[k], Lm[g][c * (c + 1) / 2 + k], s4[k & 3]);
+        __builtin_amdgcn_sched_barrier(0);
       }
+      const double sacc = Lr[c] - ((s4[0] + s4[1]) + (s4[2] + s4[3]));
+      double pc = block_bcast<G, MM>(sacc, c, g);
       badl = badl || !(pc > 0.0);
       pc = pc > 0.0 ? pc : 1.0;
       // 1/sqrt(pc): hardware estimate and one Newton step
@@ -464,8 +504,8 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
       // that no valid result reads: lane r's own entries depend only on its
       // columns k <= r, and its results at columns c > r are discarded.
       Lr[c] = sacc * inv;
-      Lm[g][r * LD + c] = Lr[c];
-      dgi[g][c] = inv;
+      if (r >= c) Lm[g][rb + c] = Lr[c];
+      myinv = r == c ? inv : myinv;
     }
     ok = !badl;
     if (__all(ok)) break;
@@ -473,30 +513,22 @@ __global__ __launch_bounds__(64) void k_factor(const double *x, const double *y,
       if (attempt == 0 && r == 0) atomicAdd(&nfail[0], 1);
       nug = attempt == 0 ? 1e-12 : nug * 100.0;
     }
-    __syncthreads();  // the next attempt rebuilds the blocks in LDS
   }
   if (!ok && r == 0 && valid) atomicAdd(&nfail[1], 1);
   // lambda = L_s^{-T} l, l = the node's row without its diagonal, column by
-  // column from the last: lambda_i = u_i / L_ii, then u_r -= L[i][r] lambda_i.
-  // With the diagonal and upper triangle of every row zeroed (the diagonal is
-  // kept in dgi) the update applies to all lanes unchanged: lanes r >= i see
-  // L[i][r] = 0.  Lane r holds u_r and ends with lambda_r = u_r / L_rr.
-  double u = r < MM - 1 ? Lm[g][(MM - 1) * LD + r] : 0.0;
-  for (int c = r; c < MM; ++c) Lm[g][r * LD + c] = 0.0;
+  // column from the last: lambda_i = u_i / L_ii (formed on lane i, whose u is
+  // final by then), then u_r -= L[i][r] lambda_i on the lanes r < i.  Lane r
+  // holds u_r and ends with lambda_r = u_r / L_rr.
+  double u = r < MM - 1 ? Lm[g][(MM - 1) * MM / 2 + r] : 0.0;
 #pragma unroll
   for (int i = MM - 2; i >= 0; --i) {
-    double ui = u;
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-      const int hi = __builtin_amdgcn_readlane(__double2hiint(u), gg * MM + i);
-      const int lo = __builtin_amdgcn_readlane(__double2loint(u), gg * MM + i);
-      ui = gg == g ? __hiloint2double(hi, lo) : ui;
-    }
-    u = fma(-Lm[g][i * LD + r], ui * dgi[g][i], u);
+    const double li = block_bcast<G, MM>(u * myinv, i, g);
+    const double lir = r < i ? Lm[g][i * (i + 1) / 2 + r] : 0.0;  // in bounds for all r
+    u = fma(-lir, li, u);
   }
-  const double v = u * dgi[g][r];
+  const double v = u * myinv;
+  const double inv_c = block_bcast<G, MM>(myinv, MM - 1, g);
   if (!valid || !ok) return;
-  const double inv_c = dgi[g][MM - 1];
   // lane r < MM-1 holds lambda of row r = pad + a; padding coefficients are 0
   if (r >= pad && r < MM - 1) coef[p * m + (r - pad)] = -v * inv_c;
   for (int a = K + r; a < m; a += MM) coef[p * m + a] = 0.0;
@@ -678,25 +710,6 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
                                                                    d_coff, cstart, gv,
                                                   gxy, pos_of_rank, qord, pl.pc_nbr, cnt));
     dfree(gxy);
-    // series coefficients of the Bessel functions (host, exact rationals in FP64)
-    double *ser = dmalloc<double>(4 * kSerTerms);
-    {
-      std::vector<double> hs(4 * kSerTerms);
-      double fk = 1.0, fk1 = 1.0, H = 0.0;  // k!, (k+1)!, H_k
-      for (int k = 0; k < kSerTerms; ++k) {
-        if (k > 0) {
-          fk *= k;
-          H += 1.0 / k;
-        }
-        fk1 = fk * (k + 1);
-        hs[k] = 1.0 / (fk * fk);
-        hs[kSerTerms + k] = H / (fk * fk);
-        hs[2 * kSerTerms + k] = 1.0 / (fk * fk1);
-        hs[3 * kSerTerms + k] = (2.0 * H + 1.0 / (k + 1) - 2.0 * kEuler) / (fk * fk1);
-      }
-      PHS_HIP(hipMemcpyAsync(ser, hs.data(), hs.size() * 8, hipMemcpyHostToDevice, s));
-      PHS_HIP(hipStreamSynchronize(s));
-    }
     // 4. factor
     pl.pc_coef = dmalloc<double>((size_t)n * m);
     pl.pc_dinv = dmalloc<double>(n);
@@ -705,17 +718,16 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<16><<<(n + 3) / 4, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
                                                          alpha, pl.pc_coef, pl.pc_dinv, nfail,
-                                                         ser, pl.neartab));
+                                                         pl.neartab));
     else if (m <= 31)
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<32><<<(n + 1) / 2, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
                                                          alpha, pl.pc_coef, pl.pc_dinv, nfail,
-                                                         ser, pl.neartab));
+                                                         pl.neartab));
     else
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
-                                              pl.pc_coef, pl.pc_dinv, nfail, ser, pl.neartab));
-    dfree(ser);
+                                              pl.pc_coef, pl.pc_dinv, nfail, pl.neartab));
     // 5. transpose: stable radix sort of the entries by row
     {
       const int64_t N = n * m;
