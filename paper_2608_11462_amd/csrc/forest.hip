@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "fmm_common.h"
 #include "phs_internal.h"
 
 namespace phs {
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(64) void kf_apply_ut(const SysDev *__restrict__ sys
                                                   const BlkRef *__restrict__ tab,
                                                   const int32_t *__restrict__ mask, int rs,
                                                   int ys) {
-  const BlkRef br = tab[blockIdx.x];
+  const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
   const int64_t j = (int64_t)br.blk * 64 + threadIdx.x;
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
                                                   const int32_t *__restrict__ mask, int ys,
                                                   int zs) {
   constexpr int LPR = kApplyLanes, RPG = LPR / 4;  // rows per lane group
-  const BlkRef br = tab[blockIdx.x];
+  const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
   const int64_t i0 = ((int64_t)br.blk * (256 / LPR) + threadIdx.x / LPR) * RPG;

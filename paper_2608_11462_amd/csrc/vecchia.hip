@@ -363,26 +363,21 @@ __device__ double matern_fast2(int nu2, double x2, const double *__restrict__ lo
   return matern_series<kSerTerms>(nu2, q, lg);
 }
 
-// value v of lane gg*MM + i, for the block gg = g this lane belongs to (i
-// uniform across the wavefront)
+// value v of lane g*MM + i (i uniform across the wavefront), g the block
+// this lane belongs to: a backward permute through the LDS crossbar for
+// several blocks per wavefront, two readlanes for one
 template <int G, int MM>
 __device__ __forceinline__ double block_bcast(double v, int i, int g) {
-  double out = v;
-#pragma unroll
-  for (int gg = 0; gg < G; ++gg) {
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), gg * MM + i);
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), gg * MM + i);
-    out = gg == g ? __hiloint2double(hi, lo) : out;
+  if constexpr (G == 1) {
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+    return __hiloint2double(hi, lo);
+  } else {
+    const int addr = (g * MM + i) * 4;
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    return __hiloint2double(hi, lo);
   }
-  return out;
-}
-
-// (a, b), b <= a, of the e-th entry of a lower triangle enumerated row by row
-__device__ __forceinline__ void tri_index(int e, int &a, int &b) {
-  a = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
-  while (a * (a + 1) / 2 > e) --a;
-  while ((a + 1) * (a + 2) / 2 <= e) ++a;
-  b = e - a * (a + 1) / 2;
 }
 
 // Factor of the Vecchia conditionals (eq. conditionals, Fig. vecchia_chol):
@@ -392,17 +387,18 @@ __device__ __forceinline__ void tri_index(int e, int &a, int &b) {
 //
 // A wavefront factors G = 64/MM nodes, MM the padded block size.  Each block
 // is padded to MM rows with identity rows in front (their entries of k and
-// lambda are zero), so every node has the same shape.  All 64 lanes first
-// build the lower triangles in LDS, packed by rows (row a starts at
-// a(a+1)/2); then lane (g, r) keeps row r of block g in registers and runs a
-// fully unrolled left-looking Cholesky: at step c it forms
+// lambda are zero), so every node has the same shape.  The block's lanes
+// first build its lower triangle in LDS, packed by rows (row a starts at
+// a(a+1)/2): rows p and MM-1-p together hold MM+1 entries, which lanes p and
+// p + MM/2 share.  Then lane (g, r) keeps row r of block g in registers and
+// runs a fully unrolled left-looking Cholesky: at step c it forms
 // A[r][c] - sum_k L[r][k] L[c][k] with row c read from LDS (the same address
-// across the block's lanes), the pivot comes from lane c by readlane, and rows
-// below scale by its reciprocal square root.  Lane r keeps 1/L[r][r].  A block
-// that is not numerically positive definite is refactored with a diagonal
-// nugget (1e-12, then x100), and the nodes that needed one, or still fail,
-// are counted.  The packed triangles (about 9.5 KB per wavefront at MM = 32)
-// and a cap of 128 VGPRs let four wavefronts share a SIMD.
+// across the block's lanes), takes the pivot from lane c, and scales by its
+// reciprocal square root.  Lane r keeps 1/L[r][r].  A block that is not
+// numerically positive definite is refactored with a diagonal nugget (1e-12,
+// then x100), and the nodes that needed one, or still fail, are counted.  The
+// packed triangles (about 9.5 KB per wavefront at MM = 32) and a cap of 168
+// VGPRs let three wavefronts share a SIMD.
 template <int MM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t *nbr,
@@ -410,10 +406,11 @@ void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t 
               int32_t *nfail, const double *logtab) {
   constexpr int G = 64 / MM;
   constexpr int T = MM * (MM + 1) / 2;
+  constexpr int H = MM / 2, NI = H + 1;  // row pairs; entries per lane
   __shared__ double Lm[G][T];
-  __shared__ double px[G][MM], py[G][MM];
+  __shared__ double2 pxy[G][MM];
   const int lane = threadIdx.x, g = lane / MM, r = lane % MM;
-  const int64_t p = (int64_t)blockIdx.x * G + g;
+  const int64_t p = xcd_remap(blockIdx.x, gridDim.x) * G + g;
   const bool valid = p < n;
   const int K = valid ? cnt[p] : 0;
   const int pad = MM - 1 - K;
@@ -428,48 +425,34 @@ void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t 
       cx = x[p];
       cy = y[p];
     }
-    px[g][r] = cx;
-    py[g][r] = cy;
+    pxy[g][r] = make_double2(cx, cy);
   }
-  int padv[G];  // padding rows of every block of the wavefront (uniform)
-#pragma unroll
-  for (int gg = 0; gg < G; ++gg) padv[gg] = __builtin_amdgcn_readlane(pad, gg * MM);
   const double a2 = alpha * alpha;
-  const int rb = r * (r + 1) / 2;  // row r in the packed triangle
-  double nug = 0.0;                // this lane's copy of its block's nugget
-  double myinv = 0.0;              // 1 / L[r][r]
+  const int rb = r * (r + 1) / 2;           // row r in the packed triangle
+  const int pr = r % H, j0 = (r / H) * NI;  // row pair (pr, MM-1-pr); first item
+  double nug = 0.0;                         // this block's nugget
+  double myinv = 0.0;                       // 1 / L[r][r]
   bool ok = false;
   for (int attempt = 0; attempt < 4; ++attempt) {
-    double nugv[G];
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-      const int hi = __builtin_amdgcn_readlane(__double2hiint(nug), gg * MM);
-      const int lo = __builtin_amdgcn_readlane(__double2loint(nug), gg * MM);
-      nugv[gg] = __hiloint2double(hi, lo);
-    }
     __syncthreads();
-    // lower triangles of all G blocks, spread over the whole wavefront
-    for (int e = lane; e < G * T; e += 64) {
-      const int gg = e / T;
-      int a, b;
-      tri_index(e - gg * T, a, b);
-      int pg = padv[0];
-      double ng = nugv[0];
-#pragma unroll
-      for (int h = 1; h < G; ++h) {
-        pg = gg == h ? padv[h] : pg;
-        ng = gg == h ? nugv[h] : ng;
-      }
+    // items j of the row pair: (pr, j) for j <= pr, else (MM-1-pr, j-pr-1)
+#pragma unroll 1
+    for (int t = 0; t < NI; ++t) {
+      const int j = j0 + t;
+      if (j > MM) continue;
+      const bool lo = j <= pr;
+      const int a = lo ? pr : MM - 1 - pr, b = lo ? j : j - pr - 1;
       double v;
       if (a == b) {
-        v = a < pg ? 1.0 : 1.0 + ng;
-      } else if (b < pg) {
+        v = a < pad ? 1.0 : 1.0 + nug;
+      } else if (b < pad) {
         v = 0.0;
       } else {
-        const double dx = px[gg][a] - px[gg][b], dy = py[gg][a] - py[gg][b];
+        const double2 qa = pxy[g][a], qb = pxy[g][b];
+        const double dx = qa.x - qb.x, dy = qa.y - qb.y;
         v = matern_fast2(nu2, a2 * (dx * dx + dy * dy), logtab);
       }
-      Lm[gg][e - gg * T] = v;
+      Lm[g][a * (a + 1) / 2 + b] = v;
     }
     __syncthreads();
     // Left-looking Cholesky, one column per step.  The block's lanes sit in one
@@ -481,18 +464,17 @@ void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t 
     bool badl = false;
 #pragma unroll
     for (int c = 0; c < MM; ++c) {
-      // four independent partial sums keep the FMA pipeline busy
-      // (row c is read in chunks of eight, so no more than eight of its
-      // entries are held in registers at once)
-      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      // two partial sums; row c is read in chunks of eight, so no more than
+      // eight of its entries are held in registers at once
+      double s2[2] = {0.0, 0.0};
 #pragma unroll
       for (int k0 = 0; k0 < c; k0 += 8) {
 #pragma unroll
         for (int k = k0; k < k0 + 8 && k < c; ++k)
-          s4[k & 3] = fma(Lr[k], Lm[g][c * (c + 1) / 2 + k], s4[k & 3]);
+          s2[k & 1] = fma(Lr[k], Lm[g][c * (c + 1) / 2 + k], s2[k & 1]);
         __builtin_amdgcn_sched_barrier(0);
       }
-      const double sacc = Lr[c] - ((s4[0] + s4[1]) + (s4[2] + s4[3]));
+      const double sacc = Lr[c] - (s2[0] + s2[1]);
       double pc = block_bcast<G, MM>(sacc, c, g);
       badl = badl || !(pc > 0.0);
       pc = pc > 0.0 ? pc : 1.0;
