@@ -175,15 +175,23 @@ __global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, 
           if (visit) {
             const int c = cy * g + cx;
             const int b = cs[c], e = cs[c + 1];
+            // the rank and coordinates of the next candidate are loaded while
+            // the current one is processed
+            int rn = b < e ? sorted_rank[b] : 0x7fffffff;
+            double2 xn = b < e ? gxy[b] : make_double2(0.0, 0.0);
             for (int q = b; q < e; ++q) {
-              const int r = sorted_rank[q];
+              const int r = rn;
+              const double2 cxy = xn;
+              if (q + 1 < e) {
+                rn = sorted_rank[q + 1];
+                xn = gxy[q + 1];
+              }
               if (r >= t) break;  // within a cell entries ascend by rank
               double d2;
               {
                 // each product rounded, then the sum: no fused multiply-add, so
                 // d^2 is symmetric in (dx, dy) and identical to the CPU reference
 #pragma clang fp contract(off)
-                const double2 cxy = gxy[q];
                 const double dx = cxy.x - qx;
                 const double dy = cxy.y - qy;
                 d2 = dx * dx + dy * dy;
