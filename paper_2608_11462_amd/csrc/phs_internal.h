@@ -455,34 +455,16 @@ void count_duplicates(const double *x, const double *y,
                       hipStream_t s);
 
 // vec.hip
-void gather_cols(const double *src_user, const int32_t *order, int64_t n,
-                 double *dst_tree, hipStream_t s);
-void scatter_cols(const double *src_tree, const int32_t *order, int64_t n,
-                  double *dst_user, hipStream_t s);
 void poly_block_tree(const double *x, const double *y, int64_t n, int d,
                      double *B, hipStream_t s);
-// Partial sums for several dot products sum_i a_t[i]*b_t[i], t < nd.
-// out (device) receives nd results.  partials holds nblocks*nd doubles.
+// Grid size of the forest's reductions (depends only on n).
 int dot_blocks(int64_t n);
-void multi_dot(const double *const *a, const double *const *b, int nd,
-               int64_t n, double *partials, double *out, hipStream_t s);
+// Gram matrix out[a*S + b] = B_a . B_b (a <= b) of the S tree-ordered columns of
+// B, by deterministic two-stage reductions; partials holds the block sums.
 void gram(const double *B, int64_t n, int S, double *partials, double *out,
           hipStream_t s);
 void apply_rinv(double *B, int64_t n, int S, const double *Rinv_dev,
                 hipStream_t s);
-void project(double *v, const double *Q, int64_t n, int S, double *partials,
-             double *scal, hipStream_t s);
-void axpby(double *y, const double *x, double a, double b, int64_t n,
-           hipStream_t s);
-void scale_copy(double *dst, const double *src, double a, int64_t n,
-                hipStream_t s);
-void pcg_update_wr(double *w, double *r, const double *p, const double *q,
-                   const double *scal, int64_t n, double *partials,
-                   double *out_rr, hipStream_t s);
-void pcg_update_p(double *p, const double *z, const double *scal, int64_t n,
-                  hipStream_t s);
-void fill(double *v, double a, int64_t n, hipStream_t s);
-void copy(double *dst, const double *src, int64_t n, hipStream_t s);
 
 // fmm_log.hip
 void build_log_tables(LogTables &t, int P);

@@ -1,7 +1,8 @@
-// Vector kernels of the projected PCG (paper eq. phs_linsys_solve and the
-// O(nS) application of the complement projector, Sec. 2): permutations, the
-// polynomial block, deterministic multi-dot reductions, the projector
-// Pi v = v - Q (Q^T v), and the fused PCG recurrences.
+// Plan-time vector kernels of the polynomial block (paper eq. phs_linsys_solve
+// and the O(nS) complement projector, Sec. 2): the block P of the tree-ordered
+// nodes, its Gram matrix by deterministic multi-dot reductions, and the
+// column transform of CholeskyQR.  The PCG's own vector kernels run on the
+// batched engine.
 //
 // Reductions are two-stage with a grid size that depends only on n, so every
 // result is bitwise reproducible run to run.
@@ -67,18 +68,6 @@ __global__ void k_reduce_final(const double *__restrict__ part, int nb, int nd,
   }
 }
 
-__global__ void k_gather(const double *__restrict__ src, const int32_t *__restrict__ order,
-                         int64_t n, double *__restrict__ dst) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < n) dst[i] = src[order[i]];
-}
-
-__global__ void k_scatter(const double *__restrict__ src, const int32_t *__restrict__ order,
-                          int64_t n, double *__restrict__ dst) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < n) dst[order[i]] = src[i];
-}
-
 __global__ void k_poly_block(const double *__restrict__ x, const double *__restrict__ y,
                              int64_t n, int d, double *__restrict__ B) {
   int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
@@ -108,75 +97,9 @@ __global__ void k_apply_rinv(double *__restrict__ B, int64_t n, int S,
   for (int j = 0; j < S; ++j) B[(int64_t)j * n + i] = o[j];
 }
 
-__global__ void k_sub_Qc(double *__restrict__ v, const double *__restrict__ Q,
-                         int64_t n, int S, const double *__restrict__ c) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int j = 0; j < S; ++j) s += Q[(int64_t)j * n + i] * c[j];
-  v[i] -= s;
-}
-
-__global__ void k_axpby(double *__restrict__ y, const double *__restrict__ x, double a,
-                        double b, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < n) y[i] = a * x[i] + b * y[i];
-}
-
-__global__ void k_scale_copy(double *__restrict__ d, const double *__restrict__ s, double a,
-                             int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < n) d[i] = a * s[i];
-}
-
-__global__ void k_fill(double *__restrict__ v, double a, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (i < n) v[i] = a;
-}
-
-// w += alpha p, r -= alpha q with alpha = num/den read from device memory,
-// and per-block partial sums of r.r.
-__global__ void k_pcg_wr(double *__restrict__ w, double *__restrict__ r,
-                         const double *__restrict__ p, const double *__restrict__ q,
-                         const double *__restrict__ num, const double *__restrict__ den,
-                         int64_t n, double *__restrict__ part) {
-  __shared__ double sh[kBlock / 64];
-  const double alpha = num[0] / den[0];
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlock) {
-    w[i] += alpha * p[i];
-    double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    acc += ri * ri;
-  }
-  double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-__global__ void k_pcg_p(double *__restrict__ p, const double *__restrict__ z,
-                        const double *__restrict__ num, const double *__restrict__ den,
-                        int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  const double beta = num[0] / den[0];
-  if (i < n) p[i] = z[i] + beta * p[i];
-}
-
 }  // namespace
 
 int dot_blocks(int64_t n) { return grid_for(n); }
-
-void gather_cols(const double *src_user, const int32_t *order, int64_t n, double *dst_tree,
-                 hipStream_t s) {
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  PHS_LAUNCH("gather", s, k_gather<<<nb, kBlock, 0, s>>>(src_user, order, n, dst_tree));
-}
-
-void scatter_cols(const double *src_tree, const int32_t *order, int64_t n, double *dst_user,
-                  hipStream_t s) {
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  PHS_LAUNCH("scatter", s, k_scatter<<<nb, kBlock, 0, s>>>(src_tree, order, n, dst_user));
-}
 
 void poly_block_tree(const double *x, const double *y, int64_t n, int d, double *B,
                      hipStream_t s) {
@@ -184,8 +107,9 @@ void poly_block_tree(const double *x, const double *y, int64_t n, int d, double 
   PHS_LAUNCH("poly_block", s, k_poly_block<<<nb, kBlock, 0, s>>>(x, y, n, d, B));
 }
 
-void multi_dot(const double *const *a, const double *const *b, int nd, int64_t n,
-               double *partials, double *out, hipStream_t s) {
+// sum_i a_t[i] b_t[i] for t < nd into out (device), two-stage
+static void multi_dot(const double *const *a, const double *const *b, int nd, int64_t n,
+                      double *partials, double *out, hipStream_t s) {
   PHS_REQUIRE(nd >= 1 && nd <= kMaxDots, PHS_ERR_INVALID_ARGUMENT, "multi_dot: bad count");
   DotArgs args;
   for (int t = 0; t < nd; ++t) {
@@ -221,54 +145,6 @@ void gram(const double *B, int64_t n, int S, double *partials, double *out, hipS
 void apply_rinv(double *B, int64_t n, int S, const double *Rinv, hipStream_t s) {
   int64_t nb = (n + kBlock - 1) / kBlock;
   PHS_LAUNCH("apply_rinv", s, k_apply_rinv<<<nb, kBlock, 0, s>>>(B, n, S, Rinv));
-}
-
-void project(double *v, const double *Q, int64_t n, int S, double *partials, double *scal,
-             hipStream_t s) {
-  const double *pa[kMaxDots], *pb[kMaxDots];
-  for (int j = 0; j < S; ++j) {
-    pa[j] = Q + (int64_t)j * n;
-    pb[j] = v;
-  }
-  multi_dot(pa, pb, S, n, partials, scal, s);
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  PHS_LAUNCH("project", s, k_sub_Qc<<<nb, kBlock, 0, s>>>(v, Q, n, S, scal));
-}
-
-void axpby(double *y, const double *x, double a, double b, int64_t n, hipStream_t s) {
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  PHS_LAUNCH("axpby", s, k_axpby<<<nb, kBlock, 0, s>>>(y, x, a, b, n));
-}
-
-void scale_copy(double *dst, const double *src, double a, int64_t n, hipStream_t s) {
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  PHS_LAUNCH("scale_copy", s, k_scale_copy<<<nb, kBlock, 0, s>>>(dst, src, a, n));
-}
-
-void fill(double *v, double a, int64_t n, hipStream_t s) {
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  PHS_LAUNCH("fill", s, k_fill<<<nb, kBlock, 0, s>>>(v, a, n));
-}
-
-void copy(double *dst, const double *src, int64_t n, hipStream_t s) {
-  PHS_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-}
-
-// num/den are scal[0]/scal[1] for the (w, r) update; the caller supplies
-// pointers to the slots it uses.
-void pcg_update_wr(double *w, double *r, const double *p, const double *q,
-                   const double *scal, int64_t n, double *partials, double *out_rr,
-                   hipStream_t s) {
-  int nb = grid_for(n);
-  PHS_LAUNCH("pcg_wr", s,
-             k_pcg_wr<<<nb, kBlock, 0, s>>>(w, r, p, q, scal, scal + 1, n, partials));
-  PHS_LAUNCH("dot_final", s, k_reduce_final<<<1, kBlock, 0, s>>>(partials, nb, 1, out_rr));
-}
-
-void pcg_update_p(double *p, const double *z, const double *scal, int64_t n,
-                  hipStream_t s) {
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  PHS_LAUNCH("pcg_p", s, k_pcg_p<<<nb, kBlock, 0, s>>>(p, z, scal, scal + 1, n));
 }
 
 }  // namespace phs
