@@ -439,8 +439,12 @@ __global__ __launch_bounds__(256) void kf_l2l_seg(const SysDev *__restrict__ sys
 // columns past the end of a short strip, get X = 0.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// Capped at 168 VGPRs (three wavefronts per SIMD instead of two at 204): the
+// grid is only a few wavefronts per SIMD, and the offsets' gathers wait on
+// memory, so occupancy hides more than the few spilled registers cost.
 template <int P>
-__global__ __launch_bounds__(64) void kf_m2l_mfma(const SysDev *__restrict__ sys,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+void kf_m2l_mfma(const SysDev *__restrict__ sys,
                                                   const BlkRef *__restrict__ tab,
                                                   const int32_t *__restrict__ mask,
                                                   const double *__restrict__ Ht,
