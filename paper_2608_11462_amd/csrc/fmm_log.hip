@@ -383,7 +383,9 @@ __global__ __launch_bounds__(256) void kf_l2l_seg(const SysDev *__restrict__ sys
     sb[e] = make_double2(bv.re, bv.im);
   }
   __syncthreads();
-  const int ci = threadIdx.x & 127, par = threadIdx.x >> 7;
+  // par (the parity of the output orders j) is uniform across each wavefront;
+  // saying so makes the Rl loads scalar and the j <= k tests branch-free
+  const int ci = threadIdx.x & 127, par = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
   const int cx = 2 * px0 + (ci & 63), cy = 2 * py + (ci >> 6);
   const int c = (cy & 1) * 2 + (cx & 1);
   const int q = (ci & 63) >> 1;
@@ -398,11 +400,12 @@ __global__ __launch_bounds__(256) void kf_l2l_seg(const SysDev *__restrict__ sys
     const double2 bv = sb[k * 32 + q];
     const C2<double> b = cmul(C2<double>{bv.x, bv.y}, uk);
     uk = cmul(uk, u);
+    const cptr<double> rk = in_place(rl);  // column k of Rl, loaded here
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
       const int j = 2 * i + par;
       if (j <= k) {
-        const double m = rl[j * P1 + k];
+        const double m = rk[j * P1 + k];
         y[i].re = fma(m, b.re, y[i].re);
         y[i].im = fma(m, b.im, y[i].im);
       }

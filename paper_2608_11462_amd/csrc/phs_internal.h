@@ -77,6 +77,15 @@ template <class T>
 __device__ __forceinline__ gptr<T> rw(T *p) {
   return (gptr<T>)(p);
 }
+// A wave-uniform read-only pointer the compiler cannot treat as loop
+// invariant: loads through it stay where they are written.  A fully unrolled
+// loop over a constant table (shift matrices, series coefficients) would
+// otherwise have every entry hoisted into registers ahead of the loop.
+template <class T>
+__device__ __forceinline__ cptr<T> in_place(cptr<T> p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
 
 // ------------------------------------------------------------------ memory
 // Device memory comes from a caching pool: a freed block is parked on the
