@@ -38,7 +38,10 @@ __host__ __device__ inline int64_t cheb_level_base(int l, int QQ, int nd) {
 
 // Lagrange basis at the Q Chebyshev nodes evaluated at x (|x| <= 1):
 // S_a(x) = (1 + 2 sum_{k>=1} T_k(x) T_k(xbar_a)) / Q.  Tk: table T_k(xbar_a), [k][a].
-template <class T, int Q>
+// IN_PLACE reads column a of the table where it is used; without it the
+// compiler may load all Q^2 entries into registers once (which pays where the
+// basis is evaluated once per point, not where the kernel holds much else).
+template <class T, int Q, bool IN_PLACE = false>
 __device__ __forceinline__ void cheb_basis(T x, const T *__restrict__ Tk, T *S) {
   T tk[Q];
   tk[0] = T(1);
@@ -47,9 +50,11 @@ __device__ __forceinline__ void cheb_basis(T x, const T *__restrict__ Tk, T *S) 
   for (int k = 2; k < Q; ++k) tk[k] = T(2) * x * tk[k - 1] - tk[k - 2];
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
+    int col = a;
+    if constexpr (IN_PLACE) asm volatile("" : "+s"(col));
     T s = T(0);
 #pragma unroll
-    for (int k = 1; k < Q; ++k) s += tk[k] * Tk[k * Q + a];
+    for (int k = 1; k < Q; ++k) s += tk[k] * Tk[k * Q + col];
     S[a] = (T(1) + T(2) * s) * (T(1) / T(Q));
   }
 }
@@ -106,10 +111,10 @@ __global__ __launch_bounds__(64) void kf_cheb_p2m(const SysDev *__restrict__ sys
         u2 = (y[j] - cy) * inv_half;
       }
       T S[Q];
-      cheb_basis<T, Q>(u1, tk, S);
+      cheb_basis<T, Q, true>(u1, tk, S);
 #pragma unroll
       for (int a = 0; a < Q; ++a) s1[lane][a] = S[a];
-      cheb_basis<T, Q>(u2, tk, S);
+      cheb_basis<T, Q, true>(u2, tk, S);
 #pragma unroll
       for (int a = 0; a < Q; ++a) s2[lane][a] = S[a];
       T v[R];
@@ -421,9 +426,10 @@ __global__ __launch_bounds__(64) void kf_cheb_leaf_eval(const SysDev *__restrict
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
+          const cptr<T> ga = in_place(g + a * Q);  // row a of the expansion, loaded here
           T sa = T(0);
 #pragma unroll
-          for (int bb = 0; bb < Q; ++bb) sa += S2[bb] * g[a * Q + bb];
+          for (int bb = 0; bb < Q; ++bb) sa += S2[bb] * ga[bb];
           s += S1[a] * sa;
         }
         far += u[r] * s;
