@@ -406,9 +406,10 @@ __device__ __forceinline__ double block_bcast(double v, int i, int g) {
 // numerically positive definite is refactored with a diagonal nugget (1e-12,
 // then x100), and the nodes that needed one, or still fail, are counted.  The
 // packed triangles (about 9.5 KB per wavefront at MM = 32) and a cap of 168
-// VGPRs let three wavefronts share a SIMD.
+// VGPRs let three wavefronts share a SIMD; at MM = 64 the row alone takes 128
+// VGPRs, so two share one (a tighter cap spills the row to scratch).
 template <int MM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MM <= 32 ? 3 : 2)))
 void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t *nbr,
               const int32_t *cnt, int nu2, double alpha, double *coef, double *dinv,
               int32_t *nfail, const double *logtab) {
@@ -470,7 +471,9 @@ void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t 
 #pragma unroll
     for (int c = 0; c < MM; ++c) Lr[c] = Lm[g][rb + c];  // c > r: never read validly
     bool badl = false;
-#pragma unroll
+    // fully unrolled at every MM, so Lr stays in registers (at MM = 64 the
+    // default heuristics unroll it only in part and index Lr in scratch)
+#pragma clang loop unroll(full)
     for (int c = 0; c < MM; ++c) {
       // two partial sums; row c is read in chunks of eight, so no more than
       // eight of its entries are held in registers at once
