@@ -362,6 +362,150 @@ __global__ __launch_bounds__(256) void kf_cheb_m2l(const SysDev *__restrict__ sy
   }
 }
 
+// FP64 M2L on the matrix cores: the tiles of kf_cheb_m2l (QQ output rows by
+// 64 columns per workgroup, the contraction staged through LDS in chunks of
+// 16), with the products by v_mfma_f64_16x16x4f64.  Wavefront w computes the
+// 16-row tiles w, w + 4, ... against all four 16-column tiles.  Lane layout of
+// the product (row m, column n, inner index k): A[m][k] at lane m + 16 k,
+// B[k][n] at lane n + 16 k, result D[m][n] at lane n + 16 (m mod 4) in
+// register m / 4.  Capped at 3 wavefronts per SIMD: left to itself the
+// compiler holds 280 VGPRs at QQ = 256 (one wavefront), where 164 suffice.
+typedef double cdbl4 __attribute__((ext_vector_type(4)));
+
+template <int QQ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void kf_cheb_m2l_mfma(const SysDev *__restrict__ sys,
+                                                        const BlkRef *__restrict__ tab,
+                                                        const int32_t *__restrict__ mask,
+                                                        const double *__restrict__ Kd) {
+  constexpr int MT = (QQ + 15) / 16;  // 16-row tiles (rows past QQ are zero)
+  constexpr int TPW = (MT + 3) / 4;   // row tiles per wavefront
+  constexpr int AST = kKc + 1, BST = kCols + 1;  // padded strides
+  __shared__ double As[MT * 16 * AST];
+  __shared__ double Bs[kKc * BST];
+  __shared__ int src_box[kCols];
+  __shared__ int any_valid;
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const cptr<double> Wall = ro((const double *)d.mp);
+  const gptr<double> Gall = rw((double *)d.loc);
+  const int L = d.L, nd = d.R;
+  const double h = d.h;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int lm = lane & 15, lk = lane >> 4;
+  // locate level and tile
+  int64_t tcol = (int64_t)br.blk * kCols;
+  int l = 2;
+  int64_t off = 0, base = 0;
+  while (l <= L) {
+    const int64_t cols_l = ((int64_t)1 << (2 * l)) * nd;
+    const int64_t tiles_l = (cols_l + kCols - 1) / kCols;
+    if (tcol < off + tiles_l * kCols) break;
+    off += tiles_l * kCols;
+    base += cols_l * QQ;
+    ++l;
+  }
+  if (l > L) return;
+  const int G = 1 << l;
+  const int64_t nb = (int64_t)G * G;
+  const int64_t col0 = tcol - off;
+  const cptr<double> Wl = Wall + base;
+  const gptr<double> Gl = Gall + base;
+  const double half_w = h / G;  // (w/2)
+  // target box of a column index (parity-class order)
+  auto tgt_of = [&](int64_t cidx, int &ix, int &iy, int &r) -> bool {
+    if (cidx >= nb * nd) return false;
+    const int64_t bi = cidx / nd;
+    r = (int)(cidx % nd);
+    const int64_t quarter = nb / 4;
+    const int cls = (int)(bi / quarter);
+    const int64_t rem = bi % quarter;
+    const int hf = G / 2;
+    ix = 2 * (int)(rem % hf) + (cls & 1);
+    iy = 2 * (int)(rem / hf) + (cls >> 1);
+    return true;
+  };
+  cdbl4 acc[TPW][4];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[t][ct] = cdbl4{0.0, 0.0, 0.0, 0.0};
+  int oi = 0;
+  for (int oy = -3; oy <= 3; ++oy)
+    for (int ox = -3; ox <= 3; ++ox) {
+      if (abs(ox) <= 1 && abs(oy) <= 1) continue;
+      const int d_idx = oi++;
+      __syncthreads();
+      if (tid == 0) any_valid = 0;
+      __syncthreads();
+      if (tid < kCols) {
+        int ix, iy, r;
+        int sb = -1;
+        if (tgt_of(col0 + tid, ix, iy, r)) {
+          const int jx = ix + ox, jy = iy + oy;
+          if (jx >= 0 && jy >= 0 && jx < G && jy < G && abs((jx >> 1) - (ix >> 1)) <= 1 &&
+              abs((jy >> 1) - (iy >> 1)) <= 1)
+            sb = (jy * G + jx) * nd + r;
+        }
+        src_box[tid] = sb;
+        if (sb >= 0) any_valid = 1;
+      }
+      __syncthreads();
+      if (!any_valid) continue;
+      const double *KD = Kd + (int64_t)d_idx * QQ * QQ;
+      for (int k0 = 0; k0 < QQ; k0 += kKc) {
+        // A tile: KD[m][k0 .. k0 + kKc), rows padded to MT * 16 with zeros
+        for (int e = tid; e < MT * 16 * kKc; e += 256) {
+          const int m = e / kKc, kk = e % kKc;
+          As[m * AST + kk] = (m < QQ && k0 + kk < QQ) ? KD[(int64_t)m * QQ + k0 + kk] : 0.0;
+        }
+        // B tile: W[src][k0 .. k0 + kKc) of each column
+        for (int e = tid; e < kKc * kCols; e += 256) {
+          const int c = e / kKc, kk = e % kKc;
+          const int sb = src_box[c];
+          Bs[kk * BST + c] = (sb >= 0 && k0 + kk < QQ) ? Wl[(int64_t)sb * QQ + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < kKc / 4; ++st) {
+          double b[4];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[(4 * st + lk) * BST + 16 * ct + lm];
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) {
+            const int rt = wave + 4 * t;
+            if (rt < MT) {  // uniform across the wavefront
+              const double a = As[(16 * rt + lm) * AST + 4 * st + lk];
+#pragma unroll
+              for (int ct = 0; ct < 4; ++ct)
+                acc[t][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct], acc[t][ct], 0, 0, 0);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  // store: D[m][n] of tile (t, ct) at lane n + 16 (m mod 4), register m / 4
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    int ix, iy, r;
+    if (!tgt_of(col0 + 16 * ct + lm, ix, iy, r)) continue;
+    const int64_t tb = ((int64_t)(iy * G + ix) * nd + r) * QQ;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int rt = wave + 4 * t;
+      if (rt >= MT) continue;
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) {
+        const int m = 16 * rt + 4 * reg + lk;
+        if (m < QQ) Gl[tb + m] = half_w * acc[t][ct][reg];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- leaf
 template <class T, class TN, int K, int Q>
 __global__ __launch_bounds__(64) void kf_cheb_leaf_eval(const SysDev *__restrict__ sys,
@@ -601,8 +745,14 @@ void far_field_q(Forest &F, const int32_t *mask, int in, const ChebTables &ct, i
   {
     const Tab tb = forest_tab(F, tab_key(9 + 16 * tier, 0, Q, 0), s);
     if (tb.count)
-      PHS_LAUNCH("cheb_m2l", s, kf_cheb_m2l<T, QQ><<<(unsigned)tb.count, 256, 0, s>>>(
-                                    F.dsys, tb.d, mask, Kd));
+    {
+      if constexpr (std::is_same<T, double>::value)
+        PHS_LAUNCH("cheb_m2l", s, kf_cheb_m2l_mfma<QQ><<<(unsigned)tb.count, 256, 0, s>>>(
+                                      F.dsys, tb.d, mask, Kd));
+      else
+        PHS_LAUNCH("cheb_m2l", s, kf_cheb_m2l<T, QQ><<<(unsigned)tb.count, 256, 0, s>>>(
+                                      F.dsys, tb.d, mask, Kd));
+    }
   }
   for (int lc = 3; lc <= maxL; ++lc) {
     const Tab tb = forest_tab(F, tab_key(8 + 16 * tier, 0, Q, lc), s);
