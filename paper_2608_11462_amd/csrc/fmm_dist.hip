@@ -59,6 +59,38 @@ __device__ __forceinline__ void cheb_basis(T x, const T *__restrict__ Tk, T *S) 
   }
 }
 
+// The bases at two points x1, x2 (the two coordinates of one target) in one
+// pass over the table, each column read once where it is used.
+template <class T, int Q>
+__device__ __forceinline__ void cheb_basis2(T x1, T x2, const T *__restrict__ Tk, T *S1, T *S2) {
+  T t1[Q], t2[Q];
+  t1[0] = T(1);
+  t2[0] = T(1);
+  if (Q > 1) {
+    t1[1] = x1;
+    t2[1] = x2;
+  }
+#pragma unroll
+  for (int k = 2; k < Q; ++k) {
+    t1[k] = T(2) * x1 * t1[k - 1] - t1[k - 2];
+    t2[k] = T(2) * x2 * t2[k - 1] - t2[k - 2];
+  }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    int col = a;
+    asm volatile("" : "+s"(col));
+    T s1 = T(0), s2 = T(0);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const T tv = Tk[k * Q + col];
+      s1 += t1[k] * tv;
+      s2 += t2[k] * tv;
+    }
+    S1[a] = (T(1) + T(2) * s1) * (T(1) / T(Q));
+    S2[a] = (T(1) + T(2) * s2) * (T(1) / T(Q));
+  }
+}
+
 // ---------------------------------------------------------------- P2M
 // Work item: one leaf of one system.
 template <class T, int K, int Q>
@@ -517,6 +549,7 @@ __global__ __launch_bounds__(64) void kf_cheb_leaf_eval(const SysDev *__restrict
   constexpr int R = Rank<K>::R;
   constexpr int QQ = Q * Q;
   __shared__ T tk[QQ];
+  __shared__ T s1s[Q * 64];  // basis S1 of each lane's target, [a][lane]
   const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
@@ -560,21 +593,25 @@ __global__ __launch_bounds__(64) void kf_cheb_leaf_eval(const SysDev *__restrict
         u2 = (yi - cy) * inv_half;
       }
       T S1[Q], S2[Q];
-      cheb_basis<T, Q>(u1, tk, S1);
-      cheb_basis<T, Q>(u2, tk, S2);
+      cheb_basis2<T, Q>(u1, u2, tk, S1, S2);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) s1s[a * 64 + lane] = S1[a];
       T u[R];
       ufac<K, T>(xi, yi, u);
+      // sum_a S1[a] sum_b S2[b] g_r[a][b]: the loop over rows a stays rolled,
+      // so each row's Q coefficients are loaded in its iteration (unrolled,
+      // all R Q^2 of them were hoisted and spilled), and S1 comes from LDS
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const cptr<T> g = Gl + r * QQ;
         T s = T(0);
-#pragma unroll
+#pragma unroll 1
         for (int a = 0; a < Q; ++a) {
-          const cptr<T> ga = in_place(g + a * Q);  // row a of the expansion, loaded here
+          const cptr<T> ga = g + a * Q;
           T sa = T(0);
 #pragma unroll
           for (int bb = 0; bb < Q; ++bb) sa += S2[bb] * ga[bb];
-          s += S1[a] * sa;
+          s += s1s[a * 64 + lane] * sa;
         }
         far += u[r] * s;
       }
