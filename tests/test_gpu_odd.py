@@ -60,3 +60,28 @@ def test_odd_solve_and_eval(k, d):
     # the weights of the odd-order systems are ill-determined (two direct
     # solvers already disagree by dw); they are compared loosely
     assert ew <= max(1e-6, 30 * dw)
+
+
+# Chebyshev order Q per axis set explicitly: every FP64 M2L tile shape
+# (QQ = 64, 100, 144, 196, 256 output rows, the last row tile partly padded
+# for QQ = 100 and 196) against the dense matvec.  The bounds follow the
+# interpolation error (measured 1e-8 at Q = 8 down to 1.3e-14 at Q = 16, k = 1),
+# with a margin of about 100; an error in
+# the tiling would show up at order one.
+_ODD_Q_TOL = {8: 1e-6, 10: 3e-8, 12: 1e-9, 14: 3e-11, 16: 1e-12}
+
+
+@pytest.mark.parametrize("k", [1, 3])
+@pytest.mark.parametrize("q", [8, 10, 12, 14, 16])
+def test_odd_matvec_every_order(k, q):
+    rng = W.rng_for(320 + k)
+    xy = W.uniform_points(rng, 3000)
+    print(f"[case] k={k} Q={q}", flush=True)
+    pl = N.Plan(dev(xy), k, leaf_size=16, expansion_order=q)
+    assert pl.order == q
+    c, rho, xi = D.normalize(xy, k)
+    v = W.rng_for(8).standard_normal(len(xy))
+    y_ref = D.matvec_dense(k, xi, v)
+    e = rel(host(pl.matvec(dev(v))), y_ref)
+    print(f"k={k} Q={q} L={pl.leaf_level}: fp64 matvec rel err {e:.2e}")
+    assert e <= _ODD_Q_TOL[q]
