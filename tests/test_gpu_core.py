@@ -116,3 +116,48 @@ def test_solve_identity_preconditioner():
     es = np.abs(s - s_ref).max() / np.abs(s_ref).max()
     print(f"interpolant at targets max rel err {es:.2e}")
     assert es <= 1e-8
+
+
+# Expansion order P set explicitly: the FP64 orders with matrix-core M2L and
+# row-segment M2M/L2L (15, 23, 27, 31) and one on the generic vector path
+# (20), against the dense matvec.  Bounds at about 100x the measured error
+# (k = 2: 9.8e-10 at P = 15 down to 1.7e-15 at P = 31); an error in a
+# kernel's tiling would show up at order one.
+_LOG_P_TOL = {15: 1e-7, 20: 1e-9, 23: 1e-10, 27: 3e-12, 31: 3e-13}
+
+
+@pytest.mark.parametrize("k", [2, 4])
+@pytest.mark.parametrize("p", [15, 20, 23, 27, 31])
+def test_matvec_every_order(k, p):
+    rng = W.rng_for(330 + k)
+    xy = W.uniform_points(rng, 12000)
+    print(f"[case] k={k} P={p}", flush=True)
+    pl = N.Plan(dev(xy), k, leaf_size=16, expansion_order=p)
+    assert pl.order == p
+    c, rho, xi = D.normalize(xy, k)
+    v = W.rng_for(9).standard_normal(len(xy))
+    y_ref = D.matvec_dense(k, xi, v)
+    e = rel(host(pl.matvec(dev(v))), y_ref)
+    print(f"k={k} P={p} L={pl.leaf_level}: fp64 matvec rel err {e:.2e}")
+    assert e <= _LOG_P_TOL[p]
+
+
+# Seven levels (L2L into level 7 by row segments) for the segment orders other
+# than the default: rows sampled from the dense matvec.
+@pytest.mark.parametrize("p", [15, 23, 31])
+def test_matvec_deep_tree_orders(p):
+    k = 2
+    rng = W.rng_for(340)
+    xy = W.uniform_points(rng, 200000)
+    print(f"[case] deep tree k={k} P={p} n={len(xy)}", flush=True)
+    pl = N.Plan(dev(xy), k, leaf_size=8, expansion_order=p)
+    assert pl.leaf_level >= 7
+    c, rho, xi = D.normalize(xy, k)
+    v = W.rng_for(10).standard_normal(len(xy))
+    y = host(pl.matvec(dev(v)))
+    rows = np.sort(W.rng_for(11).choice(len(xy), 512, replace=False))
+    y_ref = np.concatenate([D.kernel_matrix(k, xi[rows[i:i + 64]], xi) @ v
+                            for i in range(0, len(rows), 64)])
+    e = np.linalg.norm(y[rows] - y_ref) / np.linalg.norm(y_ref)
+    print(f"k={k} P={p} L={pl.leaf_level}: sampled fp64 matvec rel err {e:.2e}")
+    assert e <= _LOG_P_TOL[p]
