@@ -231,9 +231,11 @@ void fill_log_table(double *tab);
 // (|r| <= 2^-9), log1p(r) by its degree-5 Taylor polynomial (remainder
 // < |r|^6/6 < 1e-17), log x = e ln2 - log(1/c) + log1p(r), where the table
 // holds the rounded 1/c and minus the logarithm of that rounded value, so the
-// rounding of 1/c cancels.  Absolute error about 1e-16.  tab: 1/c for j < 256,
-// then -log(1/c).  x = 0 gives a finite value (m = 0, e = 0), so x log x and
-// x^2 log x are exactly 0 there.
+// rounding of 1/c cancels.  Absolute error about 1e-16.  tab: the pairs
+// (1/c, -log(1/c)) for j = 0..255, interleaved, so a lookup is one 16-byte
+// read (in LDS that halves the reads, and the bank conflicts, against two
+// separate halves).  x = 0 gives a finite value (m = 0, e = 0), so x log x
+// and x^2 log x are exactly 0 there.
 __device__ __forceinline__ double near_log_core(double x, double invc, double logc) {
   const double m = __builtin_amdgcn_frexp_mant(x);
   const int e = __builtin_amdgcn_frexp_exp(x);
@@ -249,7 +251,7 @@ template <class PT>
 __device__ __forceinline__ double near_log(double x, PT tab) {
   const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(x) >> 32);
   const int j = (int)((hi >> 12) & 255u);
-  return near_log_core(x, tab[j], tab[256 + j]);
+  return near_log_core(x, tab[2 * j], tab[2 * j + 1]);
 }
 // Host: fill the 512-entry table of near_log.
 void fill_near_log_table(double *tab);
@@ -308,8 +310,8 @@ __device__ __forceinline__ double near_range8(double xi, double yi, PXY xy2, PT 
     for (int i = 0; i < 8; ++i) {
       const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
       const int q = (int)((hi >> 12) & 255u);
-      ic[i] = tab[q];
-      lc[i] = tab[256 + q];
+      ic[i] = tab[2 * q];
+      lc[i] = tab[2 * q + 1];
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {

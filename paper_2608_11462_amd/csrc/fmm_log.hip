@@ -1132,8 +1132,8 @@ void fill_log_table(double *tab) {
 void fill_near_log_table(double *tab) {
   for (int j = 0; j < 256; ++j) {
     const double invc = 1.0 / (0.5 * (1.0 + (j + 0.5) / 256.0));
-    tab[j] = invc;
-    tab[256 + j] = (double)(-std::log((long double)invc));
+    tab[2 * j] = invc;
+    tab[2 * j + 1] = (double)(-std::log((long double)invc));
   }
 }
 
