@@ -270,15 +270,30 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
   }
   const cptr<int32_t> tstart = ro(d.tstart), tidx = ro(d.tidx);
   const cptr<double> tcoef = ro(d.tcoef), dinv = ro(d.dinv);
+  // the group's RPG rows advance together, so each lane keeps RPG
+  // independent gathers in flight (each row's sum keeps its order)
+  int b[RPG], e[RPG];
+  int len = 0;
+#pragma unroll
+  for (int k = 0; k < RPG; ++k) {
+    const bool in = i0 + k < d.n;
+    b[k] = in ? tstart[i0 + k] : 0;
+    e[k] = in ? tstart[i0 + k + 1] : 0;
+    len = max(len, e[k] - b[k]);
+  }
+  double acc[RPG];
+#pragma unroll
+  for (int k = 0; k < RPG; ++k) acc[k] = 0.0;
+  for (int o = g; o < len; o += LPR) {
+#pragma unroll
+    for (int k = 0; k < RPG; ++k)
+      if (b[k] + o < e[k]) acc[k] += tcoef[b[k] + o] * yy[tidx[b[k] + o]];
+  }
 #pragma unroll
   for (int k = 0; k < RPG; ++k) {
     const int64_t i = i0 + k;
-    const bool in = i < d.n;
-    const int b = in ? tstart[i] : 0, e = in ? tstart[i + 1] : 0;
-    double acc = 0.0;
-    for (int a = b + g; a < e; a += LPR) acc += tcoef[a] * yy[tidx[a]];
-    acc = group_sum<LPR>(acc);
-    if (in && g == wl) z[i] = dinv[i] * yy[i] + acc;
+    const double sum = group_sum<LPR>(acc[k]);
+    if (i < d.n && g == wl) z[i] = dinv[i] * yy[i] + sum;
   }
 }
 
