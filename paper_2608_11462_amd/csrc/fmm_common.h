@@ -309,9 +309,11 @@ __device__ __forceinline__ double near_range8(double xi, double yi, PXY xy2, PT 
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
-      const int q = (int)((hi >> 12) & 255u);
-      ic[i] = tab[2 * q];
-      lc[i] = tab[2 * q + 1];
+      // entry j (the top eight fraction bits) starts at byte 16 j = (hi >> 8) & 0xff0
+      const double2 e = *reinterpret_cast<const double2 *>(
+          reinterpret_cast<const char *>(tab) + ((hi >> 8) & 0xFF0u));
+      ic[i] = e.x;
+      lc[i] = e.y;
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
