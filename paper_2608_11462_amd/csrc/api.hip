@@ -399,10 +399,10 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     fill_log_table(tab.data());
     pl.logtab = dmalloc<double>(256);
     PHS_HIP(hipMemcpy(pl.logtab, tab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<double> nt(512);
+    std::vector<double> nt(kNearLogTab);
     fill_near_log_table(nt.data());
-    pl.neartab = dmalloc<double>(512);
-    PHS_HIP(hipMemcpy(pl.neartab, nt.data(), 512 * sizeof(double), hipMemcpyHostToDevice));
+    pl.neartab = dmalloc<double>(kNearLogTab);
+    PHS_HIP(hipMemcpy(pl.neartab, nt.data(), kNearLogTab * sizeof(double), hipMemcpyHostToDevice));
   }
   alloc_syswork(pl.sw, pl);
   pl.self = new Forest();

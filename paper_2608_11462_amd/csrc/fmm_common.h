@@ -240,20 +240,29 @@ __device__ __forceinline__ double near_log_core(double x, double invc, double lo
   const double m = __builtin_amdgcn_frexp_mant(x);
   const int e = __builtin_amdgcn_frexp_exp(x);
   const double r = fma(m, invc, -1.0);
-  double p = 0.2;
-  p = fma(p, r, -0.25);
+  double p;
+  if constexpr (kNearLogBits >= 9) {  // |r| <= 2^-10: degree 4, remainder < 2e-16
+    p = -0.25;
+  } else {  // |r| <= 2^-9: degree 5, remainder < 1e-17
+    p = 0.2;
+    p = fma(p, r, -0.25);
+  }
   p = fma(p, r, 1.0 / 3.0);
   p = fma(p, r, -0.5);
   p = fma(p, r, 1.0);
   return fma((double)e, 0.69314718055994530942, fma(p, r, logc));
 }
+// byte offset of the table entry of a value whose high word is hi
+__device__ __forceinline__ uint32_t near_log_offset(uint32_t hi) {
+  return (hi >> (16 - kNearLogBits)) & ((((uint32_t)1 << kNearLogBits) - 1) << 4);
+}
 template <class PT>
 __device__ __forceinline__ double near_log(double x, PT tab) {
   const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(x) >> 32);
-  const int j = (int)((hi >> 12) & 255u);
+  const int j = (int)(near_log_offset(hi) >> 4);
   return near_log_core(x, tab[2 * j], tab[2 * j + 1]);
 }
-// Host: fill the 512-entry table of near_log.
+// Host: fill the table of near_log (kNearLogTab doubles).
 void fill_near_log_table(double *tab);
 
 // sum_j phi(|x_i - y_j|) t_j over a contiguous source range, FP64.  xy2
@@ -309,9 +318,9 @@ __device__ __forceinline__ double near_range8(double xi, double yi, PXY xy2, PT 
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
-      // entry j (the top eight fraction bits) starts at byte 16 j = (hi >> 8) & 0xff0
+      // entry j (the top fraction bits) starts at byte 16 j: one shift, one mask
       const double2 e = *reinterpret_cast<const double2 *>(
-          reinterpret_cast<const char *>(tab) + ((hi >> 8) & 0xFF0u));
+          reinterpret_cast<const char *>(tab) + near_log_offset(hi));
       ic[i] = e.x;
       lc[i] = e.y;
     }

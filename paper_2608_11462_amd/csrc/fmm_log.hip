@@ -608,7 +608,7 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
                                                    int in, int out,
                                                    const double *__restrict__ logtab) {
   constexpr int R = Rank<K>::R;
-  __shared__ double ltab[512];
+  __shared__ double ltab[kNearLogTab];
   const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
   const cptr<V2<T>> Bleaf = ro((const V2<T> *)d.loc + level_base(L, P, R));
   const gptr<double> ytree = rw(d.v[out]);
   if constexpr (std::is_same<TN, double>::value && K % 2 == 0) {
-    for (int i = lane; i < 512; i += 64) ltab[i] = logtab[i];
+    for (int i = lane; i < kNearLogTab; i += 64) ltab[i] = logtab[i];
     __syncthreads();
   }
   const int b = start[leaf], e = start[leaf + 1];
@@ -1130,8 +1130,9 @@ void fill_log_table(double *tab) {
 }
 
 void fill_near_log_table(double *tab) {
-  for (int j = 0; j < 256; ++j) {
-    const double invc = 1.0 / (0.5 * (1.0 + (j + 0.5) / 256.0));
+  const int nent = 1 << kNearLogBits;
+  for (int j = 0; j < nent; ++j) {
+    const double invc = 1.0 / (0.5 * (1.0 + (j + 0.5) / nent));
     tab[2 * j] = invc;
     tab[2 * j + 1] = (double)(-std::log((long double)invc));
   }

@@ -60,6 +60,13 @@ struct ProfScope {
     PHS_HIP(hipGetLastError());                                               \
   } while (0)
 
+// Table of the near-field logarithm: 2^kNearLogBits centred subintervals of
+// the mantissa, each (1/c, -log(1/c)); kNearLogTab doubles in all.  Eight
+// bits (4 KB, degree-5 polynomial) measured faster than nine (8 KB, degree 4:
+// more LDS bank conflicts) and seven (2 KB, degree 6: one more FMA a pair).
+constexpr int kNearLogBits = 8;
+constexpr int kNearLogTab = 2 << kNearLogBits;
+
 // ------------------------------------------------------------------ address spaces
 // Kernels reach most arrays through per-system descriptors, i.e. as generic
 // pointers read from memory.  Read-only inputs are viewed through the
@@ -242,7 +249,7 @@ struct Plan {
   float *ux = nullptr, *uy = nullptr;  // FP32 offsets from the leaf centre
   double2 *xy2 = nullptr;              // packed (x, y), source records of the near field
   double *logtab = nullptr;            // 256-entry table of the 1-ulp logarithm (Matern)
-  double *neartab = nullptr;           // 512-entry table of the near-field logarithm
+  double *neartab = nullptr;           // table of the near-field logarithm (kNearLogTab)
 
   // polynomial block
   double *Q = nullptr;  // n x S column-major, tree order, orthonormal columns
