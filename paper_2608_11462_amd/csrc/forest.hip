@@ -166,6 +166,33 @@ __global__ void kf_pcg_wr(const SysDev *__restrict__ sys, const BlkRef *__restri
   if (threadIdx.x == 0) d.red[br.blk] = s;
 }
 
+// v = g (v - Q c), c = sc[SC_PROJ ..], g = sign_k if use_sign else 1, with the
+// partial sums of w.v over the dot blocks (finished by kf_dot_final): the
+// projection, the sign and the next dot product in one pass, the same
+// arithmetic and summation order as kf_sub_Qc, kf_scale_sign and kf_dot.
+__global__ void kf_sub_Qc_dot(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                              const int32_t *__restrict__ mask, int slot, int use_sign, int w) {
+  __shared__ double sh[kBlock / 64];
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  const int nb = d.nbdot;
+  const cptr<double> Q = ro(d.Q), ww = ro(d.v[w]);
+  const gptr<double> v = rw(d.v[slot]);
+  const double g = use_sign ? (double)d.sign : 1.0;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)br.blk * kBlock + threadIdx.x; i < d.n; i += (int64_t)nb * kBlock) {
+    double sq = 0.0;
+    for (int j = 0; j < d.S; ++j) sq += Q[(int64_t)j * d.n + i] * d.sc[SC_PROJ + j];
+    double vi = v[i] - sq;
+    if (use_sign) vi = g * vi;
+    v[i] = vi;
+    acc += ww[i] * vi;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) d.red[br.blk] = s;
+}
+
 __global__ void kf_sc_copy(const SysDev *__restrict__ sys, const int32_t *__restrict__ mask,
                            int nsys, int dst, int src) {
   const int sy = blockIdx.x * blockDim.x + threadIdx.x;
@@ -514,6 +541,16 @@ void f_project(Forest &F, const int32_t *mask, int slot, hipStream_t s) {
              kf_sub_Qc<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, slot));
 }
 
+void f_project_dot(Forest &F, const int32_t *mask, int slot, bool sign, int w, int out,
+                   hipStream_t s) {
+  dot_launch(F, mask, 1, 0, slot, SC_PROJ, s);
+  PHS_LAUNCH("project_dot", s,
+             kf_sub_Qc_dot<<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, slot,
+                                                            sign ? 1 : 0, w));
+  PHS_LAUNCH("dot_final", s,
+             kf_dot_final<<<(unsigned)F.nsys, kBlock, 0, s>>>(F.dsys, mask, 0, out));
+}
+
 void f_pcg_wr(Forest &F, const int32_t *mask, hipStream_t s) {
   PHS_LAUNCH("pcg_wr", s, kf_pcg_wr<<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask));
   PHS_LAUNCH("dot_final", s,
@@ -548,6 +585,12 @@ void f_precond_apply(Forest &F, const int32_t *mask, int r, int z, int tmp, hipS
 void f_precond(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s) {
   f_precond_apply(F, mask, r, z, tmp, s);
   f_project(F, mask, z, s);
+}
+
+void f_precond_dot(Forest &F, const int32_t *mask, int r, int z, int tmp, int out,
+                   hipStream_t s) {
+  f_precond_apply(F, mask, r, z, tmp, s);
+  f_project_dot(F, mask, z, false, r, out, s);
 }
 
 void f_gather_user(Forest &F, int sys, const double *src_user, int slot, hipStream_t s) {

@@ -344,6 +344,9 @@ void f_axpby(Forest &F, const int32_t *mask, int y, int x, double a, double b, h
 void f_scale_sign(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s);
 void f_dot(Forest &F, const int32_t *mask, int a, int b, int out, hipStream_t s);
 void f_project(Forest &F, const int32_t *mask, int slot, hipStream_t s);
+// v[slot] = g Pi v[slot] (g = sign_k if sign, else 1) and sc[out] = v[w].v[slot]
+void f_project_dot(Forest &F, const int32_t *mask, int slot, bool sign, int w, int out,
+                   hipStream_t s);
 void f_qt(Forest &F, const int32_t *mask, int slot, int out, hipStream_t s);
 void f_pcg_wr(Forest &F, const int32_t *mask, hipStream_t s);
 void f_pcg_p(Forest &F, const int32_t *mask, hipStream_t s);
@@ -351,6 +354,9 @@ void f_sc_copy(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s);
 void f_read_scalars(Forest &F, int off, int cnt, hipStream_t s);  // -> F.hgsc[sys*8+i]
 // z = Pi U~ U~^T r (f_precond) or U~ U~^T r (f_precond_apply)
 void f_precond(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s);
+// f_precond, then sc[out] = r.z
+void f_precond_dot(Forest &F, const int32_t *mask, int r, int z, int tmp, int out,
+                   hipStream_t s);
 void f_precond_apply(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s);
 void f_gather_user(Forest &F, int sys, const double *src_user, int slot, hipStream_t s);
 void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t s);

@@ -125,8 +125,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
     set_mask(F, MK_START, jr, [](const JobRun &r) { return r.state == J_START; }, any, s);
     if (any) {
       f_fill(F, F.mask[MK_START], V_DW, 0.0, s);
-      f_precond(F, F.mask[MK_START], V_R, V_Z, V_TMP, s);
-      f_dot(F, F.mask[MK_START], V_R, V_Z, SC_RHO, s);
+      f_precond_dot(F, F.mask[MK_START], V_R, V_Z, V_TMP, SC_RHO, s);
       f_copy(F, F.mask[MK_START], V_P, V_Z, s);
       for (auto *rp_ : jr) if (auto &r = *rp_; true)
         if (r.state == J_START) r.state = J_PCG;
@@ -149,9 +148,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       if (a64) f_matvec(F, F.mask[MK_P64], V_P, V_Q, PHS_FP64, s);
       if (a32) f_matvec(F, F.mask[MK_P32], V_P, V_Q, PHS_MIXED, s);
       if (an32) f_matvec(F, F.mask[MK_PN32], V_P, V_Q, PHS_NEAR32, s);
-      f_project(F, F.mask[MK_PCG], V_Q, s);
-      f_scale_sign(F, F.mask[MK_PCG], V_Q, V_Q, s);
-      f_dot(F, F.mask[MK_PCG], V_P, V_Q, SC_PQ, s);
+      f_project_dot(F, F.mask[MK_PCG], V_Q, true, V_P, SC_PQ, s);
       const int32_t *upd_mask = F.mask[MK_PCG];
       if (check_every == 1 && (a32 || an32)) {
         // curvature check before the update so a breakdown step of an inexact
@@ -195,8 +192,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       // z = precond(r), rho_new = r.z, p = z + (rho_new / rho) p, rho = rho_new
       set_mask(F, MK_CONT, jr, [](const JobRun &r) { return r.state == J_PCG; }, any, s);
       if (any) {
-        f_precond(F, F.mask[MK_CONT], V_R, V_Z, V_TMP, s);
-        f_dot(F, F.mask[MK_CONT], V_R, V_Z, SC_RHO_NEW, s);
+        f_precond_dot(F, F.mask[MK_CONT], V_R, V_Z, V_TMP, SC_RHO_NEW, s);
         f_pcg_p(F, F.mask[MK_CONT], s);
         f_sc_copy(F, F.mask[MK_CONT], SC_RHO, SC_RHO_NEW, s);
       }
