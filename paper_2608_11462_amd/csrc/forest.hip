@@ -418,7 +418,6 @@ Forest::~Forest() {
     }
     dfree(mask[i]);
   }
-  dfree(gsc);
   if (hpin) (void)hipHostFree(hpin);
   dfree(vec.d);
   dfree(dot.d);
@@ -466,7 +465,6 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
     PHS_HIP(hipEventRecord(F.mask_ev[i], s));
     F.mask_pending[i] = true;
   }
-  F.gsc = dmalloc<double>((size_t)F.nsys * 8);
   F.vec = upload_tab(F, std::move(hv), s);
   F.dot = upload_tab(F, std::move(hd), s);
   F.pc = upload_tab(F, std::move(hp), s);
@@ -566,12 +564,13 @@ void f_sc_copy(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s) 
              kf_sc_copy<<<(F.nsys + 63) / 64, 64, 0, s>>>(F.dsys, mask, F.nsys, dst, src));
 }
 
+// The gather writes straight into the pinned host block (device-accessible),
+// so the readback needs no copy: the kernel's completion and the stream
+// synchronisation make the values visible to the host.
 void f_read_scalars(Forest &F, int off, int cnt, hipStream_t s) {
   const int tot = F.nsys * cnt;
   PHS_LAUNCH("read_sc", s,
-             kf_read_sc<<<(tot + 255) / 256, 256, 0, s>>>(F.dsys, F.nsys, off, cnt, F.gsc));
-  PHS_HIP(hipMemcpyAsync(F.hgsc, F.gsc, (size_t)F.nsys * 8 * sizeof(double),
-                         hipMemcpyDeviceToHost, s));
+             kf_read_sc<<<(tot + 255) / 256, 256, 0, s>>>(F.dsys, F.nsys, off, cnt, F.hgsc));
   PHS_HIP(hipStreamSynchronize(s));
 }
 

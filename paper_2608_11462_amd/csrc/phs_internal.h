@@ -308,7 +308,7 @@ struct Forest {
   int32_t *hmask[kMasks] = {};   // pinned staging of the last upload
   hipEvent_t mask_ev[kMasks] = {};
   bool mask_pending[kMasks] = {};
-  double *gsc = nullptr, *hgsc = nullptr;  // packed scalar readback (nsys x 8)
+  double *hgsc = nullptr;  // packed scalar readback (nsys x 8), pinned, written by the GPU
   void *hpin = nullptr;                    // one pinned block: host masks + hgsc
   std::vector<std::vector<BlkRef>> hcopies;  // host sources of the table uploads
   Tab vec, dot, pc;                     // element blocks, dot blocks, 8-row blocks
