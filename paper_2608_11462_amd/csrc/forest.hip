@@ -127,9 +127,10 @@ __global__ void kf_dot(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   }
 }
 
-// One block per system: sc[out + t] = sum of the partials of dot t.
+// One block per system: sc[out + t] = sum of the partials of dot t, which sit
+// at slot base + t of the partial buffer.
 __global__ void kf_dot_final(const SysDev *__restrict__ sys, const int32_t *__restrict__ mask,
-                             int mode, int out) {
+                             int mode, int out, int base = 0) {
   __shared__ double sh[kBlock / 64];
   const int sy = blockIdx.x;
   if (!mask[sy]) return;
@@ -138,7 +139,7 @@ __global__ void kf_dot_final(const SysDev *__restrict__ sys, const int32_t *__re
   const int nb = d.nbdot;
   for (int t = 0; t < nd; ++t) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) v += d.red[t * nb + b];
+    for (int b = threadIdx.x; b < nb; b += kBlock) v += d.red[(base + t) * nb + b];
     const double s = block_sum(v, sh);
     if (threadIdx.x == 0) d.sc[out + t] = s;
   }
@@ -166,31 +167,45 @@ __global__ void kf_pcg_wr(const SysDev *__restrict__ sys, const BlkRef *__restri
   if (threadIdx.x == 0) d.red[br.blk] = s;
 }
 
-// v = g (v - Q c), c = sc[SC_PROJ ..], g = sign_k if use_sign else 1, with the
-// partial sums of w.v over the dot blocks (finished by kf_dot_final): the
-// projection, the sign and the next dot product in one pass, the same
-// arithmetic and summation order as kf_sub_Qc, kf_scale_sign and kf_dot.
+// Slot of the partial buffer for dots taken while slots 0.. hold another
+// reduction's partials (S <= 21 projection dots).
+constexpr int kDotSlot = 31;
+
+// v = g (v - Q c), c = Q^T v from the partials of kf_dot (mode 1) at slots
+// 0..S-1, g = sign_k if use_sign else 1, with the partial sums of w.v at slot
+// kDotSlot (finished by kf_dot_final): the projection, the sign and the next
+// dot product in one pass.  Each block finishes c itself in the order of
+// kf_dot_final, and the arithmetic and summation order are those of kf_sub_Qc,
+// kf_scale_sign and kf_dot, so the results are bitwise theirs.
 __global__ void kf_sub_Qc_dot(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
                               const int32_t *__restrict__ mask, int slot, int use_sign, int w) {
   __shared__ double sh[kBlock / 64];
+  __shared__ double cq[kDotSlot];
   const BlkRef br = tab[blockIdx.x];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
   const int nb = d.nbdot;
+  for (int t = 0; t < d.S; ++t) {
+    double c = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) c += d.red[t * nb + b];
+    const double cs = block_sum(c, sh);
+    if (threadIdx.x == 0) cq[t] = cs;
+  }
+  __syncthreads();
   const cptr<double> Q = ro(d.Q), ww = ro(d.v[w]);
   const gptr<double> v = rw(d.v[slot]);
   const double g = use_sign ? (double)d.sign : 1.0;
   double acc = 0.0;
   for (int64_t i = (int64_t)br.blk * kBlock + threadIdx.x; i < d.n; i += (int64_t)nb * kBlock) {
     double sq = 0.0;
-    for (int j = 0; j < d.S; ++j) sq += Q[(int64_t)j * d.n + i] * d.sc[SC_PROJ + j];
+    for (int j = 0; j < d.S; ++j) sq += Q[(int64_t)j * d.n + i] * cq[j];
     double vi = v[i] - sq;
     if (use_sign) vi = g * vi;
     v[i] = vi;
     acc += ww[i] * vi;
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) d.red[br.blk] = s;
+  if (threadIdx.x == 0) d.red[kDotSlot * nb + br.blk] = s;
 }
 
 __global__ void kf_sc_copy(const SysDev *__restrict__ sys, const int32_t *__restrict__ mask,
@@ -438,6 +453,8 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
     const Plan &pl = *plans[i];
     F.hsys[i] = make_sysdev(pl, *work[i]);
     F.maxS = std::max(F.maxS, pl.S);
+    if (pl.S >= kDotSlot)  // the projection's partials must not reach kDotSlot
+      throw Error{PHS_ERR_INVALID_ARGUMENT, "polynomial space too large for the PCG reductions"};
     if (pl.core_log) F.maxL_log = std::max(F.maxL_log, pl.tree.L);
     else F.maxL_dist = std::max(F.maxL_dist, pl.tree.L);
     const int64_t nv = (pl.n + kBlock - 1) / kBlock;
@@ -512,6 +529,17 @@ void f_scale_sign(Forest &F, const int32_t *mask, int dst, int src, hipStream_t 
              kf_scale_sign<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, dst, src));
 }
 
+static void dot_partials(Forest &F, const int32_t *mask, int mode, int a, int b,
+                         hipStream_t s) {
+  const int nd = mode == 0 ? 1 : F.maxS;
+  if (nd <= 1)
+    PHS_LAUNCH("dot", s, kf_dot<1><<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, mode, a, b));
+  else if (nd <= 8)
+    PHS_LAUNCH("dot", s, kf_dot<8><<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, mode, a, b));
+  else
+    PHS_LAUNCH("dot", s, kf_dot<32><<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, mode, a, b));
+}
+
 static void dot_launch(Forest &F, const int32_t *mask, int mode, int a, int b, int out,
                        hipStream_t s) {
   const int nd = mode == 0 ? 1 : F.maxS;
@@ -541,12 +569,12 @@ void f_project(Forest &F, const int32_t *mask, int slot, hipStream_t s) {
 
 void f_project_dot(Forest &F, const int32_t *mask, int slot, bool sign, int w, int out,
                    hipStream_t s) {
-  dot_launch(F, mask, 1, 0, slot, SC_PROJ, s);
+  dot_partials(F, mask, 1, 0, slot, s);  // Q^T v, finished inside kf_sub_Qc_dot
   PHS_LAUNCH("project_dot", s,
              kf_sub_Qc_dot<<<F_GRID(F.dot), kBlock, 0, s>>>(F.dsys, F.dot.d, mask, slot,
                                                             sign ? 1 : 0, w));
   PHS_LAUNCH("dot_final", s,
-             kf_dot_final<<<(unsigned)F.nsys, kBlock, 0, s>>>(F.dsys, mask, 0, out));
+             kf_dot_final<<<(unsigned)F.nsys, kBlock, 0, s>>>(F.dsys, mask, 0, out, kDotSlot));
 }
 
 void f_pcg_wr(Forest &F, const int32_t *mask, hipStream_t s) {
