@@ -89,67 +89,126 @@ __global__ void k_leaf_keys(const double *__restrict__ xy, int64_t n, double cx,
 // ---------------------------------------------------------------- radix sort
 constexpr int kRadixBits = 8;
 constexpr int kBuckets = 1 << kRadixBits;
-constexpr int kItems = 8;
+constexpr int kItems = 16;
 constexpr int kTile = kBlock * kItems;
 
+constexpr int kWaves = kBlock / 64;
+constexpr int kWaveItems = kTile / kWaves;  // each wave takes a contiguous chunk
+
+// Lanes of the wave holding the same digit as this lane (8 ballots, one per
+// digit bit), restricted to the valid lanes.
+__device__ __forceinline__ uint64_t digit_peers(int digit, bool valid) {
+  uint64_t mask = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (digit >> b) & 1;
+    const uint64_t bb = __ballot(valid && bit);
+    mask &= bit ? bb : ~bb;
+  }
+  return mask;
+}
+
+// Digit histogram of each tile: hist[digit * nblocks + tile].
 template <class K>
 __global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift,
                              int nblocks, int32_t *__restrict__ hist) {
   __shared__ int cnt[kBuckets];
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
   for (int it = 0; it < kItems; ++it) {
-    int64_t i = base + it * kBlock + threadIdx.x;
+    const int64_t i = base + it * kBlock + threadIdx.x;
     if (i < n) atomicAdd(&cnt[(int)((keys[i] >> shift) & (kBuckets - 1))], 1);
   }
   __syncthreads();
   hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Stable scatter of one tile by the digit at `shift`.  The tile is first
+// counting-sorted in LDS (wave w holds keys [w * kWaveItems, (w+1) * kWaveItems)
+// of the tile, so a key's rank among equal digits is the count in earlier
+// waves plus the count earlier in its own wave), then written out in that
+// order, so neighbouring lanes store neighbouring addresses of a bucket.
+// offs[digit * nblocks + tile] is the exclusive scan of the histograms.
 template <class K>
-__global__ void k_radix_scatter(const K *__restrict__ keys,
-                                const int32_t *__restrict__ vals, int64_t n,
-                                int shift, int nblocks,
-                                const int32_t *__restrict__ offs,
-                                K *__restrict__ okeys,
-                                int32_t *__restrict__ ovals) {
-  __shared__ int run[kBuckets];
-  __shared__ int wcnt[kBlock / 64][kBuckets];
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const K *__restrict__ keys, const int32_t *__restrict__ vals, int64_t n, int shift,
+    int nblocks, const int32_t *__restrict__ offs, K *__restrict__ okeys,
+    int32_t *__restrict__ ovals) {
+  __shared__ int wcnt[kWaves][kBuckets];  // running counts, then wave offsets
+  __shared__ int lstart[kBuckets];        // first tile slot of each digit
+  __shared__ int goff[kBuckets];          // output index of that slot
+  __shared__ int wsum[kWaves];
+  __shared__ K skey[kTile];
+  __shared__ int32_t sval[kTile];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  run[tid] = offs[tid * nblocks + blockIdx.x];
-  for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
+  for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+  goff[tid] = offs[tid * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  const int64_t base = tile0 + wave * kWaveItems;
+  K key[kItems];
+  int32_t val[kItems];
+  int rank[kItems];
+#pragma unroll
   for (int it = 0; it < kItems; ++it) {
-    int64_t i = base + it * kBlock + tid;
-    bool valid = i < n;
-    K key = valid ? keys[i] : K(0);
-    int digit = (int)((key >> shift) & (kBuckets - 1));
-    uint64_t mask = __ballot(valid);
-    for (int b = 0; b < kRadixBits; ++b) {
-      bool bit = (digit >> b) & 1;
-      uint64_t bb = __ballot(valid && bit);
-      mask &= bit ? bb : ~bb;
+    const int64_t i = base + it * 64 + lane;
+    const bool valid = i < n;
+    key[it] = valid ? keys[i] : K(0);
+    val[it] = valid ? vals[i] : 0;
+  }
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const bool valid = base + it * 64 + lane < n;
+    const int digit = (int)((key[it] >> shift) & (kBuckets - 1));
+    const uint64_t peers = digit_peers(digit, valid);
+    const int before = valid ? wcnt[wave][digit] : 0;
+    rank[it] = before + __popcll(peers & lt_mask);
+    // LDS operations of one wave complete in order: every lane has read the
+    // count before its leader stores the new one.
+    if (valid && (peers & lt_mask) == 0) wcnt[wave][digit] = before + __popcll(peers);
+  }
+  __syncthreads();
+  int tot = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    const int c = wcnt[w][tid];
+    wcnt[w][tid] = tot;
+    tot += c;
+  }
+  int incl = tot;  // inclusive scan over digits: within the wave, then across waves
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int add = 0;
+  for (int w = 0; w < wave; ++w) add += wsum[w];
+  lstart[tid] = add + incl - tot;
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    if (base + it * 64 + lane < n) {
+      const int digit = (int)((key[it] >> shift) & (kBuckets - 1));
+      const int pos = lstart[digit] + wcnt[wave][digit] + rank[it];
+      skey[pos] = key[it];
+      sval[pos] = val[it];
     }
-    int rank = __popcll(mask & lt_mask);
-    if (valid && rank == 0) wcnt[wave][digit] = __popcll(mask);
-    __syncthreads();
-    if (valid) {
-      int pos = run[digit] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][digit];
-      okeys[pos] = key;
-      ovals[pos] = vals[i];
+  }
+  __syncthreads();
+  const int64_t rem = n - tile0;
+  const int cnt = rem < kTile ? (int)rem : kTile;
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int p = it * kBlock + tid;
+    if (p < cnt) {
+      const K k = skey[p];
+      const int digit = (int)((k >> shift) & (kBuckets - 1));
+      const int64_t o = (int64_t)goff[digit] + (p - lstart[digit]);
+      okeys[o] = k;
+      ovals[o] = sval[p];
     }
-    __syncthreads();
-    int tot = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-      tot += wcnt[w][tid];
-      wcnt[w][tid] = 0;
-    }
-    run[tid] += tot;
-    __syncthreads();
   }
 }
 
