@@ -89,22 +89,6 @@ __device__ __forceinline__ T quad_sum(T v) {
   return v;
 }
 
-// z^e for 0 <= e <= 31 as (z^4)^(e/4) z^(e mod 4): five squarings/products
-// for z^2, z^3, z^4, z^8, z^16, then at most three products chosen by the bits
-// of e (lanes with different e take the same instructions).
-template <class T>
-__device__ __forceinline__ C2<T> cpow32(C2<T> z, int e) {
-  const C2<T> one = {T(1), T(0)};
-  const C2<T> z2 = cmul(z, z), z3 = cmul(z2, z), z4 = cmul(z2, z2);
-  const C2<T> z8 = cmul(z4, z4), z16 = cmul(z8, z8);
-  const int lo = e & 3;
-  C2<T> r = lo == 0 ? one : (lo == 1 ? z : (lo == 2 ? z2 : z3));
-  if (e & 4) r = cmul(r, z4);
-  if (e & 8) r = cmul(r, z8);
-  if (e & 16) r = cmul(r, z16);
-  return r;
-}
-
 // Number of core densities for order K.
 template <int K> struct Rank;
 template <> struct Rank<1> { static constexpr int R = 1; };

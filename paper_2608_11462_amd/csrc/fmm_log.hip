@@ -34,11 +34,36 @@ __host__ __device__ inline int64_t level_base(int l, int P, int nd) {
 
 // ------------------------------------------------------------------ P2M
 // Work item: 4 gpw leaves of one system, gpw = 64/(P+1) leaves per wavefront
-// (lane = coefficient), four wavefronts per block.
+// (lane = coefficient), four wavefronts per block.  The points of the wave's
+// leaves pass in chunks of ch per leaf.  For each point one lane stores in LDS
+// its powers z^0..z^3 and z^0, z^4, ..., z^{4(A-1)}, A = P/4 + 1, and its
+// density terms v_r t; the lane of coefficient k then forms z^k as
+// z^{4 floor(k/4)} z^{k mod 4}, one complex product per point.
+constexpr int kP2MPadPw = 8;   // pair slots between two leaves' power tables
+constexpr int kP2MPadQ = 16;   // scalars between two leaves' density terms
+constexpr int kP2MLdsBlock = 32768;
+
+template <class T>
+__host__ __device__ inline int p2m_wave_bytes(int P, int R, int gpw, int ch) {
+  const int ns = 4 + (P >> 2) + 1;
+  const int b = gpw * ((ch * ns + kP2MPadPw) * 2 + ch * R + kP2MPadQ) * (int)sizeof(T);
+  return (b + 15) & ~15;
+}
+
+// Points per leaf and chunk: the largest of 64/gpw, 32/gpw, ... whose tables
+// for four wavefronts fit in kP2MLdsBlock bytes.
+template <class T>
+int p2m_chunk(int P, int R, int gpw) {
+  int ch = 64 / gpw;
+  while (ch > 4 && 4 * p2m_wave_bytes<T>(P, R, gpw, ch) > kP2MLdsBlock) ch >>= 1;
+  return ch;
+}
+
 template <class T, int K>
 __global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
                                               const BlkRef *__restrict__ tab,
-                                              const int32_t *__restrict__ mask, int P, int in) {
+                                              const int32_t *__restrict__ mask, int P, int in,
+                                              int ch) {
   constexpr int R = Rank<K>::R;
   const BlkRef br = tab[blockIdx.x];
   if (!mask[br.sys]) return;
@@ -73,56 +98,61 @@ __global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
       maxcnt = max(maxcnt, eg[g] - bg[g]);
     }
   const int b = active ? bg[sub] : 0, e = active ? eg[sub] : 0;
-  const int ix = leaf % G, iy = leaf / G;
-  const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
   T are[R], aim[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) are[r] = aim[r] = T(0);
-  // The points pass through LDS in chunks of CH per leaf, one coalesced load
-  // per chunk instead of a memory round trip per point.  Each wave has its own
-  // LDS slots, and a wavefront's LDS accesses complete in program order, so no
-  // barrier is needed between a chunk's stores and the loads of it.
-  constexpr int SLOTS = 256;
-  __shared__ double sx[4][SLOTS], sy[4][SLOTS], st[4][SLOTS];
-  __shared__ float sux[4][std::is_same<T, float>::value ? SLOTS : 1];
-  __shared__ float suy[4][std::is_same<T, float>::value ? SLOTS : 1];
-  const int CH = SLOTS / gpw;
-  for (int off = 0; off < maxcnt; off += CH) {
-    for (int i = lane; i < gpw * CH; i += 64) {
-      const int g = i / CH;
-      const int j = bg[g] + off + (i - g * CH);
+  extern __shared__ __align__(16) unsigned char p2m_lds[];
+  const int na = (P >> 2) + 1, ns = 4 + na;
+  const int pw_leaf = ch * ns + kP2MPadPw, q_leaf = ch * R + kP2MPadQ;
+  unsigned char *wb = p2m_lds + wave * p2m_wave_bytes<T>(P, R, gpw, ch);
+  V2<T> *const spw = (V2<T> *)wb;
+  T *const sq = (T *)(wb + (size_t)gpw * pw_leaf * sizeof(V2<T>));
+  const V2<T> *const pa = spw + sub * pw_leaf + 4 + (kk >> 2);
+  const V2<T> *const pb = spw + sub * pw_leaf + (kk & 3);
+  const T *const qs = sq + sub * q_leaf;
+  const C2<T> one = {T(1), T(0)};
+  for (int off = 0; off < maxcnt; off += ch) {
+    if (lane < gpw * ch) {
+      const int g = lane / ch, jl = lane - g * ch;
+      const int j = bg[g] + off + jl;
       if (j < eg[g]) {
-        sx[wave][i] = x[j];
-        sy[wave][i] = y[j];
-        st[wave][i] = t[j];
+        const int lf = leaf0 + g;
+        const double xj = x[j], yj = y[j];
+        C2<T> z;
         if constexpr (std::is_same<T, float>::value) {
-          sux[wave][i] = ux[j];
-          suy[wave][i] = uy[j];
+          z = {ux[j] * (float)invw, uy[j] * (float)invw};
+        } else {
+          const double cxg = -h + (lf % G + 0.5) * w, cyg = -h + (lf / G + 0.5) * w;
+          z = {(xj - cxg) * invw, (yj - cyg) * invw};
         }
+        V2<T> *const pp = spw + g * pw_leaf + jl * ns;
+        const C2<T> z2 = cmul(z, z), z4 = cmul(z2, z2);
+        st2<T>(pp + 0, one);
+        st2<T>(pp + 1, z);
+        st2<T>(pp + 2, z2);
+        st2<T>(pp + 3, cmul(z2, z));
+        C2<T> za = one;
+        st2<T>(pp + 4, za);
+        for (int a = 1; a < na; ++a) {
+          za = cmul(za, z4);
+          st2<T>(pp + 4 + a, za);
+        }
+        T v[R];
+        vfac<K, T>(xj, yj, v);
+        const T tj = (T)t[j];
+        T *const qq = sq + g * q_leaf + jl * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) qq[r] = v[r] * tj;
       }
     }
+    // a wavefront's LDS accesses complete in program order
     __builtin_amdgcn_wave_barrier();
-    const int cnt = active ? min(CH, e - b - off) : 0;
+    const int cnt = active ? min(ch, e - b - off) : 0;
     for (int jj = 0; jj < cnt; ++jj) {
-      const int i = sub * CH + jj;
-      const double xj = sx[wave][i], yj = sy[wave][i];
-      C2<T> z;
-      if constexpr (std::is_same<T, float>::value) {
-        z = {sux[wave][i] * (float)invw, suy[wave][i] * (float)invw};
-      } else {
-        z = {(xj - cx) * invw, (yj - cy) * invw};
-      }
-      C2<T> zk;
-      if (P <= 31)
-        zk = cpow32(z, kk);
-      else
-        zk = cpow_small(z, kk);
-      T v[R];
-      vfac<K, T>(xj, yj, v);
-      const T tj = (T)st[wave][i];
+      const C2<T> zk = cmul(ld2<T>(pa + jj * ns), ld2<T>(pb + jj * ns));
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        T q = v[r] * tj;
+        const T q = qs[jj * R + r];
         are[r] += q * zk.re;
         aim[r] += q * zk.im;
       }
@@ -852,11 +882,21 @@ void far_field(Forest &F, const int32_t *mask, int in, int P, const LogTables &l
   {
     const int gpw = p2m_leaves_per_wave(P);
     const Tab t2 = forest_tab(F, tab_key(2, 2, gpw, 0), s);
-    if (t2.count)
-      PHS_LAUNCH("p2m", s, kf_p2m<T, 2><<<(unsigned)t2.count, 256, 0, s>>>(F.dsys, t2.d, mask, P, in));
+    if (t2.count) {
+      const int ch = p2m_chunk<T>(P, Rank<2>::R, gpw);
+      PHS_LAUNCH("p2m", s,
+                 kf_p2m<T, 2><<<(unsigned)t2.count, 256,
+                                4 * p2m_wave_bytes<T>(P, Rank<2>::R, gpw, ch), s>>>(
+                     F.dsys, t2.d, mask, P, in, ch));
+    }
     const Tab t4 = forest_tab(F, tab_key(2, 4, gpw, 0), s);
-    if (t4.count)
-      PHS_LAUNCH("p2m", s, kf_p2m<T, 4><<<(unsigned)t4.count, 256, 0, s>>>(F.dsys, t4.d, mask, P, in));
+    if (t4.count) {
+      const int ch = p2m_chunk<T>(P, Rank<4>::R, gpw);
+      PHS_LAUNCH("p2m", s,
+                 kf_p2m<T, 4><<<(unsigned)t4.count, 256,
+                                4 * p2m_wave_bytes<T>(P, Rank<4>::R, gpw, ch), s>>>(
+                     F.dsys, t4.d, mask, P, in, ch));
+    }
   }
   // upward pass
   // FP64 with the standard orders: row segments through LDS on the deep levels
