@@ -49,17 +49,30 @@ __global__ void k_minmax_partial(const double *__restrict__ xy, int64_t n,
   if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = s[threadIdx.x][0];
 }
 
+// min and max are exact in any order, so the tree over threads gives the
+// result of a sequential pass.
 __global__ void k_minmax_final(const double *__restrict__ part, int nb,
                                double *__restrict__ out) {
-  if (threadIdx.x != 0) return;
+  __shared__ double s[4][kBlock];
   double r[4] = {INFINITY, INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
     r[0] = fmin(r[0], part[4 * b + 0]);
     r[1] = fmin(r[1], part[4 * b + 1]);
     r[2] = fmax(r[2], part[4 * b + 2]);
     r[3] = fmax(r[3], part[4 * b + 3]);
   }
-  for (int t = 0; t < 4; ++t) out[t] = r[t];
+  for (int t = 0; t < 4; ++t) s[t][threadIdx.x] = r[t];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+      s[1][threadIdx.x] = fmin(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+      s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+      s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
 // Quantise one normalised coordinate to a grid cell index in [0, G).
@@ -369,7 +382,7 @@ void minmax_xy(const double *xy, int64_t n, double *out4, double *partials,
                int nblocks, hipStream_t s) {
   PHS_LAUNCH("minmax", s,
              k_minmax_partial<<<nblocks, kBlock, 0, s>>>(xy, n, partials));
-  PHS_LAUNCH("minmax", s, k_minmax_final<<<1, 64, 0, s>>>(partials, nblocks, out4));
+  PHS_LAUNCH("minmax", s, k_minmax_final<<<1, kBlock, 0, s>>>(partials, nblocks, out4));
 }
 
 void leaf_keys(const double *xy, int64_t n, double cx, double cy, double rho,
