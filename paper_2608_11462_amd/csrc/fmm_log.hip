@@ -118,24 +118,26 @@ __global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
       if (j < eg[g]) {
         const int lf = leaf0 + g;
         const double xj = x[j], yj = y[j];
-        C2<T> z;
+        // the powers are formed in FP64 and rounded once to T when stored
+        C2<double> z;
         if constexpr (std::is_same<T, float>::value) {
-          z = {ux[j] * (float)invw, uy[j] * (float)invw};
+          z = {(double)(ux[j] * (float)invw), (double)(uy[j] * (float)invw)};
         } else {
           const double cxg = -h + (lf % G + 0.5) * w, cyg = -h + (lf / G + 0.5) * w;
           z = {(xj - cxg) * invw, (yj - cyg) * invw};
         }
         V2<T> *const pp = spw + g * pw_leaf + jl * ns;
-        const C2<T> z2 = cmul(z, z), z4 = cmul(z2, z2);
+        const auto put = [&](int slot, C2<double> c) { st2<T>(pp + slot, {(T)c.re, (T)c.im}); };
+        const C2<double> z2 = cmul(z, z), z4 = cmul(z2, z2);
         st2<T>(pp + 0, one);
-        st2<T>(pp + 1, z);
-        st2<T>(pp + 2, z2);
-        st2<T>(pp + 3, cmul(z2, z));
-        C2<T> za = one;
-        st2<T>(pp + 4, za);
+        put(1, z);
+        put(2, z2);
+        put(3, cmul(z2, z));
+        C2<double> za = {1.0, 0.0};
+        st2<T>(pp + 4, one);
         for (int a = 1; a < na; ++a) {
           za = cmul(za, z4);
-          st2<T>(pp + 4 + a, za);
+          put(4 + a, za);
         }
         T v[R];
         vfac<K, T>(xj, yj, v);
