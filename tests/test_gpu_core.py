@@ -123,11 +123,13 @@ def test_solve_identity_preconditioner():
 # (20), against the dense matvec.  Bounds at about 100x the measured error
 # (k = 2: 9.8e-10 at P = 15 down to 1.7e-15 at P = 31); an error in a
 # kernel's tiling would show up at order one.
-_LOG_P_TOL = {15: 1e-7, 20: 1e-9, 23: 1e-10, 27: 3e-12, 31: 3e-13}
+_LOG_P_TOL = {15: 1e-7, 20: 1e-9, 23: 1e-10, 27: 3e-12, 31: 3e-13, 40: 1e-14, 63: 1e-14}
 
 
+# Orders above 31 take one leaf per wavefront in P2M (smaller point chunks in
+# LDS) and the vector-unit M2M/M2L/L2L.
 @pytest.mark.parametrize("k", [2, 4])
-@pytest.mark.parametrize("p", [15, 20, 23, 27, 31])
+@pytest.mark.parametrize("p", [15, 20, 23, 27, 31, 40, 63])
 def test_matvec_every_order(k, p):
     rng = W.rng_for(330 + k)
     xy = W.uniform_points(rng, 12000)
