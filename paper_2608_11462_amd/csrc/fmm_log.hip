@@ -16,6 +16,7 @@
 // Layout: level l holds (P+1) x nd x 4^l complex coefficients, box index
 // fastest (coalesced across neighbouring boxes), levels 2..L concatenated.
 #include <cmath>
+#include <cstring>
 #include <type_traits>
 
 #include "fmm_common.h"
@@ -1018,8 +1019,34 @@ const Plan &log_ref(const Forest &F) {
 
 }  // namespace
 
+// Host tables gathered into one device allocation and one copy: each part is
+// copied into the staging buffer when added (on a 256-byte boundary), and its
+// device address is set on upload.
+struct TableStage {
+  std::vector<std::pair<void **, size_t>> dst;
+  std::vector<unsigned char> host;
+  void add(void **d, const void *src, size_t bytes) {
+    const size_t off = (host.size() + 255) & ~(size_t)255;
+    host.resize(off + bytes);
+    std::memcpy(host.data() + off, src, bytes);
+    dst.push_back({d, off});
+  }
+  void *upload() {
+    unsigned char *dev = dmalloc<unsigned char>(host.size());
+    try {
+      PHS_HIP(hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice));
+    } catch (...) {
+      dfree(dev);
+      throw;
+    }
+    for (const auto &p : dst) *p.first = dev + p.second;
+    return dev;
+  }
+};
+
 void build_log_tables(LogTables &t, int P) {
   free_log_tables(t);
+  TableStage stage;
   t.P = P;
   const int P1 = P + 1;
   // k-major: H[k*P1 + l]; 64 zero entries of padding so a chunk of LCH
@@ -1121,46 +1148,28 @@ void build_log_tables(LogTables &t, int P) {
         pi = ni;
       }
     }
-    t.Rm64 = dmalloc<double>(Rm.size());
-    t.Rl64 = dmalloc<double>(Rl.size());
-    t.Ph64 = dmalloc<double2>(Ph.size());
-    PHS_HIP(hipMemcpy(t.Rm64, Rm.data(), Rm.size() * 8, hipMemcpyHostToDevice));
-    PHS_HIP(hipMemcpy(t.Rl64, Rl.data(), Rl.size() * 8, hipMemcpyHostToDevice));
-    PHS_HIP(hipMemcpy(t.Ph64, Ph.data(), Ph.size() * 16, hipMemcpyHostToDevice));
+    stage.add((void **)&t.Rm64, Rm.data(), Rm.size() * 8);
+    stage.add((void **)&t.Rl64, Rl.data(), Rl.size() * 8);
+    stage.add((void **)&t.Ph64, Ph.data(), Ph.size() * 16);
   }
-  t.Off64 = dmalloc<double>(Off.size());
-  PHS_HIP(hipMemcpy(t.Off64, Off.data(), Off.size() * 8, hipMemcpyHostToDevice));
   std::vector<float> Hf(H.begin(), H.end());
   std::vector<float2> M2Mf(M2M.size()), L2Lf(L2L.size());
   for (size_t i = 0; i < M2M.size(); ++i) {
     M2Mf[i] = make_float2((float)M2M[i].x, (float)M2M[i].y);
     L2Lf[i] = make_float2((float)L2L[i].x, (float)L2L[i].y);
   }
-  t.Ht64 = dmalloc<double>(H.size());
-  t.Ht32 = dmalloc<float>(H.size());
-  t.M2M64 = dmalloc<double2>(M2M.size());
-  t.L2L64 = dmalloc<double2>(L2L.size());
-  t.M2M32 = dmalloc<float2>(M2M.size());
-  t.L2L32 = dmalloc<float2>(L2L.size());
-  PHS_HIP(hipMemcpy(t.Ht64, H.data(), H.size() * 8, hipMemcpyHostToDevice));
-  PHS_HIP(hipMemcpy(t.Ht32, Hf.data(), Hf.size() * 4, hipMemcpyHostToDevice));
-  PHS_HIP(hipMemcpy(t.M2M64, M2M.data(), M2M.size() * 16, hipMemcpyHostToDevice));
-  PHS_HIP(hipMemcpy(t.L2L64, L2L.data(), L2L.size() * 16, hipMemcpyHostToDevice));
-  PHS_HIP(hipMemcpy(t.M2M32, M2Mf.data(), M2Mf.size() * 8, hipMemcpyHostToDevice));
-  PHS_HIP(hipMemcpy(t.L2L32, L2Lf.data(), L2Lf.size() * 8, hipMemcpyHostToDevice));
+  stage.add((void **)&t.Off64, Off.data(), Off.size() * 8);
+  stage.add((void **)&t.Ht64, H.data(), H.size() * 8);
+  stage.add((void **)&t.Ht32, Hf.data(), Hf.size() * 4);
+  stage.add((void **)&t.M2M64, M2M.data(), M2M.size() * 16);
+  stage.add((void **)&t.L2L64, L2L.data(), L2L.size() * 16);
+  stage.add((void **)&t.M2M32, M2Mf.data(), M2Mf.size() * 8);
+  stage.add((void **)&t.L2L32, L2Lf.data(), L2Lf.size() * 8);
+  t.block = stage.upload();
 }
 
 void free_log_tables(LogTables &t) {
-  dfree(t.Off64);
-  dfree(t.Rm64);
-  dfree(t.Rl64);
-  dfree(t.Ph64);
-  dfree(t.Ht64);
-  dfree(t.Ht32);
-  dfree(t.M2M64);
-  dfree(t.L2L64);
-  dfree(t.M2M32);
-  dfree(t.L2L32);
+  dfree(t.block);
   t = LogTables();
 }
 

@@ -165,6 +165,7 @@ struct LogTables {  // translation tables for one expansion order P
   double *Rm64 = nullptr;   // (P+1)^2 real, [l][k]
   double *Rl64 = nullptr;   // (P+1)^2 real, [j][k]
   double2 *Ph64 = nullptr;  // 4 x 32: u_c^k
+  void *block = nullptr;    // one device allocation holding all of the above
 };
 
 struct ChebTables {  // Chebyshev interpolation tables for Q nodes per axis
