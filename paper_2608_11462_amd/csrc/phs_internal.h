@@ -458,11 +458,13 @@ void minmax_xy(const double *xy, int64_t n, double *out4, double *partials,
 void leaf_keys(const double *xy, int64_t n, double cx, double cy, double rho,
                double h, int L, uint32_t *keys, int32_t *idx, hipStream_t s);
 // Stable LSD radix sort of (key, value) pairs by the low `bits` bits of key.
+// With `in_tmp` given, a result left in (keys_tmp, vals_tmp) by an odd number
+// of passes stays there and *in_tmp is set; otherwise it is copied back.
 // Temporary buffers: keys_tmp, vals_tmp (n each), hist (256*nblocks + scan ws).
 size_t radix_sort_scratch_ints(int64_t n);
 void radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, int bits,
                     uint32_t *keys_tmp, int32_t *vals_tmp, int32_t *scratch,
-                    hipStream_t s);
+                    hipStream_t s, bool *in_tmp = nullptr);
 void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits,
                     uint64_t *keys_tmp, int32_t *vals_tmp, int32_t *scratch,
                     hipStream_t s);

@@ -225,9 +225,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
   }
 }
 
+// With `in_tmp` given, an odd number of passes leaves the result in
+// (ktmp, vtmp) and *in_tmp says so; otherwise it is copied back.
 template <class K>
 void radix_sort(K *keys, int32_t *vals, int64_t n, int bits, K *ktmp,
-                int32_t *vtmp, int32_t *scratch, hipStream_t s) {
+                int32_t *vtmp, int32_t *scratch, hipStream_t s, bool *in_tmp) {
+  if (in_tmp) *in_tmp = false;
   if (n <= 1) return;
   int nblocks = (int)((n + kTile - 1) / kTile);
   int32_t *hist = scratch;
@@ -247,7 +250,9 @@ void radix_sort(K *keys, int32_t *vals, int64_t n, int bits, K *ktmp,
     std::swap(src_k, dst_k);
     std::swap(src_v, dst_v);
   }
-  if (src_k != keys) {
+  if (src_k != keys && in_tmp) {
+    *in_tmp = true;
+  } else if (src_k != keys) {
     PHS_HIP(hipMemcpyAsync(keys, src_k, n * sizeof(K), hipMemcpyDeviceToDevice, s));
     PHS_HIP(hipMemcpyAsync(vals, src_v, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
@@ -399,14 +404,14 @@ size_t radix_sort_scratch_ints(int64_t n) {
 
 void radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, int bits,
                     uint32_t *ktmp, int32_t *vtmp, int32_t *scratch,
-                    hipStream_t s) {
-  radix_sort<uint32_t>(keys, vals, n, bits, ktmp, vtmp, scratch, s);
+                    hipStream_t s, bool *in_tmp) {
+  radix_sort<uint32_t>(keys, vals, n, bits, ktmp, vtmp, scratch, s, in_tmp);
 }
 
 void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits,
                     uint64_t *ktmp, int32_t *vtmp, int32_t *scratch,
                     hipStream_t s) {
-  radix_sort<uint64_t>(keys, vals, n, bits, ktmp, vtmp, scratch, s);
+  radix_sort<uint64_t>(keys, vals, n, bits, ktmp, vtmp, scratch, s, nullptr);
 }
 
 void leaf_ranges(const uint32_t *sorted_keys, int64_t n, int nleaves,

@@ -731,9 +731,12 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
       while (((int64_t)1 << bits) <= n) ++bits;
       PHS_LAUNCH("vecchia_tkeys", s,
                  k_tkeys<<<(N + B - 1) / B, B, 0, s>>>(pl.pc_nbr, n, m, tk, tv));
-      radix_sort_u32(tk, tv, N, bits, tkt, tvt, tscr, s);
+      bool in_tmp = false;
+      radix_sort_u32(tk, tv, N, bits, tkt, tvt, tscr, s, &in_tmp);
+      const uint32_t *sk = in_tmp ? tkt : tk;  // sorted keys and values
+      const int32_t *sv = in_tmp ? tvt : tv;
       pl.pc_tstart = dmalloc<int32_t>(n + 1);
-      leaf_ranges(tk, N, (int)n, pl.pc_tstart, s);
+      leaf_ranges(sk, N, (int)n, pl.pc_tstart, s);
       int32_t nnz = 0;
       PHS_HIP(hipMemcpyAsync(&nnz, pl.pc_tstart + n, 4, hipMemcpyDeviceToHost, s));
       PHS_HIP(hipStreamSynchronize(s));
@@ -741,7 +744,7 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
       pl.pc_tcoef = dmalloc<double>(std::max(nnz, 1));
       if (nnz > 0)
         PHS_LAUNCH("vecchia_tfill", s,
-                   k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(tv, nnz, n, m, pl.pc_coef,
+                   k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(sv, nnz, n, m, pl.pc_coef,
                                                           pl.pc_tidx, pl.pc_tcoef));
       for (void *q : {(void *)tk, (void *)tkt, (void *)tv, (void *)tvt, (void *)tscr}) dfree(q);
     }
