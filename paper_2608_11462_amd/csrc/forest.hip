@@ -431,8 +431,10 @@ Forest::~Forest() {
       (void)hipEventSynchronize(mask_ev[i]);
       (void)hipEventDestroy(mask_ev[i]);
     }
-    dfree(mask[i]);
+    mask[i] = nullptr;
   }
+  dfree(mask_block);
+  mask_block = nullptr;
   if (hpin) (void)hipHostFree(hpin);
   dfree(vec.d);
   dfree(dot.d);
@@ -473,14 +475,21 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
       F.hmask[i] = (int32_t *)((char *)F.hpin + mb * i);
     F.hgsc = (double *)((char *)F.hpin + mb * Forest::kMasks);
   }
-  for (int i = 0; i < Forest::kMasks; ++i) {
-    F.mask[i] = dmalloc<int32_t>(F.nsys);
-    for (int j = 0; j < F.nsys; ++j) F.hmask[i][j] = 1;
-    PHS_HIP(hipMemcpyAsync(F.mask[i], F.hmask[i], F.nsys * sizeof(int32_t),
+  {
+    // all masks in one device block laid out like the pinned staging, one copy
+    const size_t mw = ((size_t)F.nsys * sizeof(int32_t) + 63) / 64 * 16;  // ints per mask
+    F.mask_block = dmalloc<int32_t>(mw * Forest::kMasks);
+    for (int i = 0; i < Forest::kMasks; ++i) {
+      F.mask[i] = F.mask_block + mw * i;
+      for (int j = 0; j < F.nsys; ++j) F.hmask[i][j] = 1;
+    }
+    PHS_HIP(hipMemcpyAsync(F.mask_block, F.hmask[0], mw * Forest::kMasks * sizeof(int32_t),
                            hipMemcpyHostToDevice, s));
-    PHS_HIP(hipEventCreateWithFlags(&F.mask_ev[i], hipEventDisableTiming));
-    PHS_HIP(hipEventRecord(F.mask_ev[i], s));
-    F.mask_pending[i] = true;
+    for (int i = 0; i < Forest::kMasks; ++i) {
+      PHS_HIP(hipEventCreateWithFlags(&F.mask_ev[i], hipEventDisableTiming));
+      PHS_HIP(hipEventRecord(F.mask_ev[i], s));
+      F.mask_pending[i] = true;
+    }
   }
   F.vec = upload_tab(F, std::move(hv), s);
   F.dot = upload_tab(F, std::move(hd), s);

@@ -305,7 +305,8 @@ struct Forest {
   int maxL_log = 0, maxL_dist = 0;
   // masks: device int32[nsys] each, host pinned mirrors
   static constexpr int kMasks = 10;
-  int32_t *mask[kMasks] = {};
+  int32_t *mask[kMasks] = {};   // slices of mask_block
+  int32_t *mask_block = nullptr;
   int32_t *hmask[kMasks] = {};   // pinned staging of the last upload
   hipEvent_t mask_ev[kMasks] = {};
   bool mask_pending[kMasks] = {};
