@@ -224,16 +224,12 @@ __device__ __forceinline__ double near_log_core(double x, double invc, double lo
   const double m = __builtin_amdgcn_frexp_mant(x);
   const int e = __builtin_amdgcn_frexp_exp(x);
   const double r = fma(m, invc, -1.0);
-  double p;
-  if constexpr (kNearLogBits >= 9) {  // |r| <= 2^-10: degree 4, remainder < 2e-16
-    p = -0.25;
-  } else {  // |r| <= 2^-9: degree 5, remainder < 1e-17
-    p = 0.2;
-    p = fma(p, r, -0.25);
-  }
-  p = fma(p, r, 1.0 / 3.0);
-  p = fma(p, r, -0.5);
-  p = fma(p, r, 1.0);
+  // log1p(r) = sum_k (-1)^(k+1) r^k / k to the degree whose remainder
+  // |r|^(d+1)/(d+1) with |r| <= 2^-(bits+1) is below 2e-16 (bits 8: degree 5)
+  constexpr int deg = kNearLogBits >= 9 ? 4 : kNearLogBits >= 8 ? 5 : kNearLogBits >= 6 ? 7 : 10;
+  double p = (deg % 2 ? 1.0 : -1.0) / deg;
+#pragma unroll
+  for (int k = deg - 1; k >= 1; --k) p = fma(p, r, (k % 2 ? 1.0 : -1.0) / k);
   return fma((double)e, 0.69314718055994530942, fma(p, r, logc));
 }
 // byte offset of the table entry of a value whose high word is hi
