@@ -60,7 +60,8 @@ typedef enum {
   PHS_ERR_BREAKDOWN = 5,        /* PCG curvature p^T A p <= 0 (indefinite) */
   PHS_ERR_OUT_OF_MEMORY = 6,    /* a device allocation failed */
   PHS_ERR_DEVICE = 7,           /* a HIP runtime call failed */
-  PHS_ERR_NOT_READY = 8         /* phs_solve before phs_precond_build, ... */
+  PHS_ERR_NOT_READY = 8         /* phs_precond_export / phs_precond_apply before
+                                   phs_precond_build */
 } phs_status;
 
 /* Matvec precision.  PHS_FP64: everything in FP64.  PHS_MIXED: far field
@@ -108,36 +109,56 @@ typedef struct {
 } phs_solve_opts;
 
 typedef struct {
-  int32_t iters;             /* total inner PCG iterations (all RHS) */
+  int32_t iters;             /* total inner PCG iterations (all RHS) =
+                                iters_fp32 + iters_fp64 */
   int32_t outer_refinements; /* FP64 residual recomputations (mixed mode) */
   double rel_residual;       /* ||Pi(f - M w)|| / ||Pi f|| recomputed with an
                                 FP64 matvec at exit (worst RHS) */
   double t_solve;            /* seconds, host wall clock */
+  int32_t iters_fp32;        /* inner iterations on a reduced-precision
+                                operator (PHS_MIXED or PHS_NEAR32) */
+  int32_t iters_fp64;        /* inner iterations on the FP64 operator */
+  int32_t fp64_fallback;     /* number of right-hand sides whose reduced-
+                                precision solve moved to the FP64 operator
+                                (its FP32 steps stopped reducing the FP64
+                                residual, or broke down) */
+  int32_t reserved;
+  double t_plan;             /* seconds phs_plan took for this plan */
+  double t_precond;          /* seconds the last phs_precond_build took */
 } phs_solve_info;
 
-/* Build a plan: normalise the nodes, sort them into the quadtree, build the
- * polynomial block and its thin QR.  xy: device, n x 2.  Synchronises
- * `stream` (it reads back sizes).  Errors: INVALID_ARGUMENT (n < S+1, bad
- * options), DUPLICATE_POINTS, UNISOLVENT, OUT_OF_MEMORY, DEVICE. */
+/* Build a plan for the interpolation problem of Sec. 1 (eqs. phs_interp,
+ * phs_linsys): normalise the nodes (eq. M_rho and the tuned domains of
+ * Sec. 2.2), sort them into the quadtree of the FMM (Sec. 2.1), build the
+ * polynomial block B and its thin QR (eq. phs_linsys_solve), the FMM
+ * translation tables and every work table and workspace the later calls use.
+ * xy: device, n x 2 row-major (the plan copies it).  opts: host.  out: host,
+ * receives the handle (NULL on error).  Synchronises `stream` (it reads back
+ * sizes).  Errors: INVALID_ARGUMENT (n < S, bad options), DUPLICATE_POINTS,
+ * UNISOLVENT, OUT_OF_MEMORY, DEVICE. */
 phs_status phs_plan(const double *xy, int64_t n, const phs_plan_opts *opts,
                     void *stream, phs_plan_t *out);
 
 /* y = M v for the kernel block M only (eq. matvec_hadamard; Sec. 2.1 FMM).
  * v, y: device, n x nrhs.  precision: PHS_FP64, PHS_MIXED or PHS_NEAR32.
- * Asynchronous. */
+ * Allocates no device memory.  Asynchronous. */
 phs_status phs_matvec(phs_plan_t plan, const double *v, double *y, int32_t nrhs,
                       int32_t precision, void *stream);
 
 /* Build the Vecchia factor U~ (Sigma^{-1} ~= U~ U~^T) of the Matern covariance
  * on the plan's normalised nodes (eqs. conditionals, vecchia_sumform,
- * Fig. vecchia_chol).  Synchronises `stream`. */
+ * Fig. vecchia_chol).  A rebuild replaces the previous factor only when it
+ * succeeds: on an error the plan keeps the factor it had (or none).
+ * Synchronises `stream`. */
 phs_status phs_precond_build(phs_plan_t plan, const phs_precond_opts *opts,
                              void *stream);
 
 /* Solve for w (n x nrhs) and beta (S x nrhs) by projected PCG on
  * Q_perp^T M Q_perp u = Q_perp^T f, w = Q_perp u, then R beta = Q^T (f - M w)
  * (eq. phs_linsys_solve).  f, w, beta: device.  info: host, may be NULL.
- * Synchronises `stream` every check_every iterations. */
+ * Preconditioner: the plan's Vecchia factor; before any phs_precond_build the
+ * solve runs with the identity (plain projected CG).  Allocates no device
+ * memory.  Synchronises `stream` every check_every iterations. */
 phs_status phs_solve(phs_plan_t plan, const double *f, int32_t nrhs,
                      const phs_solve_opts *opts, double *w, double *beta,
                      phs_solve_info *info, void *stream);
@@ -146,7 +167,8 @@ phs_status phs_solve(phs_plan_t plan, const double *f, int32_t nrhs,
  * out[t, r] = sum_s beta[s, r] P_s(xi_t) + sum_j w[j, r] phi(|xi_t - xi_j|).
  * targets: device m x 2; w: n x nrhs; beta: S x nrhs; out: m x nrhs.
  * Targets may lie outside the nodes' bounding box.  A target equal to a node
- * contributes phi(0) = 0 for that node.  Asynchronous. */
+ * contributes phi(0) = 0 for that node.  Allocates no device memory.
+ * Asynchronous. */
 phs_status phs_eval(phs_plan_t plan, const double *w, const double *beta,
                     int32_t nrhs, const double *targets, int64_t m, double *out,
                     void *stream);
@@ -286,6 +308,15 @@ void phs_server_destroy(phs_server_t srv);
 
 /* Message for the last non-OK status returned on this thread. */
 const char *phs_last_error(void);
+
+/* Device-memory counters of the library's caching pool (all host pointers,
+ * any may be NULL): allocations = blocks handed out so far (from the cache or
+ * fresh), device_mallocs = hipMalloc calls so far, bytes_in_use = bytes handed
+ * out and not yet released (a released block counts until the device is next
+ * idle), bytes_held = device bytes the pool owns (in use and cached).  Lets a
+ * caller check that a call allocated nothing, and what the library holds. */
+phs_status phs_memory_stats(int64_t *allocations, int64_t *device_mallocs,
+                            int64_t *bytes_in_use, int64_t *bytes_held);
 
 /* Per-kernel timing.  on = 1: each library kernel launch is bracketed by HIP
  * events on its own stream; on = 2: only the leaf, M2L, Vecchia factor and

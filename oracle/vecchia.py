@@ -79,6 +79,12 @@ def ordered_knn(xi: np.ndarray, perm: np.ndarray, rank: np.ndarray, m: int,
             out.append(np.zeros(0, dtype=np.int64))
             continue
         d2 = _d2(xi, prior, j)
+        if t > m:
+            # only candidates no farther than the m-th smallest distance can be
+            # chosen; all of them (ties included) go on to the sort
+            thr = np.partition(d2, m - 1)[m - 1]
+            keep = d2 <= thr
+            prior, d2 = prior[keep], d2[keep]
         o = np.lexsort((rank[prior], d2))[:m]
         out.append(prior[o])
     return out
@@ -92,13 +98,6 @@ def matern(nu: float, x: np.ndarray) -> np.ndarray:
     xn = x[nz]
     out[nz] = (2.0 ** (1.0 - nu) / math.gamma(nu)) * xn ** nu * ss.kv(nu, xn)
     return out
-
-
-def default_params(k: int):
-    """(nu, alpha) defaults in normalised coordinates: nu = k/2; alpha = 0.35
-    (the tuned TPS value of Sec. 2.2), 2 for k=4 and 3 for k=3 (readings: the
-    paper tunes only k = 2 and 4)."""
-    return k / 2.0, (2.0 if k == 4 else (3.0 if k == 3 else 0.35))
 
 
 def factor(xi: np.ndarray, nbrs, nu: float, alpha: float):

@@ -306,6 +306,7 @@ void build_tree(Plan &pl, const double *xy, int leaf_size, hipStream_t s) {
 
 void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_t s,
                  Plan &pl) {
+  const auto t0 = std::chrono::steady_clock::now();
   PHS_REQUIRE(xy && o, PHS_ERR_INVALID_ARGUMENT, "null argument");
   PHS_REQUIRE(o->k >= 1 && o->k <= 4, PHS_ERR_INVALID_ARGUMENT, "k must be 1..4");
   pl.k = o->k;
@@ -409,6 +410,7 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
   build_forest(*pl.self, {&pl}, {&pl.sw}, s);
   PHS_HIP(hipStreamSynchronize(s));
   pool_mark_idle();
+  pl.t_plan = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace
@@ -446,9 +448,10 @@ phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts 
   const int prec = (o && o->precision >= 0) ? o->precision : pl.precision;
   PHS_REQUIRE(prec == PHS_FP64 || prec == PHS_MIXED || prec == PHS_NEAR32,
               PHS_ERR_INVALID_ARGUMENT, "bad precision");
-  int total_iters = 0, total_outer = 0;
+  int total_iters = 0, total_outer = 0, it32 = 0, it64 = 0, falls = 0;
   double worst_rel = 0.0;
   phs_status st = PHS_OK;
+  sync_forest_pc(*pl.self, s);
   for (int c = 0; c < nrhs; ++c) {
     std::vector<SolveJob> jobs(1);
     jobs[0].sys = 0;
@@ -458,17 +461,26 @@ phs_status solve_impl(Plan &pl, const double *f, int nrhs, const phs_solve_opts 
     solve_forest(*pl.self, jobs, rtol, maxit, check_every, prec, s);
     total_iters += jobs[0].iters;
     total_outer += jobs[0].outer;
+    it32 += jobs[0].iters32;
+    it64 += jobs[0].iters64;
+    falls += jobs[0].fallback ? 1 : 0;
     worst_rel = std::max(worst_rel, jobs[0].rel);
     if (jobs[0].status != PHS_OK && st == PHS_OK) st = jobs[0].status;
     if (jobs[0].status == PHS_ERR_BREAKDOWN) st = PHS_ERR_BREAKDOWN;
   }
   PHS_HIP(hipStreamSynchronize(s));
   if (info) {
+    std::memset(info, 0, sizeof(*info));
     info->iters = total_iters;
     info->outer_refinements = total_outer;
     info->rel_residual = worst_rel;
     info->t_solve =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->iters_fp32 = it32;
+    info->iters_fp64 = it64;
+    info->fp64_fallback = falls;
+    info->t_plan = pl.t_plan;
+    info->t_precond = pl.t_precond;
   }
   if (st == PHS_ERR_NOT_CONVERGED) set_error(st, "PCG did not reach rtol within maxit");
   if (st == PHS_ERR_BREAKDOWN) set_error(st, "PCG breakdown: non-positive curvature");
@@ -547,8 +559,11 @@ phs_status phs_matvec(phs_plan_t plan, const double *v, double *y, int32_t nrhs,
 phs_status phs_precond_build(phs_plan_t plan, const phs_precond_opts *opts, void *stream) {
   return guarded([&] {
     PHS_REQUIRE(plan && opts, PHS_ERR_INVALID_ARGUMENT, "bad precond arguments");
+    const auto t0 = std::chrono::steady_clock::now();
     vecchia_build(plan->pl, *opts, S(stream));
     refresh_forest(*plan->pl.self, S(stream));
+    plan->pl.t_precond =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return PHS_OK;
   });
 }
@@ -623,6 +638,7 @@ phs_status phs_precond_apply(phs_plan_t plan, const double *r, double *z, void *
     PHS_REQUIRE(pl.has_pc, PHS_ERR_NOT_READY, "no preconditioner built");
     hipStream_t s = S(stream);
     Forest &F = *pl.self;
+    sync_forest_pc(F, s);
     f_gather_user(F, 0, r, V_IN, s);
     f_precond_apply(F, F.mask[0], V_IN, V_OUT, V_TMP, s);
     f_scatter_user(F, 0, V_OUT, z, s);
@@ -756,6 +772,12 @@ void phs_plan_destroy(phs_plan_t plan) {
 }
 
 const char *phs_last_error(void) { return g_last_error.c_str(); }
+
+phs_status phs_memory_stats(int64_t *allocations, int64_t *device_mallocs,
+                            int64_t *bytes_in_use, int64_t *bytes_held) {
+  pool_stats(allocations, device_mallocs, bytes_in_use, bytes_held);
+  return PHS_OK;
+}
 
 void phs_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

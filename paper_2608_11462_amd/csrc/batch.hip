@@ -3,6 +3,7 @@
 // FMM stage, preconditioner apply and vector step is one launch over all
 // systems still iterating.
 #include <chrono>
+#include <cstring>
 
 #include "phs_internal.h"
 
@@ -59,7 +60,7 @@ phs_status batch_solve(Batch &b, const double *const *f, double *const *w,
               PHS_ERR_INVALID_ARGUMENT, "bad precision");
   for (size_t i = 0; i < b.plans.size(); ++i)
     PHS_REQUIRE(f[i] && w[i] && beta[i], PHS_ERR_INVALID_ARGUMENT, "null batch array");
-  refresh_forest(b.F, s);  // preconditioners may have been (re)built
+  sync_forest_pc(b.F, s);  // preconditioners may have been (re)built
   std::vector<SolveJob> jobs(b.sys_plan.size());
   for (size_t k = 0; k < jobs.size(); ++k) {
     const int i = b.sys_plan[k], c = b.sys_col[k];
@@ -74,13 +75,21 @@ phs_status batch_solve(Batch &b, const double *const *f, double *const *w,
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   phs_status st = PHS_OK;
   if (info)
-    for (size_t i = 0; i < b.plans.size(); ++i) info[i] = phs_solve_info{0, 0, 0.0, t};
+    for (size_t i = 0; i < b.plans.size(); ++i) {
+      std::memset(&info[i], 0, sizeof(info[i]));
+      info[i].t_solve = t;
+      info[i].t_plan = b.plans[i]->t_plan;
+      info[i].t_precond = b.plans[i]->t_precond;
+    }
   for (size_t k = 0; k < jobs.size(); ++k) {
     const int i = b.sys_plan[k];
     if (info) {
       info[i].iters += jobs[k].iters;
       info[i].outer_refinements += jobs[k].outer;
       info[i].rel_residual = std::max(info[i].rel_residual, jobs[k].rel);
+      info[i].iters_fp32 += jobs[k].iters32;
+      info[i].iters_fp64 += jobs[k].iters64;
+      info[i].fp64_fallback += jobs[k].fallback ? 1 : 0;
     }
     if (jobs[k].status != PHS_OK && st == PHS_OK) st = jobs[k].status;
   }

@@ -365,6 +365,14 @@ Tab upload_tab(Forest &F, std::vector<BlkRef> &&h, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+thread_local int t_warm = 0;
+}
+
+bool launches_suppressed() { return t_warm > 0; }
+WarmTables::WarmTables() { ++t_warm; }
+WarmTables::~WarmTables() { --t_warm; }
+
 void SysWork::release() {
   dfree(mp);
   dfree(loc);
@@ -494,6 +502,21 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
   F.vec = upload_tab(F, std::move(hv), s);
   F.dot = upload_tab(F, std::move(hd), s);
   F.pc = upload_tab(F, std::move(hp), s);
+  // Every FMM work table a later call can look up: the matvec in each
+  // precision and, on a plan's own forest, the expansions of the evaluation.
+  // The drivers run with their launches suppressed, so this only builds and
+  // uploads tables; afterwards a lookup miss is an error, never an allocation.
+  {
+    WarmTables warm;
+    for (int prec : {PHS_FP64, PHS_MIXED, PHS_NEAR32})
+      f_matvec(F, F.mask[0], V_IN, V_OUT, prec, s);
+    for (Plan *pl : plans) {
+      if (pl->self != &F) continue;
+      if (pl->core_log) log_expansions(*pl, V_IN, s);
+      else dist_expansions(*pl, V_IN, s);
+    }
+  }
+  F.frozen = true;
 }
 
 void refresh_forest(Forest &F, hipStream_t s) {
@@ -501,6 +524,19 @@ void refresh_forest(Forest &F, hipStream_t s) {
   PHS_HIP(hipMemcpyAsync(F.dsys, F.hsys.data(), F.nsys * sizeof(SysDev), hipMemcpyHostToDevice,
                          s));
   PHS_HIP(hipStreamSynchronize(s));
+}
+
+void sync_forest_pc(Forest &F, hipStream_t s) {
+  for (int i = 0; i < F.nsys; ++i) {
+    const Plan &pl = *F.plan[i];
+    const SysDev &d = F.hsys[i];
+    if (d.has_pc != (pl.has_pc ? 1 : 0) || d.m != pl.m || d.nbr != pl.pc_nbr ||
+        d.coef != pl.pc_coef || d.dinv != pl.pc_dinv || d.tstart != pl.pc_tstart ||
+        d.tidx != pl.pc_tidx || d.tcoef != pl.pc_tcoef) {
+      refresh_forest(F, s);
+      return;
+    }
+  }
 }
 
 uint64_t tab_key(int kind, int K, int P, int level) {
@@ -648,13 +684,15 @@ void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hi
   if (F.maxL_dist > 0) dist_matvec(F, mask, in, out, precision, s);
 }
 
-// Work-item tables of the FMM kernels, built on first use per (kind, K, P,
-// level) and kept for the forest's lifetime.
+// Work-item tables of the FMM kernels, one per (kind, K, P, level), all built
+// by the warm-up pass of build_forest and kept for the forest's lifetime.
 Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s);
 
 Tab forest_tab(Forest &F, uint64_t key, hipStream_t s) {
   for (auto &kv : F.cache)
     if (kv.first == key) return kv.second;
+  PHS_REQUIRE(!F.frozen, PHS_ERR_DEVICE,
+              "internal error: an FMM work table was not built with its forest");
   const int kind = (int)(key >> 40), K = (int)((key >> 32) & 0xff),
             P = (int)((key >> 8) & 0xffffff), level = (int)(key & 0xff);
   F.cache.push_back({key, build_fmm_tab(F, kind, K, P, level, s)});

@@ -16,6 +16,7 @@ std::unordered_map<size_t, std::vector<void *>> g_free;  // rounded size -> idle
 std::unordered_map<void *, size_t> g_size;               // every block the pool owns
 std::unordered_map<void *, bool> g_idle;                 // blocks on a free list
 thread_local std::vector<void *> t_pending;
+int64_t g_allocs = 0, g_mallocs = 0, g_bytes = 0, g_inuse = 0;
 
 size_t round_size(size_t b) {
   if (b <= (size_t(1) << 20)) return (b + 255) & ~size_t(255);
@@ -36,6 +37,8 @@ void *pool_alloc(size_t bytes) {
       void *p = it->second.back();
       it->second.pop_back();
       g_idle.erase(p);
+      ++g_allocs;
+      g_inuse += (int64_t)r;
       return p;
     }
   }
@@ -52,6 +55,10 @@ void *pool_alloc(size_t bytes) {
   }
   std::lock_guard<std::mutex> lk(g_mu);
   g_size[p] = r;
+  ++g_allocs;
+  ++g_mallocs;
+  g_bytes += (int64_t)r;
+  g_inuse += (int64_t)r;
   return p;
 }
 
@@ -76,6 +83,7 @@ void pool_mark_idle() {
     if (it != g_size.end() && !g_idle.count(p)) {
       g_free[it->second].push_back(p);
       g_idle[p] = true;
+      g_inuse -= (int64_t)it->second;
     }
   }
   t_pending.clear();
@@ -87,10 +95,20 @@ void pool_trim() {
   for (auto &kv : g_free)
     for (void *p : kv.second) {
       (void)hipFree(p);
+      g_bytes -= (int64_t)g_size[p];
       g_size.erase(p);
       g_idle.erase(p);
     }
   g_free.clear();
+}
+
+void pool_stats(int64_t *allocs, int64_t *device_mallocs, int64_t *bytes_in_use,
+                int64_t *bytes_held) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (allocs) *allocs = g_allocs;
+  if (device_mallocs) *device_mallocs = g_mallocs;
+  if (bytes_in_use) *bytes_in_use = g_inuse;
+  if (bytes_held) *bytes_held = g_bytes;
 }
 
 }  // namespace phs

@@ -53,11 +53,23 @@ struct ProfScope {
   }
 };
 
+// Work-table warm-up: while a WarmTables object lives on this thread,
+// PHS_LAUNCH enqueues nothing, so running the FMM drivers over a forest only
+// builds the work tables they look up (done once when the forest is built,
+// so the per-call entry points never allocate).
+bool launches_suppressed();
+struct WarmTables {
+  WarmTables();
+  ~WarmTables();
+};
+
 #define PHS_LAUNCH(name, stream, ...)                                         \
   do {                                                                        \
-    ::phs::ProfScope ps_(name, stream);                                       \
-    __VA_ARGS__;                                                              \
-    PHS_HIP(hipGetLastError());                                               \
+    if (!::phs::launches_suppressed()) {                                      \
+      ::phs::ProfScope ps_(name, stream);                                     \
+      __VA_ARGS__;                                                            \
+      PHS_HIP(hipGetLastError());                                             \
+    }                                                                         \
   } while (0)
 
 // Table of the near-field logarithm: 2^kNearLogBits centred subintervals of
@@ -104,6 +116,11 @@ void *pool_alloc(size_t bytes);
 void pool_free(void *p);
 void pool_mark_idle();  // synchronises the device, then recycles pending blocks
 void pool_trim();       // returns every idle cached block to HIP
+// blocks handed out by pool_alloc so far, hipMalloc calls so far, device
+// bytes handed out and not yet recycled, device bytes the pool owns (in use
+// and cached)
+void pool_stats(int64_t *allocs, int64_t *device_mallocs, int64_t *bytes_in_use,
+                int64_t *bytes_held);
 
 template <class T>
 T *dmalloc(size_t count) {
@@ -277,6 +294,7 @@ struct Plan {
   int m = 0;
   double nu = 1, alpha = 0.35;
   int pc_nugget_nodes = 0;      // nodes whose block needed a diagonal nugget
+  double t_plan = 0, t_precond = 0;  // host seconds of phs_plan / the last precond build
   int32_t *pc_rank = nullptr;   // tree position -> rank
   // after the build: column-major m x n, entry s of node p at s*n + p
   int32_t *pc_nbr = nullptr;    // tree positions, -1 padded
@@ -315,6 +333,7 @@ struct Forest {
   std::vector<std::vector<BlkRef>> hcopies;  // host sources of the table uploads
   Tab vec, dot, pc;                     // element blocks, dot blocks, 8-row blocks
   std::vector<std::pair<uint64_t, Tab>> cache;  // FMM tables keyed by (kind, K, P, level)
+  bool frozen = false;  // every table is built: a lookup miss is an internal error
   ~Forest();
 };
 
@@ -324,6 +343,9 @@ struct Forest {
 void build_forest(Forest &F, const std::vector<Plan *> &plans,
                   const std::vector<SysWork *> &work, hipStream_t s);
 void refresh_forest(Forest &F, hipStream_t s);
+// refresh_forest if any system's descriptor no longer matches its plan's
+// preconditioner (a factor built or rebuilt since the forest last looked)
+void sync_forest_pc(Forest &F, hipStream_t s);
 void alloc_syswork(SysWork &w, const Plan &pl);
 Tab forest_tab(Forest &F, uint64_t key, hipStream_t s);
 // log-kernel P2M packs this many leaves per wavefront (lane = coefficient)
@@ -386,6 +408,8 @@ struct SolveJob {
   int budget = 0;
   bool fp64_finish = false, count_outer = false, apply_dw = false, have_q = false;
   bool undo_dw = false;  // the last correction raised the residual: take it back
+  int iters32 = 0, iters64 = 0;  // inner iterations on the reduced / FP64 operator
+  bool fallback = false;         // a reduced-precision solve moved to the FP64 operator
 };
 struct SolveParams {
   double rtol;

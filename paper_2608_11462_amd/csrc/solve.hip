@@ -203,6 +203,8 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       if (r.state != J_PCG_END) continue;
       r.iters += r.it;
       r.budget -= r.it;
+      if (r.inner_prec == PHS_FP64) r.iters64 += r.it;
+      else r.iters32 += r.it;
       if (r.pcg_break && r.it <= 1) {
         if (r.fp64_finish) {
           r.status = PHS_ERR_BREAKDOWN;
@@ -210,6 +212,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
           continue;
         }
         r.fp64_finish = true;  // no usable FP32 step: restart this residual in FP64
+        r.fallback = true;
         r.count_outer = false;
         r.state = J_RESID;
         continue;
@@ -248,6 +251,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
           stalled = !(rn_new < 0.5 * r.rn);
           if (stalled && !r.fp64_finish) {
             r.fp64_finish = true;  // the FP32 operator stopped helping
+            r.fallback = true;
             stalled = false;
           }
           // a final correction that raised the residual is taken back, so

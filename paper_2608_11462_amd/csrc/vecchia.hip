@@ -632,10 +632,13 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     // for FP64 PCG to reach 1e-8 up to 1e6 nodes (0.35 stalls near 1e-6 there)
     alpha = pl.k == 4 ? 2.0 : (pl.k == 3 ? 3.0 : 0.35);
   }
-  vecchia_free(pl);
-  pl.m = m;
-  pl.nu = nu;
-  pl.alpha = alpha;
+  // The new factor is built into `nf` and replaces the plan's only once it
+  // is complete: a failed rebuild leaves the previous factor (or none) in
+  // place, so no descriptor ever points at freed memory.
+  struct {
+    int32_t *rank = nullptr, *nbr = nullptr, *tstart = nullptr, *tidx = nullptr;
+    double *coef = nullptr, *dinv = nullptr, *tcoef = nullptr;
+  } nf;
   const double h = pl.tree.h;
   const int B = 256;
   // 1. ordering
@@ -669,10 +672,10 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     PHS_LAUNCH("vecchia_rank_keys", s,
                k_rank_keys<<<(n + B - 1) / B, B, 0, s>>>(n, o.seed, k64, perm));
     radix_sort_u64(k64, perm, n, 64, k64t, vt, scr, s);
-    pl.pc_rank = dmalloc<int32_t>(n);
+    nf.rank = dmalloc<int32_t>(n);
     PHS_LAUNCH("vecchia_rank_maps", s,
                k_rank_maps<<<(n + B - 1) / B, B, 0, s>>>(perm, pl.inv_order, n, pl.x, pl.y,
-                                                        pl.pc_rank, pos_of_rank, xr, yr));
+                                                        nf.rank, pos_of_rank, xr, yr));
     // 2. rank-prefix grids
     PHS_HIP(hipMemcpyAsync(d_lvl, lvl_off.data(), (T + 2) * 8, hipMemcpyHostToDevice, s));
     PHS_HIP(hipMemcpyAsync(d_coff, cell_off.data(), (T + 2) * 8, hipMemcpyHostToDevice, s));
@@ -692,35 +695,35 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     {
       uint32_t *qk = reinterpret_cast<uint32_t *>(k64), *qkt = reinterpret_cast<uint32_t *>(k64t);
       PHS_LAUNCH("vecchia_qkeys", s,
-                 k_qkeys<<<(n + B - 1) / B, B, 0, s>>>(pl.pc_rank, n, T, qk, qord));
+                 k_qkeys<<<(n + B - 1) / B, B, 0, s>>>(nf.rank, n, T, qk, qord));
       int qbits = 1;
       while ((1 << qbits) <= T) ++qbits;
       radix_sort_u32(qk, qord, n, qbits, qkt, vt, scr, s);  // sorted ranks in qord
     }
-    pl.pc_nbr = dmalloc<int32_t>((size_t)n * m);
+    nf.nbr = dmalloc<int32_t>((size_t)n * m);
     PHS_LAUNCH("vecchia_knn", s,
                k_knn<<<(n + 63) / 64, 64, (size_t)64 * m * 12, s>>>(xr, yr, n, m, T, h, d_gb,
                                                                    d_coff, cstart, gv,
-                                                  gxy, pos_of_rank, qord, pl.pc_nbr, cnt));
+                                                  gxy, pos_of_rank, qord, nf.nbr, cnt));
     dfree(gxy);
     // 4. factor
-    pl.pc_coef = dmalloc<double>((size_t)n * m);
-    pl.pc_dinv = dmalloc<double>(n);
+    nf.coef = dmalloc<double>((size_t)n * m);
+    nf.dinv = dmalloc<double>(n);
     PHS_HIP(hipMemsetAsync(nfail, 0, 8, s));
     if (m <= 15)
       PHS_LAUNCH("vecchia_factor", s,
-                 k_factor<16><<<(n + 3) / 4, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
-                                                         alpha, pl.pc_coef, pl.pc_dinv, nfail,
+                 k_factor<16><<<(n + 3) / 4, 64, 0, s>>>(pl.x, pl.y, n, m, nf.nbr, cnt, nu2,
+                                                         alpha, nf.coef, nf.dinv, nfail,
                                                          pl.neartab));
     else if (m <= 31)
       PHS_LAUNCH("vecchia_factor", s,
-                 k_factor<32><<<(n + 1) / 2, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2,
-                                                         alpha, pl.pc_coef, pl.pc_dinv, nfail,
+                 k_factor<32><<<(n + 1) / 2, 64, 0, s>>>(pl.x, pl.y, n, m, nf.nbr, cnt, nu2,
+                                                         alpha, nf.coef, nf.dinv, nfail,
                                                          pl.neartab));
     else
       PHS_LAUNCH("vecchia_factor", s,
-                 k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, pl.pc_nbr, cnt, nu2, alpha,
-                                              pl.pc_coef, pl.pc_dinv, nfail, pl.neartab));
+                 k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, nf.nbr, cnt, nu2, alpha,
+                                              nf.coef, nf.dinv, nfail, pl.neartab));
     // 5. transpose: stable radix sort of the entries by row
     {
       const int64_t N = n * m;
@@ -730,22 +733,27 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
       int bits = 1;
       while (((int64_t)1 << bits) <= n) ++bits;
       PHS_LAUNCH("vecchia_tkeys", s,
-                 k_tkeys<<<(N + B - 1) / B, B, 0, s>>>(pl.pc_nbr, n, m, tk, tv));
+                 k_tkeys<<<(N + B - 1) / B, B, 0, s>>>(nf.nbr, n, m, tk, tv));
       bool in_tmp = false;
       radix_sort_u32(tk, tv, N, bits, tkt, tvt, tscr, s, &in_tmp);
       const uint32_t *sk = in_tmp ? tkt : tk;  // sorted keys and values
       const int32_t *sv = in_tmp ? tvt : tv;
-      pl.pc_tstart = dmalloc<int32_t>(n + 1);
-      leaf_ranges(sk, N, (int)n, pl.pc_tstart, s);
-      int32_t nnz = 0;
-      PHS_HIP(hipMemcpyAsync(&nnz, pl.pc_tstart + n, 4, hipMemcpyDeviceToHost, s));
-      PHS_HIP(hipStreamSynchronize(s));
-      pl.pc_tidx = dmalloc<int32_t>(std::max(nnz, 1));
-      pl.pc_tcoef = dmalloc<double>(std::max(nnz, 1));
-      if (nnz > 0)
-        PHS_LAUNCH("vecchia_tfill", s,
-                   k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(sv, nnz, n, m, pl.pc_coef,
-                                                          pl.pc_tidx, pl.pc_tcoef));
+      try {
+        nf.tstart = dmalloc<int32_t>(n + 1);
+        leaf_ranges(sk, N, (int)n, nf.tstart, s);
+        int32_t nnz = 0;
+        PHS_HIP(hipMemcpyAsync(&nnz, nf.tstart + n, 4, hipMemcpyDeviceToHost, s));
+        PHS_HIP(hipStreamSynchronize(s));
+        nf.tidx = dmalloc<int32_t>(std::max(nnz, 1));
+        nf.tcoef = dmalloc<double>(std::max(nnz, 1));
+        if (nnz > 0)
+          PHS_LAUNCH("vecchia_tfill", s,
+                     k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(sv, nnz, n, m, nf.coef, nf.tidx,
+                                                            nf.tcoef));
+      } catch (...) {
+        for (void *q : {(void *)tk, (void *)tkt, (void *)tv, (void *)tvt, (void *)tscr}) dfree(q);
+        throw;
+      }
       for (void *q : {(void *)tk, (void *)tkt, (void *)tv, (void *)tvt, (void *)tscr}) dfree(q);
     }
     // 6. forward factor to the column-major layout of the apply
@@ -759,22 +767,37 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
         throw;
       }
       PHS_LAUNCH("vecchia_ell", s,
-                 k_ell<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(pl.pc_nbr, pl.pc_coef, n, m,
+                 k_ell<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(nf.nbr, nf.coef, n, m,
                                                                  nbrT, coefT));
-      dfree(pl.pc_nbr);
-      dfree(pl.pc_coef);
-      pl.pc_nbr = nbrT;
-      pl.pc_coef = coefT;
+      dfree(nf.nbr);
+      dfree(nf.coef);
+      nf.nbr = nbrT;
+      nf.coef = coefT;
     }
     int32_t hfail[2] = {0, 0};
     PHS_HIP(hipMemcpyAsync(hfail, nfail, 8, hipMemcpyDeviceToHost, s));
     PHS_HIP(hipStreamSynchronize(s));
     PHS_REQUIRE(hfail[1] == 0, PHS_ERR_INVALID_ARGUMENT,
                 "Matern block not positive definite even with a diagonal nugget");
+    // commit: the previous factor is released (its blocks are recycled only
+    // once the device is idle) and the plan takes the new one
+    vecchia_free(pl);
+    pl.pc_rank = nf.rank;
+    pl.pc_nbr = nf.nbr;
+    pl.pc_coef = nf.coef;
+    pl.pc_dinv = nf.dinv;
+    pl.pc_tstart = nf.tstart;
+    pl.pc_tidx = nf.tidx;
+    pl.pc_tcoef = nf.tcoef;
+    pl.m = m;
+    pl.nu = nu;
+    pl.alpha = alpha;
     pl.pc_nugget_nodes = hfail[0];
     pl.has_pc = true;
   } catch (...) {
-    vecchia_free(pl);
+    for (void *q : {(void *)nf.rank, (void *)nf.nbr, (void *)nf.coef, (void *)nf.dinv,
+                    (void *)nf.tstart, (void *)nf.tidx, (void *)nf.tcoef})
+      dfree(q);
     for (void *q : {(void *)k64, (void *)k64t, (void *)perm, (void *)vt, (void *)scr, (void *)gk,
                     (void *)gkt, (void *)gv, (void *)gvt, (void *)cstart, (void *)d_lvl,
                     (void *)d_coff, (void *)d_gb, (void *)xr, (void *)yr, (void *)pos_of_rank,

@@ -29,7 +29,7 @@ EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval
            "phs_plan_destroy", "phs_batch_create", "phs_batch_solve", "phs_batch_destroy",
            "phs_server_create", "phs_server_submit", "phs_server_step", "phs_server_poll",
            "phs_server_memory", "phs_server_destroy",
-           "phs_last_error", "phs_profile_enable", "phs_profile_read")
+           "phs_last_error", "phs_memory_stats", "phs_profile_enable", "phs_profile_read")
 PHS_REQ_QUEUED, PHS_REQ_ACTIVE, PHS_REQ_DONE, PHS_REQ_FAILED = 0, 1, 2, 3
 
 
@@ -69,7 +69,10 @@ class RequestInfo(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer_refinements", C.c_int32),
-                ("rel_residual", C.c_double), ("t_solve", C.c_double)]
+                ("rel_residual", C.c_double), ("t_solve", C.c_double),
+                ("iters_fp32", C.c_int32), ("iters_fp64", C.c_int32),
+                ("fp64_fallback", C.c_int32), ("reserved", C.c_int32),
+                ("t_plan", C.c_double), ("t_precond", C.c_double)]
 
 
 class PHSError(RuntimeError):
@@ -117,6 +120,7 @@ def lib() -> C.CDLL:
         L.phs_server_destroy.argtypes = [vp]
         L.phs_server_destroy.restype = None
         L.phs_last_error.restype = C.c_char_p
+        L.phs_memory_stats.argtypes = [C.POINTER(i64)] * 4
         L.phs_profile_enable.argtypes = [i32]
         L.phs_profile_enable.restype = None
         L.phs_profile_read.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_double), i32]
@@ -125,7 +129,7 @@ def lib() -> C.CDLL:
                      "phs_plan_info", "phs_plan_tree", "phs_precond_export",
                      "phs_precond_apply", "phs_batch_create", "phs_batch_solve",
                      "phs_server_create", "phs_server_submit", "phs_server_step",
-                     "phs_server_poll", "phs_server_memory"):
+                     "phs_server_poll", "phs_server_memory", "phs_memory_stats"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -161,6 +165,25 @@ class Info:
     rel_residual: float
     t_solve: float
     status: str
+    iters_fp32: int = 0
+    iters_fp64: int = 0
+    fp64_fallback: int = 0
+    t_plan: float = 0.0
+    t_precond: float = 0.0
+
+
+def _info(i: SolveInfo, st: int) -> Info:
+    return Info(i.iters, i.outer_refinements, i.rel_residual, i.t_solve,
+                STATUS.get(st, str(st)), i.iters_fp32, i.iters_fp64, i.fp64_fallback,
+                i.t_plan, i.t_precond)
+
+
+def memory_stats():
+    """(allocations, device_mallocs, bytes_in_use, bytes_held) of the library's
+    device pool."""
+    a, m, u, b = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().phs_memory_stats(C.byref(a), C.byref(m), C.byref(u), C.byref(b)))
+    return a.value, m.value, u.value, b.value
 
 
 class Plan:
@@ -235,8 +258,7 @@ class Plan:
                              _dev(beta, "beta"), C.byref(inf), _stream())
         if raise_on_error:
             _check(st)
-        info = Info(inf.iters, inf.outer_refinements, inf.rel_residual, inf.t_solve,
-                    STATUS.get(st, str(st)))
+        info = _info(inf, st)
         if f.dim() == 1:
             return w, beta, info
         return w.view(nrhs, self.n).t(), beta.view(nrhs, self.S).t(), info
@@ -311,8 +333,7 @@ class Batch:
                 out.append((w, b))
             else:
                 out.append((w.view(r, p.n).t(), b.view(r, p.S).t()))
-        infos = [Info(i.iters, i.outer_refinements, i.rel_residual, i.t_solve,
-                      STATUS.get(st, str(st))) for i in infs]
+        infos = [_info(i, st) for i in infs]
         return out, infos
 
     def close(self) -> None:

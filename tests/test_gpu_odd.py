@@ -57,9 +57,8 @@ def test_odd_solve_and_eval(k, d):
           f"(floor {dw:.2e}) interp {es:.2e} node residual {er:.2e}")
     assert es <= 1e-8
     assert er <= 1e-8
-    # the weights of the odd-order systems are ill-determined (two direct
-    # solvers already disagree by dw); they are compared loosely
-    assert ew <= max(1e-6, 30 * dw)
+    # floor-aware: two direct solvers already disagree on w by dw
+    assert ew <= max(1e-8, 10 * dw)
 
 
 # Chebyshev order Q per axis set explicitly: every FP64 M2L tile shape

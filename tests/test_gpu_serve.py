@@ -4,12 +4,17 @@ their PCG iterations sharing launches (continuous batching).
 
 Gates: every request finishes; its weights, coefficients and target values
 are bitwise equal to serving it alone through phs_plan + phs_precond_build +
-phs_solve + phs_eval with the same options; the server never holds more
-device memory than its budget; requests really overlapped (more than one
-active at once) and some waited for memory."""
+phs_solve + phs_eval with the same options; against the dense FP64 oracle
+(eq. phs_linsys_solve, n <= 8000) each served interpolant agrees at its
+targets to 1e-8 (max-norm relative) and its node residual
+RMS(f - M w - B beta) / RMS(f) is <= 1e-8; the device memory the library holds
+while serving (its pool's bytes in use) grows by no more than the budget;
+requests really overlapped (more than one active at once) and some waited for
+memory."""
 import numpy as np
 import pytest
 
+from oracle import phs_dense as D
 from paper_2608_11462_amd import native as N
 from paper_2608_11462_amd import workloads as W
 from tests.gpu_util import dev, host
@@ -29,6 +34,16 @@ def _requests(seed, count):
         tg = W.uniform_points(g, 300)
         out.append((xy, f, tg, k, int(rng.integers(20, 41))))
     return out
+
+
+_ORACLE = {}
+
+
+def _oracle(xy, f, k):
+    key = (len(xy), k, float(xy[0, 0]))
+    if key not in _ORACLE:
+        _ORACLE[key] = D.solve_complement(xy, f, k)
+    return _ORACLE[key]
 
 
 def _alone(xy, f, tg, k, m, precision, rtol):
@@ -51,6 +66,7 @@ def test_serving_stream_matches_alone(precision):
                                    nu=r[3] / 2.0, seed=1)).bytes for r in reqs]
     probe.close()
     budget = 3 * max(est)
+    in_use0 = N.memory_stats()[2]
     srv = N.Server(hbm_budget=budget, max_active=6, precision=precision, rtol=1e-9)
     ids = []
     pending = list(range(len(reqs)))
@@ -71,6 +87,8 @@ def test_serving_stream_matches_alone(precision):
         if queued and active:
             waited = True
         assert used <= budget and peak <= budget
+        held = N.memory_stats()[2] - in_use0  # device bytes the library really holds
+        assert held <= budget, (held, budget)
         if not pending and active == 0 and queued == 0:
             break
         assert steps < 20000
@@ -88,6 +106,16 @@ def test_serving_stream_matches_alone(precision):
         np.testing.assert_array_equal(w, wa)
         np.testing.assert_array_equal(beta, ba)
         np.testing.assert_array_equal(vals, va)
+        # against the dense oracle
+        ref = _oracle(xy, f, k)
+        s_ref = D.interpolant(ref, k, tg)
+        e_s = np.abs(vals - s_ref).max() / np.abs(s_ref).max()
+        xi = ref["xi"]
+        res = f - D.kernel_matrix(k, xi, xi) @ w - D.poly_block(xi, ref["degree"]) @ beta
+        e_r = np.sqrt(np.mean(res ** 2)) / np.sqrt(np.mean(f ** 2))
+        print(f"    vs oracle: interpolant {e_s:.2e} node residual {e_r:.2e}")
+        assert e_s <= 1e-8
+        assert e_r <= 1e-8
     srv.close()
 
 

@@ -108,6 +108,30 @@ def test_nu2_structure_k4():
     _check_structure(xy, 4, 50, 2.0, 2.0, 5, 0.0, N.PHS_RANGE_NORMALIZED)
 
 
+def test_large_tps_ordering_and_sampled_knn_bit_exact():
+    """The benchmark workload (n = 2^20, m = 30): the rank of every node, and the
+    ordered neighbour lists of 1024 sampled nodes, bitwise against the brute
+    force (the deeper rank-prefix grid levels of the search only occur here)."""
+    pr = W.large_tps()
+    print(f"[case] large_tps vecchia structure n={pr.n}", flush=True)
+    m = 30
+    pl = N.Plan(dev(pr.xy), 2, 1)
+    pl.precond_build(m=m, nu=1.0, seed=0)
+    rank_g, nbr_g, _, _ = pl.precond_export(m)
+    rank_g, nbr_g = host(rank_g), host(nbr_g)
+    pl.close()
+    c, rho, xi = D.normalize(pr.xy, 2)
+    perm, rank = V.order(pr.n, 0)
+    np.testing.assert_array_equal(rank_g, rank)
+    q = W.sample_rows(21, pr.n, 1024)
+    # the earliest ranks (full conditioning, the coarse grid levels) as well
+    q = np.unique(np.concatenate([q, perm[:64], perm[1000:1016]]))
+    nbrs = V.ordered_knn(xi, perm, rank, m, q)
+    for j, s in zip(q, nbrs):
+        np.testing.assert_array_equal(nbr_g[j, :len(s)], s)
+        assert np.all(nbr_g[j, len(s):] == -1)
+
+
 @pytest.mark.parametrize("precision", [N.PHS_FP64, N.PHS_MIXED])
 @pytest.mark.parametrize("pc", ["config", "paper"])
 def test_small_config_solve(precision, pc):

@@ -13,6 +13,7 @@ import pytest
 import scipy.linalg as sla
 from scipy.spatial import cKDTree
 
+from oracle import direct as DC
 from oracle import pcg as OP
 from oracle import phs_dense as D
 from oracle import vecchia as V
@@ -202,6 +203,44 @@ def test_sampled_rows_match_dense():
                                D.matvec_dense(3, xi, v)[rows], rtol=1e-12, atol=1e-13)
 
 
+@pytest.mark.parametrize("n", [500, 2000])
+@pytest.mark.parametrize("k", [2, 3])
+def test_eval_points_pinned(n, k):
+    """eq. phs_interp by direct summation: at the nodes it reproduces the data
+    (the interpolation conditions fix it, independently of how w and beta were
+    found); at off-node targets it equals the dense evaluation, and both the
+    numpy and the C direct sums agree with beta^T P(t) + w^T phi(|t - x|)."""
+    xy = _pts(160 + n + k, n)
+    f = W.f_small(xy)
+    sol = D.solve_complement(xy, f, k)
+    d, xi = sol["degree"], sol["xi"]
+    at_nodes = D.eval_points(k, xi, sol["w"], sol["beta"], d, xi)
+    assert np.abs(at_nodes - f).max() <= 1e-11 * np.abs(f).max()
+    at_nodes_c = DC.eval_points(k, xi, sol["w"], sol["beta"], d, xi)
+    assert np.abs(at_nodes_c - f).max() <= 1e-11 * np.abs(f).max()
+    tg = W.uniform_points(W.rng_for(170 + n), 97) * 1.2 - 0.1  # some outside the box
+    xt = (tg - sol["c"]) * sol["rho"]
+    ref = D.interpolant(sol, k, tg)
+    for got in (D.eval_points(k, xi, sol["w"], sol["beta"], d, xt, col_chunk=333),
+                DC.eval_points(k, xi, sol["w"], sol["beta"], d, xt)):
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    # the polynomial part matters: dropping it breaks interpolation
+    no_poly = DC.kernel_sums(k, xi, sol["w"], xi)
+    assert np.abs(no_poly - f).max() > 1e-3 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_c_direct_sums_match_dense(k):
+    """The C direct sums against the dense kernel matrix, on rows that include
+    the r = 0 diagonal and on targets equal to nodes."""
+    xy = _pts(180 + k, 900)
+    c, rho, xi = D.normalize(xy, k)
+    v = W.rng_for(181).standard_normal(900)
+    rows = W.sample_rows(182, 900, 64)
+    np.testing.assert_allclose(DC.matvec_rows(k, xi, v, rows), D.matvec_dense(k, xi, v)[rows],
+                               rtol=1e-12, atol=1e-12 * np.abs(v).sum())
+
+
 def test_leaf_order_cells_contain_points():
     xy = _pts(140, 3000)
     c, rho, xi = D.normalize(xy, 2)
@@ -280,6 +319,28 @@ def test_ordered_knn_against_kdtree():
         kk = min(m, t)
         dd, ii = tree.query(xi[j], k=kk)
         np.testing.assert_array_equal(np.sort(prior[np.atleast_1d(ii)]), np.sort(s))
+
+
+def test_knn_tie_order_golden():
+    """The tie rule of the ordered neighbour lists, pinned by a hand-worked 4 x 4
+    lattice (tests/golden/knn_lattice_ties.txt): equal squared distances are
+    ordered by rank."""
+    lines = [l for l in (GOLD / "knn_lattice_ties.txt").read_text().splitlines()
+             if l.strip() and not l.startswith("#")]
+    pts, ranks, expect = [], [], {}
+    for line in lines:
+        head, tail = line.split(":")
+        p, r = map(int, head.split())
+        pts.append(p)
+        ranks.append(r)
+        expect[p] = [int(t) for t in tail.split()]
+    xi = np.array([[p % 4, p // 4] for p in range(16)], dtype=np.float64)
+    rank = np.empty(16, dtype=np.int64)
+    rank[pts] = ranks
+    perm = np.argsort(rank)
+    got = V.ordered_knn(xi, perm, rank, 4)
+    for p in range(16):
+        assert list(got[p]) == expect[p], (p, list(got[p]), expect[p])
 
 
 def test_vecchia_unit_conditional_variance():
