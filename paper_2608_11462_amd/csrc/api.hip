@@ -336,11 +336,13 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
     pl.pe = std::max(pl.p64, 31);
   } else {
     // Chebyshev nodes per axis: 12 -> ~2e-12, 16 -> ~1e-14 core relative error.
-    // From 2^17 nodes on, 16: the Vecchia factor of the odd-order Matern
-    // covariance grows with the node density (entries ~1e17 at 1e6 nodes) and
-    // turns a 1e-12 matvec error into a loss of definiteness in PCG.
-    pl.q64 = o->expansion_order > 0 ? o->expansion_order
-                                    : ((tol >= 1e-13 && n < (int64_t(1) << 17)) ? 12 : 16);
+    // The default is 16 at every size: the odd-order saddle systems are
+    // ill-conditioned enough (kappa ~1e4 for k = 1, ~1e7 for k = 3 at a few
+    // thousand clustered nodes) that a 2e-12 matvec error moves the weights
+    // by 1e-8..1e-5, and from 2^17 nodes on the Vecchia factor of the
+    // odd-order Matern covariance (entries ~1e17 at 1e6 nodes) turns it into
+    // a loss of definiteness in PCG.  A looser fmm_tol (>= 1e-10) takes 12.
+    pl.q64 = o->expansion_order > 0 ? o->expansion_order : (tol >= 1e-10 ? 12 : 16);
     pl.q32 = 8;
     PHS_REQUIRE(pl.q64 == 8 || pl.q64 == 10 || pl.q64 == 12 || pl.q64 == 14 || pl.q64 == 16,
                 PHS_ERR_INVALID_ARGUMENT, "Chebyshev order must be 8, 10, 12, 14 or 16");

@@ -451,7 +451,8 @@ struct Request {
   phs_status status = PHS_OK;
   Plan *plan = nullptr;
   SolveJob job;
-  int64_t bytes = 0;
+  int64_t bytes = 0;      // estimate while queued, measured once built
+  bool measured = false;
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
@@ -460,6 +461,7 @@ struct Server {
   SolveParams P{1e-8, 500, 1, PHS_FP64};
   hipStream_t s = nullptr;
   int64_t budget = 0, in_use = 0, peak = 0;
+  int64_t forest_bytes = 0;  // descriptors and work tables of the shared forest
   int64_t next_id = 1;
   std::vector<Request *> queue;    // FIFO
   std::vector<Request *> active;

@@ -25,8 +25,10 @@ double now_s() {
 
 }  // namespace
 
-// Upper estimate of the device memory of one request with the default plan
-// options (leaf size 40/64, FP64 log orders 27 and 31, Chebyshev 12 and 16):
+// Estimate of the device memory of one request with the default plan options
+// (leaf size 40/64, FP64 log orders 27 and 31, Chebyshev 16 and FP32 8), used
+// to decide whether a waiting request may be admitted; once built, the
+// request is charged what it really holds.  Counted:
 // node arrays, polynomial block, FMM workspace of one system and its tables,
 // ten Krylov vectors, the Vecchia factor and its transpose, and the peak of
 // the temporaries of the preconditioner build.
@@ -46,7 +48,7 @@ int64_t request_bytes(int64_t n, int k, int m) {
     tables = 3 * (32LL * 32 * 8 * 9 + 512);
   } else {
     exp = 256LL * R * boxes / 3 * 8;
-    tables = 40LL * (144 * 144 * 12 + 256 * 256 * 8 + 64 * 64 * 4);
+    tables = 40LL * (256 * 256 * 8 + 64 * 64 * 4) + (4 << 20);
   }
   const int64_t nodes = n * (52 + 8LL * S + 10 * 8 + 4);
   const int64_t vecchia = n * (16 + 24LL * mm);
@@ -108,17 +110,31 @@ void fail(Server &sv, Request *r, phs_status st) {
   r->plan = nullptr;
 }
 
-// plan + preconditioner of a request; returns false (request failed) on error
+int64_t pool_in_use() {
+  int64_t u = 0;
+  pool_stats(nullptr, nullptr, &u, nullptr);
+  return u;
+}
+
+// plan + preconditioner of a request; returns false (request failed) on
+// error.  The request is then charged the device bytes it really holds (the
+// pool's bytes in use before and after the build; the build's temporaries
+// are recycled by then).
 bool admit(Server &sv, Request *r) {
   const phs_request &in = r->in;
   phs_plan_opts po{};
   po.k = in.k;
   po.poly_degree = in.poly_degree;
   po.precision = sv.opts.precision;
+  pool_mark_idle();
+  const int64_t u0 = pool_in_use();
   try {
     r->plan = new Plan();
     create_plan(in.xy, in.n, &po, sv.s, *r->plan);
     vecchia_build(*r->plan, in.precond, sv.s);
+    pool_mark_idle();
+    r->bytes = std::max<int64_t>(pool_in_use() - u0, 0);
+    r->measured = true;
   } catch (const Error &e) {
     set_error(e.code, e.msg);
     (void)hipStreamSynchronize(sv.s);
@@ -151,19 +167,41 @@ void server_step(Server &sv) {
       fail(sv, r, PHS_ERR_OUT_OF_MEMORY);
       continue;
     }
-    if (sv.in_use + r->bytes > sv.budget) break;
+    // the shared forest grows with each member (descriptors and work tables,
+    // well under 1/32 of a request's own memory): keep that much in hand
+    if (sv.in_use + sv.forest_bytes + r->bytes + r->bytes / 32 > sv.budget) break;
     sv.queue.erase(sv.queue.begin());
     if (!admit(sv, r)) continue;
+    if (sv.in_use + sv.forest_bytes + r->bytes + r->bytes / 32 > sv.budget) {
+      // its real footprint is larger than the estimate and does not fit now:
+      // release it and let it wait at the head of the queue with its
+      // measured size
+      delete r->plan;
+      r->plan = nullptr;
+      r->state = PHS_REQ_QUEUED;
+      pool_mark_idle();
+      if (r->bytes > sv.budget) {
+        set_error(PHS_ERR_OUT_OF_MEMORY, "request larger than the server's memory budget");
+        fail(sv, r, PHS_ERR_OUT_OF_MEMORY);
+        continue;
+      }
+      sv.queue.insert(sv.queue.begin(), r);
+      break;
+    }
     sv.in_use += r->bytes;
-    sv.peak = std::max(sv.peak, sv.in_use);
+    sv.peak = std::max(sv.peak, sv.in_use + sv.forest_bytes);
     sv.active.push_back(r);
     fresh.push_back(r);
     sv.changed = true;
   }
-  // 2. the forest of active systems
+  // 2. the forest of active systems (its descriptors and work tables are
+  // charged to the server as measured)
   if (sv.changed) {
     delete sv.F;
     sv.F = nullptr;
+    pool_mark_idle();
+    const int64_t u0 = pool_in_use();
+    sv.forest_bytes = 0;
     if (!sv.active.empty()) {
       std::vector<Plan *> pl;
       std::vector<SysWork *> wk;
@@ -174,6 +212,8 @@ void server_step(Server &sv) {
       }
       sv.F = new Forest();
       build_forest(*sv.F, pl, wk, s);
+      sv.forest_bytes = std::max<int64_t>(pool_in_use() - u0, 0);
+      sv.peak = std::max(sv.peak, sv.in_use + sv.forest_bytes);
     }
     sv.changed = false;
   }
@@ -235,6 +275,13 @@ void server_step(Server &sv) {
   }
   if (keep.size() != sv.active.size()) pool_mark_idle();
   sv.active = keep;
+  if (sv.active.empty()) {
+    delete sv.F;
+    sv.F = nullptr;
+    sv.forest_bytes = 0;
+    sv.changed = false;
+    pool_mark_idle();
+  }
 }
 
 void server_poll(Server &sv, int64_t id, phs_request_info &info) {

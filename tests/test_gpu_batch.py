@@ -135,15 +135,15 @@ def test_batch_uneven_many():
 
 
 def test_batch_mixed_chebyshev_orders():
-    """Odd-order plans below and above 2^17 nodes use Chebyshev orders 12 and
-    16; in one batch they run in one launch group per order and still match
-    their solo solves bitwise."""
+    """Odd-order plans with Chebyshev orders 12 (set explicitly) and 16 (the
+    default): in one batch they run in one launch group per order and still
+    match their solo solves bitwise."""
     items = []
-    for i, (n, k) in enumerate([(3000, 3), (140000, 3), (5000, 1), (2500, 2)]):
+    for i, (n, k, q) in enumerate([(3000, 3, 12), (140000, 3, 0), (5000, 1, 12), (2500, 2, 0)]):
         g = W.rng_for(7000 + i)
         xy = W.clustered_points(g, n) if i % 2 else W.uniform_points(g, n)
         f = W.fourier_field(g, kmax=4)(xy)
-        pl = N.Plan(dev(xy), k)
+        pl = N.Plan(dev(xy), k, expansion_order=q)
         pl.precond_build(m=40, nu=k / 2.0, seed=i)
         items.append((pl, f))
     print("[case] orders", [p.order for p, _ in items], flush=True)
