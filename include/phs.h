@@ -70,6 +70,10 @@ typedef enum {
  * phs_solve the two mixed modes run inside FP64 residual refinement: the exit
  * test is always on the FP64 residual. */
 enum { PHS_FP64 = 0, PHS_MIXED = 1, PHS_NEAR32 = 2 };
+/* How a plan applies M: by the FMM of Sec. 2.1, or exactly, by all-pairs
+ * summation on the GPU (the exact-matvec solver of Sec. 3.3; no FMM tables or
+ * expansions are built, and evaluation at targets sums directly too). */
+enum { PHS_MATVEC_FMM = 0, PHS_MATVEC_DIRECT = 1 };
 enum { PHS_RANGE_NORMALIZED = 0, PHS_RANGE_USER = 1 };
 
 typedef struct phs_plan_s *phs_plan_t; /* opaque; owns all device state */
@@ -86,6 +90,10 @@ typedef struct {
   int32_t leaf_size;       /* mean points per leaf box; 0 => automatic */
   int32_t expansion_order; /* log kernel: terms p; distance kernel: Chebyshev
                               nodes per axis; 0 => from fmm_tol */
+  int32_t matvec;          /* PHS_MATVEC_FMM (0) or PHS_MATVEC_DIRECT; with
+                              DIRECT the pairs are summed in FP64 for
+                              PHS_FP64 and in FP32 (FP32 accumulation) for
+                              PHS_MIXED and PHS_NEAR32 */
 } phs_plan_opts;
 
 /* Preconditioner options (Sec. 2.2; conditioning-set sizes of Sec. 3). */
@@ -308,6 +316,23 @@ void phs_server_destroy(phs_server_t srv);
 
 /* Message for the last non-OK status returned on this thread. */
 const char *phs_last_error(void);
+
+/* Direct (all-pairs) PHS kernel sums on the GPU, without a plan:
+ *   out[t] = sum_j q[j] phi(|targets_t - xy_j|),  phi(r) = r^k (k odd),
+ *   r^k log r (k even), phi(0) = 0
+ * (the kernel part of eq. phs_interp; with targets = xy it is M q, eq.
+ * phs_linsys), in FP64, in the coordinates given (no normalisation).
+ * k: 1..4.  xy: device n x 2 row-major; q: device n; targets: device m x 2;
+ * out: device m (all caller-owned).  m may be 0.  Cost O(n m): meant for
+ * sizes below the FMM's break-even and as an exact check.  The sum over the
+ * sources is split into chunks whose partial sums are added in a fixed order
+ * (results do not depend on scheduling); the partials live in device scratch
+ * that this call takes from the library's pool (released when the device is
+ * next idle).  Asynchronous (the first call on a device also uploads a
+ * 4 KB logarithm table, synchronously).  Errors: INVALID_ARGUMENT,
+ * OUT_OF_MEMORY, DEVICE. */
+phs_status phs_direct_sum(int32_t k, const double *xy, int64_t n, const double *q,
+                          const double *targets, int64_t m, double *out, void *stream);
 
 /* Device-memory counters of the library's caching pool (all host pointers,
  * any may be NULL): allocations = blocks handed out so far (from the cache or

@@ -327,6 +327,9 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
   pl.precision = o->precision;
   pl.hnorm = domain_half_width(pl.k);
   pl.tree.h = pl.hnorm;
+  PHS_REQUIRE(o->matvec == PHS_MATVEC_FMM || o->matvec == PHS_MATVEC_DIRECT,
+              PHS_ERR_INVALID_ARGUMENT, "matvec must be PHS_MATVEC_FMM or PHS_MATVEC_DIRECT");
+  pl.direct = o->matvec == PHS_MATVEC_DIRECT;
   const double tol = o->fmm_tol > 0 ? o->fmm_tol : 1e-12;
   if (pl.core_log) {
     pl.p64 = o->expansion_order > 0 ? o->expansion_order : order_for_tol(tol, true);
@@ -379,9 +382,10 @@ void plan_create(const double *xy, int64_t n, const phs_plan_opts *o, hipStream_
   poly_block_tree(pl.x, pl.y, n, pl.d, pl.Q, s);
   thin_qr(pl, s);
 
-  // FMM tables and workspace
-  size_t eb;
-  if (pl.core_log) {
+  // FMM tables and workspace (none for a plan that sums directly)
+  size_t eb = 0;
+  if (pl.direct) {
+  } else if (pl.core_log) {
     build_log_tables(pl.lt64, pl.p64);
     build_log_tables(pl.lt32, pl.p32);
     if (pl.pe != pl.p64) build_log_tables(pl.lte, pl.pe);
@@ -426,7 +430,9 @@ void eval_plan(Plan &pl, const double *w, const double *beta, int nrhs, const do
   for (int c = 0; c < nrhs; ++c) {
     f_gather_user(*pl.self, 0, w + (int64_t)c * pl.n, V_IN, s);
     const double *wt = pl.sw.v[V_IN];
-    if (pl.core_log) {
+    if (pl.direct) {
+      direct_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m, s);
+    } else if (pl.core_log) {
       log_expansions(pl, V_IN, s);
       log_eval_targets(pl, wt, beta + (int64_t)c * pl.S, targets, m, out + (int64_t)c * m, s);
     } else {
@@ -774,6 +780,29 @@ void phs_plan_destroy(phs_plan_t plan) {
 }
 
 const char *phs_last_error(void) { return g_last_error.c_str(); }
+
+phs_status phs_direct_sum(int32_t k, const double *xy, int64_t n, const double *q,
+                          const double *targets, int64_t m, double *out, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(k >= 1 && k <= 4, PHS_ERR_INVALID_ARGUMENT, "k must be 1..4");
+    PHS_REQUIRE(n >= 1 && m >= 0 && n < (int64_t(1) << 31) && m < (int64_t(1) << 31),
+                PHS_ERR_INVALID_ARGUMENT, "bad sizes");
+    PHS_REQUIRE(xy && q && (m == 0 || (targets && out)), PHS_ERR_INVALID_ARGUMENT,
+                "null argument");
+    if (m == 0) return PHS_OK;
+    hipStream_t s = S(stream);
+    const int64_t need = direct_scratch_doubles(m, n);
+    double *scr = need > 0 ? dmalloc<double>(need) : nullptr;
+    try {
+      direct_sum_plain(k, xy, n, q, targets, m, out, scr, need, s);
+    } catch (...) {
+      dfree(scr);
+      throw;
+    }
+    dfree(scr);  // recycled only once the device is idle
+    return PHS_OK;
+  });
+}
 
 phs_status phs_memory_stats(int64_t *allocations, int64_t *device_mallocs,
                             int64_t *bytes_in_use, int64_t *bytes_held) {

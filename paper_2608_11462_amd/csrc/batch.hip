@@ -22,7 +22,7 @@ void batch_create(Batch &b, const std::vector<Plan *> &plans, const std::vector<
   for (size_t i = 0; i < plans.size(); ++i) {
     PHS_REQUIRE(plans[i] && nrhs[i] >= 1, PHS_ERR_INVALID_ARGUMENT, "bad plan or rhs count");
     const Plan &p = *plans[i];
-    if (p.core_log) {
+    if (p.core_log && !p.direct) {
       if (!ev) ev = &p;
       PHS_REQUIRE(p.p64 == ev->p64 && p.p32 == ev->p32, PHS_ERR_INVALID_ARGUMENT,
                   "even-order plans of a batch must share their expansion orders");

@@ -953,7 +953,7 @@ void dist_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
   const int tier = precision == PHS_MIXED ? 1 : 0;
   std::vector<int> done;
   for (const Plan *p : F.plan) {
-    if (p->core_log) continue;
+    if (p->core_log || p->direct) continue;
     const int Q = tier ? p->q32 : p->q64;
     if (std::find(done.begin(), done.end(), Q) != done.end()) continue;
     done.push_back(Q);

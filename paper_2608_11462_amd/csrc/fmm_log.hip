@@ -1013,7 +1013,7 @@ void leaf_pass(Forest &F, const int32_t *mask, int in, int out, int P, const dou
 
 const Plan &log_ref(const Forest &F) {
   for (const Plan *p : F.plan)
-    if (p->core_log) return *p;
+    if (p->core_log && !p->direct) return *p;
   throw Error{PHS_ERR_INVALID_ARGUMENT, "forest has no even-order system"};
 }
 

@@ -379,9 +379,12 @@ void SysWork::release() {
   for (auto &p : v) dfree(p);
   dfree(red);
   dfree(sc);
+  dfree(dpart);
   mp = loc = nullptr;
   for (auto &p : v) p = nullptr;
   red = sc = nullptr;
+  dpart = nullptr;
+  dpart_cap = 0;
 }
 
 void alloc_syswork(SysWork &w, const Plan &pl) {
@@ -391,6 +394,10 @@ void alloc_syswork(SysWork &w, const Plan &pl) {
     for (auto &p : w.v) p = dmalloc<double>(pl.n);
     w.red = dmalloc<double>((size_t)dot_blocks(pl.n) * 32);
     w.sc = dmalloc<double>(kSysScal);
+    if (pl.direct) {
+      w.dpart_cap = direct_scratch_doubles(pl.n, pl.n);
+      if (w.dpart_cap > 0) w.dpart = dmalloc<double>(w.dpart_cap);
+    }
   } catch (...) {
     w.release();
     throw;
@@ -465,7 +472,8 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
     F.maxS = std::max(F.maxS, pl.S);
     if (pl.S >= kDotSlot)  // the projection's partials must not reach kDotSlot
       throw Error{PHS_ERR_INVALID_ARGUMENT, "polynomial space too large for the PCG reductions"};
-    if (pl.core_log) F.maxL_log = std::max(F.maxL_log, pl.tree.L);
+    if (pl.direct) F.any_direct = true;
+    else if (pl.core_log) F.maxL_log = std::max(F.maxL_log, pl.tree.L);
     else F.maxL_dist = std::max(F.maxL_dist, pl.tree.L);
     const int64_t nv = (pl.n + kBlock - 1) / kBlock;
     for (int64_t b = 0; b < nv; ++b) hv.push_back({i, (int32_t)b});
@@ -511,7 +519,7 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
     for (int prec : {PHS_FP64, PHS_MIXED, PHS_NEAR32})
       f_matvec(F, F.mask[0], V_IN, V_OUT, prec, s);
     for (Plan *pl : plans) {
-      if (pl->self != &F) continue;
+      if (pl->self != &F || pl->direct) continue;
       if (pl->core_log) log_expansions(*pl, V_IN, s);
       else dist_expansions(*pl, V_IN, s);
     }
@@ -682,6 +690,7 @@ void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t 
 void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hipStream_t s) {
   if (F.maxL_log > 0) log_matvec(F, mask, in, out, precision, s);
   if (F.maxL_dist > 0) dist_matvec(F, mask, in, out, precision, s);
+  if (F.any_direct) direct_matvec(F, mask, in, out, precision, s);
 }
 
 // Work-item tables of the FMM kernels, one per (kind, K, P, level), all built
@@ -714,6 +723,7 @@ Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
   const int tier = kind >> 4, base = kind & 15;
   for (int i = 0; i < F.nsys; ++i) {
     const Plan &pl = *F.plan[i];
+    if (pl.direct) continue;  // no FMM
     const int L = pl.tree.L, R = pl.R;
     const bool log_k = pl.core_log;
     const int qsel = tier == 0 ? pl.q64 : (tier == 1 ? pl.q32 : pl.qe);

@@ -239,6 +239,8 @@ struct SysWork {  // device workspace of one system
   double *v[kSysVecs] = {};
   double *red = nullptr;
   double *sc = nullptr;
+  double *dpart = nullptr;  // chunk partial sums of the direct matvec (direct plans)
+  int64_t dpart_cap = 0;    // doubles
   void release();
 };
 
@@ -249,6 +251,7 @@ struct Plan {
   int precision = PHS_FP64;
   int sign = 1;
   bool core_log = true;
+  bool direct = false;  // M applied by all-pairs summation instead of the FMM
   double c[2] = {0, 0};
   double rho = 1;
   double hnorm = 0.25;  // half-width of the normalised domain (tree.h >= hnorm)
@@ -333,6 +336,7 @@ struct Forest {
   std::vector<std::vector<BlkRef>> hcopies;  // host sources of the table uploads
   Tab vec, dot, pc;                     // element blocks, dot blocks, 8-row blocks
   std::vector<std::pair<uint64_t, Tab>> cache;  // FMM tables keyed by (kind, K, P, level)
+  bool any_direct = false;  // some system's plan applies M by direct summation
   bool frozen = false;  // every table is built: a lookup miss is an internal error
   ~Forest();
 };
@@ -540,6 +544,34 @@ void log_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                       const double *targets, int64_t m, double *out, hipStream_t s);
 void dist_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                        const double *targets, int64_t m, double *out, hipStream_t s);
+
+// direct.hip: all-pairs kernel sums out_i = sum_j q_j phi(|t_i - x_j|), t_i
+// taken as (t - c) rho; split over source chunks whose partial sums go to
+// `scratch` (nch x nt doubles, none when one chunk suffices) and are added in
+// chunk order; beta (may be null): adds the polynomial part of degree d.
+struct DirectSplit {
+  int64_t ntiles = 1;  // target tiles of 256
+  int nch = 1;         // source chunks
+  int64_t chunk = 0;   // sources per chunk (a multiple of 256)
+};
+// cap >= 0: at most cap doubles of partials (fewer chunks if needed)
+DirectSplit direct_split(int64_t nt, int64_t ns, int64_t cap);
+int64_t direct_scratch_doubles(int64_t nt, int64_t ns);  // uncapped split
+// fit_scratch: take the split that fits scratch_cap; otherwise the uncapped
+// split, which must fit (INVALID_ARGUMENT if not)
+void direct_sum(int k, bool fp64, const double *src, const double *q, int64_t ns,
+                const double *tg, int64_t nt, double tcx, double tcy, double trho,
+                const double *beta, int d, double *out, double *scratch, int64_t scratch_cap,
+                const double *neartab, const int32_t *mask, int sys, hipStream_t s,
+                bool fit_scratch);
+void direct_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
+                   hipStream_t s);
+void direct_eval_targets(Plan &pl, const double *w_tree, const double *beta,
+                         const double *targets, int64_t m, double *out, hipStream_t s);
+// plan-free FP64 direct sum in the caller's coordinates (no normalisation)
+void direct_sum_plain(int k, const double *xy, int64_t n, const double *q, const double *targets,
+                      int64_t m, double *out, double *scratch, int64_t cap, hipStream_t s);
+void fill_near_log_table(double *tab);
 
 // vecchia.hip
 void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s);

@@ -16,6 +16,7 @@ import torch
 LIB_PATH = Path(__file__).resolve().parent / "libphs.so"
 
 PHS_FP64, PHS_MIXED, PHS_NEAR32 = 0, 1, 2
+PHS_MATVEC_FMM, PHS_MATVEC_DIRECT = 0, 1
 PHS_RANGE_NORMALIZED, PHS_RANGE_USER = 0, 1
 
 STATUS = {
@@ -29,14 +30,15 @@ EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval
            "phs_plan_destroy", "phs_batch_create", "phs_batch_solve", "phs_batch_destroy",
            "phs_server_create", "phs_server_submit", "phs_server_step", "phs_server_poll",
            "phs_server_memory", "phs_server_destroy",
-           "phs_last_error", "phs_memory_stats", "phs_profile_enable", "phs_profile_read")
+           "phs_direct_sum", "phs_last_error", "phs_memory_stats", "phs_profile_enable",
+           "phs_profile_read")
 PHS_REQ_QUEUED, PHS_REQ_ACTIVE, PHS_REQ_DONE, PHS_REQ_FAILED = 0, 1, 2, 3
 
 
 class PlanOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("poly_degree", C.c_int32), ("precision", C.c_int32),
                 ("fmm_tol", C.c_double), ("leaf_size", C.c_int32),
-                ("expansion_order", C.c_int32)]
+                ("expansion_order", C.c_int32), ("matvec", C.c_int32)]
 
 
 class PrecondOpts(C.Structure):
@@ -121,6 +123,7 @@ def lib() -> C.CDLL:
         L.phs_server_destroy.restype = None
         L.phs_last_error.restype = C.c_char_p
         L.phs_memory_stats.argtypes = [C.POINTER(i64)] * 4
+        L.phs_direct_sum.argtypes = [i32, dp, i64, dp, dp, i64, dp, vp]
         L.phs_profile_enable.argtypes = [i32]
         L.phs_profile_enable.restype = None
         L.phs_profile_read.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_double), i32]
@@ -129,7 +132,8 @@ def lib() -> C.CDLL:
                      "phs_plan_info", "phs_plan_tree", "phs_precond_export",
                      "phs_precond_apply", "phs_batch_create", "phs_batch_solve",
                      "phs_server_create", "phs_server_submit", "phs_server_step",
-                     "phs_server_poll", "phs_server_memory", "phs_memory_stats"):
+                     "phs_server_poll", "phs_server_memory", "phs_memory_stats",
+                     "phs_direct_sum"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -178,6 +182,16 @@ def _info(i: SolveInfo, st: int) -> Info:
                 i.t_plan, i.t_precond)
 
 
+def direct_sum(k: int, xy: torch.Tensor, q: torch.Tensor, targets: torch.Tensor) -> torch.Tensor:
+    """out[t] = sum_j q_j phi(|targets_t - xy_j|) by all-pairs summation (FP64,
+    coordinates as given)."""
+    xy, q, tg = xy.contiguous(), q.contiguous(), targets.contiguous()
+    out = torch.empty(tg.shape[0], dtype=torch.float64, device=q.device)
+    _check(lib().phs_direct_sum(k, _dev(xy, "xy"), xy.shape[0], _dev(q, "q"),
+                                _dev(tg, "targets"), tg.shape[0], _dev(out, "out"), _stream()))
+    return out
+
+
 def memory_stats():
     """(allocations, device_mallocs, bytes_in_use, bytes_held) of the library's
     device pool."""
@@ -190,14 +204,15 @@ class Plan:
     """A PHS interpolation plan over fixed nodes (device-resident)."""
 
     def __init__(self, xy: torch.Tensor, k: int, degree: int = -1, precision: int = PHS_FP64,
-                 fmm_tol: float = 0.0, leaf_size: int = 0, expansion_order: int = 0):
+                 fmm_tol: float = 0.0, leaf_size: int = 0, expansion_order: int = 0,
+                 matvec: int = PHS_MATVEC_FMM):
         xy = xy.contiguous()
         _dev(xy, "xy")
         if xy.dim() != 2 or xy.shape[1] != 2:
             raise ValueError("xy must be n x 2")
         self.n = xy.shape[0]
         self.k = k
-        opts = PlanOpts(k, degree, precision, fmm_tol, leaf_size, expansion_order)
+        opts = PlanOpts(k, degree, precision, fmm_tol, leaf_size, expansion_order, matvec)
         h = C.c_void_p()
         _check(lib().phs_plan(C.c_void_p(xy.data_ptr()), self.n, C.byref(opts), _stream(),
                               C.byref(h)))
