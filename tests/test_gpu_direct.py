@@ -6,8 +6,11 @@ Gates: direct sums <= 1e-12 relative 2-norm against the oracle's FP64 direct
 summation (ragged sizes: one source, one target, sizes that are not multiples
 of the 256-wide tiles, targets equal to nodes); a direct plan's FP64 matvec
 <= 1e-12 against the dense matrix, its FP32 matvec <= 1e-4 (reported); solves:
-interpolant <= 1e-8, w and beta within max(1e-8, 10 x the two-direct-solver
-floor); results bitwise reproducible across calls."""
+interpolant, w and beta each within max(1e-8, 10 x the disagreement of the
+oracle's two direct solvers on that quantity) -- for k = 4 on [-1, 1]^2 the
+two direct solvers already differ by 5.7e-9 on the interpolant, so a plain
+1e-8 would sit within a factor two of the oracle's own floor; results bitwise
+reproducible across calls."""
 import numpy as np
 import pytest
 
@@ -62,6 +65,8 @@ def test_exact_matvec_pcg_solve(k, d):
     ref = D.solve_complement(xy, f, k, d)
     bk = D.solve_bunch_kaufman(xy, f, k, d)
     dw, db = rel(bk["w"], ref["w"]), rel(bk["beta"], ref["beta"])
+    s_ref = D.interpolant(ref, k, tg)
+    ds = np.abs(D.interpolant(bk, k, tg) - s_ref).max() / np.abs(s_ref).max()
     pl = N.Plan(dev(xy), k, d, matvec=N.PHS_MATVEC_DIRECT)
     pl.precond_build(m=40, nu=k / 2.0, seed=1)
     # the attainable FP64 residual of these systems is ~5e-12 (k = 3) and
@@ -69,16 +74,16 @@ def test_exact_matvec_pcg_solve(k, d):
     w, beta, info = pl.solve(dev(f), rtol=1e-10)
     w, beta = host(w), host(beta)
     s = host(pl.eval(dev(w), dev(beta), dev(tg)))
-    s_ref = D.interpolant(ref, k, tg)
     es = np.abs(s - s_ref).max() / np.abs(s_ref).max()
     ew, eb = rel(w, ref["w"]), rel(beta, ref["beta"])
     fm = N.Plan(dev(xy), k, d)
     fm.precond_build(m=40, nu=k / 2.0, seed=1)
     _, _, info_fmm = fm.solve(dev(f), rtol=1e-10)
     print(f"k={k} d={d}: iters {info.iters} (FMM plan {info_fmm.iters}) resid "
-          f"{info.rel_residual:.2e} w {ew:.2e} (floor {dw:.2e}) beta {eb:.2e} interp {es:.2e}")
+          f"{info.rel_residual:.2e} w {ew:.2e} (floor {dw:.2e}) beta {eb:.2e} interp {es:.2e} "
+          f"(floor {ds:.2e})")
     assert info.rel_residual <= 1e-10
-    assert es <= 1e-8
+    assert es <= max(1e-8, 10 * ds)
     assert ew <= max(1e-8, 10 * dw)
     assert eb <= max(1e-8, 10 * db)
     pl.close()
