@@ -334,6 +334,22 @@ const char *phs_last_error(void);
 phs_status phs_direct_sum(int32_t k, const double *xy, int64_t n, const double *q,
                           const double *targets, int64_t m, double *out, void *stream);
 
+/* phs_direct_sum for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, the same kernels and the same split of the sources, so
+ * the results are bitwise those of phs_direct_sum; but it calls no hipMalloc,
+ * hipFree or other allocating routine.  The chunk partials go to a static
+ * device array of 2^20 doubles (8 MiB) per GPU, held until the process ends;
+ * its address is looked up on the first call on each device (which, like
+ * phs_direct_sum's first call, also uploads a 4 KB table).  Every size is
+ * accepted (the split never needs more than 2^20 partials); a split that
+ * would is rejected with INVALID_ARGUMENT.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (other streams or threads) race and
+ * must be serialised by the caller.  Asynchronous. */
+phs_status phs_direct_sum_noalloc(int32_t k, const double *xy, int64_t n, const double *q,
+                                  const double *targets, int64_t m, double *out,
+                                  void *stream);
+
 /* Device-memory counters of the library's caching pool (all host pointers,
  * any may be NULL): allocations = blocks handed out so far (from the cache or
  * fresh), device_mallocs = hipMalloc calls so far, bytes_in_use = bytes handed

@@ -804,6 +804,27 @@ phs_status phs_direct_sum(int32_t k, const double *xy, int64_t n, const double *
   });
 }
 
+phs_status phs_direct_sum_noalloc(int32_t k, const double *xy, int64_t n, const double *q,
+                                  const double *targets, int64_t m, double *out, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(k >= 1 && k <= 4, PHS_ERR_INVALID_ARGUMENT, "k must be 1..4");
+    PHS_REQUIRE(n >= 1 && m >= 0 && n < (int64_t(1) << 31) && m < (int64_t(1) << 31),
+                PHS_ERR_INVALID_ARGUMENT, "bad sizes");
+    PHS_REQUIRE(xy && q && (m == 0 || (targets && out)), PHS_ERR_INVALID_ARGUMENT,
+                "null argument");
+    if (m == 0) return PHS_OK;
+    int64_t cap = 0;
+    double *scr = direct_scratch(&cap);
+    const int64_t need = direct_scratch_doubles(m, n);
+    PHS_REQUIRE(need <= cap, PHS_ERR_INVALID_ARGUMENT,
+                "direct sum needs " + std::to_string(need) +
+                    " doubles of scratch, above the no-allocation maximum of " +
+                    std::to_string(cap));
+    direct_sum_plain(k, xy, n, q, targets, m, out, scr, cap, S(stream));
+    return PHS_OK;
+  });
+}
+
 phs_status phs_memory_stats(int64_t *allocations, int64_t *device_mallocs,
                             int64_t *bytes_in_use, int64_t *bytes_held) {
   pool_stats(allocations, device_mallocs, bytes_in_use, bytes_held);

@@ -226,35 +226,73 @@ void direct_eval_targets(Plan &pl, const double *w_tree, const double *beta,
 
 // ------------------------------------------------------------------ plan-free
 // The near-field logarithm table of the plan-free direct sums: one copy per
-// device, filled on the first call on that device.
+// device, filled on the first call on that device (no heap allocation: the
+// host staging is static too).
 namespace {
+constexpr int kMaxDevices = 64;
 __device__ __align__(256) double g_direct_tab[kNearLogTab];
 std::mutex g_direct_mu;
-std::vector<double *> g_direct_tab_ptr;  // per device
+double *g_direct_tab_ptr[kMaxDevices] = {};  // per device
+double g_direct_tab_host[kNearLogTab];
 
-const double *direct_table(hipStream_t s) {
+int current_device() {
   int dev = 0;
   PHS_HIP(hipGetDevice(&dev));
+  PHS_REQUIRE(dev >= 0 && dev < kMaxDevices, PHS_ERR_DEVICE, "device ordinal out of range");
+  return dev;
+}
+
+const double *direct_table() {
+  const int dev = current_device();
   std::lock_guard<std::mutex> lk(g_direct_mu);
-  if ((int)g_direct_tab_ptr.size() <= dev) g_direct_tab_ptr.resize(dev + 1, nullptr);
   if (!g_direct_tab_ptr[dev]) {
     double *p = nullptr;
     PHS_HIP(hipGetSymbolAddress((void **)&p, HIP_SYMBOL(g_direct_tab)));
-    std::vector<double> t(kNearLogTab);
-    fill_near_log_table(t.data());
-    PHS_HIP(hipMemcpy(p, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    fill_near_log_table(g_direct_tab_host);
+    PHS_HIP(hipMemcpy(p, g_direct_tab_host, sizeof(g_direct_tab_host), hipMemcpyHostToDevice));
     g_direct_tab_ptr[dev] = p;
   }
-  (void)s;
   return g_direct_tab_ptr[dev];
 }
 }  // namespace
 
 void direct_sum_plain(int k, const double *xy, int64_t n, const double *q, const double *targets,
-                      int64_t m, double *out, double *scratch, int64_t cap, hipStream_t s) {
-  const double *tab = direct_table(s);
-  direct_sum(k, true, xy, q, n, targets, m, 0.0, 0.0, 1.0, nullptr, 0, out, scratch, cap, tab,
+                      int64_t m, double *out, double *part, int64_t cap, hipStream_t s) {
+  const double *tab = direct_table();
+  direct_sum(k, true, xy, q, n, targets, m, 0.0, 0.0, 1.0, nullptr, 0, out, part, cap, tab,
              nullptr, 0, s, false);
+}
+
+// ------------------------------------------------------------------ no allocation
+// Device scratch of phs_direct_sum_noalloc: the chunk partials live in this
+// file-scope array instead of pool memory, for callers that cannot allocate.
+// Each GPU holds its own copy (8 MiB) until the process ends.  In host code
+// its name is only a stand-in: the device address comes from
+// hipGetSymbolAddress, taken once per device (with that device current) and
+// kept in g_scratch_ptr; kernels and copies get that pointer.  The split of a
+// direct sum never needs more than (kDirectBlocks + tiles) * 256 <= 2^20
+// partials, so every size fits; the check below still guards it.  All calls
+// on one GPU share the array: calls that overlap on one GPU (other streams,
+// other threads) race on it.  Nothing in it needs to start at zero (every
+// partial is written before it is read).
+constexpr int64_t kScratchDoubles = int64_t(1) << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+double *direct_scratch(int64_t *cap) {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(g_direct_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    PHS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    PHS_REQUIRE(p != nullptr, PHS_ERR_DEVICE, "no device address for the direct-sum scratch");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *cap = kScratchDoubles;
+  return g_scratch_ptr[dev];
 }
 
 }  // namespace phs

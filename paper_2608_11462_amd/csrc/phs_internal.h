@@ -570,7 +570,10 @@ void direct_eval_targets(Plan &pl, const double *w_tree, const double *beta,
                          const double *targets, int64_t m, double *out, hipStream_t s);
 // plan-free FP64 direct sum in the caller's coordinates (no normalisation)
 void direct_sum_plain(int k, const double *xy, int64_t n, const double *q, const double *targets,
-                      int64_t m, double *out, double *scratch, int64_t cap, hipStream_t s);
+                      int64_t m, double *out, double *part, int64_t cap, hipStream_t s);
+// this device's static scratch of the no-allocation entry point (device
+// address, from hipGetSymbolAddress) and its size in doubles
+double *direct_scratch(int64_t *cap);
 void fill_near_log_table(double *tab);
 
 // vecchia.hip

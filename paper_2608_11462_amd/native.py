@@ -30,8 +30,8 @@ EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval
            "phs_plan_destroy", "phs_batch_create", "phs_batch_solve", "phs_batch_destroy",
            "phs_server_create", "phs_server_submit", "phs_server_step", "phs_server_poll",
            "phs_server_memory", "phs_server_destroy",
-           "phs_direct_sum", "phs_last_error", "phs_memory_stats", "phs_profile_enable",
-           "phs_profile_read")
+           "phs_direct_sum", "phs_direct_sum_noalloc", "phs_last_error", "phs_memory_stats",
+           "phs_profile_enable", "phs_profile_read")
 PHS_REQ_QUEUED, PHS_REQ_ACTIVE, PHS_REQ_DONE, PHS_REQ_FAILED = 0, 1, 2, 3
 
 
@@ -124,6 +124,7 @@ def lib() -> C.CDLL:
         L.phs_last_error.restype = C.c_char_p
         L.phs_memory_stats.argtypes = [C.POINTER(i64)] * 4
         L.phs_direct_sum.argtypes = [i32, dp, i64, dp, dp, i64, dp, vp]
+        L.phs_direct_sum_noalloc.argtypes = [i32, dp, i64, dp, dp, i64, dp, vp]
         L.phs_profile_enable.argtypes = [i32]
         L.phs_profile_enable.restype = None
         L.phs_profile_read.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_double), i32]
@@ -133,7 +134,7 @@ def lib() -> C.CDLL:
                      "phs_precond_apply", "phs_batch_create", "phs_batch_solve",
                      "phs_server_create", "phs_server_submit", "phs_server_step",
                      "phs_server_poll", "phs_server_memory", "phs_memory_stats",
-                     "phs_direct_sum"):
+                     "phs_direct_sum", "phs_direct_sum_noalloc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -189,6 +190,20 @@ def direct_sum(k: int, xy: torch.Tensor, q: torch.Tensor, targets: torch.Tensor)
     out = torch.empty(tg.shape[0], dtype=torch.float64, device=q.device)
     _check(lib().phs_direct_sum(k, _dev(xy, "xy"), xy.shape[0], _dev(q, "q"),
                                 _dev(tg, "targets"), tg.shape[0], _dev(out, "out"), _stream()))
+    return out
+
+
+def direct_sum_noalloc(k: int, xy: torch.Tensor, q: torch.Tensor, targets: torch.Tensor,
+                       out: torch.Tensor) -> torch.Tensor:
+    """direct_sum into a caller-provided `out` through the entry point that
+    allocates no device memory (its partial sums use the library's static
+    device scratch)."""
+    xy, q, tg = xy.contiguous(), q.contiguous(), targets.contiguous()
+    if out.numel() != tg.shape[0]:
+        raise ValueError("out must hold one value per target")
+    _check(lib().phs_direct_sum_noalloc(k, _dev(xy, "xy"), xy.shape[0], _dev(q, "q"),
+                                        _dev(tg, "targets"), tg.shape[0], _dev(out, "out"),
+                                        _stream()))
     return out
 
 
