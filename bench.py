@@ -30,17 +30,18 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
-FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (packed)
+FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64 (and FP64 matrix)
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 with packed math
+FP32_NOPACK_TFLOPS = 78.6  # MI355X vector FP32 without packed math (this build)
 
-# Algorithmic flop counts used for the roofline:
-#  near-field pair: 2 sub, r^2 (mul + fma = 3), 1 transcendental, phi scale
-#  (2 mul), accumulate (fma = 2)  -> 10 flops
-#  local-expansion evaluation (Horner) per node and density: P complex
-#  multiply-adds (8 flops each) + combine (2)
+# Algorithmic flop counts used for the rooflines (one convention throughout):
+#  near-field pair: 2 sub, r^2 (mul + fma = 3), 1 transcendental counted as 1,
+#  accumulate (fma = 2), one scale -> 9 flops
+#  local-expansion evaluation per node and density: P complex multiply-adds,
+#  8 flops each -> 8 P
 #  M2L per (target, source, density): (P+1)^2 real-by-complex MACs (4 flops)
 #  + 12 (P+1) for the two diagonal scalings
-FLOP_PAIR = 10
+FLOP_PAIR = 9
 
 
 def parse():
@@ -62,6 +63,7 @@ def parse():
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-crossover", action="store_true")
     return ap.parse_args()
 
 
@@ -93,10 +95,10 @@ def tree_work(order_leaf: np.ndarray, L: int, n: int):
 
 
 def source_sha(name: str) -> str:
-    """Hash of a kernel source file and the headers every kernel includes."""
+    """Hash of the source file that holds a kernel (counters taken on another
+    version of that file are not reported)."""
     h = hashlib.sha256()
-    for f in (name, "fmm_common.h", "phs_internal.h"):
-        h.update((ROOT / "paper_2608_11462_amd" / "csrc" / f).read_bytes())
+    h.update((ROOT / "paper_2608_11462_amd" / "csrc" / name).read_bytes())
     return h.hexdigest()[:16]
 
 
@@ -112,11 +114,25 @@ def stored_traffic(kernel: str, workload: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(seed: int = 3, n_s: int = 6144, n_t: int = 10000):
-    """The CPU oracle (dense FP64 complement solve + evaluation) on a bounded
-    sample of the same workload: n_s nodes of the same distribution and field."""
+def cpu_baseline(checks=None, seed: int = 3, n_s: int = 6144, n_t: int = 10000):
+    """The CPU oracle timed on this host, on bounded samples of the workloads:
+    (1) dense FP64 complement solve + 10^4-target evaluation on n_s nodes of
+    the n = 2^20 workload's distribution (median of 3; this is `value`), and a
+    scaling sweep of the same dense solve at n = 2k..16k (one run each, O(n^3));
+    (2) the direct-summation matvec of the n = 1e5 odd-order workload, timed on
+    4096 rows and stated as points per second of a full matvec; (3) the
+    4096-row sampled checker of the n = 2^20 workload.  `checks`: weights and
+    coefficients of the benchmark's solves, whose node residual
+    RMS(f - M w - B beta) / RMS(f) the oracle recomputes on 4096 sampled nodes."""
+    from oracle import direct as DC
     from oracle import phs_dense as D
     from paper_2608_11462_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((i.get("num_threads", 0) for i in threadpool_info()
+                    if i.get("user_api") == "blas"), default=None)
+    except Exception:  # threadpoolctl missing: report unknown
+        blas = None
     pr = W.large_tps(seed=seed, n=n_s, n_targets=n_t)
     ts = []
     for _ in range(3):
@@ -125,13 +141,78 @@ def cpu_baseline(seed: int = 3, n_s: int = 6144, n_t: int = 10000):
         D.interpolant(sol, 2, pr.targets)
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
+    sweep = {}
+    for ns in (2000, 4000, 8000, 16000):
+        p2 = W.small_tps(n=ns, n_targets=500)
+        t0 = time.perf_counter()
+        sol = D.solve_complement(p2.xy, p2.f, 2, 1)
+        D.interpolant(sol, 2, p2.targets)
+        sweep[str(ns)] = round(time.perf_counter() - t0, 3)
+    oc = W.odd_clustered()
+    _, _, xi_c = D.normalize(oc.xy, 3)
+    rows = W.sample_rows(11, oc.n, 4096)
+    vv = W.rng_for(12).standard_normal(oc.n)
+    t0 = time.perf_counter()
+    DC.matvec_rows(3, xi_c, vv, rows)
+    t_rows = time.perf_counter() - t0
+    lt = W.large_tps()
+    _, _, xi_l = D.normalize(lt.xy, 2)
+    rows_l = W.sample_rows(11, lt.n, 4096)
+    t0 = time.perf_counter()
+    DC.matvec_rows(2, xi_l, W.rng_for(12).standard_normal(lt.n), rows_l)
+    t_check = time.perf_counter() - t0
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    return {"value": n_s / t / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
-            "sample": f"dense FP64 complement solve + {n_t}-target evaluation on {n_s} nodes "
-                      f"of the same workload (median of 3: {t:.2f} s)"}
+    out = {"value": n_s / t / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
+           "blas_threads": blas, "c_threads": DC.threads(),
+           "sample": f"dense FP64 complement solve + {n_t}-target evaluation on {n_s} nodes "
+                     f"of the same workload (median of 3: {t:.2f} s)",
+           "dense_solve_sweep_s": sweep,
+           "direct_matvec_odd_clustered_pts_per_s": round(oc.n / (t_rows * oc.n / 4096), 1),
+           "direct_matvec_note": "C direct summation of 4096 rows of the n = 1e5 k = 3 "
+                                 f"matvec in {t_rows:.2f} s, scaled to a full matvec",
+           "checker_4096_rows_large_tps_s": round(t_check, 3)}
+    if checks:
+        xy_l = lt.xy
+        res = {}
+        for name, (w, beta) in checks.items():
+            Mw = DC.matvec_rows(2, xi_l, w, rows_l)
+            r = lt.f[rows_l] - Mw - D.poly_block(xi_l[rows_l], 1) @ beta
+            res[name] = float(np.sqrt(np.mean(r ** 2)) / np.sqrt(np.mean(lt.f ** 2)))
+        out["node_residual_vs_oracle_4096"] = res
+    return out
+
+
+def crossover_leg(N, W, torch):
+    """FMM against the exact (all-pairs) matvec on plans of the small
+    thin-plate workload (uniform nodes, k = 2): FP64 matvec milliseconds per
+    size, and the smallest size where the FMM is faster."""
+    dev = torch.device("cuda")
+    rows = []
+    cross = None
+    for n in (1000, 2000, 4000, 8000, 16000, 32000, 64000, 128000):
+        pr = W.small_tps(n=n, n_targets=10)
+        xy = torch.as_tensor(pr.xy, device=dev)
+        v = torch.as_tensor(W.rng_for(5).standard_normal(n), device=dev)
+        t = {}
+        for name, kind in (("fmm", N.PHS_MATVEC_FMM), ("direct", N.PHS_MATVEC_DIRECT)):
+            pl = N.Plan(xy, 2, 1, matvec=kind)
+            for _ in range(3):
+                pl.matvec(v)
+            torch.cuda.synchronize()
+            reps = 20
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                pl.matvec(v)
+            torch.cuda.synchronize()
+            t[name] = (time.perf_counter() - t0) / reps * 1e3
+            pl.close()
+        rows.append({"n": n, "fmm_ms": round(t["fmm"], 4), "direct_ms": round(t["direct"], 4)})
+        if cross is None and t["fmm"] < t["direct"]:
+            cross = n
+    return {"k": 2, "matvec_ms": rows, "fmm_faster_from_n": cross}
 
 
 def serve_leg(N, W, torch, n_req: int):
@@ -205,12 +286,19 @@ def serve_leg(N, W, torch, n_req: int):
             "worst_rel_residual": worst, "peak_hbm_bytes": peak}
 
 
+def _info_fields(info):
+    return {"pcg_iters": info.iters, "iters_fp32": info.iters_fp32,
+            "iters_fp64": info.iters_fp64, "fp64_fallback": info.fp64_fallback,
+            "outer_refinements": info.outer_refinements, "rel_residual_fp64": info.rel_residual}
+
+
 def precision_leg(N, torch, xy, f, tg, steps: int = 2):
     """The same n = 2^20 solve (plan + preconditioner + solve to 1e-8 + evaluation)
     in the two reduced-precision forms, beside the FP64 step: FP32 FMM with FP64
     Krylov and FP64 residual refinement, and FP64 far field with an FP32 near
-    field.  All reach the FP64 residual 1e-8."""
-    out = {}
+    field.  All reach the FP64 residual 1e-8.  Returns the timings and the
+    weights of each form (checked against the oracle in the CPU leg)."""
+    out, sols = {}, {}
     for name, prec in (("mixed", N.PHS_MIXED), ("near32", N.PHS_NEAR32)):
         info = None
 
@@ -221,17 +309,16 @@ def precision_leg(N, torch, xy, f, tg, steps: int = 2):
             pl.eval(w, beta, tg)
             torch.cuda.synchronize()
             pl.close()
-            return inf
+            return inf, w, beta
 
         step()
         t0 = time.perf_counter()
         for _ in range(steps):
-            info = step()
+            info, w, beta = step()
         ms = (time.perf_counter() - t0) / steps * 1e3
-        out[name] = {"ms_per_step": round(ms, 3), "pcg_iters": info.iters,
-                     "outer_refinements": info.outer_refinements,
-                     "rel_residual_fp64": info.rel_residual}
-    return out
+        out[name] = {"ms_per_step": round(ms, 3), **_info_fields(info)}
+        sols[name] = (w.cpu().numpy(), beta.cpu().numpy())
+    return out, sols
 
 
 def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
@@ -262,6 +349,16 @@ def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t1
     res_b = [i.rel_residual for i in infos]
+    it32 = sum(i.iters_fp32 for i in infos)
+    it64 = sum(i.iters_fp64 for i in infos)
+    falls = sum(i.fp64_fallback for i in infos)
+    # the same batch in FP64: batching without the precision change
+    t1 = time.perf_counter()
+    _, infos64 = batch.solve([f for _, f, _, _ in data], rtol=1e-8, maxit=maxit,
+                             precision=N.PHS_FP64, raise_on_error=False)
+    torch.cuda.synchronize()
+    t_solve64 = time.perf_counter() - t1
+    res_b64 = [i.rel_residual for i in infos64]
     batch.close()
     for pl in plans:
         pl.close()
@@ -280,8 +377,14 @@ def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
     return {"problems": n_prob, "rhs_per_problem": 4, "points": npts, "maxit": maxit,
             "batched_mixed_s": round(t_setup + t_solve, 4), "batched_setup_s": round(t_setup, 4),
             "batched_solve_s": round(t_solve, 4), "alone_fp64_s": round(t_alone, 4),
+            "batched_fp64_s": round(t_setup + t_solve64, 4),
+            "batched_fp64_solve_s": round(t_solve64, 4),
             "speedup": round(t_alone / (t_setup + t_solve), 3),
-            "at_1e-8_batched": ok(res_b), "at_1e-8_alone": ok(res_a),
+            "speedup_batching_fp64": round(t_alone / (t_setup + t_solve64), 3),
+            "speedup_mixed_over_batched_fp64": round(t_solve64 / t_solve, 3),
+            "iters_fp32": it32, "iters_fp64": it64, "fp64_fallbacks": falls,
+            "at_1e-8_batched": ok(res_b), "at_1e-8_batched_fp64": ok(res_b64),
+            "at_1e-8_alone": ok(res_a),
             "median_rel_residual_batched": float(np.median(res_b)),
             "worst_rel_residual_batched": max(res_b), "worst_rel_residual_alone": max(res_a)}
 
@@ -331,8 +434,10 @@ def main():
             phases["solve"] += t3 - t2
             phases["eval"] += t4 - t3
             last.update(iters=info.iters, outer=info.outer_refinements,
-                        resid=info.rel_residual, L=pl.leaf_level, P=pl.order, R=pl.R)
+                        resid=info.rel_residual, L=pl.leaf_level, P=pl.order, R=pl.R,
+                        info=info)
             last["leaf"] = pl.tree()[1]
+            last["w"], last["beta"] = w, beta
         pl.close()
         return s
 
@@ -369,6 +474,17 @@ def main():
             pl.matvec(v, p)
         torch.cuda.synchronize()
         mv[name] = n / ((time.perf_counter() - t) / reps) / 1e6
+    # the FP32 leaf kernel of the mixed matvec, timed with HIP events on its
+    # stream (its roofline is reported beside the FP64 step's)
+    prof32 = {}
+    if not args.no_profile:
+        N.profile_enable(2)
+        N.profile_read()
+        for _ in range(10):
+            pl.matvec(v, N.PHS_MIXED)
+        torch.cuda.synchronize()
+        prof32 = N.profile_read()
+        N.profile_enable(False)
     pl.close()
 
     # rooflines from the HIP-event durations of the timed region
@@ -379,19 +495,23 @@ def main():
         P, R, m = last["P"], last["R"], 30
         P32 = 15  # FP32 expansion order of the plan
         nnz = n * m - m * (m + 1) // 2
+        for kname in ("leaf_eval_f32", "m2l_f32"):
+            if kname in prof32:
+                prof[kname] = prof32[kname]
         models = {
             # kernel: (work per launch, unit, peak, bound)
-            "leaf_eval": (pairs * FLOP_PAIR + n * R * (8 * P + 2), "TFLOP/s",
+            "leaf_eval": (pairs * FLOP_PAIR + n * R * 8 * P, "TFLOP/s",
                           FP64_PEAK_TFLOPS, "alu"),
-            "leaf_eval_near32": (pairs * FLOP_PAIR + n * R * (8 * P + 2), "TFLOP/s",
-                                 FP32_PEAK_TFLOPS, "alu"),
-            "leaf_eval_f32": (pairs * FLOP_PAIR + n * R * (8 * P32 + 2), "TFLOP/s",
-                              FP32_PEAK_TFLOPS, "alu"),
+            "leaf_eval_near32": (pairs * FLOP_PAIR + n * R * 8 * P, "TFLOP/s",
+                                 FP32_NOPACK_TFLOPS, "alu"),
+            # FP32 without packed math: 78.6 TFLOP/s (157.3 with packed FP32)
+            "leaf_eval_f32": (pairs * FLOP_PAIR + n * R * 8 * P32, "TFLOP/s",
+                              FP32_NOPACK_TFLOPS, "alu"),
             # FP64 M2L runs on the matrix cores (FP64 MFMA peak = vector peak)
             "m2l": (m2l_pairs * R * (4 * (P + 1) ** 2 + 12 * (P + 1)), "TFLOP/s",
                     FP64_PEAK_TFLOPS, "mfma"),
             "m2l_f32": (m2l_pairs * R * (4 * (P32 + 1) ** 2 + 12 * (P32 + 1)), "TFLOP/s",
-                        FP32_PEAK_TFLOPS, "alu"),
+                        FP32_NOPACK_TFLOPS, "alu"),
             "vecchia_factor": (n * (2 * (m + 1) ** 3 / 3 + 2 * m * m
                                     + 20 * (m + 1) * (m + 2) / 2), "TFLOP/s",
                                FP64_PEAK_TFLOPS, "alu"),
@@ -412,7 +532,8 @@ def main():
                             "traffic": stored_traffic(kname, "large_tps"),
                             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
                             "work_per_launch": work, "total_ms": round(total_ms, 3)}
-    roof = max(roofs.values(), key=lambda r: r["total_ms"]) if roofs else None
+    roof = max((r for k, r in roofs.items() if k not in prof32), key=lambda r: r["total_ms"],
+               default=None)
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 3)}
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]}
 
@@ -434,20 +555,31 @@ def main():
         "phase_seconds": {k: round(v / args.steps, 4) for k, v in phases.items()},
         "pcg_iters": last.get("iters"), "outer_refinements": last.get("outer"),
         "rel_residual_fp64": last.get("resid"),
+        "plan_seconds_lib": round(last["info"].t_plan, 4) if "info" in last else None,
+        "precond_seconds_lib": round(last["info"].t_precond, 4) if "info" in last else None,
         "leaf_level": last.get("L"), "expansion_order": last.get("P"),
         "matvec_mpts_s": {k: round(v, 2) for k, v in mv.items()},
         "serve_p50_ms": None, "serve_p99_ms": None,
         "roofline": roof,
-        "rooflines": {k: {kk: v[kk] for kk in ("achieved", "unit", "frac", "avg_launch_ms")}
+        "rooflines": {k: {kk: v[kk] for kk in ("achieved", "peak", "unit", "frac",
+                                               "avg_launch_ms", "work_per_launch")}
                       for k, v in roofs.items()},
+        "flop_convention": "near pair 9, L2P 8P per point and density, M2L "
+                           "4(P+1)^2 + 12(P+1) per pair and density",
         "kernels": kernels,
     }
+    checks = None
+    if "w" in last and args.n == (1 << 20):
+        checks = {"fp64": (last["w"].cpu().numpy(), last["beta"].cpu().numpy())}
     if not args.no_precision_leg:
-        out["precision_forms"] = precision_leg(N, torch, xy, f, tg)
+        pf, sols = precision_leg(N, torch, xy, f, tg)
+        out["precision_forms"] = pf
         out["precision_forms"]["fp64"] = {"ms_per_step": round(ms_per_step, 3),
-                                          "pcg_iters": last.get("iters"),
-                                          "outer_refinements": last.get("outer"),
-                                          "rel_residual_fp64": last.get("resid")}
+                                          **_info_fields(last["info"])}
+        if checks is not None:
+            checks.update(sols)
+    if not args.no_crossover:
+        out["fmm_direct_crossover"] = crossover_leg(N, W, torch)
     if not args.no_serve and args.serve_requests > 0:
         sv = serve_leg(N, W, torch, args.serve_requests)
         out["serve_p50_ms"], out["serve_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
@@ -455,7 +587,10 @@ def main():
     if not args.no_batch and args.batch_problems > 0:
         out["batched"] = batch_leg(N, W, torch, args.batch_problems)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(checks)
+        for name, r in out["cpu_baseline"].get("node_residual_vs_oracle_4096", {}).items():
+            if name in out.get("precision_forms", {}):
+                out["precision_forms"][name]["node_residual_vs_oracle_4096"] = r
     print(json.dumps(out))
 
 
