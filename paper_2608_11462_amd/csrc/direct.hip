@@ -208,7 +208,8 @@ void direct_matvec(Forest &F, const int32_t *mask, int in, int out, int precisio
     const SysDev &d = F.hsys[i];
     const SysWork &w = *F.work[i];
     const double *xy = (const double *)pl.xy2;
-    direct_sum(pl.k, precision == PHS_FP64, xy, d.v[in], pl.n, xy, pl.n, 0.0, 0.0, 1.0,
+    const bool fp64 = precision == PHS_FP64 || precision == PHS_FP64_EVAL;
+    direct_sum(pl.k, fp64, xy, d.v[in], pl.n, xy, pl.n, 0.0, 0.0, 1.0,
                nullptr, 0, d.v[out], w.dpart, w.dpart_cap, pl.neartab, mask, i, s, false);
   }
 }

@@ -950,15 +950,18 @@ size_t cheb_expansion_bytes(int L, int Q, int nd, bool fp64) {
 // different sizes may use different orders).
 void dist_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
                  hipStream_t s) {
-  const int tier = precision == PHS_MIXED ? 1 : 0;
+  const int tier = precision == PHS_MIXED ? 1 : (precision == PHS_FP64_EVAL ? 2 : 0);
   std::vector<int> done;
   for (const Plan *p : F.plan) {
     if (p->core_log || p->direct) continue;
-    const int Q = tier ? p->q32 : p->q64;
+    const int Q = tier == 1 ? p->q32 : (tier == 2 ? p->qe : p->q64);
     if (std::find(done.begin(), done.end(), Q) != done.end()) continue;
     done.push_back(Q);
     if (precision == PHS_MIXED)
       run_q<float, float>(F, mask, in, out, true, Q, p->ct32, p->neartab, tier, s);
+    else if (precision == PHS_FP64_EVAL)
+      run_q<double, double>(F, mask, in, out, true, Q, p->qe == p->q64 ? p->ct64 : p->cte,
+                            p->neartab, tier, s);
     else if (precision == PHS_NEAR32)
       run_q<double, float>(F, mask, in, out, true, Q, p->ct64, p->neartab, tier, s);
     else

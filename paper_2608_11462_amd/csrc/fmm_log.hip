@@ -1205,6 +1205,10 @@ void log_matvec(Forest &F, const int32_t *mask, int in, int out, int precision,
   if (precision == PHS_MIXED) {
     far_field<float>(F, mask, in, ref.p32, ref.lt32, "m2l_f32", s);
     leaf_pass<float, float>(F, mask, in, out, ref.p32, ref.neartab, s);
+  } else if (precision == PHS_FP64_EVAL) {
+    far_field<double>(F, mask, in, ref.pe, ref.pe == ref.p64 ? ref.lt64 : ref.lte, "m2l_eval",
+                      s);
+    leaf_pass<double, double>(F, mask, in, out, ref.pe, ref.neartab, s);
   } else {
     far_field<double>(F, mask, in, ref.p64, ref.lt64, "m2l", s);
     if (precision == PHS_NEAR32)

@@ -516,7 +516,7 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
   // uploads tables; afterwards a lookup miss is an error, never an allocation.
   {
     WarmTables warm;
-    for (int prec : {PHS_FP64, PHS_MIXED, PHS_NEAR32})
+    for (int prec : {(int)PHS_FP64, (int)PHS_MIXED, (int)PHS_NEAR32, PHS_FP64_EVAL})
       f_matvec(F, F.mask[0], V_IN, V_OUT, prec, s);
     for (Plan *pl : plans) {
       if (pl->self != &F || pl->direct) continue;

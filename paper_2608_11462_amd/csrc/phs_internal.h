@@ -159,6 +159,11 @@ inline double domain_half_width(int k) {
 // sign of Q_perp^T M Q_perp: +1 positive definite, -1 negative definite
 inline int definiteness_sign(int k) { return (k % 4 == 2 || k % 4 == 3) ? 1 : -1; }
 
+// Internal matvec precision: FP64 at the plan's evaluation order (the
+// tighter FP64 expansion order that serves phs_eval), which a solve moves to
+// when the FP64 operator at the matvec order loses definiteness or stalls.
+constexpr int PHS_FP64_EVAL = 3;
+
 // ------------------------------------------------------------------ tree
 struct Tree {
   int L = 2;        // leaf level; grid side G = 2^L
@@ -325,7 +330,7 @@ struct Forest {
   int maxS = 1;
   int maxL_log = 0, maxL_dist = 0;
   // masks: device int32[nsys] each, host pinned mirrors
-  static constexpr int kMasks = 10;
+  static constexpr int kMasks = 12;
   int32_t *mask[kMasks] = {};   // slices of mask_block
   int32_t *mask_block = nullptr;
   int32_t *hmask[kMasks] = {};   // pinned staging of the last upload
@@ -414,6 +419,7 @@ struct SolveJob {
   bool undo_dw = false;  // the last correction raised the residual: take it back
   int iters32 = 0, iters64 = 0;  // inner iterations on the reduced / FP64 operator
   bool fallback = false;         // a reduced-precision solve moved to the FP64 operator
+  bool hi = false;               // the FP64 operator is taken at the evaluation order
 };
 struct SolveParams {
   double rtol;

@@ -13,7 +13,10 @@
 //          rtol ||b||, so usually one inner solve suffices; when the true
 //          residual misses the target (FMM error against a rough, strongly
 //          preconditioned direction) PCG restarts from it, and stops if a
-//          restart no longer halves it.
+//          restart no longer halves it.  If the FP64 operator at the matvec
+//          order breaks down at once or its restarts stall, the system moves
+//          to the FP64 operator at the plan's (higher) evaluation order for
+//          the rest of the solve, residual and coefficients included.
 //   MIXED / NEAR32: the inner operator is FP32 (far and near field, or near
 //          field only).  An inner solve that breaks down at once, or an
 //          outer step that does not halve the true residual, switches the
@@ -40,8 +43,17 @@ enum MaskSlot {
   MK_START = 6,
   MK_RESID = 7,
   MK_FINISH = 8,
-  MK_UPD = 9
+  MK_UPD = 9,
+  MK_P64H = 10,  // PCG on the FP64 operator at the evaluation order
+  MK_HI = 11     // residual / final matvecs at the evaluation order
 };
+
+// A system can move to the FP64 operator at the plan's evaluation order when
+// that order is higher than the matvec order.
+bool can_escalate(const Plan &pl) {
+  if (pl.direct) return false;
+  return pl.core_log ? pl.pe > pl.p64 : pl.qe > pl.q64;
+}
 
 using JobRun = SolveJob;
 
@@ -59,14 +71,15 @@ void set_mask(Forest &F, int slot, const std::vector<SolveJob *> &jr, bool (*pre
 
 void start_pcg(JobRun &r, const SolveParams &P) {
   const bool mixed = P.prec != PHS_FP64;
+  const int p64 = r.hi ? PHS_FP64_EVAL : PHS_FP64;
   if (!mixed) {
-    r.inner_prec = PHS_FP64;
+    r.inner_prec = p64;
     r.inner_tol = r.tol_abs;
     r.maxit_inner = r.budget;
   } else {
     // FP32 far field: small steps (its error is relative to ||M||); FP32
     // near field only: the operator is accurate enough to go to rtol at once
-    r.inner_prec = r.fp64_finish ? PHS_FP64 : P.prec;
+    r.inner_prec = r.fp64_finish ? p64 : P.prec;
     r.inner_tol = r.fp64_finish ? r.tol_abs
                                 : (P.prec == PHS_NEAR32 ? 0.5 * r.tol_abs
                                                         : std::max(r.tol_abs, 1e-4 * r.rn));
@@ -83,7 +96,7 @@ void start_pcg(JobRun &r, const SolveParams &P) {
 }  // namespace
 
 void solve_begin(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, hipStream_t s) {
-  PHS_REQUIRE(F.nsys >= 1 && Forest::kMasks >= 10, PHS_ERR_INVALID_ARGUMENT, "empty forest");
+  PHS_REQUIRE(F.nsys >= 1 && Forest::kMasks >= 12, PHS_ERR_INVALID_ARGUMENT, "empty forest");
   bool any = false;
   // ---- INIT: f in tree order, b = sign Pi f, ||b||, ||f||
   for (auto *r : jr) f_gather_user(F, r->sys, r->f, V_F, s);
@@ -134,10 +147,13 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
     // ---- PCG iteration
     set_mask(F, MK_PCG, jr, [](const JobRun &r) { return r.state == J_PCG; }, any, s);
     if (any) {
-      bool a64 = false, a32 = false, an32 = false;
+      bool a64 = false, a64h = false, a32 = false, an32 = false;
       set_mask(F, MK_P64, jr,
                [](const JobRun &r) { return r.state == J_PCG && r.inner_prec == PHS_FP64; }, a64,
                s);
+      set_mask(F, MK_P64H, jr,
+               [](const JobRun &r) { return r.state == J_PCG && r.inner_prec == PHS_FP64_EVAL; },
+               a64h, s);
       set_mask(F, MK_P32, jr,
                [](const JobRun &r) { return r.state == J_PCG && r.inner_prec == PHS_MIXED; },
                a32, s);
@@ -146,6 +162,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
                an32, s);
       // q = sign Pi M p
       if (a64) f_matvec(F, F.mask[MK_P64], V_P, V_Q, PHS_FP64, s);
+      if (a64h) f_matvec(F, F.mask[MK_P64H], V_P, V_Q, PHS_FP64_EVAL, s);
       if (a32) f_matvec(F, F.mask[MK_P32], V_P, V_Q, PHS_MIXED, s);
       if (an32) f_matvec(F, F.mask[MK_PN32], V_P, V_Q, PHS_NEAR32, s);
       f_project_dot(F, F.mask[MK_PCG], V_Q, true, V_P, SC_PQ, s);
@@ -156,7 +173,7 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
         f_read_scalars(F, SC_PQ, 1, s);
         bool drop = false;
         for (auto *rp_ : jr) if (auto &r = *rp_; true)
-          if (r.state == J_PCG && r.inner_prec != PHS_FP64 &&
+          if (r.state == J_PCG && (r.inner_prec == PHS_MIXED || r.inner_prec == PHS_NEAR32) &&
               !(F.hgsc[r.sys * 8] > 0.0)) {
             r.pcg_break = true;
             r.state = J_PCG_END;
@@ -203,10 +220,19 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       if (r.state != J_PCG_END) continue;
       r.iters += r.it;
       r.budget -= r.it;
-      if (r.inner_prec == PHS_FP64) r.iters64 += r.it;
+      if (r.inner_prec == PHS_FP64 || r.inner_prec == PHS_FP64_EVAL) r.iters64 += r.it;
       else r.iters32 += r.it;
       if (r.pcg_break && r.it <= 1) {
         if (r.fp64_finish) {
+          if (!r.hi && can_escalate(*F.plan[r.sys])) {
+            // the FP64 operator at the matvec order is not definite enough
+            // on this direction: continue at the evaluation order, from the
+            // residual recomputed there
+            r.hi = true;
+            r.count_outer = false;
+            r.state = J_RESID;
+            continue;
+          }
           r.status = PHS_ERR_BREAKDOWN;
           r.state = J_FINISH;
           continue;
@@ -227,9 +253,15 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
     for (auto *rp_ : jr) if (auto &r = *rp_; true) r.apply_dw = false;
 
     // ---- FP64 residual of the refinement: r = sign Pi (f - M64 w)
+    bool any_hi = false;
+    set_mask(F, MK_HI, jr, [](const JobRun &r) { return r.state == J_RESID && r.hi; }, any_hi,
+             s);
+    set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.state == J_RESID && !r.hi; }, any,
+             s);
+    if (any) f_matvec(F, F.mask[MK_UPD], V_W, V_Q, PHS_FP64, s);
+    if (any_hi) f_matvec(F, F.mask[MK_HI], V_W, V_Q, PHS_FP64_EVAL, s);
     set_mask(F, MK_RESID, jr, [](const JobRun &r) { return r.state == J_RESID; }, any, s);
     if (any) {
-      f_matvec(F, F.mask[MK_RESID], V_W, V_Q, PHS_FP64, s);
       f_axpby(F, F.mask[MK_RESID], V_Q, V_F, 1.0, -1.0, s);  // q = f - M w
       f_scale_sign(F, F.mask[MK_RESID], V_R, V_Q, s);
       f_project(F, F.mask[MK_RESID], V_R, s);
@@ -245,7 +277,11 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
           continue;
         }
         bool stalled = false, worse = false;
-        if (r.count_outer) {
+        if (!r.count_outer) {
+          // a residual recomputed without a correction (after a switch of
+          // operator): it is the reference the next restart must halve
+          r.rn = rn_new;
+        } else {
           // refinement steps; in FP64 only the restarts count
           if (mixed || rn_new > r.tol_abs) ++r.outer;
           stalled = !(rn_new < 0.5 * r.rn);
@@ -258,6 +294,15 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
           // the solve returns the best iterate of its restarts
           worse = stalled && rn_new > r.rn;
           if (!worse) r.rn = rn_new;
+          if (stalled && r.fp64_finish && !r.hi && can_escalate(*F.plan[r.sys])) {
+            // restarts at the matvec order stopped helping: take back a
+            // correction that raised the residual, then go on at the
+            // evaluation order from the residual recomputed there
+            r.hi = true;
+            r.undo_dw = worse;
+            r.count_outer = false;
+            continue;  // stays in J_RESID
+          }
         }
         if (r.rn > r.tol_abs && r.budget > 0 && !stalled) {
           start_pcg(r, P);
@@ -275,12 +320,16 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
     for (auto *rp_ : jr) if (auto &r = *rp_; true) r.undo_dw = false;
 
     // ---- beta from R beta = Q^T (f - M w), the FP64 residual, w to the caller
+    set_mask(F, MK_UPD, jr,
+             [](const JobRun &r) { return r.state == J_FINISH && !r.have_q && !r.hi; }, any, s);
+    if (any) f_matvec(F, F.mask[MK_UPD], V_W, V_Q, PHS_FP64, s);
+    set_mask(F, MK_HI, jr,
+             [](const JobRun &r) { return r.state == J_FINISH && !r.have_q && r.hi; }, any_hi,
+             s);
+    if (any_hi) f_matvec(F, F.mask[MK_HI], V_W, V_Q, PHS_FP64_EVAL, s);
     set_mask(F, MK_UPD, jr, [](const JobRun &r) { return r.state == J_FINISH && !r.have_q; },
              any, s);
-    if (any) {
-      f_matvec(F, F.mask[MK_UPD], V_W, V_Q, PHS_FP64, s);
-      f_axpby(F, F.mask[MK_UPD], V_Q, V_F, 1.0, -1.0, s);  // q = f - M w
-    }
+    if (any) f_axpby(F, F.mask[MK_UPD], V_Q, V_F, 1.0, -1.0, s);  // q = f - M w
     set_mask(F, MK_FINISH, jr, [](const JobRun &r) { return r.state == J_FINISH; }, any, s);
     if (any) {
       f_qt(F, F.mask[MK_FINISH], V_Q, SC_QTF, s);

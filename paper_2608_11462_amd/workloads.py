@@ -117,6 +117,22 @@ def f_interp(xy: np.ndarray) -> np.ndarray:
             + 5.0 * np.exp(-5.0 * np.sqrt((x1 - 0.25) ** 2 + (x2 - 0.75) ** 2)))
 
 
+def sobol_points(log2_n: int) -> np.ndarray:
+    """The first 2^log2_n points of the (unscrambled) two-dimensional Sobol
+    sequence on [0, 1)^2, the node sets of the accuracy experiments of Sec. 3.2
+    and 3.3.  Deterministic; shape (2^log2_n, 2)."""
+    from scipy.stats import qmc
+    return qmc.Sobol(d=2, scramble=False).random_base2(log2_n)
+
+
+def regrid_targets(g: int = 100) -> np.ndarray:
+    """The regular g x g grid on [0, 1]^2 (both ends included) at which the
+    interpolants of Sec. 3.2 and 3.3 are evaluated; shape (g*g, 2)."""
+    t = np.linspace(0.0, 1.0, g)
+    gx, gy = np.meshgrid(t, t, indexing="ij")
+    return np.stack([gx.ravel(), gy.ravel()], axis=1)
+
+
 def f_franke(xy: np.ndarray) -> np.ndarray:
     """The four-term Franke function with the weights, centres and diagonal
     metrics printed in Sec. 3.3."""
