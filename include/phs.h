@@ -317,6 +317,68 @@ void phs_server_destroy(phs_server_t srv);
 /* Message for the last non-OK status returned on this thread. */
 const char *phs_last_error(void);
 
+/* ---------------------------------------------------------------- tuning
+ * Preconditioner tuning (Sec. 2.2, closing paragraph: the range alpha and the
+ * smoothness were tuned by hand for k = 2 and 4; other orders need their own
+ * choices).  On the plan's nodes and the caller's values f (device, n), for
+ * each supported Matern smoothness nu in {k/2 - 1/2, k/2, k/2 + 1/2}, a
+ * Nelder-Mead simplex over (log alpha, m) minimises the measured seconds of
+ * phs_precond_build + phs_solve (FP64) to rtol; trials that do not converge
+ * are charged 1000 s.  The normalisation scale is not searched: for the
+ * preconditioner it only rescales alpha.  On return the plan holds the best
+ * preconditioner found and `out` its figures beside those of the library's
+ * defaults on the same problem.  Allocates (trial buffers); synchronises
+ * `stream` after every trial. */
+typedef struct {
+  int32_t max_evals;   /* simplex evaluations per nu; 0 => 16 */
+  int32_t maxit;       /* PCG iteration cap per trial; 0 => 300 */
+  double rtol;         /* 0 => 1e-8 */
+  int32_t m_min, m_max;  /* bounds of the conditioning-set size; 0 => 10, 60 */
+} phs_tune_opts;
+
+typedef struct {
+  int32_t m;              /* best conditioning-set size */
+  double nu;              /* best smoothness */
+  double alpha;           /* best inverse range (normalised coordinates) */
+  double seconds;         /* its build + solve seconds */
+  int32_t iters;          /* its PCG iterations */
+  double rel_residual;    /* its FP64 exit residual */
+  int32_t evals;          /* trials run, the default's included */
+  double default_seconds; /* the library defaults (m = 30 or 50, nu = k/2,
+                             alpha = 0.35, 3 or 2) on the same problem */
+  int32_t default_iters;
+} phs_tune_result;
+
+phs_status phs_tune_precond(phs_plan_t plan, const double *f, const phs_tune_opts *opts,
+                            phs_tune_result *out, void *stream);
+
+/* Plan autotuning: expansion order, leaf size and matvec kind for the caller's
+ * nodes xy (device, n x 2), order k and degree.  Candidates: the exact
+ * all-pairs matvec (n <= 2^17) and the FMM with leaf sizes 16, 24, 32, 48,
+ * 64, 96, 128, each at the lowest expansion order (log kernel 15, 23, 27, 31;
+ * Chebyshev 8..16) whose matvec of a seeded N(0,1) vector is within
+ * matvec_tol (relative 2-norm) of the exact all-pairs sum on 2048 sampled
+ * rows.  The fastest candidate by measured matvec time (in `precision`) wins;
+ * `best` receives its plan options (pass them to phs_plan).  Allocates;
+ * synchronises `stream`.  Errors: NOT_CONVERGED if no candidate meets the
+ * tolerance. */
+typedef struct {
+  double matvec_tol;   /* 0 => 1e-12 */
+  int32_t precision;   /* PHS_FP64 (0), PHS_MIXED, PHS_NEAR32 */
+  int32_t reps;        /* timed matvecs per candidate; 0 => 5 */
+  uint64_t seed;       /* of the test vector and the sampled rows */
+} phs_autotune_opts;
+
+typedef struct {
+  int32_t matvec, leaf_size, expansion_order, candidates;
+  double matvec_seconds;  /* per matvec of the chosen plan */
+  double rel_error;       /* its sampled-row error */
+} phs_autotune_result;
+
+phs_status phs_autotune_plan(const double *xy, int64_t n, int32_t k, int32_t poly_degree,
+                             const phs_autotune_opts *opts, phs_plan_opts *best,
+                             phs_autotune_result *out, void *stream);
+
 /* Direct (all-pairs) PHS kernel sums on the GPU, without a plan:
  *   out[t] = sum_j q[j] phi(|targets_t - xy_j|),  phi(r) = r^k (k odd),
  *   r^k log r (k even), phi(0) = 0

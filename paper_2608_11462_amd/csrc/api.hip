@@ -781,6 +781,31 @@ void phs_plan_destroy(phs_plan_t plan) {
 
 const char *phs_last_error(void) { return g_last_error.c_str(); }
 
+phs_status phs_tune_precond(phs_plan_t plan, const double *f, const phs_tune_opts *opts,
+                            phs_tune_result *out, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(plan && f && out, PHS_ERR_INVALID_ARGUMENT, "bad tune arguments");
+    phs_tune_opts o{};
+    if (opts) o = *opts;
+    *out = phs_tune_result{};
+    tune_precond(plan->pl, f, o, *out, S(stream));
+    return PHS_OK;
+  });
+}
+
+phs_status phs_autotune_plan(const double *xy, int64_t n, int32_t k, int32_t poly_degree,
+                             const phs_autotune_opts *opts, phs_plan_opts *best,
+                             phs_autotune_result *out, void *stream) {
+  return guarded([&] {
+    PHS_REQUIRE(xy && best && out && k >= 1 && k <= 4 && n >= 8 && n < (int64_t(1) << 30),
+                PHS_ERR_INVALID_ARGUMENT, "bad autotune arguments");
+    phs_autotune_opts o{};
+    if (opts) o = *opts;
+    autotune_plan(xy, n, k, poly_degree, o, *best, *out, S(stream));
+    return PHS_OK;
+  });
+}
+
 phs_status phs_direct_sum(int32_t k, const double *xy, int64_t n, const double *q,
                           const double *targets, int64_t m, double *out, void *stream) {
   return guarded([&] {

@@ -582,6 +582,12 @@ void direct_sum_plain(int k, const double *xy, int64_t n, const double *q, const
 double *direct_scratch(int64_t *cap);
 void fill_near_log_table(double *tab);
 
+// tune.hip
+void tune_precond(Plan &pl, const double *f, const phs_tune_opts &o, phs_tune_result &res,
+                  hipStream_t s);
+void autotune_plan(const double *xy, int64_t n, int k, int degree, const phs_autotune_opts &o,
+                   phs_plan_opts &best, phs_autotune_result &res, hipStream_t s);
+
 // vecchia.hip
 void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s);
 void vecchia_free(Plan &pl);

@@ -30,6 +30,7 @@ EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval
            "phs_plan_destroy", "phs_batch_create", "phs_batch_solve", "phs_batch_destroy",
            "phs_server_create", "phs_server_submit", "phs_server_step", "phs_server_poll",
            "phs_server_memory", "phs_server_destroy",
+           "phs_tune_precond", "phs_autotune_plan",
            "phs_direct_sum", "phs_direct_sum_noalloc", "phs_last_error", "phs_memory_stats",
            "phs_profile_enable", "phs_profile_read")
 PHS_REQ_QUEUED, PHS_REQ_ACTIVE, PHS_REQ_DONE, PHS_REQ_FAILED = 0, 1, 2, 3
@@ -75,6 +76,29 @@ class SolveInfo(C.Structure):
                 ("iters_fp32", C.c_int32), ("iters_fp64", C.c_int32),
                 ("fp64_fallback", C.c_int32), ("reserved", C.c_int32),
                 ("t_plan", C.c_double), ("t_precond", C.c_double)]
+
+
+class TuneOpts(C.Structure):
+    _fields_ = [("max_evals", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double),
+                ("m_min", C.c_int32), ("m_max", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("m", C.c_int32), ("nu", C.c_double), ("alpha", C.c_double),
+                ("seconds", C.c_double), ("iters", C.c_int32), ("rel_residual", C.c_double),
+                ("evals", C.c_int32), ("default_seconds", C.c_double),
+                ("default_iters", C.c_int32)]
+
+
+class AutotuneOpts(C.Structure):
+    _fields_ = [("matvec_tol", C.c_double), ("precision", C.c_int32), ("reps", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class AutotuneResult(C.Structure):
+    _fields_ = [("matvec", C.c_int32), ("leaf_size", C.c_int32),
+                ("expansion_order", C.c_int32), ("candidates", C.c_int32),
+                ("matvec_seconds", C.c_double), ("rel_error", C.c_double)]
 
 
 class PHSError(RuntimeError):
@@ -124,6 +148,9 @@ def lib() -> C.CDLL:
         L.phs_last_error.restype = C.c_char_p
         L.phs_memory_stats.argtypes = [C.POINTER(i64)] * 4
         L.phs_direct_sum.argtypes = [i32, dp, i64, dp, dp, i64, dp, vp]
+        L.phs_tune_precond.argtypes = [vp, dp, C.POINTER(TuneOpts), C.POINTER(TuneResult), vp]
+        L.phs_autotune_plan.argtypes = [dp, i64, i32, i32, C.POINTER(AutotuneOpts),
+                                        C.POINTER(PlanOpts), C.POINTER(AutotuneResult), vp]
         L.phs_direct_sum_noalloc.argtypes = [i32, dp, i64, dp, dp, i64, dp, vp]
         L.phs_profile_enable.argtypes = [i32]
         L.phs_profile_enable.restype = None
@@ -134,7 +161,8 @@ def lib() -> C.CDLL:
                      "phs_precond_apply", "phs_batch_create", "phs_batch_solve",
                      "phs_server_create", "phs_server_submit", "phs_server_step",
                      "phs_server_poll", "phs_server_memory", "phs_memory_stats",
-                     "phs_direct_sum", "phs_direct_sum_noalloc"):
+                     "phs_direct_sum", "phs_direct_sum_noalloc", "phs_tune_precond",
+                     "phs_autotune_plan"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -181,6 +209,21 @@ def _info(i: SolveInfo, st: int) -> Info:
     return Info(i.iters, i.outer_refinements, i.rel_residual, i.t_solve,
                 STATUS.get(st, str(st)), i.iters_fp32, i.iters_fp64, i.fp64_fallback,
                 i.t_plan, i.t_precond)
+
+
+def autotune_plan(xy: torch.Tensor, k: int, degree: int = -1, matvec_tol: float = 1e-12,
+                  precision: int = PHS_FP64, reps: int = 0, seed: int = 0):
+    """Pick matvec kind, leaf size and expansion order for these nodes (see
+    phs_autotune_plan).  Returns (plan keyword arguments, report dict)."""
+    xy = xy.contiguous()
+    best = PlanOpts()
+    r = AutotuneResult()
+    o = AutotuneOpts(matvec_tol, precision, reps, seed)
+    _check(lib().phs_autotune_plan(_dev(xy, "xy"), xy.shape[0], k, degree, C.byref(o),
+                                   C.byref(best), C.byref(r), _stream()))
+    kw = {"degree": best.poly_degree, "precision": best.precision, "leaf_size": best.leaf_size,
+          "expansion_order": best.expansion_order, "matvec": best.matvec}
+    return kw, {k2: getattr(r, k2) for k2, _ in AutotuneResult._fields_}
 
 
 def direct_sum(k: int, xy: torch.Tensor, q: torch.Tensor, targets: torch.Tensor) -> torch.Tensor:
@@ -257,6 +300,16 @@ class Plan:
                       range_units: int = PHS_RANGE_NORMALIZED, seed: int = 0) -> None:
         o = PrecondOpts(m, nu, range_, range_units, seed)
         _check(lib().phs_precond_build(self._h, C.byref(o), _stream()))
+
+    def tune_precond(self, f: torch.Tensor, rtol: float = 1e-8, max_evals: int = 0,
+                     maxit: int = 0, m_min: int = 0, m_max: int = 0) -> dict:
+        """Search (m, nu, alpha) for this plan and values f (see phs_tune_precond);
+        the plan keeps the best preconditioner."""
+        o = TuneOpts(max_evals, maxit, rtol, m_min, m_max)
+        r = TuneResult()
+        _check(lib().phs_tune_precond(self._h, _dev(f.contiguous(), "f"), C.byref(o), C.byref(r),
+                                      _stream()))
+        return {k: getattr(r, k) for k, _ in TuneResult._fields_}
 
     def precond_export(self, m: int):
         dev = torch.device("cuda")
