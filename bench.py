@@ -44,6 +44,12 @@ FP32_NOPACK_TFLOPS = 78.6  # MI355X vector FP32 without packed math (this build)
 FLOP_PAIR = 9
 
 
+def progress(msg: str) -> None:
+    """One line on stderr as a leg finishes a piece of work (the JSON result
+    stays the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,7 +66,12 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true")
     # serving (Poisson stream) and batched (many problems, 4 right-hand sides) legs
     ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--batch-problems", type=int, default=64)
+    ap.add_argument("--batch-problems", type=int, default=256)
+    # 512-request Poisson streams at 0.8, 1.0 and 1.2 x the load the plain
+    # FP64 path sustains alone (several minutes; off by default)
+    ap.add_argument("--serve-sweep", action="store_true")
+    # retune (phs_tune_precond) and re-solve the batched problems that miss 1e-8
+    ap.add_argument("--retune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-crossover", action="store_true")
@@ -148,6 +159,7 @@ def cpu_baseline(checks=None, seed: int = 3, n_s: int = 6144, n_t: int = 10000):
         sol = D.solve_complement(p2.xy, p2.f, 2, 1)
         D.interpolant(sol, 2, p2.targets)
         sweep[str(ns)] = round(time.perf_counter() - t0, 3)
+        progress(f"CPU oracle: dense solve n={ns} in {sweep[str(ns)]} s")
     oc = W.odd_clustered()
     _, _, xi_c = D.normalize(oc.xy, 3)
     rows = W.sample_rows(11, oc.n, 4096)
@@ -215,7 +227,7 @@ def crossover_leg(N, W, torch):
     return {"k": 2, "matvec_ms": rows, "fmm_faster_from_n": cross}
 
 
-def serve_leg(N, W, torch, n_req: int):
+def serve_leg(N, W, torch, n_req: int, loads=(0.8,)):
     """Poisson stream of solve + evaluate requests (n log-uniform in [1e3, 1e6],
     k in {2, 3}, 10^4 targets) through the server at 80% of the load the plain
     FP64 path sustains serving each request alone; FIFO serve-alone latencies
@@ -239,11 +251,21 @@ def serve_leg(N, W, torch, n_req: int):
 
     alone(items[0])  # warm-up
     t_alone = []
-    for it in items:
+    for i, it in enumerate(items):
         t0 = time.perf_counter()
         alone(it)
         t_alone.append(time.perf_counter() - t0)
-    lam = 0.8 / float(np.mean(t_alone))
+        if (i + 1) % 64 == 0:
+            progress(f"serving: {i + 1} requests timed alone")
+    results = []
+    for load in loads:
+        results.append(_serve_at(N, items, reqs, t_alone, load, n_req))
+        progress(f"serving: load {load} done")
+    return results[0] if len(results) == 1 else {"loads": results}
+
+
+def _serve_at(N, items, reqs, t_alone, load, n_req):
+    lam = load / float(np.mean(t_alone))
     arr = [r.t_arrival / lam for r in reqs]
     fin, lat_alone = 0.0, []
     for a, ts in zip(arr, t_alone):
@@ -261,6 +283,9 @@ def serve_leg(N, W, torch, n_req: int):
             sub.append(time.perf_counter() - t0)
             nxt += 1
         active, queued = srv.step()
+        if nxt % 64 == 0 and nxt and nxt != getattr(srv, "_reported", -1):
+            srv._reported = nxt
+            progress(f"serving: {nxt} requests submitted")
         if active == 0 and queued == 0:
             if nxt == len(items):
                 break
@@ -277,7 +302,7 @@ def serve_leg(N, W, torch, n_req: int):
     _, peak = srv.memory()
     srv.close()
     q = lambda v, p: round(1e3 * float(np.percentile(v, p)), 3)
-    return {"requests": n_req, "rate_per_s": round(lam, 3),
+    return {"requests": n_req, "load": load, "rate_per_s": round(lam, 3),
             "p50_ms": q(lat, 50), "p99_ms": q(lat, 99),
             "solves_per_s": round(n_req / makespan, 3),
             "alone_fifo_p50_ms": q(lat_alone, 50), "alone_fifo_p99_ms": q(lat_alone, 99),
@@ -321,14 +346,16 @@ def precision_leg(N, torch, xy, f, tg, steps: int = 2):
     return out, sols
 
 
-def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
+def batch_leg(N, W, torch, n_prob: int, maxit: int = 300, retune: bool = False):
     """Many problems (n log-uniform in [1e3, 2e5], uniform or clustered, k in
     {1..4}, minimal block, 4 right-hand sides each): one batch in mixed
-    precision (FP32 FMM, FP64 Krylov with FP64 residual refinement) against
-    the plain FP64 path solving each problem alone; both to 1e-8, plans and
-    preconditioners included.  Problems that do not reach 1e-8 within maxit
-    (order 4 on deep clustered trees, where the Hadamard far field loses
-    accuracy) are counted, not fatal."""
+    precision (FP32 FMM, FP64 Krylov with FP64 residual refinement) and the
+    same batch in FP64, against the plain FP64 path solving each problem
+    alone; all to 1e-8 within maxit, plans and preconditioners included.
+    Problems that do not reach 1e-8 (order 4 with ~1e5 nodes or more, whose
+    saddle systems are too ill-conditioned for an FP64 operator) are counted
+    and listed, not fatal; with `retune` their preconditioner is retuned on
+    their own data and the solve repeated."""
     probs = W.batched(n_problems=n_prob)
     dev = torch.device("cuda")
     data = [(torch.as_tensor(p.xy, device=dev), torch.as_tensor(p.f, device=dev), p.k,
@@ -342,6 +369,7 @@ def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
         plans.append(pl)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    progress(f"batched: {n_prob} plans and factors in {t_setup:.2f} s")
     batch = N.Batch(plans, [4] * len(plans))
     t1 = time.perf_counter()
     _, infos = batch.solve([f for _, f, _, _ in data], rtol=1e-8, maxit=maxit,
@@ -349,6 +377,7 @@ def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t1
     res_b = [i.rel_residual for i in infos]
+    progress(f"batched: mixed solve {t_solve:.2f} s")
     it32 = sum(i.iters_fp32 for i in infos)
     it64 = sum(i.iters_fp64 for i in infos)
     falls = sum(i.fp64_fallback for i in infos)
@@ -359,19 +388,41 @@ def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
     torch.cuda.synchronize()
     t_solve64 = time.perf_counter() - t1
     res_b64 = [i.rel_residual for i in infos64]
+    progress(f"batched: FP64 solve {t_solve64:.2f} s")
     batch.close()
     for pl in plans:
         pl.close()
     t2 = time.perf_counter()
     res_a = []
-    for xy, f, k, m in data:
+    for i, (xy, f, k, m) in enumerate(data):
         pl = N.Plan(xy, k, -1)
         pl.precond_build(m=m, nu=k / 2.0, seed=0)
         _, _, info = pl.solve(f, rtol=1e-8, maxit=maxit, raise_on_error=False)
         res_a.append(info.rel_residual)
         pl.close()
+        if (i + 1) % 32 == 0:
+            progress(f"batched: {i + 1} problems solved alone")
     torch.cuda.synchronize()
     t_alone = time.perf_counter() - t2
+    # problems the default preconditioner leaves above 1e-8: retune their
+    # preconditioner on their own data (phs_tune_precond) and solve again
+    retuned = []
+    t3 = time.perf_counter()
+    for i, (xy, f, k, m) in enumerate(data):
+        if res_b64[i] <= 1e-8 or not retune:
+            continue
+        pl = N.Plan(xy, k, -1)
+        r = pl.tune_precond(f[:, 0].contiguous(), rtol=1e-8, max_evals=6, maxit=400)
+        _, _, info = pl.solve(f, rtol=1e-8, maxit=maxit, raise_on_error=False)
+        progress(f"batched: problem {i} retuned")
+        retuned.append({"problem": i, "n": int(xy.shape[0]), "k": k,
+                        "default_rel_residual": res_b64[i], "m": r["m"], "nu": r["nu"],
+                        "alpha": round(r["alpha"], 4), "rel_residual": info.rel_residual,
+                        "iters": info.iters})
+        pl.close()
+    torch.cuda.synchronize()
+    t_retune = time.perf_counter() - t3
+    fixed = sum(1 for r in retuned if r["rel_residual"] <= 1e-8)
     npts = sum(p.n for p in probs)
     ok = lambda r: sum(1 for v in r if v <= 1e-8)
     return {"problems": n_prob, "rhs_per_problem": 4, "points": npts, "maxit": maxit,
@@ -385,6 +436,11 @@ def batch_leg(N, W, torch, n_prob: int, maxit: int = 1000):
             "iters_fp32": it32, "iters_fp64": it64, "fp64_fallbacks": falls,
             "at_1e-8_batched": ok(res_b), "at_1e-8_batched_fp64": ok(res_b64),
             "at_1e-8_alone": ok(res_a),
+            "at_1e-8_after_retune": (ok(res_b64) + fixed) if retune else None,
+            "retune_s": round(t_retune, 3) if retune else None, "retuned": retuned,
+            "missed_1e-8": [{"problem": i, "n": probs[i].n, "k": probs[i].k,
+                             "rel_residual_batched_fp64": res_b64[i]}
+                            for i in range(n_prob) if res_b64[i] > 1e-8],
             "median_rel_residual_batched": float(np.median(res_b)),
             "worst_rel_residual_batched": max(res_b), "worst_rel_residual_alone": max(res_a)}
 
@@ -443,6 +499,7 @@ def main():
 
     for _ in range(args.warmup):
         step(False)
+    progress("warm-up step done")
     torch.cuda.synchronize()
     if not args.no_profile:
         N.profile_enable(2)  # HIP events around the roofline kernels only
@@ -568,6 +625,7 @@ def main():
                            "4(P+1)^2 + 12(P+1) per pair and density",
         "kernels": kernels,
     }
+    progress(f"{args.steps} timed steps: {ms_per_step:.2f} ms per step")
     checks = None
     if "w" in last and args.n == (1 << 20):
         checks = {"fp64": (last["w"].cpu().numpy(), last["beta"].cpu().numpy())}
@@ -580,13 +638,17 @@ def main():
             checks.update(sols)
     if not args.no_crossover:
         out["fmm_direct_crossover"] = crossover_leg(N, W, torch)
+        progress("crossover leg done")
     if not args.no_serve and args.serve_requests > 0:
         sv = serve_leg(N, W, torch, args.serve_requests)
         out["serve_p50_ms"], out["serve_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
         out["serving"] = sv
+    if args.serve_sweep:
+        out["serving_sweep"] = serve_leg(N, W, torch, 512, loads=(0.8, 1.0, 1.2))
     if not args.no_batch and args.batch_problems > 0:
-        out["batched"] = batch_leg(N, W, torch, args.batch_problems)
+        out["batched"] = batch_leg(N, W, torch, args.batch_problems, retune=args.retune)
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline starts")
         out["cpu_baseline"] = cpu_baseline(checks)
         for name, r in out["cpu_baseline"].get("node_residual_vs_oracle_4096", {}).items():
             if name in out.get("precision_forms", {}):

@@ -158,3 +158,20 @@ def test_batch_mixed_chebyshev_orders():
         np.testing.assert_array_equal(host(w), host(wa))
         np.testing.assert_array_equal(host(b), host(ba))
     batch.close()
+
+
+@pytest.mark.skip(reason="cause known, not a defect: in the 256-problem batched workload, 11 "
+                  "order-4 problems with 9.7e4..1.9e5 nodes stop above 1e-8 (alone and "
+                  "batched alike, 2.7e-8 .. 1.0). Their saddle systems are too ill-conditioned "
+                  "for FP64: with the exact all-pairs matvec PCG loses definiteness even sooner "
+                  "than with the FMM (residual 1.0 after 2-9 iterations), and retuning the "
+                  "preconditioner (phs_tune_precond) brings one of the 11 to 1e-8. The paper "
+                  "notes k = 4 conditioning passes 1e16 for moderate n and keeps k = 4 small.")
+def test_large_order4_batched_problems_reach_1e8():
+    probs = [p for p in W.batched(n_problems=256) if p.k == 4 and p.n >= 96000]
+    for p in probs:
+        pl = N.Plan(dev(p.xy), 4)
+        pl.precond_build(m=p.precond["m"], nu=2.0)
+        _, _, info = pl.solve(dev(p.f[:, 0]), rtol=1e-8, maxit=1000, raise_on_error=False)
+        assert info.rel_residual <= 1e-8
+        pl.close()
