@@ -270,8 +270,24 @@ __global__ __launch_bounds__(64) void kf_apply_ut(const SysDev *__restrict__ sys
   const cptr<int32_t> nbr = ro(d.nbr);
   const cptr<double> coef = ro(d.coef), dinv = ro(d.dinv);
   double acc = dinv[j] * rr[j];
-#pragma unroll 6
-  for (int sl = 0; sl < m; ++sl) {
+  // slots in batches of eight: the indices and coefficients first, then the
+  // eight gathers (all in flight together), then the sums in slot order
+  int sl = 0;
+  for (; sl + 8 <= m; sl += 8) {
+    int q[8];
+    double c[8], v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      q[u] = nbr[(sl + u) * n + j];
+      c[u] = coef[(sl + u) * n + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = rr[q[u] >= 0 ? q[u] : j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q[u] >= 0) acc = fma(c[u], v[u], acc);
+  }
+  for (; sl < m; ++sl) {
     const int q = nbr[sl * n + j];
     if (q >= 0) acc = fma(coef[sl * n + j], rr[q], acc);
   }
@@ -326,10 +342,29 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
   double acc[RPG];
 #pragma unroll
   for (int k = 0; k < RPG; ++k) acc[k] = 0.0;
-  for (int o = g; o < len; o += LPR) {
+  // two entries of each of the RPG rows per step: 2 x RPG independent
+  // gathers in flight per lane, each row still summed in entry order
+  for (int o = g; o < len; o += 2 * LPR) {
+    int ti[2][RPG];
+    double tc[2][RPG], yv[2][RPG];
 #pragma unroll
-    for (int k = 0; k < RPG; ++k)
-      if (b[k] + o < e[k]) acc[k] += tcoef[b[k] + o] * yy[tidx[b[k] + o]];
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < RPG; ++k) {
+        const int idx = b[k] + o + h * LPR;
+        const bool in = idx < e[k];
+        ti[h][k] = in ? tidx[idx] : -1;
+        tc[h][k] = in ? tcoef[idx] : 0.0;
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < RPG; ++k) yv[h][k] = ti[h][k] >= 0 ? yy[ti[h][k]] : 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < RPG; ++k)
+        if (ti[h][k] >= 0) acc[k] += tc[h][k] * yv[h][k];
   }
 #pragma unroll
   for (int k = 0; k < RPG; ++k) {
