@@ -394,29 +394,44 @@ __global__ __launch_bounds__(256) void kf_cheb_m2l(const SysDev *__restrict__ sy
   }
 }
 
-// FP64 M2L on the matrix cores: the tiles of kf_cheb_m2l (QQ output rows by
-// 64 columns per workgroup, the contraction staged through LDS in chunks of
-// 16), with the products by v_mfma_f64_16x16x4f64.  Wavefront w computes the
-// 16-row tiles w, w + 4, ... against all four 16-column tiles.  Lane layout of
-// the product (row m, column n, inner index k): A[m][k] at lane m + 16 k,
-// B[k][n] at lane n + 16 k, result D[m][n] at lane n + 16 (m mod 4) in
-// register m / 4.  Capped at 3 wavefronts per SIMD: left to itself the
-// compiler holds 280 VGPRs at QQ = 256 (one wavefront), where 164 suffice.
+// FP64 M2L on the matrix cores: the tiles of kf_cheb_m2l (output rows by 64
+// columns, the contraction staged through LDS in chunks of 16), with the
+// products by v_mfma_f64_16x16x4f64.  Lane layout of the product (row m,
+// column n, inner index k): A[m][k] at lane m + 16 k, B[k][n] at lane
+// n + 16 k, result D[m][n] at lane n + 16 (m mod 4) in register m / 4.
+//
+// Row split: the QQ output rows of a tile are shared by
+// cheb_m2l_max_split(QQ) workgroups, each taking a contiguous block of 16-row
+// tiles (work item = tile * split + part), one tile per wavefront at QQ = 256.
+// Pipelining: the source boxes of all 40 offsets are found first, the
+// (offset, contraction chunk) steps then run as one flat sequence, and each
+// thread loads the next step's operands into registers while the matrix cores
+// work on the current step.  A tile was bound by the latency of its 40 x QQ/16
+// dependent load-then-compute steps (a launch took ~4.6 ms whatever the tree
+// size); every output row is still summed by one workgroup, offset by offset
+// and chunk by chunk in the original order.
 typedef double cdbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kOffsets = 40;  // M2L offsets: the 7 x 7 square minus the 3 x 3 near field
 
 template <int QQ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-void kf_cheb_m2l_mfma(const SysDev *__restrict__ sys,
-                                                        const BlkRef *__restrict__ tab,
-                                                        const int32_t *__restrict__ mask,
-                                                        const double *__restrict__ Kd) {
-  constexpr int MT = (QQ + 15) / 16;  // 16-row tiles (rows past QQ are zero)
-  constexpr int TPW = (MT + 3) / 4;   // row tiles per wavefront
+void kf_cheb_m2l_mfma(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                      const int32_t *__restrict__ mask, const double *__restrict__ Kd) {
+  constexpr int RS = cheb_m2l_max_split(QQ);
+  constexpr int MT_ALL = (QQ + 15) / 16;      // 16-row tiles (rows past QQ are zero)
+  constexpr int MT = (MT_ALL + RS - 1) / RS;  // row tiles of one part
+  constexpr int TPW = (MT + 3) / 4;           // row tiles per wavefront
+  constexpr int KS = (QQ + kKc - 1) / kKc;    // contraction chunks per offset
+  constexpr int APT = MT * 16 * kKc / 256;    // A operands a thread stages per step
+  constexpr int BPT = kKc * kCols / 256;      // B operands a thread stages per step
+  static_assert(MT * 16 * kKc % 256 == 0 && kKc * kCols % 256 == 0, "staging split");
   constexpr int AST = kKc + 1, BST = kCols + 1;  // padded strides
   __shared__ double As[MT * 16 * AST];
   __shared__ double Bs[kKc * BST];
-  __shared__ int src_box[kCols];
-  __shared__ int any_valid;
+  __shared__ int sbox[kOffsets * kCols];
+  __shared__ int vlist[kOffsets];
+  __shared__ int nvalid;
   const BlkRef br = tab[blockIdx.x];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
@@ -427,8 +442,10 @@ void kf_cheb_m2l_mfma(const SysDev *__restrict__ sys,
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lm = lane & 15, lk = lane >> 4;
+  // this part's row tiles: rt0 .. rt0 + MT (those below MT_ALL)
+  const int rt0 = (br.blk % RS) * MT;
   // locate level and tile
-  int64_t tcol = (int64_t)br.blk * kCols;
+  int64_t tcol = (int64_t)(br.blk / RS) * kCols;
   int l = 2;
   int64_t off = 0, base = 0;
   while (l <= L) {
@@ -459,66 +476,101 @@ void kf_cheb_m2l_mfma(const SysDev *__restrict__ sys,
     iy = 2 * (int)(rem / hf) + (cls >> 1);
     return true;
   };
+  // source box of each column under each offset (-1: none)
+  for (int e = tid; e < kOffsets * kCols; e += 256) {
+    const int di = e / kCols, c = e % kCols;
+    // offset di of the (oy, ox) row-major order over [-3, 3]^2 without the
+    // 3 x 3 near field: rows oy = -3, -2 and 2, 3 hold 7 offsets, rows -1..1
+    // hold 4 (ox = -3, -2, 2, 3)
+    int oy, ox;
+    if (di < 14) {
+      oy = -3 + di / 7;
+      ox = -3 + di % 7;
+    } else if (di < 26) {
+      oy = -1 + (di - 14) / 4;
+      const int j = (di - 14) % 4;
+      ox = j < 2 ? j - 3 : j;
+    } else {
+      oy = 2 + (di - 26) / 7;
+      ox = -3 + (di - 26) % 7;
+    }
+    int sb = -1;
+    int ix, iy, r;
+    if (tgt_of(col0 + c, ix, iy, r)) {
+      const int jx = ix + ox, jy = iy + oy;
+      if (jx >= 0 && jy >= 0 && jx < G && jy < G && abs((jx >> 1) - (ix >> 1)) <= 1 &&
+          abs((jy >> 1) - (iy >> 1)) <= 1)
+        sb = (jy * G + jx) * nd + r;
+    }
+    sbox[e] = sb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int nv = 0;
+    for (int di = 0; di < kOffsets; ++di) {
+      bool any = false;
+      for (int c = 0; c < kCols && !any; ++c) any = sbox[di * kCols + c] >= 0;
+      if (any) vlist[nv++] = di;
+    }
+    nvalid = nv;
+  }
+  __syncthreads();
+  const int steps = nvalid * KS;
+  double ra[APT], rb[BPT];
+  auto stage = [&](int st) {  // this thread's operands of step st into registers
+    const int di = vlist[st / KS], k0 = (st % KS) * kKc;
+    const double *KD = Kd + (int64_t)di * QQ * QQ;
+#pragma unroll
+    for (int u = 0; u < APT; ++u) {
+      const int e = tid + 256 * u;
+      const int m = 16 * rt0 + e / kKc, kk = e % kKc;
+      ra[u] = (m < QQ && k0 + kk < QQ) ? KD[(int64_t)m * QQ + k0 + kk] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kKc, kk = e % kKc;
+      const int sb = sbox[di * kCols + c];
+      rb[u] = (sb >= 0 && k0 + kk < QQ) ? Wl[(int64_t)sb * QQ + k0 + kk] : 0.0;
+    }
+  };
   cdbl4 acc[TPW][4];
 #pragma unroll
   for (int t = 0; t < TPW; ++t)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[t][ct] = cdbl4{0.0, 0.0, 0.0, 0.0};
-  int oi = 0;
-  for (int oy = -3; oy <= 3; ++oy)
-    for (int ox = -3; ox <= 3; ++ox) {
-      if (abs(ox) <= 1 && abs(oy) <= 1) continue;
-      const int d_idx = oi++;
-      __syncthreads();
-      if (tid == 0) any_valid = 0;
-      __syncthreads();
-      if (tid < kCols) {
-        int ix, iy, r;
-        int sb = -1;
-        if (tgt_of(col0 + tid, ix, iy, r)) {
-          const int jx = ix + ox, jy = iy + oy;
-          if (jx >= 0 && jy >= 0 && jx < G && jy < G && abs((jx >> 1) - (ix >> 1)) <= 1 &&
-              abs((jy >> 1) - (iy >> 1)) <= 1)
-            sb = (jy * G + jx) * nd + r;
-        }
-        src_box[tid] = sb;
-        if (sb >= 0) any_valid = 1;
-      }
-      __syncthreads();
-      if (!any_valid) continue;
-      const double *KD = Kd + (int64_t)d_idx * QQ * QQ;
-      for (int k0 = 0; k0 < QQ; k0 += kKc) {
-        // A tile: KD[m][k0 .. k0 + kKc), rows padded to MT * 16 with zeros
-        for (int e = tid; e < MT * 16 * kKc; e += 256) {
-          const int m = e / kKc, kk = e % kKc;
-          As[m * AST + kk] = (m < QQ && k0 + kk < QQ) ? KD[(int64_t)m * QQ + k0 + kk] : 0.0;
-        }
-        // B tile: W[src][k0 .. k0 + kKc) of each column
-        for (int e = tid; e < kKc * kCols; e += 256) {
-          const int c = e / kKc, kk = e % kKc;
-          const int sb = src_box[c];
-          Bs[kk * BST + c] = (sb >= 0 && k0 + kk < QQ) ? Wl[(int64_t)sb * QQ + k0 + kk] : 0.0;
-        }
-        __syncthreads();
+  if (steps > 0) stage(0);
+  for (int st = 0; st < steps; ++st) {
+    __syncthreads();  // the previous step's reads of As / Bs are done
 #pragma unroll
-        for (int st = 0; st < kKc / 4; ++st) {
-          double b[4];
+    for (int u = 0; u < APT; ++u) {
+      const int e = tid + 256 * u;
+      As[(e / kKc) * AST + e % kKc] = ra[u];
+    }
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[(4 * st + lk) * BST + 16 * ct + lm];
+    for (int u = 0; u < BPT; ++u) {
+      const int e = tid + 256 * u;
+      Bs[(e % kKc) * BST + e / kKc] = rb[u];
+    }
+    __syncthreads();
+    if (st + 1 < steps) stage(st + 1);  // in flight during the products
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) {
-            const int rt = wave + 4 * t;
-            if (rt < MT) {  // uniform across the wavefront
-              const double a = As[(16 * rt + lm) * AST + 4 * st + lk];
+    for (int q = 0; q < kKc / 4; ++q) {
+      double b[4];
 #pragma unroll
-              for (int ct = 0; ct < 4; ++ct)
-                acc[t][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct], acc[t][ct], 0, 0, 0);
-            }
-          }
+      for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[(4 * q + lk) * BST + 16 * ct + lm];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int rt = wave + 4 * t;
+        if (rt < MT && rt0 + rt < MT_ALL) {  // uniform across the wavefront
+          const double a = As[(16 * rt + lm) * AST + 4 * q + lk];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct)
+            acc[t][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct], acc[t][ct], 0, 0, 0);
         }
-        __syncthreads();
       }
     }
+  }
   // store: D[m][n] of tile (t, ct) at lane n + 16 (m mod 4), register m / 4
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) {
@@ -528,10 +580,10 @@ void kf_cheb_m2l_mfma(const SysDev *__restrict__ sys,
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int rt = wave + 4 * t;
-      if (rt >= MT) continue;
+      if (rt >= MT || rt0 + rt >= MT_ALL) continue;
 #pragma unroll
       for (int reg = 0; reg < 4; ++reg) {
-        const int m = 16 * rt + 4 * reg + lk;
+        const int m = 16 * (rt0 + rt) + 4 * reg + lk;
         if (m < QQ) Gl[tb + m] = half_w * acc[t][ct][reg];
       }
     }

@@ -756,6 +756,8 @@ int m2l_chunk(int P);
 Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
   std::vector<BlkRef> h;
   const int tier = kind >> 4, base = kind & 15;
+  // FP64 Chebyshev M2L (matrix cores): workgroups per tile
+  const int rs = (base == 9 && tier != 1) ? cheb_m2l_max_split(P * P) : 1;
   for (int i = 0; i < F.nsys; ++i) {
     const Plan &pl = *F.plan[i];
     if (pl.direct) continue;  // no FMM
@@ -828,7 +830,8 @@ Tab build_fmm_tab(Forest &F, int kind, int K, int P, int level, hipStream_t s) {
         if (cheb) {
           int64_t tiles = 0;
           for (int l = 2; l <= L; ++l) tiles += (boxes_at(l) * R + 63) / 64;
-          for (int64_t b = 0; b < tiles; ++b) h.push_back({i, (int32_t)b});
+          // FP64 tiers: rs workgroups per tile (FP32: one)
+          for (int64_t b = 0; b < tiles * rs; ++b) h.push_back({i, (int32_t)b});
         }
         break;
       default:

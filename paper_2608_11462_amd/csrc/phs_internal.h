@@ -357,6 +357,12 @@ void refresh_forest(Forest &F, hipStream_t s);
 void sync_forest_pc(Forest &F, hipStream_t s);
 void alloc_syswork(SysWork &w, const Plan &pl);
 Tab forest_tab(Forest &F, uint64_t key, hipStream_t s);
+// Workgroups sharing the output rows of one FP64 Chebyshev M2L tile (the
+// split shortens each workgroup's sequence of dependent steps; measured faster
+// at every tree size from 3e3 to 1e6 nodes)
+__host__ __device__ constexpr int cheb_m2l_max_split(int QQ) {
+  return QQ >= 256 ? 4 : (QQ >= 128 ? 2 : 1);
+}
 // log-kernel P2M packs this many leaves per wavefront (lane = coefficient)
 __host__ __device__ inline int p2m_leaves_per_wave(int P) {
   const int g = 64 / (P + 1);
