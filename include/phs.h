@@ -421,6 +421,18 @@ phs_status phs_direct_sum_noalloc(int32_t k, const double *xy, int64_t n, const 
 phs_status phs_memory_stats(int64_t *allocations, int64_t *device_mallocs,
                             int64_t *bytes_in_use, int64_t *bytes_held);
 
+/* PCG iterations through HIP graphs.  on = 1: the launch sequences of a
+ * projected-PCG iteration (operator, projection, update and scalar gather;
+ * preconditioner apply and search-direction update) are captured once per
+ * plan, batch or serving forest, the second time each runs, and replayed with
+ * one graph launch each; the results are bitwise those of the direct
+ * launches.  Iterations with an FP32 operator, solves checked less often than
+ * every iteration, and everything while per-kernel timing is on run as direct
+ * launches.  on = 0 (the default): direct launches only; on MI355X the
+ * replays measured 1-2 % slower than direct launches, from 2000-node solves
+ * to 2^20.  Process-wide; takes effect at the next iteration. */
+void phs_set_graphs(int32_t on);
+
 /* Per-kernel timing.  on = 1: each library kernel launch is bracketed by HIP
  * events on its own stream; on = 2: only the leaf, M2L, Vecchia factor and
  * KNN, and preconditioner-apply kernels; 0: off.  phs_profile_read copies up

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <atomic>
 #include <mutex>
 
 #include "phs_internal.h"
@@ -77,6 +78,11 @@ void prof_flush_locked() {
 }  // namespace
 
 bool profiling_on() { return g_prof_on; }
+
+namespace {
+std::atomic<bool> g_graphs{false};
+}
+bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed); }
 
 // level 2 times only the kernels the roofline figures use
 bool prof_wants(const char *name) {
@@ -855,6 +861,8 @@ phs_status phs_memory_stats(int64_t *allocations, int64_t *device_mallocs,
   pool_stats(allocations, device_mallocs, bytes_in_use, bytes_held);
   return PHS_OK;
 }
+
+void phs_set_graphs(int32_t on) { g_graphs.store(on != 0, std::memory_order_relaxed); }
 
 void phs_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

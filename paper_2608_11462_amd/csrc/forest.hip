@@ -475,6 +475,14 @@ SysDev make_sysdev(const Plan &pl, const SysWork &w) {
 }
 
 Forest::~Forest() {
+  bool graphs = false;
+  for (auto &g : graph) graphs = graphs || g;
+  if (graphs) {
+    (void)hipDeviceSynchronize();  // no replay may still be running
+    for (auto &g : graph)
+      if (g) (void)hipGraphExecDestroy(g);
+  }
+  if (cap) (void)hipStreamDestroy(cap);
   dfree(dsys);
   for (int i = 0; i < kMasks; ++i) {
     if (mask_ev[i]) {
@@ -683,11 +691,46 @@ void f_sc_copy(Forest &F, const int32_t *mask, int dst, int src, hipStream_t s) 
 // The gather writes straight into the pinned host block (device-accessible),
 // so the readback needs no copy: the kernel's completion and the stream
 // synchronisation make the values visible to the host.
-void f_read_scalars(Forest &F, int off, int cnt, hipStream_t s) {
+void f_read_scalars_launch(Forest &F, int off, int cnt, hipStream_t s) {
   const int tot = F.nsys * cnt;
   PHS_LAUNCH("read_sc", s,
              kf_read_sc<<<(tot + 255) / 256, 256, 0, s>>>(F.dsys, F.nsys, off, cnt, F.hgsc));
+}
+
+void f_read_scalars(Forest &F, int off, int cnt, hipStream_t s) {
+  f_read_scalars_launch(F, off, cnt, s);
   PHS_HIP(hipStreamSynchronize(s));
+}
+
+void f_run(Forest &F, int key, hipStream_t s, const std::function<void(hipStream_t)> &fn) {
+  PHS_REQUIRE(key >= 0 && key < Forest::kGraphs, PHS_ERR_INVALID_ARGUMENT, "graph key");
+  if (!graphs_enabled() || profiling_on() || launches_suppressed()) {
+    fn(s);
+    return;
+  }
+  if (!F.graph[key]) {
+    if (++F.graph_runs[key] < 2) {  // a sequence that runs once is not worth a capture
+      fn(s);
+      return;
+    }
+    if (!F.cap) PHS_HIP(hipStreamCreateWithFlags(&F.cap, hipStreamNonBlocking));
+    PHS_HIP(hipStreamBeginCapture(F.cap, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      fn(F.cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(F.cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    PHS_HIP(hipStreamEndCapture(F.cap, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    PHS_HIP(e);
+    F.graph[key] = ex;
+  }
+  PHS_HIP(hipGraphLaunch(F.graph[key], s));
 }
 
 void f_precond_apply(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s) {

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/phs.h"
@@ -343,8 +344,26 @@ struct Forest {
   std::vector<std::pair<uint64_t, Tab>> cache;  // FMM tables keyed by (kind, K, P, level)
   bool any_direct = false;  // some system's plan applies M by direct summation
   bool frozen = false;  // every table is built: a lookup miss is an internal error
+  // Launch sequences of the PCG iteration replayed from HIP graphs.  The
+  // kernels take only the forest's fixed descriptors, tables, masks and slot
+  // numbers as arguments and read masks and scalars from device memory, so a
+  // graph stays valid for the forest's lifetime; it is captured (on a stream
+  // of the forest's own, as the caller's may be the null stream) the second
+  // time its sequence runs.
+  static constexpr int kGraphs = 8;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[kGraphs] = {};
+  int graph_runs[kGraphs] = {};
   ~Forest();
 };
+
+// Run fn (launches only: no allocation, copy, memset or synchronisation) on
+// stream s, from the forest's graph number key once that is captured; eager
+// while graphs are switched off, while profiling (its events would be
+// captured), or while launches are suppressed.
+void f_run(Forest &F, int key, hipStream_t s, const std::function<void(hipStream_t)> &fn);
+// PCG iterations through HIP graphs (off by default; phs_set_graphs)
+bool graphs_enabled();
 
 // build a forest over systems (plan[i], work[i]); uploads descriptors and the
 // element/dot/preconditioner tables.  refresh_forest re-reads the plans'
@@ -375,6 +394,10 @@ SysDev make_sysdev(const Plan &pl, const SysWork &w);
 // set device mask i to m (nsys flags); uploads only when it changes, and
 // never rewrites the pinned staging buffer while its last copy is in flight
 void set_mask(Forest &F, int i, const std::vector<int32_t> &m, hipStream_t s);
+// gather cnt scalars from slot off of every system into F.hgsc (pinned); the
+// values are the host's after the stream synchronises.  f_read_scalars
+// synchronises itself.
+void f_read_scalars_launch(Forest &F, int off, int cnt, hipStream_t s);
 
 // forest vector operations (systems with mask[sys] != 0)
 void f_fill(Forest &F, const int32_t *mask, int slot, double a, hipStream_t s);

@@ -160,12 +160,28 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       set_mask(F, MK_PN32, jr,
                [](const JobRun &r) { return r.state == J_PCG && r.inner_prec == PHS_NEAR32; },
                an32, s);
+      // FP64 iterations checked every time run from graphs: (q = sign Pi M p,
+      // p.q, the w / r update, r.r, their gather) and (z = precond(r), r.z,
+      // the new p).  The kernels read the masks uploaded above.
+      const bool graphs = check_every == 1 && !a32 && !an32;
+      if (graphs) {
+        f_run(F, (a64 ? 1 : 0) | (a64h ? 2 : 0), s, [&](hipStream_t cs) {
+          if (a64) f_matvec(F, F.mask[MK_P64], V_P, V_Q, PHS_FP64, cs);
+          if (a64h) f_matvec(F, F.mask[MK_P64H], V_P, V_Q, PHS_FP64_EVAL, cs);
+          f_project_dot(F, F.mask[MK_PCG], V_Q, true, V_P, SC_PQ, cs);
+          f_pcg_wr(F, F.mask[MK_PCG], cs);
+          f_read_scalars_launch(F, 0, 4, cs);
+        });
+        PHS_HIP(hipStreamSynchronize(s));
+      }
       // q = sign Pi M p
-      if (a64) f_matvec(F, F.mask[MK_P64], V_P, V_Q, PHS_FP64, s);
-      if (a64h) f_matvec(F, F.mask[MK_P64H], V_P, V_Q, PHS_FP64_EVAL, s);
-      if (a32) f_matvec(F, F.mask[MK_P32], V_P, V_Q, PHS_MIXED, s);
-      if (an32) f_matvec(F, F.mask[MK_PN32], V_P, V_Q, PHS_NEAR32, s);
-      f_project_dot(F, F.mask[MK_PCG], V_Q, true, V_P, SC_PQ, s);
+      if (!graphs) {
+        if (a64) f_matvec(F, F.mask[MK_P64], V_P, V_Q, PHS_FP64, s);
+        if (a64h) f_matvec(F, F.mask[MK_P64H], V_P, V_Q, PHS_FP64_EVAL, s);
+        if (a32) f_matvec(F, F.mask[MK_P32], V_P, V_Q, PHS_MIXED, s);
+        if (an32) f_matvec(F, F.mask[MK_PN32], V_P, V_Q, PHS_NEAR32, s);
+        f_project_dot(F, F.mask[MK_PCG], V_Q, true, V_P, SC_PQ, s);
+      }
       const int32_t *upd_mask = F.mask[MK_PCG];
       if (check_every == 1 && (a32 || an32)) {
         // curvature check before the update so a breakdown step of an inexact
@@ -184,14 +200,14 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
           upd_mask = F.mask[MK_UPD];
         }
       }
-      f_pcg_wr(F, upd_mask, s);
+      if (!graphs) f_pcg_wr(F, upd_mask, s);
       bool need_check = false;
       for (auto *rp_ : jr) if (auto &r = *rp_; true)
         if (r.state == J_PCG) {
           ++r.it;
           if (r.it % check_every == 0 || r.it == r.maxit_inner) need_check = true;
         }
-      if (need_check) f_read_scalars(F, 0, 4, s);
+      if (need_check && !graphs) f_read_scalars(F, 0, 4, s);
       for (auto *rp_ : jr) if (auto &r = *rp_; true) {
         if (r.state != J_PCG) continue;
         if (!(r.it % check_every == 0 || r.it == r.maxit_inner)) continue;
@@ -209,9 +225,13 @@ bool solve_round(Forest &F, std::vector<SolveJob *> &jr, const SolveParams &P, h
       // z = precond(r), rho_new = r.z, p = z + (rho_new / rho) p, rho = rho_new
       set_mask(F, MK_CONT, jr, [](const JobRun &r) { return r.state == J_PCG; }, any, s);
       if (any) {
-        f_precond_dot(F, F.mask[MK_CONT], V_R, V_Z, V_TMP, SC_RHO_NEW, s);
-        f_pcg_p(F, F.mask[MK_CONT], s);
-        f_sc_copy(F, F.mask[MK_CONT], SC_RHO, SC_RHO_NEW, s);
+        auto next_p = [&](hipStream_t cs) {
+          f_precond_dot(F, F.mask[MK_CONT], V_R, V_Z, V_TMP, SC_RHO_NEW, cs);
+          f_pcg_p(F, F.mask[MK_CONT], cs);
+          f_sc_copy(F, F.mask[MK_CONT], SC_RHO, SC_RHO_NEW, cs);
+        };
+        if (graphs) f_run(F, 4, s, next_p);
+        else next_p(s);
       }
     }
 

@@ -32,7 +32,7 @@ EXPORTS = ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval
            "phs_server_memory", "phs_server_destroy",
            "phs_tune_precond", "phs_autotune_plan",
            "phs_direct_sum", "phs_direct_sum_noalloc", "phs_last_error", "phs_memory_stats",
-           "phs_profile_enable", "phs_profile_read")
+           "phs_profile_enable", "phs_profile_read", "phs_set_graphs")
 PHS_REQ_QUEUED, PHS_REQ_ACTIVE, PHS_REQ_DONE, PHS_REQ_FAILED = 0, 1, 2, 3
 
 
@@ -154,6 +154,8 @@ def lib() -> C.CDLL:
         L.phs_direct_sum_noalloc.argtypes = [i32, dp, i64, dp, dp, i64, dp, vp]
         L.phs_profile_enable.argtypes = [i32]
         L.phs_profile_enable.restype = None
+        L.phs_set_graphs.argtypes = [i32]
+        L.phs_set_graphs.restype = None
         L.phs_profile_read.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_double), i32]
         L.phs_profile_read.restype = i32
         for name in ("phs_plan", "phs_matvec", "phs_precond_build", "phs_solve", "phs_eval",
@@ -499,6 +501,11 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def set_graphs(on: bool) -> None:
+    """PCG iterations replayed from HIP graphs, or launched directly (the default)."""
+    lib().phs_set_graphs(int(bool(on)))
 
 
 def profile_enable(on=True) -> None:
