@@ -176,6 +176,65 @@ __device__ __forceinline__ float phi_scale_f() {
   return (K % 2 == 0) ? 0.34657359027997264f : 1.0f;  // 0.5 * ln 2
 }
 
+// sum_j phi(r) t_j (FP32, without phi_scale_f) over the sources js..je-1 of one
+// leaf: coordinates relative to that leaf's centre, the target (xc, yc)
+// already moved into the same frame.  The source values are wave-uniform, so
+// they arrive by scalar loads, which complete out of order: a wait for one
+// load is a wait for all.  Batches of eight therefore run one behind their
+// loads: wait for the current batch, form its coordinate differences, issue
+// the next batch's loads (the last batch re-reads itself, so no branch
+// surrounds them), then evaluate phi while they land.  The scheduling
+// barriers keep the compiler from moving the loads above the wait.  Terms are
+// added in source order.
+template <int K, class PF>
+__device__ __forceinline__ float near_range_f32(float xc, float yc, PF ux, PF uy, PF tf, int js,
+                                                int je) {
+  float acc = 0.0f;
+  const int nb = (je - js) / 8;  // full batches
+  int j = js;
+  if (nb > 0) {
+    float cx[8], cy[8], ct[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      cx[i] = ux[j + i];
+      cy[i] = uy[j + i];
+      ct[i] = tf[j + i];
+    }
+    for (int b = 0; b < nb; ++b, j += 8) {
+      float dx[8], dy[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        dx[i] = xc - cx[i];
+        dy[i] = yc - cy[i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      const int jn = b + 1 < nb ? j + 8 : j;
+      float nx[8], ny[8], nt[8];
+      const PF px = ux + jn, py = uy + jn, pt = tf + jn;  // one base, constant offsets
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        nx[i] = px[i];
+        ny[i] = py[i];
+        nt[i] = pt[i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc += phi_r2f<K>(dx[i] * dx[i] + dy[i] * dy[i]) * ct[i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        cx[i] = nx[i];
+        cy[i] = ny[i];
+        ct[i] = nt[i];
+      }
+    }
+  }
+  for (; j < je; ++j) {
+    const float dx = xc - ux[j], dy = yc - uy[j];
+    acc += phi_r2f<K>(dx * dx + dy * dy) * tf[j];
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------- near field
 // Natural logarithm of a positive normal double by table-driven range
 // reduction (Tang's method): x = m 2^e, m in [1, 2), c_j = 1 + j/128 from the

@@ -630,8 +630,15 @@ __global__ __launch_bounds__(64) void kf_cheb_leaf_eval(const SysDev *__restrict
   const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
   const cptr<T> Gl = Gleaf + (int64_t)leaf * R * QQ;
   for (int i0 = b; i0 < e; i0 += 64) {
-    const int i = i0 + lane;
-    const bool act = i < e;
+    // a pass with at most 32 targets left runs 64/W groups of W lanes on the
+    // same targets, each over its share of every source range, and sums the
+    // groups' partial sums (the lanes a plain pass would leave idle share the
+    // near field)
+    const int rem = e - i0;
+    const int W = rem <= 8 ? 8 : rem <= 16 ? 16 : rem <= 32 ? 32 : 64;
+    const int ng = 64 / W, gi = lane / W, li = lane % W;
+    const int i = i0 + li;
+    const bool act = li < rem;
     const int ii = act ? i : b;
     const double xi = x[ii], yi = y[ii];
     T far = T(0);
@@ -672,26 +679,38 @@ __global__ __launch_bounds__(64) void kf_cheb_leaf_eval(const SysDev *__restrict
     if constexpr (std::is_same<TN, double>::value) {
       for (int row = r0; row <= r1; ++row) {
         const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-        nearv += near_range<K>(xi, yi, xy2, t, js, je, logtab);
+        const int len = je - js;
+        nearv += near_range<K>(xi, yi, xy2, t, js + len * gi / ng, js + len * (gi + 1) / ng,
+                               logtab);
       }
+      for (int o = W; o < 64; o <<= 1) nearv += __shfl_xor(nearv, o);
       nearv *= near_scale<K>();
     } else {
+      // coordinates relative to each point's own leaf centre: the target is
+      // moved into the frame of each neighbouring leaf once, so a pair costs
+      // one subtraction per axis; densities from the FP32 copy
       const float uxi = ux[ii], uyi = uy[ii];
+      const cptr<float> tf = ro((const float *)d.t32);
       for (int row = r0; row <= r1; ++row) {
-        const float offy = (float)((iy - row) * w);
+        const float uyc = uyi + (float)((iy - row) * w);
         for (int col = c0; col <= c1; ++col) {
-          const float offx = (float)((ix - col) * w);
+          const float uxc = uxi + (float)((ix - col) * w);
           const int js = start[row * G + col], je = start[row * G + col + 1];
-#pragma unroll 4
-          for (int j = js; j < je; ++j) {
-            const float dx = (uxi - ux[j]) + offx, dy = (uyi - uy[j]) + offy;
-            nearv += phi_r2f<K>(dx * dx + dy * dy) * (float)t[j];
+          if (W == 64) {
+            nearv += near_range_f32<K>(uxc, uyc, ux, uy, tf, js, je);
+          } else {
+            const int len = je - js;
+            for (int j = js + len * gi / ng; j < js + len * (gi + 1) / ng; ++j) {
+              const float dx = uxc - ux[j], dy = uyc - uy[j];
+              nearv += phi_r2f<K>(dx * dx + dy * dy) * tf[j];
+            }
           }
         }
       }
+      for (int o = W; o < 64; o <<= 1) nearv += __shfl_xor(nearv, o);
       nearv *= phi_scale_f<K>();
     }
-    if (act) ytree[i] = (double)far + (double)nearv;
+    if (act && gi == 0) ytree[i] = (double)far + (double)nearv;
   }
 }
 

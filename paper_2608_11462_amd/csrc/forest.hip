@@ -40,6 +40,18 @@ __global__ void kf_fill(const SysDev *__restrict__ sys, const BlkRef *__restrict
   if (i < d.n) d.v[slot][i] = a;
 }
 
+// the densities of an FP32 near field, converted once per matvec instead of
+// once per pair
+__global__ void kf_near_t32(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                            const int32_t *__restrict__ mask, int slot) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  if (!d.t32) return;  // direct-summation systems
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  if (i < d.n) d.t32[i] = (float)d.v[slot][i];
+}
+
 __global__ void kf_copy(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
                         const int32_t *__restrict__ mask, int dst, int src) {
   const BlkRef br = tab[blockIdx.x];
@@ -415,6 +427,8 @@ void SysWork::release() {
   dfree(red);
   dfree(sc);
   dfree(dpart);
+  dfree(t32);
+  t32 = nullptr;
   mp = loc = nullptr;
   for (auto &p : v) p = nullptr;
   red = sc = nullptr;
@@ -432,6 +446,8 @@ void alloc_syswork(SysWork &w, const Plan &pl) {
     if (pl.direct) {
       w.dpart_cap = direct_scratch_doubles(pl.n, pl.n);
       if (w.dpart_cap > 0) w.dpart = dmalloc<double>(w.dpart_cap);
+    } else {
+      w.t32 = dmalloc<float>(std::max<int64_t>(pl.n, 1));
     }
   } catch (...) {
     w.release();
@@ -461,6 +477,7 @@ SysDev make_sysdev(const Plan &pl, const SysWork &w) {
   for (int i = 0; i < kSysVecs; ++i) d.v[i] = w.v[i];
   d.red = w.red;
   d.sc = w.sc;
+  d.t32 = w.t32;
   d.n = pl.n;
   d.h = pl.tree.h;
   d.S = pl.S;
@@ -766,6 +783,9 @@ void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t 
 }
 
 void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hipStream_t s) {
+  if ((precision == PHS_MIXED || precision == PHS_NEAR32) && F.maxL_log + F.maxL_dist > 0)
+    PHS_LAUNCH("near_t32", s,
+               kf_near_t32<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, in));
   if (F.maxL_log > 0) log_matvec(F, mask, in, out, precision, s);
   if (F.maxL_dist > 0) dist_matvec(F, mask, in, out, precision, s);
   if (F.any_direct) direct_matvec(F, mask, in, out, precision, s);

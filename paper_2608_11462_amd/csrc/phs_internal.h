@@ -231,6 +231,7 @@ struct SysDev {
   double *v[kSysVecs];
   double *red;
   double *sc;
+  float *t32;
   int64_t n;
   double h;
   int32_t S, L, k, R, sign, nbdot, m, has_pc;
@@ -247,6 +248,7 @@ struct SysWork {  // device workspace of one system
   double *sc = nullptr;
   double *dpart = nullptr;  // chunk partial sums of the direct matvec (direct plans)
   int64_t dpart_cap = 0;    // doubles
+  float *t32 = nullptr;     // FP32 copy of the densities of an FP32 near field (FMM plans)
   void release();
 };
 
