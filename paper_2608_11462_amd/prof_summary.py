@@ -3,10 +3,15 @@
     python -m paper_2608_11462_amd.prof_summary kernels <dir> <out.md> "<command>"
     python -m paper_2608_11462_amd.prof_summary traffic <fetch_dir> <write_dir> <out.md> \
         "<fetch command>" "<write command>"
+    python -m paper_2608_11462_amd.prof_summary sq <out.md> <dir> "<command>" [<dir> "<command>" ...]
 
 `kernels` reads the `*_kernel_stats.csv` and `*_kernel_trace.csv` files that
 `rocprofv3 --kernel-trace --stats --output-format csv` writes and tabulates
 calls, total and average duration, share, VGPRs and LDS bytes per kernel.
+
+`sq` reads the `*_counter_collection.csv` files of one or more `--pmc` passes of
+SQ counters and tabulates, for the step's main kernels, each counter per
+dispatch (summed over the dispatch's wavefronts) and per wavefront.
 
 `traffic` reads the `*_counter_collection.csv` files of two `--pmc` passes
 (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), scales them by what the same
@@ -130,9 +135,61 @@ def traffic(fetch_dir: str, write_dir: str, out: str, fcmd: str, wcmd: str) -> N
             "commands": [fcmd, wcmd]}, indent=1) + "\n")
 
 
+SQ_KERNELS = ["kf_leaf_eval<double, double, 2>", "kf_m2l_mfma<27>", "k_factor<32>", "k_knn",
+              "kf_apply_u", "kf_apply_ut"]
+
+
+def sq(out: str, passes) -> None:
+    """passes: [(dir, command), ...]; one table row per kernel of SQ_KERNELS."""
+    vals = defaultdict(dict)
+    counters = []
+    for d, _ in passes:
+        tot, cnt = defaultdict(float), defaultdict(int)
+        for r in _rows(Path(d), "_counter_collection.csv"):
+            key = (_short(r["Kernel_Name"]), r["Counter_Name"])
+            tot[key] += float(r["Counter_Value"])
+            cnt[key] += 1
+        for (k, c), v in tot.items():
+            if c not in counters:
+                counters.append(c)
+            vals[k][c] = v / cnt[(k, c)]  # per dispatch (its records are per dispatch)
+    lines = ["# SQ counters per dispatch: n=2^20 thin-plate solve (large_tps), FP64", "",
+             "Commands (one pass per counter set, from the repository root):", "", "```"]
+    lines += [c for _, c in passes]
+    lines += ["```", "",
+              "Each value is the counter summed over one dispatch's wavefronts, averaged over "
+              "the dispatches of the run; `/wave` divides by `SQ_WAVES` where that was "
+              "collected.", ""]
+    cols = [c for c in counters]
+    lines.append("| kernel | " + " | ".join(cols) + " |")
+    lines.append("|---|" + "---:|" * len(cols))
+    for k in SQ_KERNELS:
+        if k not in vals:
+            continue
+        row = []
+        for c in cols:
+            v = vals[k].get(c)
+            row.append("" if v is None else f"{v:.4g}")
+        lines.append(f"| `{k}` | " + " | ".join(row) + " |")
+    if any("SQ_WAVES" in vals[k] for k in vals):
+        lines += ["", "Per wavefront:", "", "| kernel | " + " | ".join(c for c in cols if c != "SQ_WAVES") + " |",
+                  "|---|" + "---:|" * (len(cols) - 1)]
+        for k in SQ_KERNELS:
+            if k not in vals or not vals[k].get("SQ_WAVES"):
+                continue
+            wv = vals[k]["SQ_WAVES"]
+            lines.append(f"| `{k}` | " + " | ".join(
+                "" if vals[k].get(c) is None else f"{vals[k][c] / wv:.4g}"
+                for c in cols if c != "SQ_WAVES") + " |")
+    Path(out).write_text("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         kernels(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "sq":
+        rest = sys.argv[3:]
+        sq(sys.argv[2], [(rest[i], rest[i + 1]) for i in range(0, len(rest), 2)])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
     else:
