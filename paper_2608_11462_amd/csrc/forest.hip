@@ -262,14 +262,18 @@ __device__ __forceinline__ double half_sum(double v) {
 // yv = U^T r over the forward factor in column-major (ELL) layout: one lane
 // per row, the m entries of row j at s*n + j, so a wavefront's loads of one
 // slot are contiguous; 64 rows per block (8 * kPcRows).
-__global__ __launch_bounds__(64) void kf_apply_ut(const SysDev *__restrict__ sys,
-                                                  const BlkRef *__restrict__ tab,
-                                                  const int32_t *__restrict__ mask, int rs,
-                                                  int ys) {
-  const BlkRef br = tab[xcd_remap(blockIdx.x, gridDim.x)];
+__global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sys,
+                                                   const BlkRef *__restrict__ tab, int64_t ntab,
+                                                   const int32_t *__restrict__ mask, int rs,
+                                                   int ys) {
+  // four 64-row blocks per workgroup, one per wavefront (wave-uniform index)
+  const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (item >= ntab) return;
+  const BlkRef br = tab[item];
   if (!mask[br.sys]) return;
   const SysDev &d = sys[br.sys];
-  const int64_t j = (int64_t)br.blk * 64 + threadIdx.x;
+  const int64_t j = (int64_t)br.blk * 64 + (threadIdx.x & 63);
   if (j >= d.n) return;
   const cptr<double> rr = ro(d.v[rs]);
   const gptr<double> yv = rw(d.v[ys]);
@@ -752,7 +756,9 @@ void f_run(Forest &F, int key, hipStream_t s, const std::function<void(hipStream
 
 void f_precond_apply(Forest &F, const int32_t *mask, int r, int z, int tmp, hipStream_t s) {
   PHS_LAUNCH("precond_ut", s,
-             kf_apply_ut<<<F_GRID(F.pc), 64, 0, s>>>(F.dsys, F.pc.d, mask, r, tmp));
+             kf_apply_ut<<<(unsigned)((F.pc.count + 3) / 4), 256, 0, s>>>(F.dsys, F.pc.d,
+                                                                        F.pc.count, mask, r,
+                                                                        tmp));
   PHS_LAUNCH("precond_u", s,
              kf_apply_u<<<F_GRID(F.pc), 256, 0, s>>>(F.dsys, F.pc.d, mask, tmp, z));
 }
