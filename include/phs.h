@@ -299,17 +299,24 @@ phs_status phs_server_create(const phs_server_opts *opts, void *stream, phs_serv
  * host, receives the request id.  Errors: INVALID_ARGUMENT. */
 phs_status phs_server_submit(phs_server_t srv, const phs_request *req, int64_t *id);
 
-/* One scheduling step: admit waiting requests that fit, run one PCG round of
- * every active request, evaluate and release those that finished.  active,
- * queued: host, may be NULL, receive the counts after the step.  A failure of
- * one request (bad input, out of memory, breakdown) is recorded in that
- * request and does not fail the step.  Synchronises `stream`. */
+/* One scheduling step: requests whose plan and preconditioner builds have
+ * finished join the active set; waiting requests that fit (slots and memory
+ * budget, at most two at a time) are handed to the server's build thread,
+ * which builds them on a stream of its own while the steps go on; one PCG
+ * round of every active request runs; finished requests are evaluated and
+ * released.  With no request active and a build running, the step waits for
+ * the build.  active, queued: host, may be NULL, receive the counts after the
+ * step (queued includes requests being built).  A failure of one request
+ * (bad input, out of memory, breakdown) is recorded in that request and does
+ * not fail the step.  Synchronises `stream`. */
 phs_status phs_server_step(phs_server_t srv, int32_t *active, int32_t *queued);
 
 /* State and timing of a request.  info: host. */
 phs_status phs_server_poll(phs_server_t srv, int64_t id, phs_request_info *info);
 
-/* Device bytes held by requests now and at most so far (host, may be NULL). */
+/* Device bytes held by requests (active ones, builds in progress at their
+ * estimate, and the shared batching structures) now and at most so far
+ * (host, may be NULL). */
 phs_status phs_server_memory(phs_server_t srv, int64_t *in_use, int64_t *peak);
 
 void phs_server_destroy(phs_server_t srv);

@@ -751,7 +751,7 @@ phs_status phs_server_step(phs_server_t srv, int32_t *active, int32_t *queued) {
     PHS_REQUIRE(srv, PHS_ERR_INVALID_ARGUMENT, "null server");
     server_step(srv->sv);
     if (active) *active = (int32_t)srv->sv.active.size();
-    if (queued) *queued = (int32_t)srv->sv.queue.size();
+    if (queued) *queued = (int32_t)(srv->sv.queue.size() + srv->sv.building);
     return PHS_OK;
   });
 }
@@ -767,7 +767,7 @@ phs_status phs_server_poll(phs_server_t srv, int64_t id, phs_request_info *info)
 phs_status phs_server_memory(phs_server_t srv, int64_t *in_use, int64_t *peak) {
   return guarded([&] {
     PHS_REQUIRE(srv, PHS_ERR_INVALID_ARGUMENT, "null server");
-    if (in_use) *in_use = srv->sv.in_use;
+    if (in_use) *in_use = srv->sv.in_use + srv->sv.reserved + srv->sv.forest_bytes;
     if (peak) *peak = srv->sv.peak;
     return PHS_OK;
   });

@@ -16,6 +16,7 @@ std::unordered_map<size_t, std::vector<void *>> g_free;  // rounded size -> idle
 std::unordered_map<void *, size_t> g_size;               // every block the pool owns
 std::unordered_map<void *, bool> g_idle;                 // blocks on a free list
 thread_local std::vector<void *> t_pending;
+thread_local int64_t t_net = 0;  // bytes this thread took from the pool minus those it returned
 int64_t g_allocs = 0, g_mallocs = 0, g_bytes = 0, g_inuse = 0;
 
 size_t round_size(size_t b) {
@@ -39,6 +40,7 @@ void *pool_alloc(size_t bytes) {
       g_idle.erase(p);
       ++g_allocs;
       g_inuse += (int64_t)r;
+      t_net += (int64_t)r;
       return p;
     }
   }
@@ -59,6 +61,7 @@ void *pool_alloc(size_t bytes) {
   ++g_mallocs;
   g_bytes += (int64_t)r;
   g_inuse += (int64_t)r;
+  t_net += (int64_t)r;
   return p;
 }
 
@@ -69,10 +72,14 @@ void pool_free(void *p) {
     if (q == p) return;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_idle.count(p) || !g_size.count(p)) return;
+    auto it = g_size.find(p);
+    if (g_idle.count(p) || it == g_size.end()) return;
+    t_net -= (int64_t)it->second;
   }
   t_pending.push_back(p);
 }
+
+int64_t pool_thread_net() { return t_net; }
 
 void pool_mark_idle() {
   if (t_pending.empty()) return;

@@ -6,6 +6,10 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <thread>
+#include <mutex>
+#include <condition_variable>
+#include <deque>
 #include <functional>
 #include <vector>
 
@@ -122,6 +126,9 @@ void pool_trim();       // returns every idle cached block to HIP
 // and cached)
 void pool_stats(int64_t *allocs, int64_t *device_mallocs, int64_t *bytes_in_use,
                 int64_t *bytes_held);
+// bytes the calling thread has taken from the pool minus the bytes it has
+// released (a block counts as released when freed, before it is recycled)
+int64_t pool_thread_net();
 
 template <class T>
 T *dmalloc(size_t count) {
@@ -493,6 +500,11 @@ struct Request {
   Plan *plan = nullptr;
   SolveJob job;
   int64_t bytes = 0;      // estimate while queued, measured once built
+  int64_t reserve = 0;    // bytes reserved while its build runs
+  // the build thread's results, read by the scheduling thread once the build
+  // is handed back (poll reads the fields above only)
+  int64_t built_bytes = 0;
+  phs_status built_status = PHS_OK;
   bool measured = false;
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
@@ -510,6 +522,19 @@ struct Server {
   Forest *F = nullptr;
   bool changed = false;
   double t0 = 0;
+  // Plans and preconditioners of admitted requests are built by a worker
+  // thread on a stream of its own while the lockstep rounds go on; a request
+  // handed to it reserves its estimated bytes until its build is collected.
+  std::thread builder;
+  std::mutex bmu;
+  std::condition_variable bcv;
+  std::deque<Request *> to_build;
+  std::vector<Request *> built;
+  int building = 0;        // handed to the worker, not yet collected
+  int64_t reserved = 0;    // estimated bytes of those
+  bool stop = false;
+  int device = 0;
+  hipStream_t bs = nullptr;
   ~Server();
 };
 void server_create(Server &sv, const phs_server_opts &o, hipStream_t s);

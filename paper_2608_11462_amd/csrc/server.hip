@@ -1,8 +1,9 @@
 // Serving: a request loop with continuous batching over the lockstep PCG
 // engine.  Requests wait in FIFO order until a slot and device memory are
-// free; an admitted request builds its plan (tree, polynomial block, FMM
-// tables, workspace) and Vecchia preconditioner, which stay resident in HBM
-// with its Krylov vectors until it finishes.  Each step runs one PCG round of
+// free; an admitted request's plan (tree, polynomial block, FMM tables,
+// workspace) and Vecchia preconditioner are built by a worker thread on a
+// stream of its own while the lockstep rounds of the active requests go on,
+// and stay resident in HBM with its Krylov vectors until it finishes.  Each step runs one PCG round of
 // every active request in shared launches; requests that finish are evaluated
 // at their targets and release their memory, and the forest of active systems
 // is rebuilt before the next round.  Requests much smaller than the largest
@@ -57,13 +58,80 @@ int64_t request_bytes(int64_t n, int k, int m) {
 }
 
 Server::~Server() {
+  {
+    std::lock_guard<std::mutex> lk(bmu);
+    stop = true;
+  }
+  bcv.notify_all();
+  if (builder.joinable()) builder.join();
   (void)hipDeviceSynchronize();
   delete F;
   for (Request *r : all) {
     delete r->plan;
     delete r;
   }
+  if (bs) (void)hipStreamDestroy(bs);
 }
+
+namespace {
+
+// The worker: builds the plan and preconditioner of each request handed to
+// it, on its own stream, and hands it back with the device bytes the build
+// left held (this thread's pool tally; the build's temporaries are returned
+// by then).  A failed build leaves no plan and the error in the request.
+void build_request(Server &sv, Request *r) {
+  const phs_request &in = r->in;
+  phs_plan_opts po{};
+  po.k = in.k;
+  po.poly_degree = in.poly_degree;
+  po.precision = sv.opts.precision;
+  const int64_t n0 = pool_thread_net();
+  try {
+    r->plan = new Plan();
+    create_plan(in.xy, in.n, &po, sv.bs, *r->plan);
+    vecchia_build(*r->plan, in.precond, sv.bs);
+    PHS_HIP(hipStreamSynchronize(sv.bs));
+    r->built_bytes = std::max<int64_t>(pool_thread_net() - n0, 0);
+    r->built_status = PHS_OK;
+  } catch (const Error &e) {
+    (void)hipStreamSynchronize(sv.bs);
+    delete r->plan;
+    r->plan = nullptr;
+    r->built_status = e.code;
+  } catch (const std::bad_alloc &) {
+    (void)hipStreamSynchronize(sv.bs);
+    delete r->plan;
+    r->plan = nullptr;
+    r->built_status = PHS_ERR_OUT_OF_MEMORY;
+  }
+  pool_mark_idle();
+}
+
+void builder_loop(Server *sv) {
+  (void)hipSetDevice(sv->device);
+  for (;;) {
+    Request *r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sv->bmu);
+      sv->bcv.wait(lk, [&] { return sv->stop || !sv->to_build.empty(); });
+      if (sv->stop) return;
+      // smallest request first: a small request is not held behind the build
+      // of a large one
+      auto it = std::min_element(sv->to_build.begin(), sv->to_build.end(),
+                                 [](const Request *a, const Request *b) { return a->in.n < b->in.n; });
+      r = *it;
+      sv->to_build.erase(it);
+    }
+    build_request(*sv, r);
+    {
+      std::lock_guard<std::mutex> lk(sv->bmu);
+      sv->built.push_back(r);
+    }
+    sv->bcv.notify_all();
+  }
+}
+
+}  // namespace
 
 void server_create(Server &sv, const phs_server_opts &o, hipStream_t s) {
   PHS_REQUIRE(o.precision == PHS_FP64 || o.precision == PHS_MIXED || o.precision == PHS_NEAR32,
@@ -82,6 +150,9 @@ void server_create(Server &sv, const phs_server_opts &o, hipStream_t s) {
     sv.budget = (int64_t)(fr / 4 * 3);
   }
   sv.t0 = now_s();
+  PHS_HIP(hipGetDevice(&sv.device));
+  PHS_HIP(hipStreamCreateWithFlags(&sv.bs, hipStreamNonBlocking));
+  sv.builder = std::thread(builder_loop, &sv);
 }
 
 int64_t server_submit(Server &sv, const phs_request &r) {
@@ -110,69 +181,35 @@ void fail(Server &sv, Request *r, phs_status st) {
   r->plan = nullptr;
 }
 
-int64_t pool_in_use() {
-  int64_t u = 0;
-  pool_stats(nullptr, nullptr, &u, nullptr);
-  return u;
-}
-
-// plan + preconditioner of a request; returns false (request failed) on
-// error.  The request is then charged the device bytes it really holds (the
-// pool's bytes in use before and after the build; the build's temporaries
-// are recycled by then).
-bool admit(Server &sv, Request *r) {
-  const phs_request &in = r->in;
-  phs_plan_opts po{};
-  po.k = in.k;
-  po.poly_degree = in.poly_degree;
-  po.precision = sv.opts.precision;
-  pool_mark_idle();
-  const int64_t u0 = pool_in_use();
-  try {
-    r->plan = new Plan();
-    create_plan(in.xy, in.n, &po, sv.s, *r->plan);
-    vecchia_build(*r->plan, in.precond, sv.s);
-    pool_mark_idle();
-    r->bytes = std::max<int64_t>(pool_in_use() - u0, 0);
-    r->measured = true;
-  } catch (const Error &e) {
-    set_error(e.code, e.msg);
-    (void)hipStreamSynchronize(sv.s);
-    fail(sv, r, e.code);
-    return false;
-  } catch (const std::bad_alloc &) {
-    fail(sv, r, PHS_ERR_OUT_OF_MEMORY);
-    return false;
-  }
-  r->state = PHS_REQ_ACTIVE;
-  r->t_admit = now_s() - sv.t0;
-  r->job = SolveJob();
-  r->job.f = in.f;
-  r->job.w_out = in.w;
-  r->job.beta_out = in.beta;
-  return true;
-}
 
 }  // namespace
 
 void server_step(Server &sv) {
   hipStream_t s = sv.s;
-  // 1. admission, FIFO, by slot and memory budget
+  // 1. requests whose builds finished join the active set (with nothing
+  // active, wait for one rather than return empty-handed)
   std::vector<Request *> fresh;
-  while (!sv.queue.empty() && (int)sv.active.size() < sv.opts.max_active) {
-    Request *r = sv.queue.front();
-    if (r->bytes > sv.budget) {
-      sv.queue.erase(sv.queue.begin());
-      set_error(PHS_ERR_OUT_OF_MEMORY, "request larger than the server's memory budget");
-      fail(sv, r, PHS_ERR_OUT_OF_MEMORY);
+  std::vector<Request *> got;
+  {
+    std::unique_lock<std::mutex> lk(sv.bmu);
+    if (sv.active.empty() && sv.building > 0 && sv.built.empty())
+      sv.bcv.wait(lk, [&] { return !sv.built.empty(); });
+    got.swap(sv.built);
+  }
+  for (Request *r : got) {
+    --sv.building;
+    sv.reserved -= r->reserve;
+    r->reserve = 0;
+    if (!r->plan) {
+      set_error(r->built_status, "request build failed");
+      fail(sv, r, r->built_status);
       continue;
     }
+    r->bytes = r->built_bytes;
+    r->measured = true;
     // the shared forest grows with each member (descriptors and work tables,
     // well under 1/32 of a request's own memory): keep that much in hand
-    if (sv.in_use + sv.forest_bytes + r->bytes + r->bytes / 32 > sv.budget) break;
-    sv.queue.erase(sv.queue.begin());
-    if (!admit(sv, r)) continue;
-    if (sv.in_use + sv.forest_bytes + r->bytes + r->bytes / 32 > sv.budget) {
+    if (sv.in_use + sv.reserved + sv.forest_bytes + r->bytes + r->bytes / 32 > sv.budget) {
       // its real footprint is larger than the estimate and does not fit now:
       // release it and let it wait at the head of the queue with its
       // measured size
@@ -186,21 +223,55 @@ void server_step(Server &sv) {
         continue;
       }
       sv.queue.insert(sv.queue.begin(), r);
-      break;
+      continue;
     }
+    r->state = PHS_REQ_ACTIVE;
+    r->t_admit = now_s() - sv.t0;
+    r->job = SolveJob();
+    r->job.f = r->in.f;
+    r->job.w_out = r->in.w;
+    r->job.beta_out = r->in.beta;
     sv.in_use += r->bytes;
-    sv.peak = std::max(sv.peak, sv.in_use + sv.forest_bytes);
     sv.active.push_back(r);
     fresh.push_back(r);
     sv.changed = true;
   }
-  // 2. the forest of active systems (its descriptors and work tables are
+  // 2. waiting requests go to the builder, FIFO, by slot and memory budget
+  // (their estimated bytes reserved); at most kBuilding handed over at a time
+  constexpr int kBuilding = 8;
+  while (!sv.queue.empty() && (int)sv.active.size() + sv.building < sv.opts.max_active &&
+         sv.building < kBuilding) {
+    Request *r = sv.queue.front();
+    if (r->bytes > sv.budget) {
+      sv.queue.erase(sv.queue.begin());
+      set_error(PHS_ERR_OUT_OF_MEMORY, "request larger than the server's memory budget");
+      fail(sv, r, PHS_ERR_OUT_OF_MEMORY);
+      continue;
+    }
+    // a build reserves half again its estimate (its temporaries come and go
+    // while it runs beside the steps), or what room is left if nothing else
+    // is active or building
+    const int64_t room = sv.budget - (sv.in_use + sv.reserved + sv.forest_bytes);
+    if (r->bytes + r->bytes / 32 > room) break;
+    if (r->bytes + r->bytes / 2 > room && (!sv.active.empty() || sv.building > 0)) break;
+    sv.queue.erase(sv.queue.begin());
+    r->reserve = std::min(r->bytes + r->bytes / 2, room);
+    sv.reserved += r->reserve;
+    ++sv.building;
+    {
+      std::lock_guard<std::mutex> lk(sv.bmu);
+      sv.to_build.push_back(r);
+    }
+    sv.bcv.notify_all();
+  }
+  sv.peak = std::max(sv.peak, sv.in_use + sv.reserved + sv.forest_bytes);
+  // 3. the forest of active systems (its descriptors and work tables are
   // charged to the server as measured)
   if (sv.changed) {
     delete sv.F;
     sv.F = nullptr;
     pool_mark_idle();
-    const int64_t u0 = pool_in_use();
+    const int64_t u0 = pool_thread_net();
     sv.forest_bytes = 0;
     if (!sv.active.empty()) {
       std::vector<Plan *> pl;
@@ -212,8 +283,8 @@ void server_step(Server &sv) {
       }
       sv.F = new Forest();
       build_forest(*sv.F, pl, wk, s);
-      sv.forest_bytes = std::max<int64_t>(pool_in_use() - u0, 0);
-      sv.peak = std::max(sv.peak, sv.in_use + sv.forest_bytes);
+      sv.forest_bytes = std::max<int64_t>(pool_thread_net() - u0, 0);
+      sv.peak = std::max(sv.peak, sv.in_use + sv.reserved + sv.forest_bytes);
     }
     sv.changed = false;
   }
@@ -224,7 +295,7 @@ void server_step(Server &sv) {
     for (Request *r : fresh) js.push_back(&r->job);
     solve_begin(F, js, sv.P, s);
   }
-  // 3. one lockstep round of every active request
+  // 4. one lockstep round of every active request
   std::vector<SolveJob *> js;
   int64_t n_big = 0;
   for (Request *r : sv.active) {
@@ -234,7 +305,7 @@ void server_step(Server &sv) {
   const double ta = now_s();
   solve_round(F, js, sv.P, s);
   const double t_full = now_s() - ta;
-  // 4. time sharing: a round lasts as long as the largest request's
+  // 5. time sharing: a round lasts as long as the largest request's
   // iteration, so requests at most a quarter of its size get extra rounds of
   // their own, for up to half the time of the full round
   std::vector<SolveJob *> small;
@@ -249,7 +320,7 @@ void server_step(Server &sv) {
                                [](const SolveJob *j) { return j->state == J_DONE; }),
                 small.end());
   }
-  // 5. finished requests: evaluate, release
+  // 6. finished requests: evaluate, release
   std::vector<Request *> keep;
   for (Request *r : sv.active) {
     if (r->job.state != J_DONE) {
