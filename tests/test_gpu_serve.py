@@ -10,7 +10,9 @@ targets to 1e-8 (max-norm relative) and its node residual
 RMS(f - M w - B beta) / RMS(f) is <= 1e-8; the device memory the library holds
 while serving (its pool's bytes in use) grows by no more than the budget;
 requests really overlapped (more than one active at once) and some waited for
-memory."""
+memory.  A request whose plan cannot be built fails with its status on the
+build thread while the others are served, and a server closed with builds
+still running shuts down cleanly."""
 import numpy as np
 import pytest
 
@@ -128,4 +130,44 @@ def test_oversized_request_fails_cleanly():
     inf = srv.poll(rid)
     assert inf.state == N.PHS_REQ_FAILED and inf.status == 6  # PHS_ERR_OUT_OF_MEMORY
     assert srv.memory() == (0, 0)
+    srv.close()
+
+
+def test_failed_build_and_close_during_builds():
+    """A request whose plan cannot be built (two coincident nodes) fails on the
+    build thread with its status while the others are served; a server closed
+    while builds are in flight shuts down cleanly."""
+    print("[case] serving: failing build among good requests", flush=True)
+    reqs = _requests(91, 4)
+    bad_xy = reqs[1][0].copy()
+    bad_xy[7] = bad_xy[3]  # duplicate node
+    srv = N.Server(hbm_budget=1 << 34, max_active=8)
+    ids = []
+    for i, (xy, f, tg, k, m) in enumerate(reqs):
+        ids.append(srv.submit(dev(bad_xy if i == 1 else xy), dev(f), k, targets=dev(tg), m=m,
+                              nu=k / 2.0, seed=1))
+    steps = 0
+    while True:
+        active, queued = srv.step()
+        steps += 1
+        if active == 0 and queued == 0:
+            break
+        assert steps < 20000
+    for i, rid in enumerate(ids):
+        inf = srv.poll(rid)
+        if i == 1:
+            assert inf.state == N.PHS_REQ_FAILED and inf.status == 2  # DUPLICATE_POINTS
+        else:
+            assert inf.state == N.PHS_REQ_DONE and inf.status == 0, (i, inf.state, inf.status)
+            xy, f, tg, k, m = reqs[i]
+            wa, ba, va, _ = _alone(xy, f, tg, k, m, N.PHS_FP64, 1e-8)
+            w, beta, vals = (host(t) for t in srv.result(rid))
+            np.testing.assert_array_equal(vals, va)
+    assert srv.memory()[0] == 0
+    srv.close()
+    # close with builds still running
+    srv = N.Server(hbm_budget=1 << 34, max_active=8)
+    for xy, f, tg, k, m in reqs:
+        srv.submit(dev(xy), dev(f), k, targets=dev(tg), m=m, nu=k / 2.0, seed=1)
+    srv.step()
     srv.close()
