@@ -15,6 +15,7 @@
 //
 // Layout: level l holds (P+1) x nd x 4^l complex coefficients, box index
 // fastest (coalesced across neighbouring boxes), levels 2..L concatenated.
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -630,12 +631,209 @@ __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   st2<T>(dst, cadd(ld2<T>(dst), acc));
 }
 
+// ------------------------------------------------------- symmetric near field
+// The near field of two neighbouring leaves A and B needs phi(|x_i - x_j|) for
+// every i in A and j in B twice: in the sum of each target of A over B's
+// densities, and in the sum of each target of B over A's.  The wavefront of A
+// forms each such phi once for the neighbours that follow A in the grid's
+// row-major order (E, and NW, N, NE in the row above): lane i adds phi t_j to
+// its own sum, and the sum over i of phi t_i, the contribution of A to source
+// j, is reduced across the lanes and stored in one of four partial-sum slots
+// of j, chosen by the direction from j's leaf to A.  Every slot has a single
+// writer, so the results do not depend on the order in which wavefronts run;
+// a combine pass adds the slots to the leaf pass's output.
+
+constexpr int kDppRor8 = 0x128;        // row_ror:8 (lane l ^ 8 within a row)
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror (lane l ^ 7 within 8)
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+
+template <int C>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), C, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), C, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One halving step of a reduce-scatter across lane bit B: lanes whose bit B is
+// clear return lo plus the partner's lo, the others hi plus the partner's hi,
+// the partner differing in bit B (at B = 2 also in bits 1 and 0).  Bits 5 and
+// 4 use the lane-swap instructions, which exchange the upper half of one
+// register's lanes (or odd rows) with the lower half (even rows) of another,
+// so the two registers then hold both addends without selects.
+template <int B>
+__device__ __forceinline__ double lane_halve(double lo, double hi, int lane) {
+  if constexpr (B == 5 || B == 4) {
+    const unsigned lh = (unsigned)__double2hiint(lo), ll = (unsigned)__double2loint(lo);
+    const unsigned hh = (unsigned)__double2hiint(hi), hl = (unsigned)__double2loint(hi);
+    const auto sh = B == 5 ? __builtin_amdgcn_permlane32_swap(lh, hh, false, false)
+                           : __builtin_amdgcn_permlane16_swap(lh, hh, false, false);
+    const auto sl = B == 5 ? __builtin_amdgcn_permlane32_swap(ll, hl, false, false)
+                           : __builtin_amdgcn_permlane16_swap(ll, hl, false, false);
+    return __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
+  } else {
+    constexpr int C = B == 3 ? kDppRor8 : B == 2 ? kDppHalfMirror : B == 1 ? kDppXor2 : kDppXor1;
+    const bool up = (lane >> B) & 1;
+    return (up ? hi : lo) + dpp_f64<C>(up ? lo : hi);
+  }
+}
+
+// one full summing step across lane bit B <= 2 (B = 2: the partner l ^ 7)
+template <int B>
+__device__ __forceinline__ double lane_fold(double v) {
+  constexpr int C = B == 2 ? kDppHalfMirror : B == 1 ? kDppXor2 : kDppXor1;
+  return v + dpp_f64<C>(v);
+}
+
+// Sums of eight per-lane values over each aligned group of 2^LW lanes
+// (LW = 3..6): three halving steps over the group's top lane bits, then full
+// steps over the rest.  Lane l returns the group total of value
+// (l >> (LW - 3)) & 7; the partner masks of the steps are linearly
+// independent, so each total covers every lane of the group once.
+template <int LW>
+__device__ __forceinline__ double lane_sum8(const double (&T)[8], int lane) {
+  double a[4], b[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = lane_halve<LW - 1>(T[k], T[k + 4], lane);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) b[k] = lane_halve<LW - 2>(a[k], a[k + 2], lane);
+  double c = lane_halve<LW - 3>(b[0], b[1], lane);
+  if constexpr (LW >= 6) c = lane_fold<2>(c);
+  if constexpr (LW >= 5) c = lane_fold<1>(c);
+  if constexpr (LW >= 4) c = lane_fold<0>(c);
+  return c;
+}
+
+// Where the symmetric sums of a source range go.  Slot d of a node in leaf B
+// holds the sum from the leaf A that takes the pair (A, B): d = 3 for A the
+// west neighbour of B, d = 0, 1, 2 for A in the row below at column offset
+// d - 1.  Seen from A at column ix, a source j of the row above lies in column
+// ix - 1, ix or ix + 1, i.e. slot 2, 1 or 0: dir(j) = dbase - (j >= bnd1) -
+// (j >= bnd2) with dbase = 2 and bnd1, bnd2 the first nodes of columns ix and
+// ix + 1 there; the E leaf has dbase = 3 and no bounds.
+struct SymDst {
+  double *part;
+  int64_t n;
+  int dbase, bnd1, bnd2;
+  bool accum;  // add to the slots (a later pass over the same target leaf)
+};
+
+// One batch of up to eight sources of a symmetric range for the W = 2^LW
+// lanes of a group: cnt (per group) sources from j.  Adds the target sums to
+// acc and stores the source sums.  FULL (eight sources, wave-uniform): the
+// sixteen coordinates and eight densities are read from one base address at
+// constant offsets (a few wide scalar loads and one wait), then four table
+// reads and their arithmetic at a time; otherwise one source at a time with
+// the index clamped to jmax (the padded last batch and the lane-group form,
+// whose loads are per lane).
+template <int K, int LW, bool FULL, class PXY, class PT, class PTAB>
+__device__ __forceinline__ void sym_batch(double xi, double yi, double ti, PXY xy2, PT t, int j,
+                                          int cnt, int jmax, PTAB tab, int lane,
+                                          const SymDst &o, double &acc) {
+  double T[8];
+  const int k = (lane >> (LW - 3)) & 7;
+  const int jk = j + k;
+  const bool wr = (lane & ((1 << (LW - 3)) - 1)) == 0 && k < cnt;
+  const gptr<double> dst = rw(o.part + (int64_t)(o.dbase - (jk >= o.bnd1) - (jk >= o.bnd2)) * o.n + jk);
+  const double prev = (o.accum && wr) ? *dst : 0.0;
+  if constexpr (FULL) {
+    const auto pxy = xy2 + 2 * j;
+    const auto pt = t + j;
+    double sx[8], sy[8], tj[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      sx[i] = pxy[2 * i];
+      sy[i] = pxy[2 * i + 1];
+      tj[i] = pt[i];
+    }
+#pragma unroll
+    for (int h = 0; h < 8; h += 4) {
+      double r2[4], ic[4], lc[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double dx = xi - sx[h + i], dy = yi - sy[h + i];
+        r2[i] = fma(dy, dy, dx * dx);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
+        const double2 e = *reinterpret_cast<const double2 *>(
+            reinterpret_cast<const char *>(tab) + near_log_offset(hi));
+        ic[i] = e.x;
+        lc[i] = e.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double ph = r2[i] * near_log_core(r2[i], ic[i], lc[i]);
+        if constexpr (K == 4) ph *= r2[i];
+        acc = fma(ph, tj[h + i], acc);
+        T[h + i] = ph * ti;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int jj = j + i < jmax ? j + i : jmax;
+      const double dx = xi - xy2[2 * jj], dy = yi - xy2[2 * jj + 1];
+      const double r2 = fma(dy, dy, dx * dx);
+      const double tj = i < cnt ? t[jj] : 0.0;
+      double ph = r2 * near_log(r2, tab);
+      if constexpr (K == 4) ph *= r2;
+      acc = fma(ph, tj, acc);
+      T[i] = ph * ti;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  const double v = lane_sum8<LW>(T, lane);
+  if (wr) *dst = prev + v;
+}
+
+// Symmetric range [js, je) for all 64 lanes (one target per lane): full
+// batches read their eight sources from one base address (uniform, so scalar
+// loads), the last batch is padded.
+template <int K, class PXY, class PT, class PTAB>
+__device__ __forceinline__ double near_sym64(double xi, double yi, double ti, PXY xy2, PT t,
+                                             int js, int je, PTAB tab, int lane,
+                                             const SymDst &o) {
+  double acc = 0.0;
+  int j = js;
+  for (; j + 8 <= je; j += 8)
+    sym_batch<K, 6, true>(xi, yi, ti, xy2, t, j, 8, j + 7, tab, lane, o, acc);
+  if (j < je) sym_batch<K, 6, false>(xi, yi, ti, xy2, t, j, je - j, je - 1, tab, lane, o, acc);
+  return acc;
+}
+
+// Symmetric range [js, je) for 64/W groups of W = 2^LW lanes on the same
+// targets: group g takes the sub-range [js + len g / ng, js + len (g+1) / ng)
+// in batches of eight (the batch count is that of the longest sub-range, so
+// every group runs the same steps; a group past its end has no valid source).
+template <int K, int LW, class PXY, class PT, class PTAB>
+__device__ __forceinline__ double near_sym_split(double xi, double yi, double ti, PXY xy2, PT t,
+                                                 int js, int je, PTAB tab, int lane,
+                                                 const SymDst &o) {
+  constexpr int ng = 64 >> LW;
+  const int g = lane >> LW, len = je - js;
+  const int gs = js + len * g / ng, ge = js + len * (g + 1) / ng;
+  const int nb = ((len + ng - 1) / ng + 7) / 8;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const int j = gs + 8 * b;
+    const int cnt = ge - j;
+    sym_batch<K, LW, false>(xi, yi, ti, xy2, t, j, cnt < 0 ? 0 : (cnt > 8 ? 8 : cnt), je - 1, tab,
+                            lane, o, acc);
+  }
+  return acc;
+}
+
 // ------------------------------------------------------------------ leaf
 // One wavefront per leaf: each lane one target node.  Far field by Horner on
 // the leaf's incoming expansions (L2P) combined with U_r; near field by
 // direct phi over the 3x3 neighbouring leaves (step 2: direct evaluation).
+// k = 4 (one more multiply a pair) is held to 96 VGPRs, five wavefronts per
+// SIMD: measured 0.678 against 0.697 ms at n = 2^20 with a few spilled set-up
+// values; k = 2 fits four wavefronts without a cap and was not faster at five.
 template <class T, class TN, int K>
-__global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sys,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 4 ? 5 : 1))) void kf_leaf_eval(const SysDev *__restrict__ sys,
                                                    const BlkRef *__restrict__ tab,
                                                    const int32_t *__restrict__ mask, int P,
                                                    int in, int out,
@@ -671,7 +869,34 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
   const double cx = -h + (ix + 0.5) * w, cy = -h + (iy + 0.5) * w;
   const int r0 = iy > 0 ? iy - 1 : 0, r1 = iy + 1 < G ? iy + 1 : G - 1;
   const int c0 = ix > 0 ? ix - 1 : 0, c1 = ix + 1 < G ? ix + 1 : G - 1;
+  // FP64 near field: the own leaf directly, the E neighbour and the row above
+  // symmetrically (the W neighbour and the row below deliver their pairs
+  // through this leaf's partial-sum slots; a slot whose writer leaf is absent
+  // or empty is cleared here)
+  constexpr bool kSym = std::is_same<TN, double>::value;
+  int eE = e, us = 0, ue = 0, ub1 = 0, ub2 = 0, zmask = 0;
+  if constexpr (kSym) {
+    if (ix + 1 < G) eE = start[leaf + 2];
+    if (iy + 1 < G) {
+      const int rb = (iy + 1) * G;
+      us = start[rb + c0];
+      ue = start[rb + c1 + 1];
+      ub1 = start[rb + ix];
+      ub2 = start[rb + ix + 1];
+    }
+    if (!(ix > 0 && start[leaf - 1] < b)) zmask |= 8;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+      const int col = ix + dd - 1;
+      const bool has = iy > 0 && col >= 0 && col < G &&
+                       start[(iy - 1) * G + col] < start[(iy - 1) * G + col + 1];
+      if (!has) zmask |= 1 << dd;
+    }
+  }
   for (int i0 = b; i0 < e; i0 += 64) {
+    // a later pass over this leaf adds to the source sums the first one stored
+    // (possibly from other lanes): the barrier orders those accesses
+    if (kSym && i0 > b) __syncthreads();
     // A pass with at most 32 targets left (the tail of a leaf of more than 64
     // nodes, or a small leaf) runs G = 64/W groups of W lanes on the same W
     // targets, each group over 1/G of every source range, and sums the groups'
@@ -705,19 +930,33 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
     }
     // near field
     TN nearv = TN(0);
-    if constexpr (std::is_same<TN, double>::value) {
+    if constexpr (kSym) {
+      // the lane index, opaque to the compiler: the lane-group forms' per-lane
+      // set-up (group sub-ranges of each range, for each group width) is then
+      // computed where it is used instead of being hoisted out of the pass
+      // loop and held in registers through the whole kernel
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      const double ti = act ? t[i] : 0.0;
+      const SymDst oE{d.npart, d.n, 3, INT_MAX, INT_MAX, i0 > b};
+      const SymDst oU{d.npart, d.n, 2, ub1, ub2, i0 > b};
       if (W == 64) {
-        for (int row = r0; row <= r1; ++row) {
-          const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-          nearv += near_range8<K>(xi, yi, xy2, t, js, je, ltab);
-        }
+        nearv = near_range8<K>(xi, yi, xy2, t, b, e, ltab);
+        if (eE > e) nearv += near_sym64<K>(xi, yi, ti, xy2, t, e, eE, ltab, ln, oE);
+        if (ue > us) nearv += near_sym64<K>(xi, yi, ti, xy2, t, us, ue, ltab, ln, oU);
       } else {
         const int ng = 64 / W;
-        for (int row = r0; row <= r1; ++row) {
-          const int js = start[row * G + c0], je = start[row * G + c1 + 1];
-          const int len = je - js;
-          nearv += near_range<K>(xi, yi, xy2, t, js + len * gi / ng, js + len * (gi + 1) / ng,
-                                 ltab);
+        const int len = e - b;
+        nearv = near_range<K>(xi, yi, xy2, t, b + len * gi / ng, b + len * (gi + 1) / ng, ltab);
+        if (W == 32) {
+          if (eE > e) nearv += near_sym_split<K, 5>(xi, yi, ti, xy2, t, e, eE, ltab, ln, oE);
+          if (ue > us) nearv += near_sym_split<K, 5>(xi, yi, ti, xy2, t, us, ue, ltab, ln, oU);
+        } else if (W == 16) {
+          if (eE > e) nearv += near_sym_split<K, 4>(xi, yi, ti, xy2, t, e, eE, ltab, ln, oE);
+          if (ue > us) nearv += near_sym_split<K, 4>(xi, yi, ti, xy2, t, us, ue, ltab, ln, oU);
+        } else {
+          if (eE > e) nearv += near_sym_split<K, 3>(xi, yi, ti, xy2, t, e, eE, ltab, ln, oE);
+          if (ue > us) nearv += near_sym_split<K, 3>(xi, yi, ti, xy2, t, us, ue, ltab, ln, oU);
         }
         for (int o = W; o < 64; o <<= 1) nearv += __shfl_xor(nearv, o);
       }
@@ -748,7 +987,14 @@ __global__ __launch_bounds__(64) void kf_leaf_eval(const SysDev *__restrict__ sy
       for (int o = W; o < 64; o <<= 1) nearv += __shfl_xor(nearv, o);
       nearv *= phi_scale_f<K>();
     }
-    if (act && gi == 0) ytree[i] = (double)far + (double)nearv;
+    if (act && gi == 0) {
+      ytree[i] = (double)far + (double)nearv;
+      if constexpr (kSym) {
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd)
+          if ((zmask >> dd) & 1) d.npart[(int64_t)dd * d.n + i] = 0.0;
+      }
+    }
   }
 }
 
@@ -1017,6 +1263,7 @@ void leaf_pass(Forest &F, const int32_t *mask, int in, int out, int P, const dou
     PHS_LAUNCH(name, s,
                kf_leaf_eval<T, TN, 4><<<(unsigned)t4.count, 64, 0, s>>>(F.dsys, t4.d, mask, P,
                                                                       in, out, logtab));
+  if (std::is_same<TN, double>::value && t2.count + t4.count > 0) f_near_combine(F, mask, out, s);
 }
 
 const Plan &log_ref(const Forest &F) {

@@ -52,6 +52,21 @@ __global__ void kf_near_t32(const SysDev *__restrict__ sys, const BlkRef *__rest
   if (i < d.n) d.t32[i] = (float)d.v[slot][i];
 }
 
+// Adds the partial-sum slots of the symmetric FP64 near field of the log-kernel
+// leaf pass (times the 1/2 of phi = (1/2) r^k log r^2) to its output.
+__global__ void kf_near_combine(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
+                                const int32_t *__restrict__ mask, int out) {
+  const BlkRef br = tab[blockIdx.x];
+  if (!mask[br.sys]) return;
+  const SysDev &d = sys[br.sys];
+  if (!d.npart) return;  // not a log-kernel FMM system
+  const int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  if (i >= d.n) return;
+  const cptr<double> p = ro((const double *)d.npart);
+  const double s = (p[i] + p[d.n + i]) + (p[2 * d.n + i] + p[3 * d.n + i]);
+  d.v[out][i] += 0.5 * s;
+}
+
 __global__ void kf_copy(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
                         const int32_t *__restrict__ mask, int dst, int src) {
   const BlkRef br = tab[blockIdx.x];
@@ -122,7 +137,33 @@ __global__ void kf_dot(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   double acc[ND];
 #pragma unroll
   for (int t = 0; t < ND; ++t) acc[t] = 0.0;
-  for (int64_t i = (int64_t)br.blk * kBlock + threadIdx.x; i < d.n; i += (int64_t)nb * kBlock) {
+  // four strided elements per step, loaded before they are summed (each
+  // partial still adds its elements in index order)
+  const int64_t st = (int64_t)nb * kBlock;
+  int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  for (; i + 3 * st < d.n; i += 4 * st) {
+    double bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) bv[u] = vb[i + u * st];
+    if (mode == 0) {
+      double av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = va[i + u * st];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[0] += av[u] * bv[u];
+    } else {
+#pragma unroll
+      for (int t = 0; t < ND; ++t)
+        if (t < nd) {
+          double qv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) qv[u] = Q[(int64_t)t * d.n + i + u * st];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[t] += qv[u] * bv[u];
+        }
+    }
+  }
+  for (; i < d.n; i += st) {
     const double bi = vb[i];
     if (mode == 0) {
       acc[0] += va[i] * bi;
@@ -169,7 +210,26 @@ __global__ void kf_pcg_wr(const SysDev *__restrict__ sys, const BlkRef *__restri
   const gptr<double> w = rw(d.v[V_DW]), r = rw(d.v[V_R]);
   const cptr<double> p = ro(d.v[V_P]), q = ro(d.v[V_Q]);
   double acc = 0.0;
-  for (int64_t i = (int64_t)br.blk * kBlock + threadIdx.x; i < d.n; i += (int64_t)nb * kBlock) {
+  const int64_t st = (int64_t)nb * kBlock;
+  int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  for (; i + 3 * st < d.n; i += 4 * st) {  // four elements' loads in flight together
+    double pv[4], qv[4], rv[4], wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pv[u] = p[i + u * st];
+      qv[u] = q[i + u * st];
+      rv[u] = r[i + u * st];
+      wv[u] = w[i + u * st];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      w[i + u * st] = wv[u] + alpha * pv[u];
+      const double ri = rv[u] - alpha * qv[u];
+      r[i + u * st] = ri;
+      acc += ri * ri;
+    }
+  }
+  for (; i < d.n; i += st) {
     w[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
@@ -208,7 +268,31 @@ __global__ void kf_sub_Qc_dot(const SysDev *__restrict__ sys, const BlkRef *__re
   const gptr<double> v = rw(d.v[slot]);
   const double g = use_sign ? (double)d.sign : 1.0;
   double acc = 0.0;
-  for (int64_t i = (int64_t)br.blk * kBlock + threadIdx.x; i < d.n; i += (int64_t)nb * kBlock) {
+  const int64_t st = (int64_t)nb * kBlock;
+  int64_t i = (int64_t)br.blk * kBlock + threadIdx.x;
+  for (; i + 3 * st < d.n; i += 4 * st) {  // four elements' loads in flight together
+    double sq[4] = {0.0, 0.0, 0.0, 0.0}, vv[4], wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vv[u] = v[i + u * st];
+      wv[u] = ww[i + u * st];
+    }
+    for (int j = 0; j < d.S; ++j) {
+      double qv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) qv[u] = Q[(int64_t)j * d.n + i + u * st];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sq[u] += qv[u] * cq[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double vi = vv[u] - sq[u];
+      if (use_sign) vi = g * vi;
+      v[i + u * st] = vi;
+      acc += wv[u] * vi;
+    }
+  }
+  for (; i < d.n; i += st) {
     double sq = 0.0;
     for (int j = 0; j < d.S; ++j) sq += Q[(int64_t)j * d.n + i] * cq[j];
     double vi = v[i] - sq;
@@ -433,6 +517,8 @@ void SysWork::release() {
   dfree(dpart);
   dfree(t32);
   t32 = nullptr;
+  dfree(npart);
+  npart = nullptr;
   mp = loc = nullptr;
   for (auto &p : v) p = nullptr;
   red = sc = nullptr;
@@ -452,6 +538,7 @@ void alloc_syswork(SysWork &w, const Plan &pl) {
       if (w.dpart_cap > 0) w.dpart = dmalloc<double>(w.dpart_cap);
     } else {
       w.t32 = dmalloc<float>(std::max<int64_t>(pl.n, 1));
+      if (pl.core_log) w.npart = dmalloc<double>(4 * std::max<int64_t>(pl.n, 1));
     }
   } catch (...) {
     w.release();
@@ -482,6 +569,7 @@ SysDev make_sysdev(const Plan &pl, const SysWork &w) {
   d.red = w.red;
   d.sc = w.sc;
   d.t32 = w.t32;
+  d.npart = w.npart;
   d.n = pl.n;
   d.h = pl.tree.h;
   d.S = pl.S;
@@ -786,6 +874,11 @@ void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t 
   PHS_LAUNCH("scatter", s,
              k_scatter_one<<<(unsigned)((d.n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
                  d.v[slot], d.order, d.n, dst_user));
+}
+
+void f_near_combine(Forest &F, const int32_t *mask, int out, hipStream_t s) {
+  PHS_LAUNCH("near_combine", s,
+             kf_near_combine<<<F_GRID(F.vec), kBlock, 0, s>>>(F.dsys, F.vec.d, mask, out));
 }
 
 void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hipStream_t s) {

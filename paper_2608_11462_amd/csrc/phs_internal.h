@@ -239,6 +239,7 @@ struct SysDev {
   double *red;
   double *sc;
   float *t32;
+  double *npart;
   int64_t n;
   double h;
   int32_t S, L, k, R, sign, nbdot, m, has_pc;
@@ -256,6 +257,9 @@ struct SysWork {  // device workspace of one system
   double *dpart = nullptr;  // chunk partial sums of the direct matvec (direct plans)
   int64_t dpart_cap = 0;    // doubles
   float *t32 = nullptr;     // FP32 copy of the densities of an FP32 near field (FMM plans)
+  // near-field sums of a node received from the four leaves that take its
+  // leaf's pairs symmetrically (log-kernel FMM plans): 4 n doubles
+  double *npart = nullptr;
   void release();
 };
 
@@ -433,6 +437,8 @@ void f_gather_user(Forest &F, int sys, const double *src_user, int slot, hipStre
 void f_scatter_user(Forest &F, int sys, int slot, double *dst_user, hipStream_t s);
 // y[out] = M v[in] for every masked system, in tree order
 void f_matvec(Forest &F, const int32_t *mask, int in, int out, int precision, hipStream_t s);
+// adds the symmetric near-field partial sums of the log-kernel systems to v[out]
+void f_near_combine(Forest &F, const int32_t *mask, int out, hipStream_t s);
 
 // one right-hand side of one system: inputs in caller order, results, and
 // the state of its solve between rounds

@@ -30,7 +30,8 @@ double now_s() {
 // (leaf size 40/64, FP64 log orders 27 and 31, Chebyshev 16 and FP32 8), used
 // to decide whether a waiting request may be admitted; once built, the
 // request is charged what it really holds.  Counted:
-// node arrays, polynomial block, FMM workspace of one system and its tables,
+// node arrays, polynomial block, FMM workspace of one system and its tables
+// (with the four near-field partial sums per node of a log-kernel plan),
 // ten Krylov vectors, the Vecchia factor and its transpose, and the peak of
 // the temporaries of the preconditioner build.
 int64_t request_bytes(int64_t n, int k, int m) {
@@ -51,7 +52,7 @@ int64_t request_bytes(int64_t n, int k, int m) {
     exp = 256LL * R * boxes / 3 * 8;
     tables = 40LL * (256 * 256 * 8 + 64 * 64 * 4) + (4 << 20);
   }
-  const int64_t nodes = n * (52 + 8LL * S + 10 * 8 + 4);
+  const int64_t nodes = n * (52 + 8LL * S + 10 * 8 + 4 + (log_k ? 32 : 0));
   const int64_t vecchia = n * (16 + 24LL * mm);
   const int64_t transient = n * (100 + 16LL * mm);
   return 2 * exp + tables + nodes + vecchia + transient + (int64_t)(1 << 22);
