@@ -720,12 +720,12 @@ struct SymDst {
 
 // One batch of up to eight sources of a symmetric range for the W = 2^LW
 // lanes of a group: cnt (per group) sources from j.  Adds the target sums to
-// acc and stores the source sums.  FULL (eight sources, wave-uniform): the
-// sixteen coordinates and eight densities are read from one base address at
-// constant offsets (a few wide scalar loads and one wait), then four table
-// reads and their arithmetic at a time; otherwise one source at a time with
-// the index clamped to jmax (the padded last batch and the lane-group form,
-// whose loads are per lane).
+// acc and stores the source sums.  Two halves of four sources: their loads,
+// then their table reads, then their arithmetic.  FULL (eight sources,
+// wave-uniform): the coordinates and densities are read from one base address
+// at constant offsets (wide scalar loads, one wait); otherwise each index is
+// clamped to jmax and a padding source gets density 0 (the padded last batch
+// and the lane-group form, whose loads are per lane).
 template <int K, int LW, bool FULL, class PXY, class PT, class PTAB>
 __device__ __forceinline__ void sym_batch(double xi, double yi, double ti, PXY xy2, PT t, int j,
                                           int cnt, int jmax, PTAB tab, int lane,
@@ -734,55 +734,49 @@ __device__ __forceinline__ void sym_batch(double xi, double yi, double ti, PXY x
   const int k = (lane >> (LW - 3)) & 7;
   const int jk = j + k;
   const bool wr = (lane & ((1 << (LW - 3)) - 1)) == 0 && k < cnt;
-  const gptr<double> dst = rw(o.part + (int64_t)(o.dbase - (jk >= o.bnd1) - (jk >= o.bnd2)) * o.n + jk);
+  const gptr<double> dst =
+      rw(o.part + (int64_t)(o.dbase - (jk >= o.bnd1) - (jk >= o.bnd2)) * o.n + jk);
   const double prev = (o.accum && wr) ? *dst : 0.0;
-  if constexpr (FULL) {
-    const auto pxy = xy2 + 2 * j;
-    const auto pt = t + j;
-    double sx[8], sy[8], tj[8];
+  const auto pxy = xy2 + 2 * j;
+  const auto pt = t + j;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      sx[i] = pxy[2 * i];
-      sy[i] = pxy[2 * i + 1];
-      tj[i] = pt[i];
-    }
+  for (int h = 0; h < 8; h += 4) {
+    double sx[4], sy[4], tj[4], r2[4], ic[4], lc[4];
 #pragma unroll
-    for (int h = 0; h < 8; h += 4) {
-      double r2[4], ic[4], lc[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double dx = xi - sx[h + i], dy = yi - sy[h + i];
-        r2[i] = fma(dy, dy, dx * dx);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
-        const double2 e = *reinterpret_cast<const double2 *>(
-            reinterpret_cast<const char *>(tab) + near_log_offset(hi));
-        ic[i] = e.x;
-        lc[i] = e.y;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        double ph = r2[i] * near_log_core(r2[i], ic[i], lc[i]);
-        if constexpr (K == 4) ph *= r2[i];
-        acc = fma(ph, tj[h + i], acc);
-        T[h + i] = ph * ti;
+    for (int i = 0; i < 4; ++i) {
+      if constexpr (FULL) {
+        sx[i] = pxy[2 * (h + i)];
+        sy[i] = pxy[2 * (h + i) + 1];
+        tj[i] = pt[h + i];
+      } else {
+        const int jj = j + h + i < jmax ? j + h + i : jmax;
+        sx[i] = xy2[2 * jj];
+        sy[i] = xy2[2 * jj + 1];
+        const double tv = t[jj];
+        tj[i] = h + i < cnt ? tv : 0.0;
       }
     }
-  } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int jj = j + i < jmax ? j + i : jmax;
-      const double dx = xi - xy2[2 * jj], dy = yi - xy2[2 * jj + 1];
-      const double r2 = fma(dy, dy, dx * dx);
-      const double tj = i < cnt ? t[jj] : 0.0;
-      double ph = r2 * near_log(r2, tab);
-      if constexpr (K == 4) ph *= r2;
-      acc = fma(ph, tj, acc);
-      T[i] = ph * ti;
-      __builtin_amdgcn_sched_barrier(0);
+    for (int i = 0; i < 4; ++i) {
+      const double dx = xi - sx[i], dy = yi - sy[i];
+      r2[i] = fma(dy, dy, dx * dx);
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
+      const double2 e = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(tab) +
+                                                           near_log_offset(hi));
+      ic[i] = e.x;
+      lc[i] = e.y;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double ph = r2[i] * near_log_core(r2[i], ic[i], lc[i]);
+      if constexpr (K == 4) ph *= r2[i];
+      acc = fma(ph, tj[i], acc);
+      T[h + i] = ph * ti;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the halves apart (registers)
   }
   const double v = lane_sum8<LW>(T, lane);
   if (wr) *dst = prev + v;
@@ -829,11 +823,12 @@ __device__ __forceinline__ double near_sym_split(double xi, double yi, double ti
 // One wavefront per leaf: each lane one target node.  Far field by Horner on
 // the leaf's incoming expansions (L2P) combined with U_r; near field by
 // direct phi over the 3x3 neighbouring leaves (step 2: direct evaluation).
-// k = 4 (one more multiply a pair) is held to 96 VGPRs, five wavefronts per
-// SIMD: measured 0.678 against 0.697 ms at n = 2^20 with a few spilled set-up
-// values; k = 2 fits four wavefronts without a cap and was not faster at five.
+// Held to 96 VGPRs, five wavefronts per SIMD (the FP64 form otherwise takes
+// 121 at k = 2: four): at n = 2^20 the FP64 leaf pass took 0.441 against
+// 0.454 ms at k = 2 and 0.683 against 0.685 ms at k = 4, with a few lane-group
+// set-up values spilled.
 template <class T, class TN, int K>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 4 ? 5 : 1))) void kf_leaf_eval(const SysDev *__restrict__ sys,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void kf_leaf_eval(const SysDev *__restrict__ sys,
                                                    const BlkRef *__restrict__ tab,
                                                    const int32_t *__restrict__ mask, int P,
                                                    int in, int out,
