@@ -160,10 +160,11 @@ def test_batch_mixed_chebyshev_orders():
     batch.close()
 
 
-@pytest.mark.skip(reason="cause known, not a defect: in the 256-problem batched workload, 11-12 "
+@pytest.mark.skip(reason="cause known, not a defect: in the 256-problem batched workload, 10-12 "
                   "order-4 problems with 9.7e4..1.9e5 nodes stop above 1e-8 (alone and "
-                  "batched alike, 1.1e-8 .. 1.0; whether the two that end within 1.3x of 1e-8 "
-                  "make it depends on the summation order of the preconditioner). Their saddle "
+                  "batched alike, 1.1e-8 .. 1.0; whether those that end near 1e-8 make it "
+                  "depends on the summation order of the preconditioner and the near field). "
+                  "Their saddle "
                   "systems are too ill-conditioned for FP64: with the exact all-pairs matvec PCG "
                   "loses definiteness even sooner than with the FMM (residual 1.0 after 2-9 "
                   "iterations), and retuning the preconditioner (phs_tune_precond) brings one "
