@@ -291,6 +291,16 @@ __device__ __forceinline__ double near_log_core(double x, double invc, double lo
   for (int k = deg - 1; k >= 1; --k) p = fma(p, r, (k % 2 ? 1.0 : -1.0) / k);
   return fma((double)e, 0.69314718055994530942, fma(p, r, logc));
 }
+// near_log_core after its first step, r = frexp_mant(x) * invc - 1, was
+// taken by the caller (the same operations in the same order)
+__device__ __forceinline__ double near_log_rest(double x, double r, double logc) {
+  const int e = __builtin_amdgcn_frexp_exp(x);
+  constexpr int deg = kNearLogBits >= 9 ? 4 : kNearLogBits >= 8 ? 5 : kNearLogBits >= 6 ? 7 : 10;
+  double p = (deg % 2 ? 1.0 : -1.0) / deg;
+#pragma unroll
+  for (int k = deg - 1; k >= 1; --k) p = fma(p, r, (k % 2 ? 1.0 : -1.0) / k);
+  return fma((double)e, 0.69314718055994530942, fma(p, r, logc));
+}
 // byte offset of the table entry of a value whose high word is hi
 __device__ __forceinline__ uint32_t near_log_offset(uint32_t hi) {
   return (hi >> (16 - kNearLogBits)) & ((((uint32_t)1 << kNearLogBits) - 1) << 4);
@@ -331,43 +341,69 @@ __device__ __forceinline__ double near_range(double xi, double yi, PXY xy2, PT t
   return acc;
 }
 
-// near_range in batches of eight sources: the eight source loads (merged
-// into wide scalar loads from one base address), then the eight table
-// reads, then the arithmetic, so a wavefront waits on its loads about twice
-// per eight pairs instead of once per pair (scalar and LDS loads share one
-// completion counter).  Even k only; the sums are bitwise those of
-// near_range (same operations in the same order).
+// near_range in batches of eight sources, pipelined: the eight sources'
+// coordinates and densities are wave-uniform (wide scalar loads from one base
+// address); the next batch's are requested once this batch's eight table
+// reads have been waited for, so they are in flight during its logarithms.
+// (Scalar and LDS loads share one completion counter and scalar loads return
+// out of order: a scalar load issued before a table read would be waited for
+// with it.)  Even k only; the sums are bitwise those of near_range (same
+// operations in the same order).
 template <int K, class PXY, class PT, class PTAB>
 __device__ __forceinline__ double near_range8(double xi, double yi, PXY xy2, PT t, int js, int je,
                                               PTAB tab) {
   static_assert(K % 2 == 0, "even k");
   double acc = 0.0;
+  const int nfull = (je - js) >> 3;
   int j = js;
-  for (; j + 8 <= je; j += 8) {
-    double r2[8], tj[8], ic[8], lc[8];
-    // one base address per batch, constant offsets: wide merged loads
-    const auto pxy = xy2 + 2 * j;
-    const auto pt = t + j;
+  if (nfull > 0) {
+    double sx[8], sy[8], tj[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const double dx = xi - pxy[2 * i], dy = yi - pxy[2 * i + 1];
-      r2[i] = fma(dy, dy, dx * dx);
-      tj[i] = pt[i];
+      sx[i] = xy2[2 * (j + i)];
+      sy[i] = xy2[2 * (j + i) + 1];
+      tj[i] = t[j + i];
     }
+    for (int bi = 0; bi < nfull; ++bi, j += 8) {
+      double r2[8], ic[8], lc[8], rr[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
-      // entry j (the top fraction bits) starts at byte 16 j: one shift, one mask
-      const double2 e = *reinterpret_cast<const double2 *>(
-          reinterpret_cast<const char *>(tab) + near_log_offset(hi));
-      ic[i] = e.x;
-      lc[i] = e.y;
-    }
+      for (int i = 0; i < 8; ++i) {
+        const double dx = xi - sx[i], dy = yi - sy[i];
+        r2[i] = fma(dy, dy, dx * dx);
+      }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      double ph = r2[i] * near_log_core(r2[i], ic[i], lc[i]);
-      if constexpr (K == 4) ph *= r2[i];
-      acc = fma(ph, tj[i], acc);
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
+        // entry j (the top fraction bits) starts at byte 16 j: one shift, one mask
+        const double2 e = *reinterpret_cast<const double2 *>(
+            reinterpret_cast<const char *>(tab) + near_log_offset(hi));
+        ic[i] = e.x;
+        lc[i] = e.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) rr[i] = fma(__builtin_amdgcn_frexp_mant(r2[i]), ic[i], -1.0);
+      __builtin_amdgcn_sched_barrier(0);
+      double nsx[8], nsy[8], ntj[8];
+      const int jn = bi + 1 < nfull ? j + 8 : j;  // the last batch reloads its own
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        nsx[i] = xy2[2 * (jn + i)];
+        nsy[i] = xy2[2 * (jn + i) + 1];
+        ntj[i] = t[jn + i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        double ph = r2[i] * near_log_rest(r2[i], rr[i], lc[i]);
+        if constexpr (K == 4) ph *= r2[i];
+        acc = fma(ph, tj[i], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        sx[i] = nsx[i];
+        sy[i] = nsy[i];
+        tj[i] = ntj[i];
+      }
     }
   }
   for (; j < je; ++j) {

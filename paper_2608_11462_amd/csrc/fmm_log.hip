@@ -650,8 +650,9 @@ constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
 
 template <int C>
 __device__ __forceinline__ double dpp_f64(double v) {
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), C, 0xf, 0xf, false);
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), C, 0xf, 0xf, false);
+  // every lane's source lane is valid for these controls, so no old value
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), C, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), C, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -782,17 +783,95 @@ __device__ __forceinline__ void sym_batch(double xi, double yi, double ti, PXY x
   if (wr) *dst = prev + v;
 }
 
-// Symmetric range [js, je) for all 64 lanes (one target per lane): full
-// batches read their eight sources from one base address (uniform, so scalar
-// loads), the last batch is padded.
+// Symmetric range [js, je) for all 64 lanes (one target per lane).  Full
+// batches of eight sources run as a pipeline: the next batch's coordinates
+// and densities (wave-uniform, wide scalar loads from one base address) are
+// requested once the current batch's last table reads have been waited for,
+// so the scalar loads are in flight during that batch's remaining logarithms,
+// its cross-lane reduction and its store.  (Scalar loads return out of order
+// and share their completion counter with the LDS reads, so a scalar load
+// issued before a table read would be waited for with it.)  After a batch's
+// reduction the eight lanes holding source k's sum all hold it; lane
+// 8k + m keeps the sum of batch m of each group of eight batches, and a group
+// is stored at once: 64 consecutive sources, one store per lane.  The last
+// batch is padded.
 template <int K, class PXY, class PT, class PTAB>
 __device__ __forceinline__ double near_sym64(double xi, double yi, double ti, PXY xy2, PT t,
                                              int js, int je, PTAB tab, int lane,
                                              const SymDst &o) {
   double acc = 0.0;
+  const int nfull = (je - js) >> 3;
   int j = js;
-  for (; j + 8 <= je; j += 8)
-    sym_batch<K, 6, true>(xi, yi, ti, xy2, t, j, 8, j + 7, tab, lane, o, acc);
+  if (nfull > 0) {
+    double sx[8], sy[8], tj[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      sx[i] = xy2[2 * (j + i)];
+      sy[i] = xy2[2 * (j + i) + 1];
+      tj[i] = t[j + i];
+    }
+    const int k = lane >> 3, m = lane & 7;
+    double held = 0.0;
+    for (int bi = 0; bi < nfull; ++bi, j += 8) {
+      double T[8], r2[8], ic[8], lc[8];
+#pragma unroll
+      for (int h = 0; h < 8; h += 4) {
+#pragma unroll
+        for (int i = h; i < h + 4; ++i) {
+          const double dx = xi - sx[i], dy = yi - sy[i];
+          r2[i] = fma(dy, dy, dx * dx);
+        }
+#pragma unroll
+        for (int i = h; i < h + 4; ++i) {
+          const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
+          const double2 e = *reinterpret_cast<const double2 *>(
+              reinterpret_cast<const char *>(tab) + near_log_offset(hi));
+          ic[i] = e.x;
+          lc[i] = e.y;
+        }
+      }
+      // the logarithms' first step consumes every table entry: all LDS reads
+      // of this batch have completed past this point
+      double rr[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) rr[i] = fma(__builtin_amdgcn_frexp_mant(r2[i]), ic[i], -1.0);
+      __builtin_amdgcn_sched_barrier(0);
+      double ntj[8], nsx[8], nsy[8];
+      const int jn = bi + 1 < nfull ? j + 8 : j;  // the last batch reloads its own
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        nsx[i] = xy2[2 * (jn + i)];
+        nsy[i] = xy2[2 * (jn + i) + 1];
+        ntj[i] = t[jn + i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        double ph = r2[i] * near_log_rest(r2[i], rr[i], lc[i]);
+        if constexpr (K == 4) ph *= r2[i];
+        acc = fma(ph, tj[i], acc);
+        T[i] = ph * ti;
+      }
+      const double v = lane_sum8<6>(T, lane);
+      const int bm = bi & 7;
+      held = m == bm ? v : held;
+      if (bm == 7 || bi + 1 == nfull) {
+        // batches j - 8 bm .. j of this group: lane (k, m) stores batch m's source k
+        const int jk = j - 8 * bm + 8 * m + k;
+        if (m <= bm) {
+          const gptr<double> dst =
+              rw(o.part + (int64_t)(o.dbase - (jk >= o.bnd1) - (jk >= o.bnd2)) * o.n + jk);
+          *dst = (o.accum ? *dst : 0.0) + held;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        sx[i] = nsx[i];
+        sy[i] = nsy[i];
+        tj[i] = ntj[i];
+      }
+    }
+  }
   if (j < je) sym_batch<K, 6, false>(xi, yi, ti, xy2, t, j, je - j, je - 1, tab, lane, o, acc);
   return acc;
 }
