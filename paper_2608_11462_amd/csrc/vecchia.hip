@@ -354,13 +354,15 @@ __device__ double matern_fast(int nu2, double x, const double *__restrict__ logt
 // The same from x2 = x^2, the form the factor kernel needs: for the K_1 and
 // K_2 forms on x <= 2 no square root is taken (q = x^2/4 and
 // log(x/2) = log(q)/2), and the series stops once q^k/(k!)^2 < 1e-17.
-// out of line: the factor kernel reaches it only for odd orders and for
-// x > 2, and inlined it would raise the register count of the whole kernel
-__device__ __forceinline__ double matern_far(int nu2, double x2, const double *__restrict__ logtab) {
+// The odd orders and x > 2 go through an out-of-line call (the Bessel and
+// exponential paths would raise the register count of the whole factor
+// kernel); the even-order series path is inlined into the caller.
+__device__ __noinline__ double matern_far(int nu2, double x2, const double *__restrict__ logtab) {
   return matern_fast(nu2, sqrt(x2), logtab);
 }
 
-__device__ double matern_fast2(int nu2, double x2, const double *__restrict__ logtab) {
+__device__ __forceinline__ double matern_fast2(int nu2, double x2,
+                                               const double *__restrict__ logtab) {
   if (x2 == 0.0) return 1.0;
   if ((nu2 & 1) || x2 > 4.0) return matern_far(nu2, x2, logtab);
   const double q = 0.25 * x2;
@@ -471,6 +473,12 @@ void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t 
 #pragma unroll
     for (int c = 0; c < MM; ++c) Lr[c] = Lm[g][rb + c];  // c > r: never read validly
     bool badl = false;
+    // the row index, opaque to the compiler: the per-column lane masks
+    // (r >= c, r == c) are then formed where they are used instead of being
+    // hoisted out of the retry loop as 2 x MM scalar register pairs, which
+    // spilled to vector-register lanes (a read-lane at every use)
+    int rq = r;
+    asm volatile("" : "+v"(rq));
     // fully unrolled at every MM, so Lr stays in registers (at MM = 64 the
     // default heuristics unroll it only in part and index Lr in scratch)
 #pragma clang loop unroll(full)
@@ -497,8 +505,8 @@ void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t 
       // that no valid result reads: lane r's own entries depend only on its
       // columns k <= r, and its results at columns c > r are discarded.
       Lr[c] = sacc * inv;
-      if (r >= c) Lm[g][rb + c] = Lr[c];
-      myinv = r == c ? inv : myinv;
+      if (rq >= c) Lm[g][rb + c] = Lr[c];
+      myinv = rq == c ? inv : myinv;
     }
     ok = !badl;
     if (__all(ok)) break;
