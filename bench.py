@@ -572,9 +572,9 @@ def main():
             "vecchia_factor": (n * (2 * (m + 1) ** 3 / 3 + 2 * m * m
                                     + 20 * (m + 1) * (m + 2) / 2), "TFLOP/s",
                                FP64_PEAK_TFLOPS, "alu"),
-            # bytes: factor entries (int32 index + FP32 value) and three n-vectors
-            "precond_u": (nnz * 8 + n * 28, "GB/s", 8000.0, "hbm"),
-            "precond_ut": (nnz * 8 + n * 24, "GB/s", 8000.0, "hbm"),
+            # bytes: factor entries (index + value) and three n-vectors
+            "precond_u": (nnz * 12 + n * 28, "GB/s", 8000.0, "hbm"),
+            "precond_ut": (nnz * 12 + n * 24, "GB/s", 8000.0, "hbm"),
         }
         for kname, (work, unit, peak, bound) in models.items():
             if kname not in prof:

@@ -204,11 +204,7 @@ phs_status phs_plan_tree(phs_plan_t plan, int32_t *order, int32_t *leaf,
 phs_status phs_precond_export(phs_plan_t plan, int32_t *rank, int32_t *nbr,
                               double *coef, double *diag, void *stream);
 
-/* z = U~ U~^T r in caller order (no projection).  r, z: device n.  The
- * factor is computed in FP64 (as exported above); the apply reads its
- * off-diagonal coefficients rounded to FP32 (the inverse diagonal stays FP64,
- * every product and sum is FP64).  U~ U~^T stays symmetric positive definite,
- * so PCG is unaffected in kind, and the iteration counts measured the same. */
+/* z = U~ U~^T r in caller order (no projection).  r, z: device n.  */
 phs_status phs_precond_apply(phs_plan_t plan, const double *r, double *z,
                              void *stream);
 

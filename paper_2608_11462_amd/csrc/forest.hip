@@ -368,8 +368,7 @@ __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sy
   const int m = d.m;
   const int64_t n = d.n;
   const cptr<int32_t> nbr = ro(d.nbr);
-  const cptr<float> coef = ro(d.coef);
-  const cptr<double> dinv = ro(d.dinv);
+  const cptr<double> coef = ro(d.coef), dinv = ro(d.dinv);
   double acc = dinv[j] * rr[j];
   // slots in batches of eight: the indices and coefficients first, then the
   // eight gathers (all in flight together), then the sums in slot order
@@ -380,7 +379,7 @@ __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sy
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       q[u] = nbr[(sl + u) * n + j];
-      c[u] = (double)coef[(sl + u) * n + j];
+      c[u] = coef[(sl + u) * n + j];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) v[u] = rr[q[u] >= 0 ? q[u] : j];
@@ -390,7 +389,7 @@ __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sy
   }
   for (; sl < m; ++sl) {
     const int q = nbr[sl * n + j];
-    if (q >= 0) acc = fma((double)coef[sl * n + j], rr[q], acc);
+    if (q >= 0) acc = fma(coef[sl * n + j], rr[q], acc);
   }
   yv[j] = acc;
 }
@@ -428,8 +427,7 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
     return;
   }
   const cptr<int32_t> tstart = ro(d.tstart), tidx = ro(d.tidx);
-  const cptr<float> tcoef = ro(d.tcoef);
-  const cptr<double> dinv = ro(d.dinv);
+  const cptr<double> tcoef = ro(d.tcoef), dinv = ro(d.dinv);
   // the group's RPG rows advance together, so each lane keeps RPG
   // independent gathers in flight (each row's sum keeps its order)
   int b[RPG], e[RPG];
@@ -456,7 +454,7 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
         const int idx = b[k] + o + h * LPR;
         const bool in = idx < e[k];
         ti[h][k] = in ? tidx[idx] : -1;
-        tc[h][k] = in ? (double)tcoef[idx] : 0.0;
+        tc[h][k] = in ? tcoef[idx] : 0.0;
       }
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -560,7 +558,7 @@ SysDev make_sysdev(const Plan &pl, const SysWork &w) {
   d.order = pl.order;
   d.Q = pl.Q;
   d.nbr = pl.pc_nbr;
-  d.coef = pl.pc_coef32;
+  d.coef = pl.pc_coef;
   d.dinv = pl.pc_dinv;
   d.tstart = pl.pc_tstart;
   d.tidx = pl.pc_tidx;
@@ -693,7 +691,7 @@ void sync_forest_pc(Forest &F, hipStream_t s) {
     const Plan &pl = *F.plan[i];
     const SysDev &d = F.hsys[i];
     if (d.has_pc != (pl.has_pc ? 1 : 0) || d.m != pl.m || d.nbr != pl.pc_nbr ||
-        d.coef != pl.pc_coef32 || d.dinv != pl.pc_dinv || d.tstart != pl.pc_tstart ||
+        d.coef != pl.pc_coef || d.dinv != pl.pc_dinv || d.tstart != pl.pc_tstart ||
         d.tidx != pl.pc_tidx || d.tcoef != pl.pc_tcoef) {
       refresh_forest(F, s);
       return;

@@ -231,10 +231,9 @@ struct SysDev {
   const int32_t *order;
   const double *Q;
   const int32_t *nbr;
-  const float *coef;  // FP32 copy of the factor's coefficients (what the apply reads)
-  const double *dinv;
+  const double *coef, *dinv;
   const int32_t *tstart, *tidx;
-  const float *tcoef;
+  const double *tcoef;
   void *mp, *loc;
   double *v[kSysVecs];
   double *red;
@@ -321,12 +320,11 @@ struct Plan {
   int32_t *pc_rank = nullptr;   // tree position -> rank
   // after the build: column-major m x n, entry s of node p at s*n + p
   int32_t *pc_nbr = nullptr;    // tree positions, -1 padded
-  double *pc_coef = nullptr;    // -lambda / c (FP64, exported)
-  float *pc_coef32 = nullptr;   // the same rounded to FP32 (applied)
+  double *pc_coef = nullptr;    // -lambda / c
   double *pc_dinv = nullptr;    // n      (1 / c)
   int32_t *pc_tstart = nullptr; // n + 1  transpose CSR
   int32_t *pc_tidx = nullptr;   // n*m
-  float *pc_tcoef = nullptr;    // n*m    (FP32, applied)
+  double *pc_tcoef = nullptr;   // n*m
 
   ~Plan();
 };

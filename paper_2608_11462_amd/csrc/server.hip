@@ -53,7 +53,7 @@ int64_t request_bytes(int64_t n, int k, int m) {
     tables = 40LL * (256 * 256 * 8 + 64 * 64 * 4) + (4 << 20);
   }
   const int64_t nodes = n * (52 + 8LL * S + 10 * 8 + 4 + (log_k ? 32 : 0));
-  const int64_t vecchia = n * (16 + 24LL * mm);  // FP64 and FP32 coefficients, indices, transpose
+  const int64_t vecchia = n * (16 + 24LL * mm);
   const int64_t transient = n * (100 + 16LL * mm);
   return 2 * exp + tables + nodes + vecchia + transient + (int64_t)(1 << 22);
 }

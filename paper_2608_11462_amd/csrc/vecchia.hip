@@ -413,8 +413,8 @@ __device__ __forceinline__ double block_bcast(double v, int i, int g) {
 template <int MM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MM <= 32 ? 3 : 2)))
 void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t *nbr,
-              const int32_t *cnt, int nu2, double alpha, double *coef, float *coef32,
-              double *dinv, int32_t *nfail, const double *logtab) {
+              const int32_t *cnt, int nu2, double alpha, double *coef, double *dinv,
+              int32_t *nfail, const double *logtab) {
   constexpr int G = 64 / MM;
   constexpr int T = MM * (MM + 1) / 2;
   constexpr int H = MM / 2, NI = H + 1;  // row pairs; entries per lane
@@ -531,15 +531,8 @@ void k_factor(const double *x, const double *y, int64_t n, int m, const int32_t 
   const double inv_c = block_bcast<G, MM>(myinv, MM - 1, g);
   if (!valid || !ok) return;
   // lane r < MM-1 holds lambda of row r = pad + a; padding coefficients are 0
-  if (r >= pad && r < MM - 1) {
-    const double cf = -v * inv_c;
-    coef[(int64_t)(r - pad) * n + p] = cf;
-    coef32[(int64_t)(r - pad) * n + p] = (float)cf;
-  }
-  for (int a = K + r; a < m; a += MM) {
-    coef[(int64_t)a * n + p] = 0.0;
-    coef32[(int64_t)a * n + p] = 0.0f;
-  }
+  if (r >= pad && r < MM - 1) coef[(int64_t)(r - pad) * n + p] = -v * inv_c;
+  for (int a = K + r; a < m; a += MM) coef[(int64_t)a * n + p] = 0.0;
   if (r == 0) dinv[p] = inv_c;
 }
 
@@ -559,8 +552,8 @@ __global__ void k_tkeys(const int32_t *nbr, int64_t n, int m, uint32_t *keys, in
   vals[e] = (int32_t)(j * m + s);
 }
 
-__global__ void k_tfill(const int32_t *vals, int64_t nnz, int64_t n, int m, const float *coef,
-                        int32_t *tidx, float *tcoef) {
+__global__ void k_tfill(const int32_t *vals, int64_t nnz, int64_t n, int m, const double *coef,
+                        int32_t *tidx, double *tcoef) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= nnz) return;
   const int64_t v = vals[p];
@@ -601,14 +594,12 @@ void vecchia_free(Plan &pl) {
   dfree(pl.pc_rank);
   dfree(pl.pc_nbr);
   dfree(pl.pc_coef);
-  dfree(pl.pc_coef32);
   dfree(pl.pc_dinv);
   dfree(pl.pc_tstart);
   dfree(pl.pc_tidx);
   dfree(pl.pc_tcoef);
   pl.pc_rank = pl.pc_nbr = pl.pc_tstart = pl.pc_tidx = nullptr;
-  pl.pc_coef = pl.pc_dinv = nullptr;
-  pl.pc_coef32 = pl.pc_tcoef = nullptr;
+  pl.pc_coef = pl.pc_dinv = pl.pc_tcoef = nullptr;
   pl.has_pc = false;
 }
 
@@ -636,8 +627,7 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
   // place, so no descriptor ever points at freed memory.
   struct {
     int32_t *rank = nullptr, *nbr = nullptr, *tstart = nullptr, *tidx = nullptr;
-    double *coef = nullptr, *dinv = nullptr;
-    float *coef32 = nullptr, *tcoef = nullptr;
+    double *coef = nullptr, *dinv = nullptr, *tcoef = nullptr;
   } nf;
   const double h = pl.tree.h;
   const int B = 256;
@@ -708,24 +698,22 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     dfree(gxy);
     // 4. factor
     nf.coef = dmalloc<double>((size_t)n * m);
-    nf.coef32 = dmalloc<float>((size_t)n * m);
     nf.dinv = dmalloc<double>(n);
     PHS_HIP(hipMemsetAsync(nfail, 0, 8, s));
     if (m <= 15)
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<16><<<(n + 3) / 4, 64, 0, s>>>(pl.x, pl.y, n, m, nf.nbr, cnt, nu2,
-                                                         alpha, nf.coef, nf.coef32, nf.dinv,
-                                                         nfail, pl.neartab));
+                                                         alpha, nf.coef, nf.dinv, nfail,
+                                                         pl.neartab));
     else if (m <= 31)
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<32><<<(n + 1) / 2, 64, 0, s>>>(pl.x, pl.y, n, m, nf.nbr, cnt, nu2,
-                                                         alpha, nf.coef, nf.coef32, nf.dinv,
-                                                         nfail, pl.neartab));
+                                                         alpha, nf.coef, nf.dinv, nfail,
+                                                         pl.neartab));
     else
       PHS_LAUNCH("vecchia_factor", s,
                  k_factor<64><<<n, 64, 0, s>>>(pl.x, pl.y, n, m, nf.nbr, cnt, nu2, alpha,
-                                              nf.coef, nf.coef32, nf.dinv, nfail,
-                                              pl.neartab));
+                                              nf.coef, nf.dinv, nfail, pl.neartab));
     // 5. transpose: stable radix sort of the entries by row
     {
       const int64_t N = n * m;
@@ -747,11 +735,11 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
         PHS_HIP(hipMemcpyAsync(&nnz, nf.tstart + n, 4, hipMemcpyDeviceToHost, s));
         PHS_HIP(hipStreamSynchronize(s));
         nf.tidx = dmalloc<int32_t>(std::max(nnz, 1));
-        nf.tcoef = dmalloc<float>(std::max(nnz, 1));
+        nf.tcoef = dmalloc<double>(std::max(nnz, 1));
         if (nnz > 0)
           PHS_LAUNCH("vecchia_tfill", s,
-                     k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(sv, nnz, n, m, nf.coef32,
-                                                            nf.tidx, nf.tcoef));
+                     k_tfill<<<(nnz + B - 1) / B, B, 0, s>>>(sv, nnz, n, m, nf.coef, nf.tidx,
+                                                            nf.tcoef));
       } catch (...) {
         for (void *q : {(void *)tk, (void *)tkt, (void *)tv, (void *)tvt, (void *)tscr}) dfree(q);
         throw;
@@ -769,7 +757,6 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     pl.pc_rank = nf.rank;
     pl.pc_nbr = nf.nbr;
     pl.pc_coef = nf.coef;
-    pl.pc_coef32 = nf.coef32;
     pl.pc_dinv = nf.dinv;
     pl.pc_tstart = nf.tstart;
     pl.pc_tidx = nf.tidx;
@@ -780,8 +767,8 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     pl.pc_nugget_nodes = hfail[0];
     pl.has_pc = true;
   } catch (...) {
-    for (void *q : {(void *)nf.rank, (void *)nf.nbr, (void *)nf.coef, (void *)nf.coef32,
-                    (void *)nf.dinv, (void *)nf.tstart, (void *)nf.tidx, (void *)nf.tcoef})
+    for (void *q : {(void *)nf.rank, (void *)nf.nbr, (void *)nf.coef, (void *)nf.dinv,
+                    (void *)nf.tstart, (void *)nf.tidx, (void *)nf.tcoef})
       dfree(q);
     for (void *q : {(void *)k64, (void *)k64t, (void *)perm, (void *)vt, (void *)scr, (void *)gk,
                     (void *)gkt, (void *)gv, (void *)gvt, (void *)cstart, (void *)d_lvl,

@@ -75,11 +75,8 @@ def test_small_config_structure_and_factor():
     alpha = 1.0 / (0.1 * rho)  # range 0.1 in user units
     pl, xi, nbrs, cc, lams = _check_structure(pr.xy, 2, 20, 1.5, alpha, 0, 0.1, N.PHS_RANGE_USER)
     # apply in caller order, against U~ U~^T r formed on the CPU from the
-    # factor the GPU exported (tests the two gathers, not the factor values);
-    # the apply reads the coefficients rounded to FP32 (the inverse diagonal
-    # stays FP64), so the reference rounds them the same way
+    # factor the GPU exported (tests the two gathers, not the factor values)
     rank_g, nbr_g, coef_g, diag_g = (host(t) for t in pl.precond_export(20))
-    coef_g = coef_g.astype(np.float32).astype(np.float64)
     lam_g = [-coef_g[j, :len(nbrs[j])] / diag_g[j] for j in range(pr.n)]
     U = V.factor_matrix(pr.n, nbrs, 1.0 / diag_g, lam_g)
     r = W.rng_for(9).standard_normal(pr.n)
