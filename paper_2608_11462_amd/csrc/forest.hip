@@ -487,14 +487,15 @@ __global__ void k_scatter_one(const double *__restrict__ src, const int32_t *__r
 }
 
 // The host copy stays alive with the forest, so the copy needs no wait.
+// A work table joins the forest's host table block (at a 256-byte boundary);
+// its device address is set when build_forest uploads the block.
 Tab upload_tab(Forest &F, std::vector<BlkRef> &&h, hipStream_t s) {
+  (void)s;
   Tab t;
   t.count = (int64_t)h.size();
-  t.d = dmalloc<BlkRef>(std::max<size_t>(h.size(), 1));
-  F.hcopies.push_back(std::move(h));
-  const auto &hc = F.hcopies.back();
-  if (!hc.empty())
-    PHS_HIP(hipMemcpyAsync(t.d, hc.data(), hc.size() * sizeof(BlkRef), hipMemcpyHostToDevice, s));
+  t.off = (int64_t)((F.htab.size() + 31) & ~(size_t)31);
+  F.htab.resize((size_t)t.off);
+  F.htab.insert(F.htab.end(), h.begin(), h.end());
   return t;
 }
 
@@ -603,10 +604,7 @@ Forest::~Forest() {
   dfree(mask_block);
   mask_block = nullptr;
   if (hpin) (void)hipHostFree(hpin);
-  dfree(vec.d);
-  dfree(dot.d);
-  dfree(pc.d);
-  for (auto &kv : cache) dfree(kv.second.d);
+  dfree(tab_block);
 }
 
 void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector<SysWork *> &work,
@@ -676,6 +674,13 @@ void build_forest(Forest &F, const std::vector<Plan *> &plans, const std::vector
       else dist_expansions(*pl, V_IN, s);
     }
   }
+  // all tables in one allocation and one copy
+  F.tab_block = dmalloc<BlkRef>(std::max<size_t>(F.htab.size(), 1));
+  if (!F.htab.empty())
+    PHS_HIP(hipMemcpyAsync(F.tab_block, F.htab.data(), F.htab.size() * sizeof(BlkRef),
+                           hipMemcpyHostToDevice, s));
+  for (Tab *t : {&F.vec, &F.dot, &F.pc}) t->d = F.tab_block + t->off;
+  for (auto &kv : F.cache) kv.second.d = F.tab_block + kv.second.off;
   F.frozen = true;
 }
 

@@ -333,6 +333,7 @@ struct Plan {
 struct Tab {
   BlkRef *d = nullptr;
   int64_t count = 0;
+  int64_t off = 0;  // first entry in the forest's table block
 };
 
 struct Forest {
@@ -352,7 +353,11 @@ struct Forest {
   bool mask_pending[kMasks] = {};
   double *hgsc = nullptr;  // packed scalar readback (nsys x 8), pinned, written by the GPU
   void *hpin = nullptr;                    // one pinned block: host masks + hgsc
-  std::vector<std::vector<BlkRef>> hcopies;  // host sources of the table uploads
+  // every work table of the forest, concatenated on the host while the forest
+  // is built and uploaded in one copy into tab_block at its end (the host
+  // copy is the source of that copy and is kept with the forest)
+  std::vector<BlkRef> htab;
+  BlkRef *tab_block = nullptr;
   Tab vec, dot, pc;                     // element blocks, dot blocks, 8-row blocks
   std::vector<std::pair<uint64_t, Tab>> cache;  // FMM tables keyed by (kind, K, P, level)
   bool any_direct = false;  // some system's plan applies M by direct summation
