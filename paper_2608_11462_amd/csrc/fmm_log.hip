@@ -199,7 +199,19 @@ __global__ void kf_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   for (int c = c0; c < c1; ++c) {
     const int child = (2 * iy + (c >> 1)) * Gc + 2 * ix + (c & 1);
     const V2<T> *row = m2m + ((int64_t)c * (P + 1) + lc) * (P + 1);
-    for (int k = 0; k <= lc; ++k)
+    // four terms' loads in flight at a time, summed in k order
+    int k = 0;
+    for (; k + 4 <= lc + 1; k += 4) {
+      C2<T> mv[4], av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        mv[u] = ld2<T>(row + k + u);
+        av[u] = ld2<T>(&Ac[((int64_t)(k + u) * nd + r) * nbc + child]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = cadd(acc, cmul(mv[u], av[u]));
+    }
+    for (; k <= lc; ++k)
       acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Ac[((int64_t)k * nd + r) * nbc + child])));
   }
   if (split == 4) {
@@ -620,7 +632,19 @@ __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   const int parent = (iy >> 1) * Gp + (ix >> 1);
   const V2<T> *row = l2l + ((int64_t)c * (P + 1) + j) * (P + 1);
   C2<T> acc = {T(0), T(0)};
-  for (int k = j + sq; k <= P; k += split)
+  // four terms' loads in flight at a time, summed in k order
+  int k = j + sq;
+  for (; k + 3 * split <= P; k += 4 * split) {
+    C2<T> mv[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      mv[u] = ld2<T>(row + k + u * split);
+      bv[u] = ld2<T>(&Bp[((int64_t)(k + u * split) * nd + r) * nbp + parent]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = cadd(acc, cmul(mv[u], bv[u]));
+  }
+  for (; k <= P; k += split)
     acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Bp[((int64_t)k * nd + r) * nbp + parent])));
   if (split == 4) {
     acc.re = quad_sum(acc.re);
