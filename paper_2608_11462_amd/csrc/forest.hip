@@ -387,9 +387,21 @@ __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sy
     for (int u = 0; u < 8; ++u)
       if (q[u] >= 0) acc = fma(c[u], v[u], acc);
   }
-  for (; sl < m; ++sl) {
-    const int q = nbr[sl * n + j];
-    if (q >= 0) acc = fma(coef[sl * n + j], rr[q], acc);
+  if (sl < m) {
+    // the last m mod 8 slots as one padded batch (their loads in flight together)
+    int q[8];
+    double c[8], v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = sl + u < m;
+      q[u] = in ? nbr[(sl + u) * n + j] : -1;
+      c[u] = in ? coef[(sl + u) * n + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = rr[q[u] >= 0 ? q[u] : j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q[u] >= 0) acc = fma(c[u], v[u], acc);
   }
   yv[j] = acc;
 }
@@ -439,9 +451,13 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
     e[k] = in ? tstart[i0 + k + 1] : 0;
     len = max(len, e[k] - b[k]);
   }
-  double acc[RPG];
+  double acc[RPG], dg[RPG];
 #pragma unroll
-  for (int k = 0; k < RPG; ++k) acc[k] = 0.0;
+  for (int k = 0; k < RPG; ++k) {
+    acc[k] = 0.0;
+    // the diagonal term, loaded before the gathers (it does not depend on them)
+    dg[k] = i0 + k < d.n ? dinv[i0 + k] * yy[i0 + k] : 0.0;
+  }
   // two entries of each of the RPG rows per step: 2 x RPG independent
   // gathers in flight per lane, each row still summed in entry order
   for (int o = g; o < len; o += 2 * LPR) {
@@ -470,7 +486,7 @@ __global__ __launch_bounds__(256) void kf_apply_u(const SysDev *__restrict__ sys
   for (int k = 0; k < RPG; ++k) {
     const int64_t i = i0 + k;
     const double sum = group_sum<LPR>(acc[k]);
-    if (i < d.n && g == wl) z[i] = dinv[i] * yy[i] + sum;
+    if (i < d.n && g == wl) z[i] = dg[k] + sum;
   }
 }
 
