@@ -406,12 +406,33 @@ __device__ __forceinline__ double near_range8(double xi, double yi, PXY xy2, PT 
       }
     }
   }
-  for (; j < je; ++j) {
-    const double dx = xi - xy2[2 * j], dy = yi - xy2[2 * j + 1];
-    const double r2 = fma(dy, dy, dx * dx);
-    double ph = r2 * near_log(r2, tab);
-    if constexpr (K == 4) ph *= r2;
-    acc = fma(ph, t[j], acc);
+  if (j < je) {
+    // the last (je - js) mod 8 sources as one padded batch: loads clamped to
+    // the range, padding with density 0 (each adds an exact zero)
+    const int cnt = je - j;
+    double r2[8], tj[8], ic[8], lc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int jj = i < cnt ? j + i : je - 1;
+      const double dx = xi - xy2[2 * jj], dy = yi - xy2[2 * jj + 1];
+      r2[i] = fma(dy, dy, dx * dx);
+      const double tv = t[jj];
+      tj[i] = i < cnt ? tv : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(r2[i]) >> 32);
+      const double2 e = *reinterpret_cast<const double2 *>(
+          reinterpret_cast<const char *>(tab) + near_log_offset(hi));
+      ic[i] = e.x;
+      lc[i] = e.y;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      double ph = r2[i] * near_log_core(r2[i], ic[i], lc[i]);
+      if constexpr (K == 4) ph *= r2[i];
+      acc = fma(ph, tj[i], acc);
+    }
   }
   return acc;
 }
