@@ -926,12 +926,13 @@ __device__ __forceinline__ double near_sym_split(double xi, double yi, double ti
 // One wavefront per leaf: each lane one target node.  Far field by Horner on
 // the leaf's incoming expansions (L2P) combined with U_r; near field by
 // direct phi over the 3x3 neighbouring leaves (step 2: direct evaluation).
-// Held to 96 VGPRs, five wavefronts per SIMD (the FP64 form otherwise takes
-// 121 at k = 2: four): at n = 2^20 the FP64 leaf pass took 0.441 against
-// 0.454 ms at k = 2 and 0.683 against 0.685 ms at k = 4, with a few lane-group
-// set-up values spilled.
+// Held to 96 VGPRs, five wavefronts per SIMD, at k = 2 (the FP64 form
+// otherwise takes 121: four): at n = 2^20 the FP64 leaf pass took 0.441
+// against 0.454 ms, with a few lane-group set-up values spilled; six were no
+// faster.  k = 4 (one more multiply a pair) is held to 80 VGPRs, six
+// wavefronts: 0.62 against 0.64 ms.
 template <class T, class TN, int K>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void kf_leaf_eval(const SysDev *__restrict__ sys,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 4 ? 6 : 5))) void kf_leaf_eval(const SysDev *__restrict__ sys,
                                                    const BlkRef *__restrict__ tab,
                                                    const int32_t *__restrict__ mask, int P,
                                                    int in, int out,
