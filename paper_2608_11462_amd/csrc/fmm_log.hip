@@ -922,6 +922,116 @@ __device__ __forceinline__ double near_sym_split(double xi, double yi, double ti
   return acc;
 }
 
+// FP32 forms of the lane exchanges and of the symmetric batch (the FP32 near
+// field of the mixed and near32 matvecs): a 32-bit value moves in one swap or
+// DPP operation.
+template <int C>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), C, 0xf, 0xf, false));
+}
+template <int B>
+__device__ __forceinline__ float lane_halve_f(float lo, float hi, int lane) {
+  if constexpr (B == 5 || B == 4) {
+    const auto sw = B == 5 ? __builtin_amdgcn_permlane32_swap((unsigned)__float_as_int(lo),
+                                                               (unsigned)__float_as_int(hi),
+                                                               false, false)
+                           : __builtin_amdgcn_permlane16_swap((unsigned)__float_as_int(lo),
+                                                               (unsigned)__float_as_int(hi),
+                                                               false, false);
+    return __int_as_float((int)sw[0]) + __int_as_float((int)sw[1]);
+  } else {
+    constexpr int C = B == 3 ? kDppRor8 : B == 2 ? kDppHalfMirror : B == 1 ? kDppXor2 : kDppXor1;
+    const bool up = (lane >> B) & 1;
+    return (up ? hi : lo) + dpp_f32<C>(up ? lo : hi);
+  }
+}
+template <int B>
+__device__ __forceinline__ float lane_fold_f(float v) {
+  constexpr int C = B == 2 ? kDppHalfMirror : B == 1 ? kDppXor2 : kDppXor1;
+  return v + dpp_f32<C>(v);
+}
+template <int LW>
+__device__ __forceinline__ float lane_sum8_f(const float (&T)[8], int lane) {
+  float a[4], b[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = lane_halve_f<LW - 1>(T[k], T[k + 4], lane);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) b[k] = lane_halve_f<LW - 2>(a[k], a[k + 2], lane);
+  float c = lane_halve_f<LW - 3>(b[0], b[1], lane);
+  if constexpr (LW >= 6) c = lane_fold_f<2>(c);
+  if constexpr (LW >= 5) c = lane_fold_f<1>(c);
+  if constexpr (LW >= 4) c = lane_fold_f<0>(c);
+  return c;
+}
+
+// One FP32 batch of up to eight sources of one neighbouring leaf (coordinates
+// relative to its centre, the target moved into that frame) for the W = 2^LW
+// lanes of a group.  phi is formed from log2, so the source sums are stored
+// times ln 2 (the combine pass applies the 1/2 of phi = (1/2) r^k log r^2).
+template <int K, int LW, bool FULL, class PF>
+__device__ __forceinline__ void sym_batch_f(float xc, float yc, float ti, PF ux, PF uy, PF tf,
+                                            int j, int cnt, int jmax, int lane,
+                                            const SymDst &o, float &acc) {
+  float T[8];
+  const int k = (lane >> (LW - 3)) & 7;
+  const int jk = j + k;
+  const bool wr = (lane & ((1 << (LW - 3)) - 1)) == 0 && k < cnt;
+  const gptr<double> dst = rw(o.part + (int64_t)o.dbase * o.n + jk);
+  const double prev = (o.accum && wr) ? *dst : 0.0;
+  float sx[8], sy[8], tj[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if constexpr (FULL) {
+      sx[i] = ux[j + i];
+      sy[i] = uy[j + i];
+      tj[i] = tf[j + i];
+    } else {
+      const int jj = j + i < jmax ? j + i : jmax;
+      sx[i] = ux[jj];
+      sy[i] = uy[jj];
+      const float tv = tf[jj];
+      tj[i] = i < cnt ? tv : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float dx = xc - sx[i], dy = yc - sy[i];
+    const float ph = phi_r2f<K>(dx * dx + dy * dy);
+    acc += ph * tj[i];
+    T[i] = ph * ti;
+  }
+  const float v = lane_sum8_f<LW>(T, lane);
+  if (wr) *dst = prev + 0.69314718055994530942 * (double)v;
+}
+
+// The FP32 symmetric sums of one neighbouring leaf [js, je) into slot dbase:
+// all 64 lanes on one target each (batches of eight, the last padded), or
+// 64/W groups of W = 2^LW lanes on the same targets over 1/(64/W) of the
+// sources each.
+template <int K, int LW, class PF>
+__device__ __forceinline__ float near_sym_f(float xc, float yc, float ti, PF ux, PF uy, PF tf,
+                                            int js, int je, int lane, const SymDst &o) {
+  float acc = 0.0f;
+  if constexpr (LW == 6) {
+    int j = js;
+    for (; j + 8 <= je; j += 8)
+      sym_batch_f<K, 6, true>(xc, yc, ti, ux, uy, tf, j, 8, j + 7, lane, o, acc);
+    if (j < je) sym_batch_f<K, 6, false>(xc, yc, ti, ux, uy, tf, j, je - j, je - 1, lane, o, acc);
+  } else {
+    constexpr int ng = 64 >> LW;
+    const int g = lane >> LW, len = je - js;
+    const int gs = js + len * g / ng, ge = js + len * (g + 1) / ng;
+    const int nb = ((len + ng - 1) / ng + 7) / 8;
+    for (int b = 0; b < nb; ++b) {
+      const int j = gs + 8 * b;
+      const int cnt = ge - j;
+      sym_batch_f<K, LW, false>(xc, yc, ti, ux, uy, tf, j, cnt < 0 ? 0 : (cnt > 8 ? 8 : cnt),
+                                je - 1, lane, o, acc);
+    }
+  }
+  return acc;
+}
+
 // ------------------------------------------------------------------ leaf
 // One wavefront per leaf: each lane one target node.  Far field by Horner on
 // the leaf's incoming expansions (L2P) combined with U_r; near field by
@@ -972,6 +1082,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 4 ? 6 :
   // symmetrically (the W neighbour and the row below deliver their pairs
   // through this leaf's partial-sum slots; a slot whose writer leaf is absent
   // or empty is cleared here)
+  // (the FP32 near fields, of the mixed and near32 matvecs, take the same
+  // pairs symmetrically, leaf by leaf in each leaf's own frame)
   constexpr bool kSym = std::is_same<TN, double>::value;
   int eE = e, us = 0, ue = 0, ub1 = 0, ub2 = 0, zmask = 0;
   if constexpr (kSym) {
@@ -983,19 +1095,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 4 ? 6 :
       ub1 = start[rb + ix];
       ub2 = start[rb + ix + 1];
     }
-    if (!(ix > 0 && start[leaf - 1] < b)) zmask |= 8;
+  }
+  if (!(ix > 0 && start[leaf - 1] < b)) zmask |= 8;
 #pragma unroll
-    for (int dd = 0; dd < 3; ++dd) {
-      const int col = ix + dd - 1;
-      const bool has = iy > 0 && col >= 0 && col < G &&
-                       start[(iy - 1) * G + col] < start[(iy - 1) * G + col + 1];
-      if (!has) zmask |= 1 << dd;
-    }
+  for (int dd = 0; dd < 3; ++dd) {
+    const int col = ix + dd - 1;
+    const bool has = iy > 0 && col >= 0 && col < G &&
+                     start[(iy - 1) * G + col] < start[(iy - 1) * G + col + 1];
+    if (!has) zmask |= 1 << dd;
   }
   for (int i0 = b; i0 < e; i0 += 64) {
     // a later pass over this leaf adds to the source sums the first one stored
     // (possibly from other lanes): the barrier orders those accesses
-    if (kSym && i0 > b) __syncthreads();
+    if (i0 > b) __syncthreads();
     // A pass with at most 32 targets left (the tail of a leaf of more than 64
     // nodes, or a small leaf) runs G = 64/W groups of W lanes on the same W
     // targets, each group over 1/G of every source range, and sums the groups'
@@ -1063,36 +1175,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 4 ? 6 :
     } else {
       // coordinates relative to each point's own leaf centre: the target is
       // moved into the frame of each neighbouring leaf once, so a pair costs
-      // one subtraction per axis; densities from the FP32 copy
+      // one subtraction per axis; densities from the FP32 copy.  The own leaf
+      // one-sided, the E leaf and the three leaves of the row above
+      // symmetrically, one leaf (one frame) at a time.
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
       const float uxi = ux[ii], uyi = uy[ii];
       const cptr<float> tf = ro((const float *)d.t32);
+      const float ti = act ? tf[i] : 0.0f;
       const int ng = 64 / W;
-      for (int row = r0; row <= r1; ++row) {
-        const float uyc = uyi + (float)((iy - row) * w);
-        for (int col = c0; col <= c1; ++col) {
-          const float uxc = uxi + (float)((ix - col) * w);
-          const int js = start[row * G + col], je = start[row * G + col + 1];
-          if (W == 64) {
-            nearv += near_range_f32<K>(uxc, uyc, ux, uy, tf, js, je);
-          } else {
-            const int len = je - js;
-            for (int j = js + len * gi / ng; j < js + len * (gi + 1) / ng; ++j) {
-              const float dx = uxc - ux[j], dy = uyc - uy[j];
-              nearv += phi_r2f<K>(dx * dx + dy * dy) * tf[j];
-            }
-          }
+      if (W == 64) {
+        nearv = near_range_f32<K>(uxi, uyi, ux, uy, tf, b, e);
+      } else {
+        const int len = e - b;
+        for (int j = b + len * gi / ng; j < b + len * (gi + 1) / ng; ++j) {
+          const float dx = uxi - ux[j], dy = uyi - uy[j];
+          nearv += phi_r2f<K>(dx * dx + dy * dy) * tf[j];
         }
       }
+      const auto fwd = [&](int row, int col, int dir) {
+        const int js = start[row * G + col], je = start[row * G + col + 1];
+        if (je <= js) return;
+        const float uyc = uyi + (float)((iy - row) * w);
+        const float uxc = uxi + (float)((ix - col) * w);
+        const SymDst o{d.npart, d.n, dir, INT_MAX, INT_MAX, i0 > b};
+        if (W == 64)
+          nearv += near_sym_f<K, 6>(uxc, uyc, ti, ux, uy, tf, js, je, ln, o);
+        else if (W == 32)
+          nearv += near_sym_f<K, 5>(uxc, uyc, ti, ux, uy, tf, js, je, ln, o);
+        else if (W == 16)
+          nearv += near_sym_f<K, 4>(uxc, uyc, ti, ux, uy, tf, js, je, ln, o);
+        else
+          nearv += near_sym_f<K, 3>(uxc, uyc, ti, ux, uy, tf, js, je, ln, o);
+      };
+      if (ix + 1 < G) fwd(iy, ix + 1, 3);
+      if (iy + 1 < G)
+        for (int col = c0; col <= c1; ++col) fwd(iy + 1, col, ix - col + 1);
       for (int o = W; o < 64; o <<= 1) nearv += __shfl_xor(nearv, o);
       nearv *= phi_scale_f<K>();
     }
     if (act && gi == 0) {
       ytree[i] = (double)far + (double)nearv;
-      if constexpr (kSym) {
 #pragma unroll
-        for (int dd = 0; dd < 4; ++dd)
-          if ((zmask >> dd) & 1) d.npart[(int64_t)dd * d.n + i] = 0.0;
-      }
+      for (int dd = 0; dd < 4; ++dd)
+        if ((zmask >> dd) & 1) d.npart[(int64_t)dd * d.n + i] = 0.0;
     }
   }
 }
@@ -1362,7 +1488,7 @@ void leaf_pass(Forest &F, const int32_t *mask, int in, int out, int P, const dou
     PHS_LAUNCH(name, s,
                kf_leaf_eval<T, TN, 4><<<(unsigned)t4.count, 64, 0, s>>>(F.dsys, t4.d, mask, P,
                                                                       in, out, logtab));
-  if (std::is_same<TN, double>::value && t2.count + t4.count > 0) f_near_combine(F, mask, out, s);
+  if (t2.count + t4.count > 0) f_near_combine(F, mask, out, s);
 }
 
 const Plan &log_ref(const Forest &F) {
