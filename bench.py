@@ -42,6 +42,7 @@ FP32_NOPACK_TFLOPS = 78.6  # MI355X vector FP32 without packed math (this build)
 #  M2L per (target, source, density): (P+1)^2 real-by-complex MACs (4 flops)
 #  + 12 (P+1) for the two diagonal scalings
 FLOP_PAIR = 9
+N_P2P = 1 << 16  # nodes of the all-pairs P2P measurement
 
 
 def progress(msg: str) -> None:
@@ -543,6 +544,26 @@ def main():
         prof32 = N.profile_read()
         N.profile_enable(False)
     pl.close()
+    # the all-pairs P2P kernel of exact-matvec plans (the hybrid solver's
+    # operator), FP32 and FP64, on the first N_P2P nodes of the workload:
+    # every one of the N_P2P^2 pairs is formed, so the work is known exactly
+    if not args.no_profile:
+        pd = N.Plan(xy[:N_P2P].contiguous(), 2, 1, matvec=N.PHS_MATVEC_DIRECT)
+        vd = v[:N_P2P].contiguous()
+        for p in (N.PHS_FP64, N.PHS_MIXED):
+            pd.matvec(vd, p)
+        torch.cuda.synchronize()
+        N.profile_enable(2)
+        N.profile_read()
+        for _ in range(10):
+            for p in (N.PHS_FP64, N.PHS_MIXED):
+                pd.matvec(vd, p)
+        torch.cuda.synchronize()
+        for kname, val in N.profile_read().items():
+            if kname in ("direct", "direct_f32"):
+                prof32[kname] = val
+        N.profile_enable(False)
+        pd.close()
 
     # rooflines from the HIP-event durations of the timed region
     roofs = {}
@@ -552,7 +573,7 @@ def main():
         P, R, m = last["P"], last["R"], 30
         P32 = 15  # FP32 expansion order of the plan
         nnz = n * m - m * (m + 1) // 2
-        for kname in ("leaf_eval_f32", "m2l_f32"):
+        for kname in ("leaf_eval_f32", "m2l_f32", "direct", "direct_f32"):
             if kname in prof32:
                 prof[kname] = prof32[kname]
         models = {
@@ -569,6 +590,9 @@ def main():
                     FP64_PEAK_TFLOPS, "mfma"),
             "m2l_f32": (m2l_pairs * R * (4 * (P32 + 1) ** 2 + 12 * (P32 + 1)), "TFLOP/s",
                         FP32_NOPACK_TFLOPS, "alu"),
+            # all-pairs P2P: N_P2P^2 pairs at the near-pair flop count
+            "direct": (N_P2P * N_P2P * FLOP_PAIR, "TFLOP/s", FP64_PEAK_TFLOPS, "alu"),
+            "direct_f32": (N_P2P * N_P2P * FLOP_PAIR, "TFLOP/s", FP32_NOPACK_TFLOPS, "alu"),
             "vecchia_factor": (n * (2 * (m + 1) ** 3 / 3 + 2 * m * m
                                     + 20 * (m + 1) * (m + 2) / 2), "TFLOP/s",
                                FP64_PEAK_TFLOPS, "alu"),

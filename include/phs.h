@@ -442,7 +442,7 @@ void phs_set_graphs(int32_t on);
 
 /* Per-kernel timing.  on = 1: each library kernel launch is bracketed by HIP
  * events on its own stream; on = 2: only the leaf, M2L, Vecchia factor and
- * KNN, and preconditioner-apply kernels; 0: off.  phs_profile_read copies up
+ * KNN, preconditioner-apply and all-pairs kernels; 0: off.  phs_profile_read copies up
  * to `cap` records (name, launches, total milliseconds) to host arrays and
  * resets the counters.  names: host array of `cap` char[48].  Returns the
  * number of records. */

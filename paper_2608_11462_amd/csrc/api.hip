@@ -87,9 +87,9 @@ bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed); }
 // level 2 times only the kernels the roofline figures use
 bool prof_wants(const char *name) {
   if (g_prof_level != 2) return true;
-  static const char *keep[] = {"leaf_eval", "leaf_eval_near32", "leaf_eval_f32", "m2l",
-                               "m2l_f32", "vecchia_factor", "vecchia_knn", "precond_u",
-                               "precond_ut"};
+  static const char *keep[] = {"leaf_eval",  "leaf_eval_near32", "leaf_eval_f32", "m2l",
+                               "m2l_f32",    "vecchia_factor",   "vecchia_knn",   "precond_u",
+                               "precond_ut", "direct",           "direct_f32"};
   for (const char *k : keep)
     if (std::strcmp(k, name) == 0) return true;
   return false;
