@@ -370,37 +370,22 @@ __global__ __launch_bounds__(256) void kf_apply_ut(const SysDev *__restrict__ sy
   const cptr<int32_t> nbr = ro(d.nbr);
   const cptr<double> coef = ro(d.coef), dinv = ro(d.dinv);
   double acc = dinv[j] * rr[j];
-  // slots in batches of eight: the indices and coefficients first, then the
-  // eight gathers (all in flight together), then the sums in slot order
-  int sl = 0;
-  for (; sl + 8 <= m; sl += 8) {
-    int q[8];
-    double c[8], v[8];
+  // slots in batches of sixteen, the last one padded: the indices and
+  // coefficients first, then the sixteen gathers (all in flight together),
+  // then the sums in slot order
+  for (int sl = 0; sl < m; sl += 16) {
+    int q[16];
+    double c[16], v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      q[u] = nbr[(sl + u) * n + j];
-      c[u] = coef[(sl + u) * n + j];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = rr[q[u] >= 0 ? q[u] : j];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (q[u] >= 0) acc = fma(c[u], v[u], acc);
-  }
-  if (sl < m) {
-    // the last m mod 8 slots as one padded batch (their loads in flight together)
-    int q[8];
-    double c[8], v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const bool in = sl + u < m;
       q[u] = in ? nbr[(sl + u) * n + j] : -1;
       c[u] = in ? coef[(sl + u) * n + j] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = rr[q[u] >= 0 ? q[u] : j];
+    for (int u = 0; u < 16; ++u) v[u] = rr[q[u] >= 0 ? q[u] : j];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
       if (q[u] >= 0) acc = fma(c[u], v[u], acc);
   }
   yv[j] = acc;
