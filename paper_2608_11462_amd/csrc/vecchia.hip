@@ -119,115 +119,261 @@ __global__ void k_qkeys(const int32_t *__restrict__ rank, int64_t n, int T, uint
   vals[p] = t;
 }
 
-// Ordered nearest predecessors; one thread per query (in the order above),
-// lists in LDS.
-__global__ __launch_bounds__(64) void k_knn(const double *xr, const double *yr, int64_t n,
-                                            int m, int T, double h, const int32_t *gbits,
-                                            const int64_t *cell_off, const int32_t *cell_start,
-                                            const int32_t *sorted_rank,
-                                            const double2 *__restrict__ gxy,
-                                            const int32_t *pos_of_rank,
-                                            const int32_t *__restrict__ qord, int32_t *nbr,
-                                            int32_t *cnt_out) {
-  // per-lane candidate lists, m entries each (dynamic LDS: 64 m (8 + 4) bytes)
-  extern __shared__ double d2s[];
-  int *rks = (int *)(d2s + 64 * m);
-  const int lane = threadIdx.x;
-  const int64_t qi = blockIdx.x * (int64_t)64 + lane;
-  if (qi >= n) return;
-  const int64_t t = qord[qi];  // query rank
-  const int K = (int)(t < m ? t : m);
-  const int p = pos_of_rank[t];
-  if (K == 0) {
-    cnt_out[p] = 0;
-    for (int s = 0; s < m; ++s) nbr[(int64_t)s * n + p] = -1;
-    return;
-  }
-  int lv = 64 - __clzll((unsigned long long)t);  // smallest lv with 2^lv >= t+1
-  if (lv > T) lv = T;
-  const int gb = gbits[lv];
-  const int g = 1 << gb;
-  const double cw = 2.0 * h / g;
-  const double qx = xr[t], qy = yr[t];
-  const int cqx = grid_cell(qx, h, g), cqy = grid_cell(qy, h, g);
-  const int32_t *cs = cell_start + cell_off[lv];
-  int cnt = 0;
-  // worst kept candidate (the list's last entry), cached in registers
-  double wd2 = INFINITY;
-  int wrk = 0x7fffffff;
-  const int maxR = max(max(cqx, g - 1 - cqx), max(cqy, g - 1 - cqy));
-  for (int R = 0; R <= maxR; ++R) {
-    for (int cy = cqy - R; cy <= cqy + R; ++cy) {
-      if (cy < 0 || cy >= g) continue;
-      const bool edge_row = (cy == cqy - R) || (cy == cqy + R);
-      const int step = edge_row ? 1 : 2 * R;
-      for (int cx = cqx - R; cx <= cqx + R; cx += (step > 0 ? step : 1)) {
-        if (cx >= 0 && cx < g) {
-          bool visit = true;
-          if (cnt == K) {
-            // skip a cell that cannot hold a point closer than the worst kept
-            // one (strictly; a tie at equal d^2 could still win on rank)
-            const double lo_x = -h + cx * cw, lo_y = -h + cy * cw;
-            const double ex = fmax(fmax(lo_x - qx, qx - (lo_x + cw)), 0.0);
-            const double ey = fmax(fmax(lo_y - qy, qy - (lo_y + cw)), 0.0);
-            visit = (ex * ex + ey * ey) * (1.0 - 1e-12) <= wd2;
-          }
-          if (visit) {
-            const int c = cy * g + cx;
-            const int b = cs[c], e = cs[c + 1];
-            // the rank and coordinates of the next candidate are loaded while
-            // the current one is processed
-            int rn = b < e ? sorted_rank[b] : 0x7fffffff;
-            double2 xn = b < e ? gxy[b] : make_double2(0.0, 0.0);
-            for (int q = b; q < e; ++q) {
-              const int r = rn;
-              const double2 cxy = xn;
-              if (q + 1 < e) {
-                rn = sorted_rank[q + 1];
-                xn = gxy[q + 1];
-              }
-              if (r >= t) break;  // within a cell entries ascend by rank
-              double d2;
-              {
-                // each product rounded, then the sum: no fused multiply-add, so
-                // d^2 is symmetric in (dx, dy) and identical to the CPU reference
+// Squared distance with each product rounded, then the sum: no fused
+// multiply-add, so d^2 is symmetric in (dx, dy) and identical to the CPU
+// reference.
+__device__ __forceinline__ double sq_dist(double ax, double ay, double qx, double qy) {
 #pragma clang fp contract(off)
-                const double dx = cxy.x - qx;
-                const double dy = cxy.y - qy;
-                d2 = dx * dx + dy * dy;
-              }
-              int pos;
-              if (cnt < K) {
-                pos = cnt++;
-              } else {
-                if (!lessp(d2, r, wd2, wrk)) continue;
-                pos = K - 1;
-              }
-              while (pos > 0 && lessp(d2, r, d2s[(pos - 1) * 64 + lane], rks[(pos - 1) * 64 + lane])) {
-                d2s[pos * 64 + lane] = d2s[(pos - 1) * 64 + lane];
-                rks[pos * 64 + lane] = rks[(pos - 1) * 64 + lane];
-                --pos;
-              }
-              d2s[pos * 64 + lane] = d2;
-              rks[pos * 64 + lane] = r;
-              if (cnt == K) {
-                wd2 = d2s[(K - 1) * 64 + lane];
-                wrk = rks[(K - 1) * 64 + lane];
-              }
-            }
+  const double dx = ax - qx;
+  const double dy = ay - qy;
+  return dx * dx + dy * dy;
+}
+
+// Lane exchanges within a 16-lane group (one DPP row): xor 1, 2, 8 and the
+// mirrors of 4, 8 and 16 lanes by DPP, xor 4 by a swizzle.
+constexpr int kX1 = 0xB1, kX2 = 0x4E, kX4 = -1, kX8 = 0x128;
+constexpr int kM4 = 0x1B, kM8 = 0x141, kM16 = 0x140;
+
+template <int C>
+__device__ __forceinline__ int xchg_i(int v) {
+  if constexpr (C == kX4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);  // and 31, xor 4
+  else return __builtin_amdgcn_update_dpp(0, v, C, 0xF, 0xF, false);
+}
+template <int C>
+__device__ __forceinline__ double xchg_d(double v) {
+  return __hiloint2double(xchg_i<C>(__double2hiint(v)), xchg_i<C>(__double2loint(v)));
+}
+
+// Compare-exchange of the key (d, r) with the partner lane's: this lane keeps
+// the smaller key if keep_min, else the larger.  Keys are unique but for the
+// empty key (+inf, INT_MAX), whose copies are interchangeable.
+template <int C>
+__device__ __forceinline__ void cmp_xchg(double &d, int &r, bool keep_min) {
+  const double pd = xchg_d<C>(d);
+  const int pr = xchg_i<C>(r);
+  const bool pless = lessp(pd, pr, d, r);
+  if (keep_min == pless) {
+    d = pd;
+    r = pr;
+  }
+}
+
+// Ascending sort of one key per lane over a 16-lane group: bitonic merges of
+// 2, 4, 8, 16 keys, each a flip (lane against its mirror in the block) and
+// half-cleaners.
+__device__ __forceinline__ void sort16(double &d, int &r, int li) {
+  cmp_xchg<kX1>(d, r, !(li & 1));
+  cmp_xchg<kM4>(d, r, !(li & 2));
+  cmp_xchg<kX1>(d, r, !(li & 1));
+  cmp_xchg<kM8>(d, r, !(li & 4));
+  cmp_xchg<kX2>(d, r, !(li & 2));
+  cmp_xchg<kX1>(d, r, !(li & 1));
+  cmp_xchg<kM16>(d, r, !(li & 8));
+  cmp_xchg<kX4>(d, r, !(li & 4));
+  cmp_xchg<kX2>(d, r, !(li & 2));
+  cmp_xchg<kX1>(d, r, !(li & 1));
+}
+
+// The 16E smallest of a sorted list (entry e*16 + li in Ld[e], Lr[e]) and 16
+// sorted keys (one per lane): the list against the keys reversed and padded
+// with empty keys below them, the smaller of each pair, is a bitonic sequence
+// of the 16E smallest; half-cleaners sort it.
+template <int E>
+__device__ __forceinline__ void merge16(double (&Ld)[E], int (&Lr)[E], double d, int r, int li) {
+  const double md = xchg_d<kM16>(d);
+  const int mr = xchg_i<kM16>(r);
+  if (lessp(md, mr, Ld[E - 1], Lr[E - 1])) {
+    Ld[E - 1] = md;
+    Lr[E - 1] = mr;
+  }
+#pragma unroll
+  for (int D = E / 2; D >= 1; D /= 2)  // distances 16 D, within a lane
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (!(e & D) && lessp(Ld[e + D], Lr[e + D], Ld[e], Lr[e])) {
+        const double td = Ld[e];
+        const int tr = Lr[e];
+        Ld[e] = Ld[e + D];
+        Lr[e] = Lr[e + D];
+        Ld[e + D] = td;
+        Lr[e + D] = tr;
+      }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    cmp_xchg<kX8>(Ld[e], Lr[e], !(li & 8));
+    cmp_xchg<kX4>(Ld[e], Lr[e], !(li & 4));
+    cmp_xchg<kX2>(Ld[e], Lr[e], !(li & 2));
+    cmp_xchg<kX1>(Ld[e], Lr[e], !(li & 1));
+  }
+}
+
+// Ordered nearest predecessors: sigma(j) = the K = min(m, rank) predecessors
+// with the smallest (d^2, rank).  A group of 16 lanes takes one query (four
+// per wavefront, in the order above) and keeps its list sorted across its
+// lanes, 16E entries (16E >= m).  Rings of cells around the query's cell are
+// searched outwards: the group's lanes take 16 cells of a ring at a time
+// (cells that cannot hold a key below the K-th kept one are skipped once the
+// list holds K), a prefix sum over the cells' entry counts numbers their
+// entries, and the entries go in chunks of 16, one per lane.  A chunk with a
+// predecessor below the K-th kept key (any predecessor while the list holds
+// fewer than K) is sorted and merged into the list.  The search stops when
+// the ring just searched bounds every unsearched cell beyond the K-th key.
+// The comparisons are exact, so the lists are those of the definition,
+// whatever the order the cells are visited in.
+template <int E>
+__global__ __launch_bounds__(256) void k_knn(const double *xr, const double *yr, int64_t n,
+                                             int m, int T, double h, const int32_t *gbits,
+                                             const int64_t *cell_off, const int32_t *cell_start,
+                                             const int32_t *sorted_rank,
+                                             const double2 *__restrict__ gxy,
+                                             const int32_t *pos_of_rank,
+                                             const int32_t *__restrict__ qord, int32_t *nbr,
+                                             int32_t *cnt_out) {
+  // per lane: start and exclusive entry prefix of the cell it took
+  __shared__ int s_b[256], s_x[256];
+  const int lane = threadIdx.x & 63, li = lane & 15;
+  const int gl = lane & 48;            // the group's first lane in the wavefront
+  const int gt = threadIdx.x & ~15;    // ... and its first thread in the block
+  const int64_t qi = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const bool live = qi < n;
+  int64_t t = 0;
+  int K = 0, p = 0, g = 1, cqx = 0, cqy = 0, maxR = 0;
+  double cw = 1.0, qx = 0.0, qy = 0.0;
+  const int32_t *cs = cell_start;
+  if (live) {
+    t = qord[qi];
+    K = (int)(t < m ? t : m);
+    p = pos_of_rank[t];
+    int lv = 64 - __clzll((unsigned long long)t);  // smallest lv with 2^lv >= t+1
+    if (lv > T) lv = T;
+    g = 1 << gbits[lv];
+    cw = 2.0 * h / g;
+    qx = xr[t];
+    qy = yr[t];
+    cqx = grid_cell(qx, h, g);
+    cqy = grid_cell(qy, h, g);
+    cs = cell_start + cell_off[lv];
+    maxR = max(max(cqx, g - 1 - cqx), max(cqy, g - 1 - cqy));
+  }
+  double Ld[E];
+  int Lr[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    Ld[e] = INFINITY;
+    Lr[e] = 0x7fffffff;
+  }
+  int seen = 0;  // predecessors offered to the list (the group's count)
+  double wd2 = INFINITY;  // the K-th kept key once seen >= K
+  int wrk = 0x7fffffff;
+  bool done = !live || K == 0;
+  for (int R = 0;; ++R) {
+    if (!done) {
+      const int ncells = R == 0 ? 1 : 8 * R;
+      for (int cb = 0; cb < ncells; cb += 16) {
+        // the ring's cells: the row below (2R+1), the row above (2R+1), then
+        // the two side columns in between
+        const int ci = cb + li;
+        int cx = cqx, cy = cqy;
+        if (R > 0) {
+          if (ci < 2 * R + 1) {
+            cx = cqx - R + ci;
+            cy = cqy - R;
+          } else if (ci < 4 * R + 2) {
+            cx = cqx - R + (ci - 2 * R - 1);
+            cy = cqy + R;
+          } else {
+            const int sidx = ci - 4 * R - 2;
+            cy = cqy - R + 1 + (sidx >> 1);
+            cx = (sidx & 1) ? cqx + R : cqx - R;
           }
         }
-        if (R == 0) break;
+        bool cv = ci < ncells && cx >= 0 && cx < g && cy >= 0 && cy < g;
+        if (cv && seen >= K) {
+          // skip a cell that cannot hold a point closer than the K-th kept
+          // one (strictly; a tie at equal d^2 could still win on rank)
+          const double lo_x = -h + cx * cw, lo_y = -h + cy * cw;
+          const double ex = fmax(fmax(lo_x - qx, qx - (lo_x + cw)), 0.0);
+          const double ey = fmax(fmax(lo_y - qy, qy - (lo_y + cw)), 0.0);
+          cv = (ex * ex + ey * ey) * (1.0 - 1e-12) <= wd2;
+        }
+        int b = 0, cnt = 0;
+        if (cv) {
+          const int c = cy * g + cx;
+          b = cs[c];
+          cnt = cs[c + 1] - b;
+        }
+        // inclusive prefix sum of the counts over the group's 16 lanes
+        int inc = cnt;
+        inc += __builtin_amdgcn_update_dpp(0, inc, 0x111, 0xF, 0xF, false);  // row_shr:1
+        inc += __builtin_amdgcn_update_dpp(0, inc, 0x112, 0xF, 0xF, false);  // row_shr:2
+        inc += __builtin_amdgcn_update_dpp(0, inc, 0x114, 0xF, 0xF, false);  // row_shr:4
+        inc += __builtin_amdgcn_update_dpp(0, inc, 0x118, 0xF, 0xF, false);  // row_shr:8
+        const int total = __shfl(inc, gl + 15);
+        s_b[threadIdx.x] = b;
+        s_x[threadIdx.x] = inc - cnt;
+        __builtin_amdgcn_wave_barrier();
+        for (int j0 = 0; j0 < total; j0 += 16) {
+          const int j = j0 + li;
+          // the cell of entry j: the last of the group's cells whose
+          // exclusive prefix is at most j (empty cells share their successor's)
+          int c = 0;
+#pragma unroll
+          for (int st = 8; st >= 1; st >>= 1)
+            if (s_x[gt + c + st] <= j) c += st;
+          double d2 = INFINITY;
+          int r = 0x7fffffff;
+          bool valid = false;
+          if (j < total) {
+            const int q = s_b[gt + c] + (j - s_x[gt + c]);
+            const int rq = sorted_rank[q];
+            if (rq < t) {
+              const double2 cxy = gxy[q];
+              d2 = sq_dist(cxy.x, cxy.y, qx, qy);
+              r = rq;
+              valid = true;
+            }
+          }
+          const bool better = valid && (seen < K || lessp(d2, r, wd2, wrk));
+          const unsigned gv = (unsigned)(__ballot(valid) >> gl) & 0xFFFFu;
+          const unsigned gb = (unsigned)(__ballot(better) >> gl) & 0xFFFFu;
+          if (gb) {
+            sort16(d2, r, li);
+            merge16<E>(Ld, Lr, d2, r, li);
+          }
+          seen += __popc(gv);
+          if (gb && seen >= K) {
+            const int kr = (K - 1) >> 4, kl = (K - 1) & 15;
+            double wv = Ld[0];
+            int wr = Lr[0];
+#pragma unroll
+            for (int e = 1; e < E; ++e)
+              if (e == kr) {
+                wv = Ld[e];
+                wr = Lr[e];
+              }
+            wd2 = __shfl(wv, gl + kl);
+            wrk = __shfl(wr, gl + kl);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (R >= maxR) {
+        done = true;
+      } else if (seen >= K && R >= 1) {
+        const double bound = (double)R * cw;
+        if (wd2 < bound * bound * (1.0 - 1e-12)) done = true;
       }
     }
-    if (cnt == K && R >= 1) {
-      const double bound = (double)R * cw;
-      if (wd2 < bound * bound * (1.0 - 1e-12)) break;
-    }
+    if (__ballot(!done) == 0) break;
   }
-  cnt_out[p] = cnt;
-  for (int s = 0; s < m; ++s)
-    nbr[(int64_t)s * n + p] = s < cnt ? pos_of_rank[rks[s * 64 + lane]] : -1;
+  if (!live) return;
+  const int cnt = seen < K ? seen : K;
+  if (li == 0) cnt_out[p] = cnt;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int s = e * 16 + li;
+    if (s < m) nbr[(int64_t)s * n + p] = s < cnt ? pos_of_rank[Lr[e]] : -1;
+  }
 }
 
 // ---------------------------------------------------------------- Matern
@@ -692,9 +838,9 @@ void vecchia_build(Plan &pl, const phs_precond_opts &o, hipStream_t s) {
     }
     nf.nbr = dmalloc<int32_t>((size_t)n * m);
     PHS_LAUNCH("vecchia_knn", s,
-               k_knn<<<(n + 63) / 64, 64, (size_t)64 * m * 12, s>>>(xr, yr, n, m, T, h, d_gb,
-                                                                   d_coff, cstart, gv,
-                                                  gxy, pos_of_rank, qord, nf.nbr, cnt));
+               (m <= 16 ? k_knn<1> : m <= 32 ? k_knn<2> : k_knn<4>)<<<(n + 15) / 16, 256, 0, s>>>(
+                   xr, yr, n, m, T, h, d_gb, d_coff, cstart, gv, gxy, pos_of_rank, qord, nf.nbr,
+                   cnt));
     dfree(gxy);
     // 4. factor
     nf.coef = dmalloc<double>((size_t)n * m);

@@ -135,7 +135,7 @@ def traffic(fetch_dir: str, write_dir: str, out: str, fcmd: str, wcmd: str) -> N
             "commands": [fcmd, wcmd]}, indent=1) + "\n")
 
 
-SQ_KERNELS = ["kf_leaf_eval<double, double, 2>", "kf_m2l_mfma<27>", "k_factor<32>", "k_knn",
+SQ_KERNELS = ["kf_leaf_eval<double, double, 2>", "kf_m2l_mfma<27>", "k_factor<32>", "k_knn<2>",
               "kf_apply_u", "kf_apply_ut"]
 
 
