@@ -102,6 +102,34 @@ def test_lattice_ties_bit_exact():
     _check_structure(xy, 2, 12, 1.5, 5.0, 77, 0.2, N.PHS_RANGE_NORMALIZED)
 
 
+@pytest.mark.parametrize("m", [1, 8, 16, 17, 32, 33, 63])
+def test_conditioning_sets_bit_exact_list_sizes(m):
+    """The search keeps each query's ordered list in blocks of 16 entries
+    spread over 16 lanes (one, two or four blocks for m <= 16, 32, 63): every
+    block count and the boundaries between them, on uniform nodes mixed with
+    a lattice (many exactly tied distances, broken by rank), against the
+    oracle's brute force (Sec. 3: the m nearest predecessors in the random
+    ordering).  Only the ordering and the sets are compared."""
+    g = np.arange(16) / 15.0
+    lat = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
+    xy = np.concatenate([W.uniform_points(W.rng_for(900 + m), 1500), 0.5 * lat + 0.25])
+    n = len(xy)
+    print(f"[case] conditioning sets m={m} n={n}", flush=True)
+    pl = N.Plan(dev(xy), 2)
+    pl.precond_build(m=m, nu=0.5, seed=m)
+    rank_g, nbr_g, _, _ = (host(t) for t in pl.precond_export(m))
+    pl.close()
+    c, rho, xi = D.normalize(xy, 2)
+    perm, rank = V.order(n, m)
+    np.testing.assert_array_equal(rank_g, rank)
+    nbrs = V.ordered_knn(xi, perm, rank, m)
+    for j in range(n):
+        s = nbrs[j]
+        assert len(s) == min(m, rank[j])
+        np.testing.assert_array_equal(nbr_g[j, :len(s)], s)
+        assert np.all(nbr_g[j, len(s):] == -1)
+
+
 def test_nu2_structure_k4():
     xy = W.uniform_points(W.rng_for(42), 1500)
     print("[case] k=4 nu=2 n=1500", flush=True)
