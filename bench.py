@@ -32,7 +32,7 @@ sys.path.insert(0, str(ROOT))
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64 (and FP64 matrix)
 FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 with packed math
-FP32_NOPACK_TFLOPS = 78.6  # MI355X vector FP32 without packed math (this build)
+FP32_NOPACK_TFLOPS = 78.6  # MI355X vector FP32 without packed math (the kernels are built without it)
 
 # Algorithmic flop counts used for the rooflines (one convention throughout):
 #  near-field pair: 2 sub, r^2 (mul + fma = 3), 1 transcendental counted as 1,
@@ -449,8 +449,8 @@ def batch_leg(N, W, torch, n_prob: int, maxit: int = 300, retune: bool = False):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are "
-                          "not part of it (see DESIGN.md for how the path would shard)",
+        print(json.dumps({"error": "bench.py measures one GPU only: the solver runs on a "
+                          "single MI355X and has no multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
