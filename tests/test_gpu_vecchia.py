@@ -130,6 +130,28 @@ def test_conditioning_sets_bit_exact_list_sizes(m):
         assert np.all(nbr_g[j, len(s):] == -1)
 
 
+@pytest.mark.parametrize("n,m", [(3, 30), (7, 30), (17, 16), (33, 63), (65, 63), (100, 63)])
+def test_conditioning_sets_small_n(n, m):
+    """Fewer nodes than (or about as many as) the set size: node j keeps all
+    min(m, rank_j) predecessors, and queries end their search at the grid's
+    edge rather than by the ring bound."""
+    xy = W.uniform_points(W.rng_for(950 + n), n)
+    print(f"[case] small conditioning sets n={n} m={m}", flush=True)
+    pl = N.Plan(dev(xy), 2)
+    pl.precond_build(m=m, nu=0.5, seed=n)
+    rank_g, nbr_g, _, _ = (host(t) for t in pl.precond_export(m))
+    pl.close()
+    c, rho, xi = D.normalize(xy, 2)
+    perm, rank = V.order(n, n)
+    np.testing.assert_array_equal(rank_g, rank)
+    nbrs = V.ordered_knn(xi, perm, rank, m)
+    for j in range(n):
+        s = nbrs[j]
+        assert len(s) == min(m, rank[j])
+        np.testing.assert_array_equal(nbr_g[j, :len(s)], s)
+        assert np.all(nbr_g[j, len(s):] == -1)
+
+
 def test_nu2_structure_k4():
     xy = W.uniform_points(W.rng_for(42), 1500)
     print("[case] k=4 nu=2 n=1500", flush=True)
