@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-crossover", action="store_true")
+    ap.add_argument("--no-tree-leg", action="store_true",
+                    help="skip the uniform-against-clustered tree cost leg")
     return ap.parse_args()
 
 
@@ -226,6 +228,64 @@ def crossover_leg(N, W, torch):
         if cross is None and t["fmm"] < t["direct"]:
             cross = n
     return {"k": 2, "matvec_ms": rows, "fmm_faster_from_n": cross}
+
+
+def tree_leg(N, W, torch, n: int = 1 << 20):
+    """Cost of the uniform quadtree on clustered nodes: the FP64 k = 2 matvec
+    on n uniform nodes against n nodes of which 30 % lie in ten Gaussian
+    clusters of sigma 0.02 (the serving stream's clustered requests).  The
+    clustered tree is deeper (its leaf level keeps the largest leaf below a
+    bound), so empty boxes pay M2L and sparse leaves pay the near-field pass;
+    the uniform matvec at the same n is what an adaptive tree could at best
+    recover.  Leaf and M2L milliseconds from HIP events, the whole matvec by
+    wall clock."""
+    dev = torch.device("cuda")
+    out = {"n": n, "k": 2}
+    for name, xy in (("uniform", W.uniform_points(W.rng_for(31), n)),
+                     ("clustered", W.clustered_points(W.rng_for(32), n))):
+        pl = N.Plan(torch.as_tensor(xy, device=dev), 2, 1)
+        v = torch.as_tensor(W.rng_for(33).standard_normal(n), device=dev)
+        for _ in range(3):
+            pl.matvec(v)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pl.matvec(v)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps * 1e3
+        N.profile_enable(2)
+        N.profile_read()
+        for _ in range(reps):
+            pl.matvec(v)
+        torch.cuda.synchronize()
+        prof = N.profile_read()
+        N.profile_enable(False)
+        out[name] = {"leaf_level": pl.leaf_level, "matvec_ms": round(wall, 4),
+                     **{k + "_ms": round(prof[k][1] / prof[k][0], 4)
+                        for k in ("leaf_eval", "m2l") if k in prof}}
+        pl.close()
+    out["clustered_over_uniform"] = round(out["clustered"]["matvec_ms"]
+                                          / out["uniform"]["matvec_ms"], 3)
+    # the clustered nodes at other leaf sizes (the level follows from the
+    # size, deepened while the largest leaf exceeds 16 times it)
+    xy = torch.as_tensor(W.clustered_points(W.rng_for(32), n), device=dev)
+    v = torch.as_tensor(W.rng_for(33).standard_normal(n), device=dev)
+    rows = []
+    for ls in (256, 64, 16):
+        pl = N.Plan(xy, 2, 1, leaf_size=ls)
+        for _ in range(3):
+            pl.matvec(v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            pl.matvec(v)
+        torch.cuda.synchronize()
+        rows.append({"leaf_size": ls, "leaf_level": pl.leaf_level,
+                     "matvec_ms": round((time.perf_counter() - t0) / 10 * 1e3, 4)})
+        pl.close()
+    out["clustered_by_leaf_size"] = rows
+    return out
 
 
 def serve_leg(N, W, torch, n_req: int, loads=(0.8,)):
@@ -664,6 +724,9 @@ def main():
     if not args.no_crossover:
         out["fmm_direct_crossover"] = crossover_leg(N, W, torch)
         progress("crossover leg done")
+    if not args.no_tree_leg:
+        out["tree_cost"] = tree_leg(N, W, torch)
+        progress("tree cost leg done")
     if not args.no_serve and args.serve_requests > 0:
         sv = serve_leg(N, W, torch, args.serve_requests)
         out["serve_p50_ms"], out["serve_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
