@@ -89,6 +89,17 @@ __device__ __forceinline__ T quad_sum(T v) {
   return v;
 }
 
+// Sum over each group of sixteen consecutive lanes (one DPP row: quad
+// permutations, then the half-row and row mirrors), the result in all
+// sixteen lanes.  The whole row must be active.
+template <class T>
+__device__ __forceinline__ T row_sum16(T v) {
+  v = quad_sum(v);
+  v += __builtin_amdgcn_update_dpp(T(0), v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(T(0), v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return v;
+}
+
 // Number of core densities for order K.
 template <int K> struct Rank;
 template <> struct Rank<1> { static constexpr int R = 1; };

@@ -173,7 +173,8 @@ __global__ __launch_bounds__(256) void kf_p2m(const SysDev *__restrict__ sys,
 // ------------------------------------------------------------------ M2M
 // Work item: 256 lanes over (parent box, density, coefficient) triples of one
 // level; on coarse levels four lanes per triple, lane c summing child c's
-// contribution, added over the quad.
+// contribution, added over the quad, and on the coarsest sixteen, lane 4q + c
+// summing child c's terms k = q mod 4, added over the row.
 template <class T>
 __global__ void kf_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
                        const int32_t *__restrict__ mask, int lp, int P,
@@ -186,11 +187,13 @@ __global__ void kf_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   const int64_t nbp = (int64_t)Gp * Gp, nbc = 4 * nbp;
   const int split = shift_split(lp);
   const int64_t tid = (int64_t)br.blk * 256 + threadIdx.x;
-  if (tid >= nbp * nd * (P + 1) * split) return;  // whole quads
+  if (tid >= nbp * nd * (P + 1) * split) return;  // whole lane groups
   const cptr<V2<T>> Ac = ro((const V2<T> *)d.mp + level_base(lp + 1, P, nd));
   const gptr<V2<T>> Ap = rw((V2<T> *)d.mp + level_base(lp, P, nd));
-  const int64_t o = split == 4 ? tid >> 2 : tid;
-  const int c0 = split == 4 ? (int)(tid & 3) : 0, c1 = split == 4 ? c0 + 1 : 4;
+  const int sub = (int)(tid & (split - 1));
+  const int64_t o = tid / split;
+  const int c0 = split >= 4 ? (sub & 3) : 0, c1 = split >= 4 ? c0 + 1 : 4;
+  const int ks = split == 16 ? 4 : 1, kq = split == 16 ? (sub >> 2) : 0;  // terms k = kq mod ks
   const int box = (int)(o % nbp);
   const int64_t rest = o / nbp;
   const int r = (int)(rest % nd), lc = (int)(rest / nd);
@@ -200,24 +203,28 @@ __global__ void kf_m2m(const SysDev *__restrict__ sys, const BlkRef *__restrict_
     const int child = (2 * iy + (c >> 1)) * Gc + 2 * ix + (c & 1);
     const V2<T> *row = m2m + ((int64_t)c * (P + 1) + lc) * (P + 1);
     // four terms' loads in flight at a time, summed in k order
-    int k = 0;
-    for (; k + 4 <= lc + 1; k += 4) {
+    int k = kq;
+    for (; k + 3 * ks <= lc; k += 4 * ks) {
       C2<T> mv[4], av[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        mv[u] = ld2<T>(row + k + u);
-        av[u] = ld2<T>(&Ac[((int64_t)(k + u) * nd + r) * nbc + child]);
+        mv[u] = ld2<T>(row + k + u * ks);
+        av[u] = ld2<T>(&Ac[((int64_t)(k + u * ks) * nd + r) * nbc + child]);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc = cadd(acc, cmul(mv[u], av[u]));
     }
-    for (; k <= lc; ++k)
+    for (; k <= lc; k += ks)
       acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Ac[((int64_t)k * nd + r) * nbc + child])));
   }
-  if (split == 4) {
+  if (split == 16) {
+    acc.re = row_sum16(acc.re);
+    acc.im = row_sum16(acc.im);
+    if (sub != 0) return;
+  } else if (split == 4) {
     acc.re = quad_sum(acc.re);
     acc.im = quad_sum(acc.im);
-    if (c0 != 0) return;
+    if (sub != 0) return;
   }
   st2<T>(&Ap[((int64_t)lc * nd + r) * nbp + box], acc);
 }
@@ -605,8 +612,8 @@ void kf_m2l_mfma(const SysDev *__restrict__ sys,
 
 // ------------------------------------------------------------------ L2L
 // Work item: 256 lanes over (child box, density, coefficient) triples of one
-// level; on coarse levels four lanes per triple over every fourth parent
-// coefficient, added over the quad.
+// level; on coarse levels four or sixteen lanes per triple over every fourth
+// or sixteenth parent coefficient, added over the quad or the row.
 template <class T>
 __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict__ tab,
                        const int32_t *__restrict__ mask, int lc, int P,
@@ -619,11 +626,11 @@ __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   const int64_t nbc = (int64_t)Gc * Gc, nbp = nbc / 4;
   const int split = shift_split(lc);
   const int64_t tid = (int64_t)br.blk * 256 + threadIdx.x;
-  if (tid >= nbc * nd * (P + 1) * split) return;  // whole quads
+  if (tid >= nbc * nd * (P + 1) * split) return;  // whole lane groups
   const gptr<V2<T>> Bp = rw((V2<T> *)d.loc + level_base(lc - 1, P, nd));
   const gptr<V2<T>> Bc = rw((V2<T> *)d.loc + level_base(lc, P, nd));
-  const int64_t o = split == 4 ? tid >> 2 : tid;
-  const int sq = split == 4 ? (int)(tid & 3) : 0;
+  const int64_t o = tid / split;
+  const int sq = (int)(tid & (split - 1));
   const int box = (int)(o % nbc);
   const int64_t rest = o / nbc;
   const int r = (int)(rest % nd), j = (int)(rest / nd);
@@ -646,7 +653,11 @@ __global__ void kf_l2l(const SysDev *__restrict__ sys, const BlkRef *__restrict_
   }
   for (; k <= P; k += split)
     acc = cadd(acc, cmul(ld2<T>(row + k), ld2<T>(&Bp[((int64_t)k * nd + r) * nbp + parent])));
-  if (split == 4) {
+  if (split == 16) {
+    acc.re = row_sum16(acc.re);
+    acc.im = row_sum16(acc.im);
+    if (sq != 0) return;
+  } else if (split == 4) {
     acc.re = quad_sum(acc.re);
     acc.im = quad_sum(acc.im);
     if (sq != 0) return;

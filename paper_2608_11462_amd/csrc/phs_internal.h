@@ -144,7 +144,10 @@ inline int64_t boxes_at(int l) { return int64_t(1) << (2 * l); }
 // Lanes per output of the log M2M / L2L kernels on level l: the coarse levels,
 // whose few threads each run a long chain of dependent loads, split every
 // sum over a quad of lanes.
-__host__ __device__ inline int shift_split(int l) { return l <= 5 ? 4 : 1; }
+// lanes per output coefficient of the generic M2M / L2L kernels: the coarse
+// levels have few boxes, so each output is spread over more lanes (shorter
+// chains of dependent loads per lane)
+__host__ __device__ inline int shift_split(int l) { return l <= 3 ? 16 : l <= 5 ? 4 : 1; }
 
 // Number of core-kernel densities (Hadamard rank) for order k.
 inline int hadamard_rank(int k) {
